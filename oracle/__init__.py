@@ -1,0 +1,135 @@
+"""CPU oracle for restarted GMRES(m) with level-1 MGS, one-reduce lagged MGS and
+two-reduce lagged CGS2 (arXiv:1809.05805, Sections II-III).
+
+TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package. The arithmetic lives in
+``oracle_gmres.c`` (plain sequential FP64 C, built with gcc, no HIP); this
+module is its ctypes wrapper plus NumPy diagnostics that read the basis and the
+Hessenberg matrix the oracle dumps. It shares no code with the GPU library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle_gmres.c")
+_LIB = os.path.join(_HERE, "liboracle_gmres.so")
+
+SCHEMES = {"mgs": 0, "mgs1r": 1, "cgs2": 2}
+STATUS = {0: "ok", -1: "invalid argument", -3: "non-finite value"}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2: no FMA contraction, no vector ISA flags)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                        "-ffp-contract=off", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("cycles", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("breakdown", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("rel_res_true", ctypes.c_double),
+                ("rel_res_est", ctypes.c_double), ("reductions", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_gmres_solve.restype = ctypes.c_int
+        lib.oracle_gmres_solve.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, ctypes.c_int32,
+                                           ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_int64,
+                                           ctypes.POINTER(_Info), P, P, P, P, P, P, P]
+        lib.oracle_spmv.restype = None
+        lib.oracle_spmv.argtypes = [ctypes.c_int64, P, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class OracleResult:
+    status: int
+    x: np.ndarray
+    iters: int
+    cycles: int
+    converged: bool
+    breakdown: bool
+    rel_res_true: float
+    rel_res_est: float
+    reductions: int
+    hist: np.ndarray          # |g_k|/||b|| per completed column
+    j: int = 0                # columns of the last cycle that completed any
+    V: np.ndarray | None = None   # n x (m+2), basis of that cycle
+    H: np.ndarray | None = None   # (m+1) x m, unrotated Hessenberg matrix
+    T: np.ndarray | None = None   # (m+2) x (m+2), Malard-Paige T (one-reduce only)
+    g: np.ndarray | None = None   # rotated right-hand side
+    S2: np.ndarray | None = None  # (m+1) x m, CGS2 second-pass coefficients
+
+
+def solve(row_ptr, col_idx, vals, b, x0, m: int, scheme: str = "mgs1r", rtol: float = 1e-8,
+          max_iters: int | None = None, dump: bool = False) -> OracleResult:
+    """Restarted GMRES(m) on host arrays; see ``oracle_gmres.h`` for the contract."""
+    lib = _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = row_ptr.shape[0] - 1
+    x = np.array(x0, dtype=np.float64, copy=True)
+    if max_iters is None:
+        max_iters = min(10 * n, 10**6)
+    hist = np.full(max(int(max_iters), 1), np.nan)
+    V = H = T = g = S2 = None
+    if dump:
+        V = np.zeros((m + 2, n))            # row-major (m+2, n) == column-major n x (m+2)
+        H = np.zeros((m, m + 1))
+        T = np.zeros((m + 2, m + 2))
+        g = np.zeros(m + 2)
+        S2 = np.zeros((m, m + 1))
+    j = ctypes.c_int32(0)
+    info = _Info()
+    st = lib.oracle_gmres_solve(n, col_idx.shape[0], _ptr(row_ptr), _ptr(col_idx), _ptr(vals), m,
+                                SCHEMES[scheme], _ptr(b), _ptr(x), float(rtol), int(max_iters),
+                                ctypes.byref(info), _ptr(hist), _ptr(V), _ptr(H), _ptr(T), _ptr(g),
+                                _ptr(S2), ctypes.byref(j))
+    res = OracleResult(st, x, info.iters, info.cycles, bool(info.converged), bool(info.breakdown),
+                       info.rel_res_true, info.rel_res_est, info.reductions,
+                       hist[: info.iters].copy(), j.value)
+    if dump:
+        res.V = V.T          # n x (m+2) view
+        res.H = H.T          # (m+1) x m
+        res.T = T.T
+        res.g = g
+        res.S2 = S2.T
+    return res
+
+
+def spmv(row_ptr, col_idx, vals, x) -> np.ndarray:
+    lib = _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(row_ptr.shape[0] - 1)
+    lib.oracle_spmv(y.shape[0], _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(x), _ptr(y))
+    return y

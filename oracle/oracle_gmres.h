@@ -1,0 +1,81 @@
+/*
+ * CPU oracle for restarted GMRES(m) with three Gram-Schmidt schemes, written
+ * from Swirydowicz, Langou, Ananthan, Yang, Thomas, "Low synchronization GMRES
+ * algorithms" (arXiv:1809.05805).
+ *
+ * TEST INFRASTRUCTURE ONLY. This is the slow, obviously sequential FP64
+ * reference that the GPU library is checked against. Only the tests, the
+ * smoke check and the benchmark's CPU-baseline leg may load it. It shares no
+ * source with the GPU library: no headers, kernels, helpers or constants.
+ *
+ * All pointers are host pointers. Sums are taken in index order, one at a
+ * time, with no blocking or reordering, so a reader can check every line
+ * against the paper.
+ */
+#ifndef ORACLE_GMRES_H
+#define ORACLE_GMRES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Orthogonalization scheme. */
+enum {
+  ORACLE_MGS = 0,    /* level-1 MGS-GMRES (Algorithm "MGS-GMRES", Section III)     */
+  ORACLE_MGS_1R = 1, /* one-synchronization lagged compact-WY MGS (Sections II-III) */
+  ORACLE_CGS2 = 2    /* two-synchronization lagged CGS2 (Section II, level-2 CGS2)  */
+};
+
+enum {
+  ORACLE_OK = 0,
+  ORACLE_ERR_ARG = -1,
+  ORACLE_ERR_NONFINITE = -3
+};
+
+typedef struct {
+  int64_t iters;       /* Arnoldi columns completed over all cycles            */
+  int32_t cycles;      /* restart cycles that completed at least one column    */
+  int32_t converged;   /* 1 if the true residual met rtol*||b||                */
+  int32_t breakdown;   /* 1 if some cycle ended on an exact (happy) breakdown  */
+  int32_t pad;
+  double rel_res_true; /* ||b - A x||_2 / ||b||_2 at exit                      */
+  double rel_res_est;  /* last implicit |g_j| / ||b||_2                        */
+  int64_t reductions;  /* global reductions (inner-product synchronizations)   */
+} oracle_info;
+
+/*
+ * Solve A x = b by restarted GMRES(m).
+ *   n, nnz, row_ptr[n+1], col_idx[nnz], vals[nnz]: CSR matrix, int32 indices.
+ *   m >= 1: restart length. scheme: ORACLE_MGS / ORACLE_MGS_1R / ORACLE_CGS2.
+ *   b[n]; x[n]: initial guess on entry, solution on exit.
+ *   rtol >= 0: stop when the residual 2-norm is <= rtol*||b||_2.
+ *   max_iters >= 0: cap on Arnoldi columns.
+ *   info: filled on return (may be NULL).
+ *   hist_res (nullable, length max_iters): |g_k|/||b|| after each column.
+ *   Dump of the last cycle (each nullable):
+ *     V_out  n x (m+2), column-major, ld = n: the basis;
+ *     H_out  (m+1) x m, column-major, ld = m+1: the unrotated Hessenberg matrix;
+ *     T_out  (m+2) x (m+2), column-major: Malard-Paige T (one-reduce only);
+ *     g_out  m+2: the rotated right-hand side;
+ *     S2_out (m+1) x m, column-major: CGS2's second-pass coefficients s
+ *            (zero for the other schemes);
+ *     j_out  number of columns the last cycle completed.
+ * Returns ORACLE_OK, ORACLE_ERR_ARG or ORACLE_ERR_NONFINITE.
+ */
+int oracle_gmres_solve(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                       const double* vals, int32_t m, int32_t scheme, const double* b, double* x,
+                       double rtol, int64_t max_iters, oracle_info* info, double* hist_res,
+                       double* V_out, double* H_out, double* T_out, double* g_out, double* S2_out,
+                       int32_t* j_out);
+
+/* y = A x, sequential sum over each row in CSR order. */
+void oracle_spmv(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
+                 const double* x, double* y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

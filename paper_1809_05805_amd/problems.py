@@ -1,0 +1,228 @@
+"""Seeded synthetic linear systems ``A x = b`` in CSR form.
+
+This module only builds inputs: matrices, right-hand sides and initial guesses.
+It holds none of the solver's arithmetic, and it is the one module that both the
+GPU path's callers (tests, benchmark) and the CPU oracle's callers draw inputs
+from.
+
+The paper's matrices (thermal1, Parabolic FEM, the Nalu wind-turbine systems of
+Section V) are not available, so the workloads are synthetic stand-ins with the
+same row structure (7 and 27 nonzeros per row) and the same physics family
+(advection-diffusion, Section V's incompressible-flow momentum systems):
+
+* ``convdiff``: -eps*Laplace(u) + a.grad(u) on the unit square/cube, N interior
+  points per side, h = 1/(N+1), zero Dirichlet boundary with the boundary
+  couplings dropped, lexicographic ordering with x fastest, first-order upwind
+  convection, global Peclet number Pe = |a|_2 / eps.
+* ``stencil27_illcond``: 27-point stencil with unit diagonal, off-diagonals
+  N(0,1)/27, rows scaled by 10**(8*U(0,1)) for a condition number near 1e8.
+* ``simonici``: the diagonal test matrix of Section V-A,
+  diag(1e-8, 2, 3, ..., 100) with a normalized random right-hand side.
+
+Random numbers come from ``numpy.random.PCG64`` seeded by
+``SeedSequence([config_id, stream, seed])``; stream 0 draws x_true, stream 1
+off-diagonal values, stream 2 row scales, stream 3 right-hand sides.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "Problem",
+    "CONFIGS",
+    "rng",
+    "csr_from_scipy",
+    "convdiff",
+    "stencil27_illcond",
+    "simonici",
+    "cyclic_shift",
+    "random_dense",
+    "make_config",
+]
+
+
+@dataclass
+class Problem:
+    """A CSR system with everything a solve needs.
+
+    ``row_ptr`` int32[n+1], ``col_idx`` int32[nnz] (sorted within each row),
+    ``vals`` float64[nnz]; ``b``, ``x0`` and ``x_true`` float64[n] (``x_true``
+    may be None when b is not built from a known solution).
+    """
+
+    name: str
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    vals: np.ndarray
+    b: np.ndarray
+    x0: np.ndarray
+    x_true: np.ndarray | None
+    m: int
+    rtol: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.row_ptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.shape[0])
+
+    def scipy(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.vals, self.col_idx, self.row_ptr), shape=(self.n, self.n))
+
+
+def rng(config_id: int, stream: int, seed: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([config_id, stream, seed])))
+
+
+def csr_from_scipy(A) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """int32/float64 CSR arrays with sorted column indices and no duplicates."""
+    A = sp.csr_matrix(A)
+    A.sum_duplicates()
+    A.sort_indices()
+    if A.nnz >= 2**31:
+        raise ValueError("nnz does not fit int32 indices")
+    return (np.ascontiguousarray(A.indptr, dtype=np.int32),
+            np.ascontiguousarray(A.indices, dtype=np.int32),
+            np.ascontiguousarray(A.data, dtype=np.float64))
+
+
+def _upwind_1d(N: int, h: float, eps: float, a: float) -> sp.csr_matrix:
+    """1-D operator for -eps u'' + a u' on N interior points, first-order upwind."""
+    main = np.full(N, 2.0 * eps / h**2 + abs(a) / h)
+    off = np.full(N - 1, -eps / h**2)
+    lower = off.copy()
+    upper = off.copy()
+    if a > 0:      # information flows from the left: the upwind neighbour is i-1
+        lower = lower - a / h
+    elif a < 0:    # upwind neighbour is i+1
+        upper = upper - abs(a) / h
+    return sp.diags([lower, main, upper], [-1, 0, 1], shape=(N, N), format="csr")
+
+
+def convdiff(N: int, dim: int, wind, peclet: float) -> sp.csr_matrix:
+    """Upwind convection-diffusion matrix on an N^dim grid (x index fastest)."""
+    wind = np.asarray(wind, dtype=np.float64)
+    if wind.shape != (dim,):
+        raise ValueError("wind must have one component per dimension")
+    eps = float(np.linalg.norm(wind)) / peclet
+    h = 1.0 / (N + 1)
+    A = None
+    for d in range(dim):
+        K = _upwind_1d(N, h, eps, float(wind[d]))
+        term = sp.kron(sp.kron(sp.identity(N ** (dim - 1 - d), format="csr"), K, format="csr"),
+                       sp.identity(N ** d, format="csr"), format="csr")
+        A = term if A is None else (A + term)
+    return sp.csr_matrix(A)
+
+
+def stencil27_illcond(N: int, config_id: int = 3, seed: int = 0, log10_scale: float = 8.0):
+    """27-point stencil, M_ii = 1, M_ij ~ N(0,1)/27 over in-grid neighbours, A = D M.
+
+    D_ii = 10**(log10_scale * U_i), U_i ~ U(0,1). Returns (row_ptr, col_idx, vals).
+    """
+    n = N ** 3
+    g_off = rng(config_id, 1, seed)
+    g_row = rng(config_id, 2, seed)
+    idx = np.arange(n, dtype=np.int64)
+    ix = idx % N
+    iy = (idx // N) % N
+    iz = idx // (N * N)
+    rows, cols, vals = [], [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == 0 and dy == 0 and dz == 0:
+                    rows.append(idx)
+                    cols.append(idx)
+                    vals.append(np.ones(n))
+                    continue
+                # one full draw per offset, in a fixed order, masked afterwards
+                v = g_off.standard_normal(n) / 27.0
+                ok = ((ix + dx >= 0) & (ix + dx < N) & (iy + dy >= 0) & (iy + dy < N)
+                      & (iz + dz >= 0) & (iz + dz < N))
+                rows.append(idx[ok])
+                cols.append(idx[ok] + dx + N * dy + N * N * dz)
+                vals.append(v[ok])
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    scale = 10.0 ** (log10_scale * g_row.random(n))
+    vals = vals * scale[rows]
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    return csr_from_scipy(A)
+
+
+def simonici(seed: int = 0) -> Problem:
+    """Section V-A test: A = diag(1e-8, 2, ..., 100), b = randn normalized, no preconditioner."""
+    d = np.concatenate([[1e-8], np.arange(2.0, 101.0)])
+    A = sp.diags(d, 0, format="csr")
+    b = rng(100, 3, seed).standard_normal(100)
+    b /= np.linalg.norm(b)
+    rp, ci, va = csr_from_scipy(A)
+    return Problem("simonici", rp, ci, va, b, np.zeros(100), None, m=100, rtol=0.0,
+                   meta={"kappa": 1e10})
+
+
+def cyclic_shift(n: int) -> Problem:
+    """A e_i = e_{i+1 mod n}, b = e_0: GMRES stagnates at |r| = 1 until step n."""
+    rows = np.arange(n)
+    cols = (rows - 1) % n
+    A = sp.csr_matrix((np.ones(n), (rows, cols)), shape=(n, n))
+    rp, ci, va = csr_from_scipy(A)
+    b = np.zeros(n)
+    b[0] = 1.0
+    x_true = np.zeros(n)
+    x_true[n - 1] = 1.0
+    return Problem(f"cyclic{n}", rp, ci, va, b, np.zeros(n), x_true, m=n, rtol=0.0)
+
+
+def random_dense(n: int, seed: int = 0, shift: float = 4.0) -> Problem:
+    """Dense nonsymmetric, well-conditioned matrix shift*I + randn/sqrt(n), stored as CSR."""
+    g = rng(200 + n, 1, seed)
+    M = g.standard_normal((n, n)) / np.sqrt(n) + shift * np.eye(n)
+    x_true = rng(200 + n, 0, seed).uniform(-1.0, 1.0, n)
+    b = M @ x_true
+    rp, ci, va = csr_from_scipy(sp.csr_matrix(M))
+    return Problem(f"dense{n}", rp, ci, va, b, np.zeros(n), x_true, m=n, rtol=0.0)
+
+
+# name -> (config id, description)
+CONFIGS = {
+    "cfg1": (1, "2D 5-point upwind convection-diffusion, 64^2, wind (1,1), Pe 10, m=30, rtol 1e-8"),
+    "cfg2": (2, "3D 7-point upwind convection-diffusion, 128^3, wind (1,0.5,0.25), Pe 50, m=50, rtol 1e-10"),
+    "cfg3": (3, "3D 27-point random stencil, 100^3, rows scaled log-uniform in [1,1e8], m=100, rtol 1e-10"),
+}
+
+
+def make_config(name: str, seed: int = 0, N: int | None = None) -> Problem:
+    """Build one of the named workloads. ``N`` overrides the grid side (smaller test copies)."""
+    if name not in CONFIGS:
+        raise KeyError(f"unknown config {name!r}; known: {sorted(CONFIGS)}")
+    cid = CONFIGS[name][0]
+    if name == "cfg1":
+        N = 64 if N is None else N
+        A = convdiff(N, 2, (1.0, 1.0), 10.0)
+        rp, ci, va = csr_from_scipy(A)
+        m, rtol = 30, 1e-8
+    elif name == "cfg2":
+        N = 128 if N is None else N
+        A = convdiff(N, 3, (1.0, 0.5, 0.25), 50.0)
+        rp, ci, va = csr_from_scipy(A)
+        m, rtol = 50, 1e-10
+    else:
+        N = 100 if N is None else N
+        rp, ci, va = stencil27_illcond(N, cid, seed)
+        m, rtol = 100, 1e-10
+    n = rp.shape[0] - 1
+    x_true = rng(cid, 0, seed).uniform(-1.0, 1.0, n)
+    b = sp.csr_matrix((va, ci, rp), shape=(n, n)) @ x_true
+    return Problem(name, rp, ci, va, np.ascontiguousarray(b), np.zeros(n), x_true, m, rtol,
+                   meta={"N": N, "config_id": cid})
+
