@@ -1,0 +1,172 @@
+/*
+ * gmres.h - restarted GMRES(m) on one AMD MI355X (gfx950), FP64, with three
+ * Gram-Schmidt schemes for the Arnoldi process, after Swirydowicz, Langou,
+ * Ananthan, Yang, Thomas, "Low synchronization GMRES algorithms"
+ * (arXiv:1809.05805):
+ *
+ *   GMRES_MGS_1R  one global reduction per Arnoldi step: the level-2 MGS in
+ *                 compact WY form with lagged normalization of R's diagonal
+ *                 (Section II, level-2 MGS with normalization lag; Section III,
+ *                 one-synchronization MGS-GMRES). Each step is a CSR SpMV of
+ *                 the still-unnormalized newest column, one fused projection
+ *                 [V^T u, V^T w] with a single device-wide reduction, the lagged
+ *                 norm and the (I + L)^{-1} correction through the Malard-Paige
+ *                 T matrix, and one MAXPY.
+ *   GMRES_MGS     level-1 MGS-GMRES (Section III, the Saad-Schultz listing):
+ *                 i+2 reductions in iteration i.
+ *   GMRES_CGS2    two reductions per step: lagged iterated classical
+ *                 Gram-Schmidt (Section II, level-2 CGS2 with normalization lag).
+ *
+ * The problem is A x = b with residual r = b - A x and initial guess x0
+ * (Section III); A is in CSR form (Section V-B); all vectors live in device
+ * memory (Section V-B). The relative tolerance is on ||b - A x||_2 / ||b||_2.
+ *
+ * Pointers are DEVICE pointers unless marked "host". The library never
+ * allocates or frees device memory: the caller passes one workspace buffer.
+ * Its only allocations are the host-side context and a small pinned host
+ * buffer (hipHostMalloc) for per-cycle status readback.
+ *
+ * Every call is enqueued on the HIP stream given to gmres_create. A context is
+ * bound to that stream and is not thread-safe; use one context per stream.
+ */
+#ifndef GMRES_H
+#define GMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmres_ctx gmres_ctx; /* opaque */
+
+typedef enum { GMRES_MGS = 0, GMRES_MGS_1R = 1, GMRES_CGS2 = 2 } gmres_scheme;
+
+typedef enum {
+  GMRES_OK = 0,
+  GMRES_ERR_ARG = -1,       /* invalid argument or malformed CSR structure          */
+  GMRES_ERR_HIP = -2,       /* a HIP runtime call or kernel launch failed           */
+  GMRES_ERR_NONFINITE = -3, /* NaN or Inf in a norm, Hessenberg entry or residual   */
+  GMRES_ERR_WORKSPACE = -4  /* workspace smaller than gmres_workspace_bytes()        */
+} gmres_status;
+
+/* Largest restart length the kernels' on-chip buffers are sized for. */
+#define GMRES_MAX_RESTART 256
+
+typedef struct {
+  int64_t iters;       /* Arnoldi columns completed, summed over cycles              */
+  int32_t cycles;      /* restart cycles that completed at least one column          */
+  int32_t converged;   /* 1 if ||b - A x|| <= rtol ||b|| was verified on the device  */
+  int32_t breakdown;   /* 1 if a cycle ended on an exact (happy) breakdown, rho == 0  */
+  int32_t pad;
+  double rel_res_true; /* ||b - A x||_2 / ||b||_2 at exit, recomputed from x          */
+  double rel_res_est;  /* last implicit |g_j| / ||b||_2 from the Givens recurrence    */
+  int64_t reductions;  /* device-wide reductions performed, counted on the device     */
+} gmres_info;
+
+/*
+ * Bytes of device workspace gmres_create needs for n rows, restart m and the
+ * given scheme (0 if the arguments are invalid). The workspace holds the
+ * basis V (n x (m+2), column-major, leading dimension n rounded up to 32),
+ * the Hessenberg and T matrices, Givens data and reduction scratch.
+ */
+size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
+
+/*
+ * Bind a CSR matrix and a workspace to a new context.
+ *   n >= 1 rows (square A); nnz in [0, 2^31); row_ptr int32[n+1], col_idx
+ *   int32[nnz] (any order within a row), vals float64[nnz]: caller-owned
+ *   device arrays that must stay valid and unchanged while the context lives.
+ *   1 <= m <= GMRES_MAX_RESTART; scheme a gmres_scheme value.
+ *   workspace: device buffer of ws_bytes >= gmres_workspace_bytes(n, m, scheme),
+ *   256-byte aligned, caller-owned, exclusively used by this context.
+ *   hip_stream: the hipStream_t all work is enqueued on (NULL = default stream).
+ * The CSR structure is checked on the device (row_ptr[0] == 0, row_ptr[n] ==
+ * nnz, non-decreasing row_ptr, 0 <= col_idx < n); a malformed matrix gives
+ * GMRES_ERR_ARG and no context. On success *out holds the context.
+ */
+int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                 const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
+                 void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Solve A x = b by restarted GMRES(m) with the context's scheme.
+ *   b: float64[n]; x: float64[n], the initial guess on entry, the iterate on exit.
+ *   rtol >= 0: stop once ||b - A x||_2 <= rtol ||b||_2 holds for the true
+ *   residual. Inside a cycle the implicit Givens residual |g_k| decides when the
+ *   cycle ends (for the lagged schemes one step after column k-1 is formed,
+ *   since its last Hessenberg entry arrives with the next reduction); every
+ *   restart then recomputes b - A x, and only that true residual ends the solve.
+ *   max_iters >= 0: cap on Arnoldi columns over all cycles.
+ *   info (host, nullable): filled on return.
+ *   hist_res (host, nullable, max_iters doubles): |g_k| / ||b|| after each column.
+ * Blocks until the solve has finished on the stream. Returns GMRES_OK when the
+ * solve ran to convergence or to max_iters (info->converged tells which),
+ * GMRES_ERR_NONFINITE if a NaN or Inf appeared (x then holds the last finished
+ * cycle's iterate), or GMRES_ERR_ARG / GMRES_ERR_HIP. If ||b|| == 0, x is set to
+ * zero and the solve reports convergence with no iterations.
+ */
+int gmres_solve(gmres_ctx* ctx, const double* b, double* x, double rtol, int64_t max_iters,
+                gmres_info* info, double* hist_res);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+int gmres_destroy(gmres_ctx* ctx);
+
+/* Static English description of a gmres_status value. */
+const char* gmres_status_string(int status);
+
+/*
+ * y = A x with the context's matrix and SpMV kernel, enqueued on its stream
+ * without waiting. x and y: float64[n], must not overlap.
+ */
+int gmres_spmv(gmres_ctx* ctx, const double* x, double* y);
+
+/*
+ * Diagnostics of the last cycle that completed at least one column (host
+ * copies, each nullable):
+ *   H (host, (m+1) x m, column-major): the unrotated Hessenberg matrix;
+ *   T (host, (m+2) x (m+2), column-major): for GMRES_MGS_1R the Malard-Paige
+ *     T = (I + L^T)^{-1} built one column per step, whose leading blocks give
+ *     Paige's loss-of-orthogonality measure S = I - T (Section II); for
+ *     GMRES_CGS2 the strictly lower L with V^T V = I + L + L^T, one row per
+ *     step; zeros for GMRES_MGS;
+ *   g (host, m+2): the rotated right-hand side of the least-squares problem;
+ *   j (host): the number of columns that cycle completed.
+ */
+int gmres_last_cycle(gmres_ctx* ctx, double* H, double* T, double* g, int32_t* j);
+
+/*
+ * Device pointer to the basis V inside the workspace and its leading
+ * dimension (in elements). Columns 0..j-1 of the last cycle hold its
+ * orthonormal basis until the next solve, except that a solve that ends by
+ * converging overwrites column 0 with the final residual it verified.
+ */
+int gmres_basis(gmres_ctx* ctx, double** V, int64_t* ldv);
+
+/*
+ * Per-kernel timing for measurement (lagged schemes). When enabled, every
+ * launch of the fused step kernel (SpMV + projection + device-wide reduction +
+ * small dense step) and of the MAXPY kernel carries start/stop HIP events
+ * attached to its dispatch (hipExtLaunchKernel), so they time the kernel
+ * alone; launches that the cycle's done flag skipped are not counted. bytes is the algorithmic HBM traffic of the counted launches:
+ *   step k with SpMV:  12 nnz + 4 (n+1) + 8 n (k+1) + 8 n   (CSR, V[:,0:k+1], w written)
+ *   step k norm-only:  8 n (k+1)
+ *   CGS2 second pass:  8 n (k+2)                          (V[:,0:k+1] and z)
+ *   MAXPY at step k:   8 n (k+1) + 16 n                   (V[:,0:k+1], w or z, new column)
+ * gmres_set_timing(ctx, 1) enables and clears the totals; (ctx, 0) disables.
+ */
+enum { GMRES_KSTAT_STEP = 0, GMRES_KSTAT_MAXPY = 1, GMRES_KSTAT_COUNT = 2 };
+typedef struct {
+  double ms;        /* summed event-to-event time of the counted launches */
+  double bytes;     /* summed algorithmic bytes */
+  int64_t launches; /* counted launches */
+} gmres_kernel_stat;
+int gmres_set_timing(gmres_ctx* ctx, int enable);
+int gmres_get_timing(gmres_ctx* ctx, gmres_kernel_stat* stats /* host, GMRES_KSTAT_COUNT */);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMRES_H */

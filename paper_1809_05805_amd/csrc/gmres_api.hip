@@ -1,0 +1,501 @@
+// Host driver and C ABI of the GMRES library (include/gmres.h).
+//
+// Restarted GMRES(m) after Swirydowicz, Langou, Ananthan, Yang, Thomas, "Low
+// synchronization GMRES algorithms" (arXiv:1809.05805). Each restart cycle is
+// enqueued as a whole: every step's kernels read a "done" flag that the
+// device sets when the cycle ends (converged, flushed, broke down or failed),
+// so later launches of the cycle return at once and the host waits on the
+// stream only once per cycle, to read a few scalars and the small matrices.
+#include "gmres.h"
+#include "gmres_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+using namespace gmres;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Rows per lane of the row-tiled kernels: the largest of 8, 4, 2 that still
+// leaves at least 512 tiles of 256*rpt rows (two per compute unit), else 1.
+int pick_rpt(int64_t n) {
+  for (int r : {8, 4, 2})
+    if ((n + 256 * r - 1) / (256 * r) >= 512) return r;
+  return 1;
+}
+
+// Tiles of 256*rpt rows, padded to a multiple of 8 (one per XCD) when there
+// are at least 8, so the XCD-aware tile mapping is a bijection.
+int pick_grid(int64_t n, int rpt) {
+  int64_t tiles = (n + 256 * rpt - 1) / (256 * rpt);
+  if (tiles >= 8) tiles = (tiles + 7) / 8 * 8;
+  return (int)tiles;
+}
+
+// Lanes per CSR row: the power of two at or above the mean row length, at
+// least 8 (the SpMV keeps 8 rows in flight per lane group) and at most 64.
+int pick_lanes(int64_t n, int64_t nnz) {
+  const int64_t avg = (nnz + n - 1) / n;
+  int s = 8;
+  while (s < avg && s < 64) s <<= 1;
+  return s;
+}
+
+struct Layout {
+  int64_t ldv;
+  int rpt, G, NG, pstride;
+  size_t V, w, H, R, T, g, gh, cs, sn, coef, coef2, y, partials, gpartials, counters, state, total;
+};
+
+bool make_layout(int64_t n, int m, Layout* L) {
+  if (n < 1 || m < 1 || m > GMRES_MAX_RESTART) return false;
+  L->ldv = (int64_t)round_up((size_t)n, 32);
+  L->rpt = pick_rpt(n);
+  L->G = pick_grid(n, L->rpt);
+  L->NG = (L->G + kGroup - 1) / kGroup;
+  L->pstride = (int)round_up((size_t)(2 * (m + 2)), 32);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = round_up(off + bytes, kAlign);
+    return at;
+  };
+  const size_t d = sizeof(double);
+  L->V = take((size_t)L->ldv * (size_t)(m + 2) * d);
+  L->w = take((size_t)L->ldv * d);
+  L->H = take((size_t)(m + 1) * (size_t)m * d);
+  L->R = take((size_t)(m + 1) * (size_t)m * d);
+  L->T = take((size_t)(m + 2) * (size_t)(m + 2) * d);
+  L->g = take((size_t)(m + 2) * d);
+  L->gh = take((size_t)(m + 2) * d);
+  L->cs = take((size_t)(m + 2) * d);
+  L->sn = take((size_t)(m + 2) * d);
+  L->coef = take((size_t)(m + 2) * d);
+  L->coef2 = take((size_t)(m + 2) * d);
+  L->y = take((size_t)(m + 2) * d);
+  L->partials = take((size_t)L->G * (size_t)L->pstride * d);
+  L->gpartials = take((size_t)L->NG * (size_t)L->pstride * d);
+  L->counters = take((size_t)(L->NG + 1) * sizeof(unsigned));
+  L->state = take(sizeof(DevState));
+  L->total = off;
+  return true;
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct gmres_ctx {
+  Csr A;
+  int64_t nnz;
+  int m, scheme, S;
+  Layout L;
+  Ws ws;
+  hipStream_t stream;
+  // pinned host mirror: DevState, g, gh, H, T
+  void* pinned;
+  DevState* h_st;
+  double* h_g;
+  double* h_gh;
+  double* h_H;
+  double* h_T;
+  // host snapshot of the last cycle that completed a column
+  std::vector<double> last_H, last_T, last_g;
+  int last_j;
+  // per-launch event timing (measurement only)
+  bool timing;
+  std::vector<hipEvent_t> ev;  // pairs: start, stop
+  struct Rec {
+    int cls;      // GMRES_KSTAT_*
+    int step;     // Arnoldi step k of the launch
+    int runs_to;  // the launch ran iff the cycle's j >= runs_to
+    double bytes;
+  };
+  std::vector<Rec> recs;
+  gmres_kernel_stat stats[GMRES_KSTAT_COUNT];
+};
+
+namespace {
+
+int sync_state(gmres_ctx* c, bool with_matrices) {
+  const int m = c->m;
+  if (hipMemcpyAsync(c->h_st, c->ws.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return GMRES_ERR_HIP;
+  if (with_matrices) {
+    if (hipMemcpyAsync(c->h_g, c->ws.g, sizeof(double) * (m + 2), hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->h_gh, c->ws.gh, sizeof(double) * (m + 2), hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->h_H, c->ws.H, sizeof(double) * (size_t)(m + 1) * m,
+                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->h_T, c->ws.T, sizeof(double) * (size_t)(m + 2) * (m + 2),
+                       hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return GMRES_ERR_HIP;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GMRES_ERR_HIP;
+  return GMRES_OK;
+}
+
+#define TRY(x)                  \
+  do {                          \
+    int _rc = (x);              \
+    if (_rc) return GMRES_ERR_HIP; \
+  } while (0)
+
+// Start/stop events attached to one launch when timing is on (null otherwise).
+struct TimedLaunch {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TimedLaunch(gmres_ctx* c, int cls, int step, int runs_to, double bytes) {
+    if (!c->timing) return;
+    const size_t slot = c->recs.size();
+    if (2 * slot + 2 > c->ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        c->timing = false;
+        return;
+      }
+      c->ev.push_back(a);
+      c->ev.push_back(b);
+    }
+    c->recs.push_back({cls, step, runs_to, bytes});
+    e0 = c->ev[2 * slot];
+    e1 = c->ev[2 * slot + 1];
+  }
+};
+
+// After the cycle has finished on the stream: add the launches that ran.
+void collect_timing(gmres_ctx* c, int j, bool stopped_at_restart) {
+  if (!c->timing) return;
+  for (size_t i = 0; i < c->recs.size(); ++i) {
+    const auto& r = c->recs[i];
+    const bool ran = stopped_at_restart ? (r.step == 0 && r.cls == GMRES_KSTAT_STEP && r.runs_to == 0)
+                                        : j >= r.runs_to;
+    if (!ran) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) continue;
+    c->stats[r.cls].ms += ms;
+    c->stats[r.cls].bytes += r.bytes;
+    c->stats[r.cls].launches += 1;
+  }
+  c->recs.clear();
+}
+
+// Enqueue one restart cycle with m_eff >= 1 columns at most.
+int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
+  const Ws& ws = c->ws;
+  hipStream_t s = c->stream;
+  const int rpt = c->L.rpt, G = c->L.G;
+  const double n8 = 8.0 * (double)c->A.n;
+  const double csr = 12.0 * (double)c->nnz + 4.0 * (double)(c->A.n + 1);
+  auto col = [&](int q) { return ws.V + (size_t)q * (size_t)ws.ldv; };
+  TRY(launch_cycle_begin(ws, s));
+  TRY(launch_spmv(c->A, c->S, x, b, col(0), nullptr, s));  // V[:,0] = b - A x
+  if (c->scheme == kSchemeMgs) {
+    TRY(launch_axpy_dot(ws, rpt, col(0), nullptr, nullptr, col(0), kTailMgsBeta, 0, 0, m_eff, 0.0,
+                        G, s));
+    TRY(launch_scale(ws, col(0), s));
+    for (int i = 0; i < m_eff; ++i) {
+      double* w = col(i + 1);
+      TRY(launch_spmv(c->A, c->S, col(i), nullptr, w, ws.st, s));
+      for (int q = 0; q <= i; ++q) {
+        const double* a = q > 0 ? col(q - 1) : nullptr;
+        const double* cf = q > 0 ? ws.H + (size_t)i * ws.ldh + (q - 1) : nullptr;
+        TRY(launch_axpy_dot(ws, rpt, w, a, cf, col(q), kTailMgsH, i, q, m_eff, 0.0, G, s));
+      }
+      TRY(launch_axpy_dot(ws, rpt, w, col(i), ws.H + (size_t)i * ws.ldh + i, w, kTailMgsNorm, i, 0,
+                          m_eff, 0.0, G, s));
+      TRY(launch_scale(ws, w, s));
+    }
+  } else {
+    const int tail = c->scheme == kSchemeMgs1r ? kTailLagged1r : kTailLaggedCgs2;
+    // Step k's fused kernel runs iff the cycle reaches step k (j >= k, or the
+    // restart check at k = 0 ends it); the rest of step k runs iff j > k.
+    for (int k = 0; k <= m_eff; ++k) {
+      {
+        const double bytes = k < m_eff ? csr + n8 * (k + 1) + n8 : n8 * (k + 1);
+        TimedLaunch t(c, GMRES_KSTAT_STEP, k, k, bytes);
+        TRY(launch_fused(c->A, c->S, ws, rpt, k, k < m_eff, m_eff, tail, G, s, t.e0, t.e1));
+      }
+      if (k == m_eff) break;
+      {
+        TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
+        TRY(launch_maxpy(ws, rpt, k, 0, G, s, t.e0, t.e1));
+      }
+      if (c->scheme == kSchemeCgs2) {
+        {
+          TimedLaunch t(c, GMRES_KSTAT_STEP, k, k + 1, n8 * (k + 2));
+          TRY(launch_fused(c->A, c->S, ws, rpt, k + 1, false, m_eff, kTailCgs2Second, G, s, t.e0,
+                           t.e1));
+        }
+        TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
+        TRY(launch_maxpy(ws, rpt, k, 1, G, s, t.e0, t.e1));
+      }
+    }
+  }
+  TRY(launch_cycle_end(ws, rpt, x, G, s));
+  return GMRES_OK;
+}
+
+// ||b - A x|| into the state's beta, without touching the basis.
+int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
+  const Ws& ws = c->ws;
+  TRY(launch_cycle_begin(ws, c->stream));
+  TRY(launch_spmv(c->A, c->S, x, b, ws.w, nullptr, c->stream));
+  TRY(launch_axpy_dot(ws, c->L.rpt, ws.w, nullptr, nullptr, ws.w, kTailFinalRes, 0, 0, 0, 0.0,
+                      c->L.G, c->stream));
+  return GMRES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme) {
+  if (scheme < GMRES_MGS || scheme > GMRES_CGS2) return 0;
+  Layout L;
+  if (!make_layout(n, m, &L)) return 0;
+  return L.total;
+}
+
+const char* gmres_status_string(int status) {
+  switch (status) {
+    case GMRES_OK: return "ok";
+    case GMRES_ERR_ARG: return "invalid argument";
+    case GMRES_ERR_HIP: return "HIP runtime error";
+    case GMRES_ERR_NONFINITE: return "non-finite value (NaN or Inf) in the iteration";
+    case GMRES_ERR_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                 const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
+                 void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out) return GMRES_ERR_ARG;
+  *out = nullptr;
+  if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31) || m < 1 ||
+      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_CGS2)
+    return GMRES_ERR_ARG;
+  if (!is_device_ptr(row_ptr) || !is_device_ptr(workspace) ||
+      (nnz > 0 && (!is_device_ptr(col_idx) || !is_device_ptr(vals))))
+    return GMRES_ERR_ARG;
+  if (((uintptr_t)workspace % kAlign) != 0) return GMRES_ERR_ARG;
+  Layout L;
+  if (!make_layout(n, m, &L)) return GMRES_ERR_ARG;
+  if (ws_bytes < L.total) return GMRES_ERR_WORKSPACE;
+
+  gmres_ctx* c = new (std::nothrow) gmres_ctx();
+  if (!c) return GMRES_ERR_ARG;
+  c->A = Csr{row_ptr, col_idx, vals, n, nnz};
+  c->nnz = nnz;
+  c->m = m;
+  c->scheme = scheme;
+  c->S = pick_lanes(n, nnz);
+  c->L = L;
+  c->stream = (hipStream_t)hip_stream;
+  char* base = (char*)workspace;
+  Ws& ws = c->ws;
+  ws.V = (double*)(base + L.V);
+  ws.w = (double*)(base + L.w);
+  ws.H = (double*)(base + L.H);
+  ws.R = (double*)(base + L.R);
+  ws.T = (double*)(base + L.T);
+  ws.g = (double*)(base + L.g);
+  ws.gh = (double*)(base + L.gh);
+  ws.cs = (double*)(base + L.cs);
+  ws.sn = (double*)(base + L.sn);
+  ws.coef = (double*)(base + L.coef);
+  ws.coef2 = (double*)(base + L.coef2);
+  ws.y = (double*)(base + L.y);
+  ws.partials = (double*)(base + L.partials);
+  ws.gpartials = (double*)(base + L.gpartials);
+  ws.counters = (unsigned*)(base + L.counters);
+  ws.st = (DevState*)(base + L.state);
+  ws.n = n;
+  ws.ldv = L.ldv;
+  ws.ldh = m + 1;
+  ws.ldt = m + 2;
+  ws.pstride = L.pstride;
+  ws.m = m;
+
+  const size_t pin = round_up(sizeof(DevState), 64) +
+                     sizeof(double) * (2 * (size_t)(m + 2) + (size_t)(m + 1) * m + (size_t)(m + 2) * (m + 2));
+  if (hipHostMalloc(&c->pinned, pin, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return GMRES_ERR_HIP;
+  }
+  c->h_st = (DevState*)c->pinned;
+  c->h_g = (double*)((char*)c->pinned + round_up(sizeof(DevState), 64));
+  c->h_gh = c->h_g + (m + 2);
+  c->h_H = c->h_gh + (m + 2);
+  c->h_T = c->h_H + (size_t)(m + 1) * m;
+  c->last_H.assign((size_t)(m + 1) * m, 0.0);
+  c->last_T.assign((size_t)(m + 2) * (m + 2), 0.0);
+  c->last_g.assign((size_t)(m + 2), 0.0);
+  c->last_j = 0;
+  c->timing = false;
+  memset(c->stats, 0, sizeof(c->stats));
+
+  int rc = GMRES_OK;
+  if (launch_init(ws, L.NG + 1, c->stream) || launch_validate(c->A, nnz, ws.st, c->stream))
+    rc = GMRES_ERR_HIP;
+  if (rc == GMRES_OK) rc = sync_state(c, false);
+  if (rc == GMRES_OK && c->h_st->bad_csr) rc = GMRES_ERR_ARG;
+  if (rc != GMRES_OK) {
+    (void)hipHostFree(c->pinned);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return GMRES_OK;
+}
+
+int gmres_destroy(gmres_ctx* c) {
+  if (!c) return GMRES_ERR_ARG;
+  int rc = GMRES_OK;
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->pinned && hipHostFree(c->pinned) != hipSuccess) rc = GMRES_ERR_HIP;
+  delete c;
+  return rc;
+}
+
+int gmres_spmv(gmres_ctx* c, const double* x, double* y) {
+  if (!c || !x || !y || x == y) return GMRES_ERR_ARG;
+  return launch_spmv(c->A, c->S, x, nullptr, y, nullptr, c->stream) ? GMRES_ERR_HIP : GMRES_OK;
+}
+
+int gmres_basis(gmres_ctx* c, double** V, int64_t* ldv) {
+  if (!c) return GMRES_ERR_ARG;
+  if (V) *V = c->ws.V;
+  if (ldv) *ldv = c->ws.ldv;
+  return GMRES_OK;
+}
+
+int gmres_set_timing(gmres_ctx* c, int enable) {
+  if (!c) return GMRES_ERR_ARG;
+  c->timing = enable != 0;
+  c->recs.clear();
+  memset(c->stats, 0, sizeof(c->stats));
+  return GMRES_OK;
+}
+
+int gmres_get_timing(gmres_ctx* c, gmres_kernel_stat* stats) {
+  if (!c || !stats) return GMRES_ERR_ARG;
+  memcpy(stats, c->stats, sizeof(c->stats));
+  return GMRES_OK;
+}
+
+int gmres_last_cycle(gmres_ctx* c, double* H, double* T, double* g, int32_t* j) {
+  if (!c) return GMRES_ERR_ARG;
+  if (H) memcpy(H, c->last_H.data(), sizeof(double) * c->last_H.size());
+  if (T) memcpy(T, c->last_T.data(), sizeof(double) * c->last_T.size());
+  if (g) memcpy(g, c->last_g.data(), sizeof(double) * c->last_g.size());
+  if (j) *j = c->last_j;
+  return GMRES_OK;
+}
+
+int gmres_solve(gmres_ctx* c, const double* b, double* x, double rtol, int64_t max_iters,
+                gmres_info* info, double* hist_res) {
+  gmres_info loc;
+  memset(&loc, 0, sizeof(loc));
+  if (info) *info = loc;
+  if (!c || !b || !x || !(rtol >= 0.0) || max_iters < 0) return GMRES_ERR_ARG;
+  if (!is_device_ptr(b) || !is_device_ptr(x)) return GMRES_ERR_ARG;
+  const Ws& ws = c->ws;
+  hipStream_t s = c->stream;
+  const int m = c->m;
+  int rc;
+
+  if (launch_solve_begin(ws, s) ||
+      launch_axpy_dot(ws, c->L.rpt, (double*)b, nullptr, nullptr, b, kTailBnorm, 0, 0, 0, rtol,
+                      c->L.G, s))
+    return GMRES_ERR_HIP;
+  if ((rc = sync_state(c, false))) return rc;
+  if (c->h_st->status) {
+    loc.reductions = c->h_st->reductions;
+    if (info) *info = loc;
+    return GMRES_ERR_NONFINITE;
+  }
+  const double bnorm = c->h_st->bnorm;
+  if (bnorm == 0.0) {
+    if (hipMemsetAsync(x, 0, sizeof(double) * (size_t)c->A.n, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GMRES_ERR_HIP;
+    loc.converged = 1;
+    loc.reductions = c->h_st->reductions;
+    if (info) *info = loc;
+    return GMRES_OK;
+  }
+  const double tol_abs = c->h_st->tol_abs;
+
+  int64_t it = 0;
+  rc = GMRES_OK;
+  for (;;) {
+    const int64_t left = max_iters - it;
+    const int m_eff = left < (int64_t)m ? (int)left : m;
+    if (m_eff == 0) {
+      if (enqueue_true_residual(c, b, x)) return GMRES_ERR_HIP;
+      if ((rc = sync_state(c, false))) return rc;
+      if (c->h_st->status) {
+        rc = GMRES_ERR_NONFINITE;
+        break;
+      }
+      loc.rel_res_true = c->h_st->beta / bnorm;
+      loc.converged = c->h_st->beta <= tol_abs;
+      if (loc.cycles == 0) loc.rel_res_est = loc.rel_res_true;
+      break;
+    }
+    if (enqueue_cycle(c, b, x, m_eff)) return GMRES_ERR_HIP;
+    if ((rc = sync_state(c, true))) return rc;
+    const DevState& st = *c->h_st;
+    collect_timing(c, st.j, st.true_conv != 0);
+    if (st.status) {
+      rc = GMRES_ERR_NONFINITE;
+      break;
+    }
+    if (st.true_conv) {
+      loc.converged = 1;
+      loc.rel_res_true = st.beta / bnorm;
+      if (loc.cycles == 0) loc.rel_res_est = loc.rel_res_true;
+      break;
+    }
+    const int j = st.j;
+    if (j > 0) {
+      if (hist_res)
+        for (int q = 0; q < j; ++q) hist_res[it + q] = c->h_gh[q + 1] / bnorm;
+      loc.cycles += 1;
+      loc.rel_res_est = fabs(c->h_g[j]) / bnorm;
+      memcpy(c->last_H.data(), c->h_H, sizeof(double) * c->last_H.size());
+      memcpy(c->last_T.data(), c->h_T, sizeof(double) * c->last_T.size());
+      memcpy(c->last_g.data(), c->h_g, sizeof(double) * c->last_g.size());
+      c->last_j = j;
+    }
+    if (st.breakdown) loc.breakdown = 1;
+    if (j == 0) break;  // no progress is possible; cannot happen for m_eff >= 1
+    it += j;
+  }
+  loc.iters = it;
+  loc.reductions = c->h_st->reductions;
+  if (info) *info = loc;
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,1066 @@
+// HIP kernels for restarted GMRES(m) on gfx950 (FP64), after Swirydowicz,
+// Langou, Ananthan, Yang, Thomas, "Low synchronization GMRES algorithms"
+// (arXiv:1809.05805).
+//
+// The Arnoldi step of the one-reduce scheme (Section II, level-2 MGS with R
+// normalization lag; Section III, one-synchronization MGS-GMRES) runs as two
+// launches:
+//   k_fused  - CSR SpMV w = A u of the unnormalized newest column u = V[:,k],
+//              the tall-skinny projection [V[:,0:k+1]^T u, V[:,0:k+1]^T w], one
+//              device-wide reduction (two-level ticket reduction in a fixed
+//              order, so results are bitwise reproducible) and, in the last
+//              workgroup to finish, the small dense step: lagged norm, new T
+//              column, h = T^T r, Givens rotation, convergence flag;
+//   k_maxpy  - V[:,k] = u / rho and V[:,k+1] = w / rho - V[:,0:k+1] h.
+// The level-1 MGS and two-reduce CGS2 baselines reuse the same building
+// blocks. Everything is memory-bound BLAS-2 work: no matrix cores.
+#include "gmres_internal.h"
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+namespace gmres {
+
+// ---------------------------------------------------------------- helpers
+
+// Workgroup tile -> rows. Workgroups are handed to the 8 XCDs round-robin by
+// blockIdx.x; when the grid is a multiple of 8, consecutive tiles are given to
+// workgroups of the same XCD so that the SpMV's neighbour gathers stay in one
+// XCD's L2.
+__device__ inline int tile_of_block(int G) {
+  const int b = blockIdx.x;
+  if ((G & 7) == 0) return (b & 7) * (G >> 3) + (b >> 3);
+  return b;
+}
+
+__device__ inline double atomic_ld(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void atomic_st(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of v over the 64 lanes of a wavefront, returned in every lane.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Reduce NV values per lane over the wavefront with a halving butterfly:
+// log2(NV) exchange steps each move half of the remaining values, then
+// 6 - log2(NV) full steps. Lane l ends holding in v[0] the total of value
+// index (l >> (6 - log2 NV)); that costs NV - 1 + 6 - log2(NV) shuffles
+// instead of 6 NV.
+template <int NV>
+__device__ inline double wave_multi_sum(double (&v)[NV], int lane) {
+  static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two");
+  int mask = 32;
+#pragma unroll
+  for (int h = NV / 2; h >= 1; h >>= 1) {
+    const bool upper = (lane & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double send = upper ? v[i] : v[i + h];
+      const double keep = upper ? v[i + h] : v[i];
+      v[i] = keep + __shfl_xor(send, mask, 64);
+    }
+    mask >>= 1;
+  }
+  for (; mask >= 1; mask >>= 1) v[0] += __shfl_xor(v[0], mask, 64);
+  return v[0];
+}
+
+// Sum 8 values per lane over aligned segments of S lanes (S >= 8): three
+// halving exchanges (4 + 2 + 1 shuffles), then log2(S/8) full steps. Lane sl
+// of a segment ends holding the total of value index sl / (S/8).
+template <int S>
+__device__ inline double seg_sum8(double (&v)[8], int sl) {
+  static_assert(S >= 8 && S <= 64 && (S & (S - 1)) == 0, "S must be a power of two >= 8");
+  int mask = S / 2;
+#pragma unroll
+  for (int h = 4; h >= 1; h >>= 1) {
+    const bool upper = (sl & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double send = upper ? v[i] : v[i + h];
+      const double keep = upper ? v[i + h] : v[i];
+      v[i] = keep + __shfl_xor(send, mask, S);
+    }
+    mask >>= 1;
+  }
+  for (; mask >= 1; mask >>= 1) v[0] += __shfl_xor(v[0], mask, S);
+  return v[0];
+}
+
+// One pass of the CSR SpMV over 8 * (256 / S) consecutive local rows starting
+// at local row p0: S lanes per row, and each lane group works on 8 rows at
+// once, so every lane has 8 independent load chains (row pointers, then
+// indices and values, then the gathered x) in flight. Rows with more than S
+// nonzeros finish in a strided loop. emit(local_row, value) is called by one
+// lane per row; rows at or past n give 0.
+template <int S, typename Emit>
+__device__ inline void spmv_pass8(const Csr& A, const double* __restrict__ x, int64_t row0, int p0,
+                                  Emit emit) {
+  constexpr int NSUB = 256 / S;
+  const int tid = threadIdx.x;
+  const int sub = tid / S, sl = tid % S;
+  const int64_t n = A.n;
+  // All loads below are unconditional, at indices clamped into range, and the
+  // values they bring are masked afterwards: conditional loads would become
+  // branches that wait on each row in turn.
+  int e0[8], e1[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int64_t r = row0 + p0 + q * NSUB + sub;
+    const int64_t rc = r < n ? r : n - 1;
+    const int a = A.rp[rc], b = A.rp[rc + 1];
+    e0[q] = a;
+    e1[q] = r < n ? b : a;
+  }
+  double acc[8];
+  if (A.nnz > 0) {
+    int c[8];
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0[q] + sl;
+      const int ec = e < e1[q] ? e : 0;
+      c[q] = A.ci[ec];
+      v[q] = A.va[ec];
+    }
+    double xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = x[(unsigned)c[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = (e0[q] + sl < e1[q]) ? v[q] * xv[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      for (int e = e0[q] + sl + S; e < e1[q]; e += S) acc[q] += A.va[e] * x[A.ci[e]];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  }
+  const double tot = seg_sum8<S>(acc, sl);
+  if ((sl & (S / 8 - 1)) == 0) {
+    const int q = sl / (S / 8);
+    emit(p0 + q * NSUB + sub, tot);
+  }
+}
+
+// Device-wide sum of cnt doubles, one row of partials per slot (tile). Every
+// workgroup calls it; it returns true only in the one workgroup that finishes
+// last, with the totals in vals (LDS). Slots are summed in index order in
+// groups of kGroup, then the group sums in index order, so the result does not
+// depend on which workgroup arrives last. Counters are reset by the workgroup
+// that consumes them, ready for the next launch on the stream.
+//
+// Cross-workgroup visibility: partials travel only through agent-scope atomic
+// stores and loads, which the L2 of each XCD keeps coherent at device level,
+// and every thread waits for its stores to complete (s_waitcnt vmcnt(0))
+// before the workgroup takes its ticket. No other data written in this launch
+// is read by another workgroup, so no device-wide release fence (an L2
+// write-back on every workgroup) is needed.
+__device__ inline void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int nslots) {
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  const int bs = blockDim.x;
+  const int ng = (nslots + kGroup - 1) / kGroup;
+  const int grp = slot / kGroup;
+  const int gbeg = grp * kGroup;
+  const int gcnt = min(kGroup, nslots - gbeg);
+  for (int i = tid; i < cnt; i += bs) atomic_st(ws.partials + (size_t)slot * ws.pstride + i, vals[i]);
+  wait_stores();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned t = atomicAdd(ws.counters + grp, 1u);
+    s_last = (t == (unsigned)(gcnt - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  for (int i = tid; i < cnt; i += bs) {
+    double s = 0.0;
+    for (int q = 0; q < gcnt; ++q) s += atomic_ld(ws.partials + (size_t)(gbeg + q) * ws.pstride + i);
+    if (ng == 1)
+      vals[i] = s;
+    else
+      atomic_st(ws.gpartials + (size_t)grp * ws.pstride + i, s);
+  }
+  if (tid == 0) atomicExch(ws.counters + grp, 0u);
+  if (ng == 1) {
+    __syncthreads();
+    return true;
+  }
+  wait_stores();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned t = atomicAdd(ws.counters + ng, 1u);
+    s_last = (t == (unsigned)(ng - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  for (int i = tid; i < cnt; i += bs) {
+    double s = 0.0;
+    for (int q = 0; q < ng; ++q) s += atomic_ld(ws.gpartials + (size_t)q * ws.pstride + i);
+    vals[i] = s;
+  }
+  if (tid == 0) atomicExch(ws.counters + ng, 0u);
+  __syncthreads();
+  return true;
+}
+
+// Plane rotation [c s; -s c] taking (a, b) to (r, 0).
+__device__ inline void rot_make(double a, double b, double* c, double* s) {
+  if (b == 0.0) {
+    *c = 1.0;
+    *s = 0.0;
+    return;
+  }
+  const double r = hypot(a, b);
+  *c = a / r;
+  *s = b / r;
+}
+
+// Givens least squares on Hessenberg column col (complete, in H): rotate a copy
+// into R with the earlier rotations, form rotation col, update g. Serial; runs
+// in one thread. Returns |g[col+1]|, the residual norm after col+1 columns.
+__device__ double givens_column(const Ws& ws, int col) {
+  const double* Hc = ws.H + (size_t)col * ws.ldh;
+  double* Rc = ws.R + (size_t)col * ws.ldh;
+  double a = Hc[0];
+  for (int i = 0; i < col; ++i) {
+    const double b = Hc[i + 1];
+    const double c = ws.cs[i], s = ws.sn[i];
+    Rc[i] = c * a + s * b;
+    a = -s * a + c * b;
+  }
+  const double b = Hc[col + 1];
+  double c, s;
+  rot_make(a, b, &c, &s);
+  Rc[col] = c * a + s * b;
+  Rc[col + 1] = 0.0;
+  ws.cs[col] = c;
+  ws.sn[col] = s;
+  const double gk = ws.g[col];
+  ws.g[col] = c * gk;
+  ws.g[col + 1] = -s * gk;
+  const double res = fabs(ws.g[col + 1]);
+  ws.gh[col + 1] = res;
+  return res;
+}
+
+// The same rotation step with the column, cosines and sines already staged in
+// LDS by the whole workgroup (hc[0..col+1], csl[0..col-1], snl[0..col-1]), so
+// the serial loop does not wait on global memory. Writes R, cs, sn, g, gh.
+__device__ double givens_column_lds(const Ws& ws, int col, const double* hc, const double* csl,
+                                    const double* snl) {
+  double* Rc = ws.R + (size_t)col * ws.ldh;
+  double a = hc[0];
+#pragma unroll 4
+  for (int i = 0; i < col; ++i) {
+    const double b = hc[i + 1];
+    const double c = csl[i], s = snl[i];
+    Rc[i] = c * a + s * b;
+    a = -s * a + c * b;
+  }
+  const double b = hc[col + 1];
+  double c, s;
+  rot_make(a, b, &c, &s);
+  Rc[col] = c * a + s * b;
+  Rc[col + 1] = 0.0;
+  ws.cs[col] = c;
+  ws.sn[col] = s;
+  const double gk = ws.g[col];
+  ws.g[col] = c * gk;
+  ws.g[col + 1] = -s * gk;
+  const double res = fabs(ws.g[col + 1]);
+  ws.gh[col + 1] = res;
+  return res;
+}
+
+// ----------------------------------------------------------- small kernels
+
+__global__ void k_init(Ws ws, int ncounters) {
+  for (int i = threadIdx.x; i < ncounters; i += blockDim.x) ws.counters[i] = 0u;
+  if (threadIdx.x == 0) {
+    DevState* st = ws.st;
+    st->done = 0;
+    st->j = 0;
+    st->true_conv = 0;
+    st->breakdown = 0;
+    st->status = 0;
+    st->bad_csr = 0;
+    st->reductions = 0;
+    st->bnorm = st->tol_abs = st->beta = st->rho = st->inv_rho = st->gk = 0.0;
+  }
+}
+
+// Start of a cycle: clear the flags and the small dense matrices (H, R, T,
+// g, gh), whose untouched entries must read as zero.
+__global__ void k_cycle_begin(Ws ws) {
+  const int m = ws.m;
+  const size_t nh = (size_t)(m + 1) * m, nt = (size_t)(m + 2) * (m + 2);
+  const size_t tot = 2 * nh + nt + 2 * (size_t)(m + 2);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < nh)
+      ws.H[i] = 0.0;
+    else if (i < 2 * nh)
+      ws.R[i - nh] = 0.0;
+    else if (i < 2 * nh + nt)
+      ws.T[i - 2 * nh] = 0.0;
+    else if (i < 2 * nh + nt + (m + 2))
+      ws.g[i - 2 * nh - nt] = 0.0;
+    else
+      ws.gh[i - 2 * nh - nt - (m + 2)] = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    DevState* st = ws.st;
+    st->done = 0;
+    st->j = 0;
+    st->true_conv = 0;
+    st->breakdown = 0;
+  }
+}
+
+__global__ void k_solve_begin(Ws ws) {
+  DevState* st = ws.st;
+  st->done = 0;
+  st->j = 0;
+  st->true_conv = 0;
+  st->breakdown = 0;
+  st->status = 0;
+  st->reductions = 0;
+}
+
+// CSR structure check: row_ptr[0] == 0, row_ptr[n] == nnz, non-decreasing
+// row_ptr, 0 <= col_idx < n.
+__global__ void k_validate_csr(const int* __restrict__ rp, const int* __restrict__ ci, int64_t n,
+                               int64_t nnz, DevState* st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int bad = 0;
+  if (t0 == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) bad = 1;
+  for (int64_t i = t0; i < n; i += stride)
+    if (rp[i + 1] < rp[i]) bad = 1;
+  for (int64_t e = t0; e < nnz; e += stride) {
+    const int c = ci[e];
+    if (c < 0 || (int64_t)c >= n) bad = 1;
+  }
+  if (bad) atomicOr(&st->bad_csr, 1);
+}
+
+// y = A x (b == nullptr) or y = b - A x: one pass of 8 * (256 / S) rows per
+// workgroup. Skipped when a state is given and its cycle is done.
+template <int S>
+__global__ __launch_bounds__(256) void k_spmv(Csr A, const double* __restrict__ x,
+                                               const double* __restrict__ b, double* __restrict__ y,
+                                               const DevState* st) {
+  if (st && st->done) return;
+  constexpr int RPP = 8 * (256 / S);
+  const int64_t row0 = (int64_t)blockIdx.x * RPP;
+  spmv_pass8<S>(A, x, row0, 0, [&](int lr, double v) {
+    const int64_t r = row0 + lr;
+    if (r < A.n) y[r] = b ? b[r] - v : v;
+  });
+}
+
+// ------------------------------------------------ the fused projection step
+
+// Dynamic LDS layout of k_fused (doubles):
+//   wl[TR]          w = A u for this tile (SpMV phase)
+//   red[4][P]       per-wavefront column sums, P = 2 (m + 2)
+//   vals[P]         this tile's sums, then the device-wide totals
+//   scr[6 (m + 2)]  scratch for the small dense step
+__host__ __device__ inline size_t fused_lds_doubles(int rpt, int m) {
+  const int P = 2 * (m + 2);
+  return (size_t)256 * rpt + 4 * (size_t)P + P + 6 * (size_t)(m + 2);
+}
+
+// The small dense step of a lagged scheme (one-reduce MGS or CGS2, first
+// reduction), run by the last workgroup with the totals in vals:
+//   vals[2q] = V_q . u, vals[2q+1] = V_q . w (q < k), vals[2k] = u.u, vals[2k+1] = u.w.
+__device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, int m_eff,
+                            int scheme) {
+  __shared__ double s_rho;
+  __shared__ int s_go;  // 0: nothing more; 1: extend T (or L) only; 2: also the MAXPY coefficients
+  const int tid = threadIdx.x, bs = blockDim.x;
+  DevState* st = ws.st;
+  const int M2 = ws.m + 2;
+  double* hc = scr + 3 * M2;   // column k-1 of H, then rho
+  double* csl = scr + 4 * M2;
+  double* snl = scr + 5 * M2;
+  if (k >= 1) {
+    const double* Hc = ws.H + (size_t)(k - 1) * ws.ldh;
+    for (int i = tid; i < k; i += bs) hc[i] = Hc[i];
+    for (int i = tid; i < k - 1; i += bs) {
+      csl[i] = ws.cs[i];
+      snl[i] = ws.sn[i];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    st->reductions += 1;
+    const double alpha = vals[2 * k];
+    int go = 2;
+    double rho = 0.0;
+    if (!(alpha >= 0.0) || !isfinite(alpha)) {
+      st->status = kNonfinite;
+      st->done = 1;
+      go = 0;
+    } else {
+      rho = sqrt(alpha);
+      if (k == 0) {
+        st->beta = rho;
+        ws.g[0] = rho;
+        if (rho <= st->tol_abs) {
+          st->true_conv = 1;
+          st->done = 1;
+          st->j = 0;
+          go = 0;
+        }
+      } else {
+        ws.H[(size_t)(k - 1) * ws.ldh + k] = rho;
+        hc[k] = rho;
+        const double gk = givens_column_lds(ws, k - 1, hc, csl, snl);
+        st->gk = gk;
+        if (!isfinite(gk)) {
+          st->status = kNonfinite;
+          st->done = 1;
+          go = 0;
+        } else if (rho == 0.0) {
+          st->breakdown = 1;
+          st->done = 1;
+          st->j = k;
+          go = 0;
+        } else if (gk <= st->tol_abs || k == m_eff) {
+          st->done = 1;
+          st->j = k;
+          go = 1;
+        }
+      }
+      if (go) {
+        st->rho = rho;
+        st->inv_rho = 1.0 / rho;
+      }
+    }
+    s_rho = rho;
+    s_go = go;
+  }
+  __syncthreads();
+  const int go = s_go;
+  if (go == 0) return;
+  const double rho = s_rho;
+  const int ldt = ws.ldt;
+  double* ell = scr;                 // l = V[:,0:k]^T v_k, the new row of L
+  double* rr = scr + (ws.m + 2);     // r = V[:,0:k+1]^T A v_k
+  double* tcol = scr + 2 * (ws.m + 2);
+  for (int q = tid; q < k; q += bs) ell[q] = vals[2 * q] / rho;
+  __syncthreads();
+  if (scheme == kSchemeMgs1r) {
+    // Malard-Paige: T[0:k,k] = -T[0:k,0:k] l, T[k,k] = 1, so T = (I + L^T)^{-1}.
+    for (int i = tid; i < k; i += bs) {
+      double s = 0.0;
+#pragma unroll 8
+      for (int q = i; q < k; ++q) s += ws.T[(size_t)q * ldt + i] * ell[q];
+      tcol[i] = -s;
+      ws.T[(size_t)k * ldt + i] = -s;
+    }
+    if (tid == 0) {
+      tcol[k] = 1.0;
+      ws.T[(size_t)k * ldt + k] = 1.0;
+    }
+  } else {
+    for (int q = tid; q < k; q += bs) ws.T[(size_t)q * ldt + k] = ell[q];  // L[k,q]
+  }
+  if (go == 1) return;
+  for (int q = tid; q < k; q += bs) rr[q] = vals[2 * q + 1] / rho;
+  if (tid == 0) rr[k] = (vals[2 * k + 1] / rho) / rho;
+  __syncthreads();
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  if (scheme == kSchemeMgs1r) {
+    // h = T^T r = (I + L)^{-1} V^T A v_k: the MGS coefficients.
+    for (int i = tid; i <= k; i += bs) {
+      double s = 0.0;
+      if (i < k) {
+#pragma unroll 8
+        for (int q = 0; q < i; ++q) s += ws.T[(size_t)i * ldt + q] * rr[q];
+      } else {
+        for (int q = 0; q < k; ++q) s += tcol[q] * rr[q];
+      }
+      s += rr[i];
+      ws.coef[i] = s;
+      ws.H[(size_t)k * ws.ldh + i] = s;
+      if (!isfinite(s)) s_bad = 1;
+    }
+  } else {
+    // CGS2: first-pass coefficients corrected to first order, (I - L) r.
+    for (int i = tid; i <= k; i += bs) {
+      double s = rr[i];
+      if (i < k) {
+        for (int q = 0; q < i; ++q) s -= ws.T[(size_t)q * ldt + i] * rr[q];
+      } else {
+        for (int q = 0; q < k; ++q) s -= ell[q] * rr[q];
+      }
+      ws.coef[i] = s;
+      if (!isfinite(s)) s_bad = 1;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && s_bad) {
+    st->status = kNonfinite;
+    st->done = 1;
+  }
+}
+
+// CGS2 second reduction: vals[2q] = V_q . z for q <= k; H[:,k] = (I - L) r + s.
+__device__ void tail_cgs2_second(const Ws& ws, const double* vals, int k) {
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  if (tid == 0) {
+    ws.st->reductions += 1;
+    s_bad = 0;
+  }
+  __syncthreads();
+  for (int i = tid; i <= k; i += bs) {
+    const double s = vals[2 * i];
+    ws.coef2[i] = s;
+    const double h = ws.coef[i] + s;
+    ws.H[(size_t)k * ws.ldh + i] = h;
+    if (!isfinite(h)) s_bad = 1;
+  }
+  __syncthreads();
+  if (tid == 0 && s_bad) {
+    ws.st->status = kNonfinite;
+    ws.st->done = 1;
+  }
+}
+
+// Fused Arnoldi step for the lagged schemes, K = index of the column being
+// normalized (u = V[:,K]):
+//   HAS_SPMV: w = A u for the tile (written to ws.w and kept in LDS);
+//   sums over the tile of V_q . u and V_q . w for q < K, u.u and u.w;
+//   device-wide reduction; the last workgroup runs the tail.
+// Without HAS_SPMV (the norm-only flush, or CGS2's second projection with
+// u = z) w is zero and only the u column sums are formed.
+// RPT rows per lane, 256 threads = 4 wavefronts; lane l of wavefront wv owns
+// rows tile0 + wv*64*RPT + i*64 + l, so every column read is 512 contiguous
+// bytes per wavefront.
+template <int RPT, int S, bool HAS_SPMV>
+__global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int m_eff, int tail, int G) {
+  extern __shared__ double lds[];
+  constexpr int TR = 256 * RPT;
+  constexpr int CB = 4;  // columns per butterfly chunk
+  if (ws.st->done) return;
+  const int P = 2 * (ws.m + 2);
+  double* wl = lds;
+  double* red = lds + TR;
+  double* vals = red + 4 * P;
+  double* scr = vals + P;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int tile = tile_of_block(G);
+  const int64_t row0 = (int64_t)tile * TR;
+  const int64_t n = A.n;
+  const double* __restrict__ V = ws.V;
+  const int64_t ldv = ws.ldv;
+  const double* __restrict__ u_g = V + (size_t)K * ldv;
+
+  if constexpr (HAS_SPMV) {
+    // SpMV of the tile, 8 rows per lane group per pass.
+    for (int p0 = 0; p0 < TR; p0 += 8 * (256 / S))
+      spmv_pass8<S>(A, u_g, row0, p0, [&](int lr, double v) { wl[lr] = v; });
+    __syncthreads();
+  }
+
+  // This lane's rows (clamped into range for loads), its u and w values;
+  // rows past n carry u = w = 0 and so add nothing.
+  double u[RPT], w[RPT];
+  int64_t rows[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int lr = wv * 64 * RPT + i * 64 + lane;
+    const int64_t r = row0 + lr;
+    const bool ok = r < n;
+    rows[i] = ok ? r : n - 1;
+    const double uv = u_g[rows[i]];
+    u[i] = ok ? uv : 0.0;
+    w[i] = (HAS_SPMV && ok) ? wl[lr] : 0.0;
+    if (HAS_SPMV && ok) ws.w[r] = w[i];
+  }
+  double* myred = red + wv * P;
+
+  // Columns 0..K-1 in chunks of CB, then the rest one at a time. The loads of
+  // a chunk (CB columns x RPT rows) are all issued before any is used.
+  constexpr int NVC = HAS_SPMV ? 2 * CB : CB;
+  int j0 = 0;
+  for (; j0 + CB <= K; j0 += CB) {
+    double vv[CB][RPT];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) vv[c][i] = V[(size_t)(j0 + c) * ldv + rows[i]];
+    double acc[NVC];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      double p = 0.0, q = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        p += vv[c][i] * u[i];
+        if constexpr (HAS_SPMV) q += vv[c][i] * w[i];
+      }
+      if constexpr (HAS_SPMV) {
+        acc[2 * c] = p;
+        acc[2 * c + 1] = q;
+      } else {
+        acc[c] = p;
+      }
+    }
+    const double tot = wave_multi_sum<NVC>(acc, lane);
+    constexpr int LOGNV = (NVC == 8) ? 3 : 2;
+    if ((lane & ((64 / NVC) - 1)) == 0) {
+      const int vi = lane >> (6 - LOGNV);
+      if constexpr (HAS_SPMV) {
+        myred[2 * j0 + vi] = tot;
+      } else {
+        myred[2 * (j0 + vi)] = tot;
+        myred[2 * (j0 + vi) + 1] = 0.0;
+      }
+    }
+  }
+  for (; j0 < K; ++j0) {
+    double vv[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) vv[i] = V[(size_t)j0 * ldv + rows[i]];
+    double p = 0.0, c = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      p += vv[i] * u[i];
+      if constexpr (HAS_SPMV) c += vv[i] * w[i];
+    }
+    p = wave_sum(p);
+    if constexpr (HAS_SPMV) c = wave_sum(c);
+    if (lane == 0) {
+      myred[2 * j0] = p;
+      myred[2 * j0 + 1] = HAS_SPMV ? c : 0.0;
+    }
+  }
+  {
+    double al = 0.0, ga = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      al += u[i] * u[i];
+      if constexpr (HAS_SPMV) ga += u[i] * w[i];
+    }
+    al = wave_sum(al);
+    if constexpr (HAS_SPMV) ga = wave_sum(ga);
+    if (lane == 0) {
+      myred[2 * K] = al;
+      myred[2 * K + 1] = HAS_SPMV ? ga : 0.0;
+    }
+  }
+  __syncthreads();
+  const int cnt = 2 * (K + 1);
+  for (int i = tid; i < cnt; i += 256) vals[i] = ((red[i] + red[P + i]) + red[2 * P + i]) + red[3 * P + i];
+  __syncthreads();
+  if (!grid_reduce(vals, cnt, ws, tile, G)) return;
+  if (tail == kTailCgs2Second)
+    tail_cgs2_second(ws, vals, K - 1);
+  else
+    tail_lagged(ws, vals, scr, K, m_eff, tail == kTailLagged1r ? kSchemeMgs1r : kSchemeCgs2);
+}
+
+// ------------------------------------------------------------------ MAXPY
+
+// mode 0 (lagged step k): V[:,k] = u / rho and V[:,k+1] = w / rho - V[:,0:k+1] coef,
+//   where column k enters already normalized;
+// mode 1 (CGS2 second pass): V[:,k+1] -= V[:,0:k+1] coef2.
+template <int RPT>
+__global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
+  constexpr int TR = 256 * RPT;
+  if (ws.st->done) return;
+  const int tile = tile_of_block(G);
+  const int64_t row0 = (int64_t)tile * TR;
+  const int64_t n = ws.n;
+  const int tid = threadIdx.x;
+  double* __restrict__ V = ws.V;
+  const int64_t ldv = ws.ldv;
+  const double* __restrict__ cf = mode == 0 ? ws.coef : ws.coef2;
+  const double invr = ws.st->inv_rho;
+  // Loads at clamped rows (unconditional, so they are all in flight at once);
+  // only rows below n are stored.
+  double acc[RPT];
+  int64_t rows[RPT];
+  const double* __restrict__ src0 = mode == 0 ? ws.w : V + (size_t)(k + 1) * ldv;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = row0 + i * 256 + tid;
+    rows[i] = r < n ? r : n - 1;
+    acc[i] = mode == 0 ? src0[rows[i]] * invr : src0[rows[i]];
+  }
+  int q = 0;
+  for (; q + 4 <= k; q += 4) {
+    const double c0 = cf[q], c1 = cf[q + 1], c2 = cf[q + 2], c3 = cf[q + 3];
+    double v[4][RPT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) v[t][i] = V[(size_t)(q + t) * ldv + rows[i]];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) acc[i] = acc[i] - v[0][i] * c0 - v[1][i] * c1 - v[2][i] * c2 - v[3][i] * c3;
+  }
+  for (; q < k; ++q) {
+    const double c0 = cf[q];
+    double v[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) v[i] = V[(size_t)q * ldv + rows[i]];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) acc[i] -= v[i] * c0;
+  }
+  const double ck = cf[k];
+  double vk[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) vk[i] = V[(size_t)k * ldv + rows[i]];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = row0 + i * 256 + tid;
+    if (r < n) {
+      double x = vk[i];
+      if (mode == 0) {
+        x *= invr;
+        V[(size_t)k * ldv + r] = x;
+      }
+      V[(size_t)(k + 1) * ldv + r] = acc[i] - x * ck;
+    }
+  }
+}
+
+// ------------------------------------------- level-1 MGS building blocks
+
+// w -= coef * a (if a != nullptr; coef read from device memory), then the
+// device-wide dot product w . v (v may alias w). The last workgroup runs the
+// tail selected by `tail`. Skipped when the cycle is done (except for the
+// norm of b and the final residual, which run outside cycles).
+template <int RPT>
+__global__ __launch_bounds__(256) void k_axpy_dot(Ws ws, double* wv_,
+                                                   const double* __restrict__ a,
+                                                   const double* __restrict__ coef,
+                                                   const double* v, int tail, int i_col,
+                                                   int q_row, int m_eff, double aux, int G) {
+  constexpr int TR = 256 * RPT;
+  __shared__ double red[4];
+  __shared__ double vals[2];
+  if (tail != kTailBnorm && tail != kTailFinalRes && ws.st->done) return;
+  const int tile = tile_of_block(G);
+  const int64_t row0 = (int64_t)tile * TR;
+  const int64_t n = ws.n;
+  const int tid = threadIdx.x;
+  const double cf = a ? *coef : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = row0 + i * 256 + tid;
+    if (r < n) {
+      double x = wv_[r];
+      if (a) {
+        x -= cf * a[r];
+        wv_[r] = x;
+      }
+      s += x * (v == wv_ ? x : v[r]);
+    }
+  }
+  s = wave_sum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) vals[0] = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  if (!grid_reduce(vals, 1, ws, tile, G)) return;
+  if (tid != 0) return;
+  DevState* st = ws.st;
+  st->reductions += 1;
+  const double d = vals[0];
+  switch (tail) {
+    case kTailBnorm: {
+      const double bn = sqrt(d);
+      st->bnorm = bn;
+      st->tol_abs = aux * bn;
+      if (!isfinite(bn)) st->status = kNonfinite;
+      break;
+    }
+    case kTailFinalRes: {
+      const double r = sqrt(d);
+      st->beta = r;
+      if (!isfinite(r)) st->status = kNonfinite;
+      break;
+    }
+    case kTailMgsBeta: {
+      const double beta = sqrt(d);
+      st->beta = beta;
+      ws.g[0] = beta;
+      if (!isfinite(beta)) {
+        st->status = kNonfinite;
+        st->done = 1;
+      } else if (beta <= st->tol_abs) {
+        st->true_conv = 1;
+        st->done = 1;
+        st->j = 0;
+      } else {
+        st->inv_rho = 1.0 / beta;
+      }
+      break;
+    }
+    case kTailMgsH: {
+      ws.H[(size_t)i_col * ws.ldh + q_row] = d;
+      if (!isfinite(d)) {
+        st->status = kNonfinite;
+        st->done = 1;
+      }
+      break;
+    }
+    case kTailMgsNorm: {
+      const double hn = sqrt(d);
+      ws.H[(size_t)i_col * ws.ldh + i_col + 1] = hn;
+      if (!isfinite(hn)) {
+        st->status = kNonfinite;
+        st->done = 1;
+        break;
+      }
+      const double gk = givens_column(ws, i_col);
+      st->gk = gk;
+      if (!isfinite(gk)) {
+        st->status = kNonfinite;
+        st->done = 1;
+      } else if (hn == 0.0) {
+        st->breakdown = 1;
+        st->done = 1;
+        st->j = i_col + 1;
+      } else {
+        st->inv_rho = 1.0 / hn;
+        if (gk <= st->tol_abs || i_col + 1 == m_eff) {
+          st->done = 1;
+          st->j = i_col + 1;
+        }
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// v *= inv_rho (level-1 MGS normalization), skipped once the cycle is done:
+// a column formed by the step that ends the cycle is not part of the solution.
+__global__ __launch_bounds__(256) void k_scale(Ws ws, double* __restrict__ v) {
+  const DevState* st = ws.st;
+  if (st->done) return;
+  const double s = st->inv_rho;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ws.n; r += stride) v[r] *= s;
+}
+
+// --------------------------------------------------------- end of a cycle
+
+// y = R[0:j,0:j]^{-1} g[0:j] by column-oriented back substitution; a zero
+// pivot (singular A) gives a zero component. One workgroup.
+__global__ __launch_bounds__(256) void k_backsolve(Ws ws) {
+  extern __shared__ double gg[];
+  __shared__ double s_y;
+  const DevState* st = ws.st;
+  const int j = st->j;
+  if (st->status || j <= 0) return;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  for (int i = tid; i < j; i += bs) gg[i] = ws.g[i];
+  __syncthreads();
+  for (int i = j - 1; i >= 0; --i) {
+    if (tid == 0) {
+      const double piv = ws.R[(size_t)i * ws.ldh + i];
+      const double yi = piv != 0.0 ? gg[i] / piv : 0.0;
+      ws.y[i] = yi;
+      s_y = yi;
+    }
+    __syncthreads();
+    const double yi = s_y;
+    for (int t = tid; t < i; t += bs) gg[t] -= ws.R[(size_t)i * ws.ldh + t] * yi;
+    __syncthreads();
+  }
+}
+
+// x += V[:,0:j] y.
+template <int RPT>
+__global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, int G) {
+  constexpr int TR = 256 * RPT;
+  const DevState* st = ws.st;
+  const int j = st->j;
+  if (st->status || j <= 0) return;
+  const int tile = tile_of_block(G);
+  const int64_t row0 = (int64_t)tile * TR;
+  const int64_t n = ws.n;
+  const double* __restrict__ V = ws.V;
+  const int64_t ldv = ws.ldv;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = row0 + i * 256 + threadIdx.x;
+    if (r < n) {
+      double s = x[r];
+      for (int q = 0; q < j; ++q) s += V[(size_t)q * ldv + r] * ws.y[q];
+      x[r] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+#define GMRES_CHECK_LAUNCH()                          \
+  do {                                                \
+    if (hipGetLastError() != hipSuccess) return -2;   \
+  } while (0)
+
+int launch_init(const Ws& ws, int ncounters, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, ws, ncounters);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_solve_begin(const Ws& ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(1), 0, s, ws);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_cycle_begin(const Ws& ws, hipStream_t s) {
+  const size_t tot = 2 * (size_t)(ws.m + 1) * ws.m + (size_t)(ws.m + 2) * (ws.m + 4);
+  const unsigned blocks = (unsigned)((tot + 255) / 256 < 64 ? (tot + 255) / 256 : 64);
+  hipLaunchKernelGGL(k_cycle_begin, dim3(blocks), dim3(256), 0, s, ws);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_validate(const Csr& A, int64_t nnz, DevState* st, hipStream_t s) {
+  int64_t work = A.n > nnz ? A.n : nnz;
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_validate_csr, dim3((unsigned)blocks), dim3(256), 0, s, A.rp, A.ci, A.n, nnz,
+                     st);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+template <int S>
+static void spmv_s(const Csr& A, const double* x, const double* b, double* y, const DevState* st,
+                   hipStream_t s) {
+  constexpr int RPP = 8 * (256 / S);
+  const int64_t blocks = (A.n + RPP - 1) / RPP;
+  hipLaunchKernelGGL(k_spmv<S>, dim3((unsigned)blocks), dim3(256), 0, s, A, x, b, y, st);
+}
+
+int launch_spmv(const Csr& A, int S, const double* x, const double* b, double* y,
+                const DevState* st, hipStream_t s) {
+  switch (S) {
+    case 8: spmv_s<8>(A, x, b, y, st, s); break;
+    case 16: spmv_s<16>(A, x, b, y, st, s); break;
+    case 32: spmv_s<32>(A, x, b, y, st, s); break;
+    default: spmv_s<64>(A, x, b, y, st, s); break;
+  }
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+// The step kernels are launched with hipExtLaunchKernelGGL so that optional
+// start/stop events are attached to the dispatch itself and time the kernel
+// alone.
+template <int RPT, int S, bool HS>
+static void fused_t(const Csr& A, const Ws& ws, int K, int m_eff, int tail, int G, hipStream_t s,
+                    hipEvent_t e0, hipEvent_t e1) {
+  const uint32_t lds = (uint32_t)(fused_lds_doubles(RPT, ws.m) * sizeof(double));
+  hipExtLaunchKernelGGL((k_fused<RPT, S, HS>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A, ws, K,
+                        m_eff, tail, G);
+}
+
+template <int RPT, bool HS>
+static void fused_r(const Csr& A, int S, const Ws& ws, int K, int m_eff, int tail, int G,
+                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (!HS) {
+    fused_t<RPT, 8, false>(A, ws, K, m_eff, tail, G, s, e0, e1);
+    return;
+  }
+  switch (S) {
+    case 8: fused_t<RPT, 8, true>(A, ws, K, m_eff, tail, G, s, e0, e1); break;
+    case 16: fused_t<RPT, 16, true>(A, ws, K, m_eff, tail, G, s, e0, e1); break;
+    case 32: fused_t<RPT, 32, true>(A, ws, K, m_eff, tail, G, s, e0, e1); break;
+    default: fused_t<RPT, 64, true>(A, ws, K, m_eff, tail, G, s, e0, e1); break;
+  }
+}
+
+int launch_fused(const Csr& A, int S, const Ws& ws, int rpt, int K, bool has_spmv, int m_eff,
+                 int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  switch (rpt) {
+    case 1: has_spmv ? fused_r<1, true>(A, S, ws, K, m_eff, tail, G, s, e0, e1)
+                     : fused_r<1, false>(A, S, ws, K, m_eff, tail, G, s, e0, e1); break;
+    case 2: has_spmv ? fused_r<2, true>(A, S, ws, K, m_eff, tail, G, s, e0, e1)
+                     : fused_r<2, false>(A, S, ws, K, m_eff, tail, G, s, e0, e1); break;
+    case 4: has_spmv ? fused_r<4, true>(A, S, ws, K, m_eff, tail, G, s, e0, e1)
+                     : fused_r<4, false>(A, S, ws, K, m_eff, tail, G, s, e0, e1); break;
+    default: has_spmv ? fused_r<8, true>(A, S, ws, K, m_eff, tail, G, s, e0, e1)
+                      : fused_r<8, false>(A, S, ws, K, m_eff, tail, G, s, e0, e1); break;
+  }
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s, hipEvent_t e0,
+                 hipEvent_t e1) {
+  switch (rpt) {
+    case 1: hipExtLaunchKernelGGL(k_maxpy<1>, dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+    case 2: hipExtLaunchKernelGGL(k_maxpy<2>, dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+    case 4: hipExtLaunchKernelGGL(k_maxpy<4>, dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+    default: hipExtLaunchKernelGGL(k_maxpy<8>, dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+  }
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_axpy_dot(const Ws& ws, int rpt, double* w, const double* a, const double* coef,
+                    const double* v, int tail, int i_col, int q_row, int m_eff, double aux, int G,
+                    hipStream_t s) {
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL(k_axpy_dot<1>, dim3(G), dim3(256), 0, s, ws, w, a, coef, v, tail, i_col, q_row, m_eff, aux, G); break;
+    case 2: hipLaunchKernelGGL(k_axpy_dot<2>, dim3(G), dim3(256), 0, s, ws, w, a, coef, v, tail, i_col, q_row, m_eff, aux, G); break;
+    case 4: hipLaunchKernelGGL(k_axpy_dot<4>, dim3(G), dim3(256), 0, s, ws, w, a, coef, v, tail, i_col, q_row, m_eff, aux, G); break;
+    default: hipLaunchKernelGGL(k_axpy_dot<8>, dim3(G), dim3(256), 0, s, ws, w, a, coef, v, tail, i_col, q_row, m_eff, aux, G); break;
+  }
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_scale(const Ws& ws, double* v, hipStream_t s) {
+  int64_t blocks = (ws.n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(256), 0, s, ws, v);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(256), (size_t)(ws.m + 2) * sizeof(double), s, ws);
+  GMRES_CHECK_LAUNCH();
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL(k_xupdate<1>, dim3(G), dim3(256), 0, s, ws, x, G); break;
+    case 2: hipLaunchKernelGGL(k_xupdate<2>, dim3(G), dim3(256), 0, s, ws, x, G); break;
+    case 4: hipLaunchKernelGGL(k_xupdate<4>, dim3(G), dim3(256), 0, s, ws, x, G); break;
+    default: hipLaunchKernelGGL(k_xupdate<8>, dim3(G), dim3(256), 0, s, ws, x, G); break;
+  }
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+size_t fused_lds_bytes(int rpt, int m) { return fused_lds_doubles(rpt, m) * sizeof(double); }
+
+}  // namespace gmres

@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP kernels and the host driver of the
+// GMRES library. Not part of the public C ABI (include/gmres.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gmres {
+
+constexpr int kGroup = 32;  // tiles per first-level group of the grid reduction
+
+constexpr int kSchemeMgs = 0;
+constexpr int kSchemeMgs1r = 1;
+constexpr int kSchemeCgs2 = 2;
+
+constexpr int kNonfinite = -3;
+
+// Tail selectors: what the last workgroup of a reduction does with the totals.
+enum Tail {
+  kTailLagged1r = 1,    // one-reduce MGS step
+  kTailLaggedCgs2 = 2,  // CGS2 step, first reduction
+  kTailCgs2Second = 3,  // CGS2 step, second reduction
+  kTailBnorm = 4,       // ||b||, tolerance
+  kTailFinalRes = 5,    // ||b - A x|| at exit
+  kTailMgsBeta = 6,     // level-1 MGS restart norm
+  kTailMgsH = 7,        // level-1 MGS coefficient h_{q,i}
+  kTailMgsNorm = 8      // level-1 MGS h_{i+1,i}, Givens, flags
+};
+
+// Per-solve state in device memory; the host reads it once per cycle.
+struct DevState {
+  int32_t done;       // the current cycle has ended: later launches return at once
+  int32_t j;          // columns the cycle completed
+  int32_t true_conv;  // the restart residual met the tolerance
+  int32_t breakdown;  // exact breakdown, rho == 0
+  int32_t status;     // 0 or kNonfinite
+  int32_t bad_csr;    // set by the structure check
+  int64_t reductions; // device-wide reductions completed
+  double bnorm, tol_abs, beta, rho, inv_rho, gk;
+};
+
+struct Csr {
+  const int* rp;
+  const int* ci;
+  const double* va;
+  int64_t n;
+  int64_t nnz;
+};
+
+// Views into the caller's workspace.
+struct Ws {
+  double* V;         // n x (m+2), column-major, leading dimension ldv
+  double* w;         // ldv: SpMV output of the current step
+  double* H;         // (m+1) x m unrotated Hessenberg matrix, ld = ldh
+  double* R;         // (m+1) x m Givens-rotated copy
+  double* T;         // (m+2) x (m+2): Malard-Paige T (one-reduce) or L rows (CGS2), ld = ldt
+  double* g;         // m+2 rotated right-hand side
+  double* gh;        // m+2: gh[k] = |g_k| as it stood right after rotation k-1
+  double* cs;        // m+1 rotation cosines
+  double* sn;        // m+1 rotation sines
+  double* coef;      // m+2 MAXPY coefficients of the current step
+  double* coef2;     // m+2 second-pass coefficients (CGS2)
+  double* y;         // m+2 least-squares solution
+  double* partials;  // G x pstride tile sums
+  double* gpartials; // ceil(G / kGroup) x pstride group sums
+  unsigned* counters;// ceil(G / kGroup) + 1 tickets
+  DevState* st;
+  int64_t n;
+  int64_t ldv;
+  int ldh, ldt, pstride, m;
+};
+
+int launch_init(const Ws& ws, int ncounters, hipStream_t s);
+int launch_solve_begin(const Ws& ws, hipStream_t s);
+int launch_cycle_begin(const Ws& ws, hipStream_t s);
+int launch_validate(const Csr& A, int64_t nnz, DevState* st, hipStream_t s);
+int launch_spmv(const Csr& A, int S, const double* x, const double* b, double* y,
+                const DevState* st, hipStream_t s);
+int launch_fused(const Csr& A, int S, const Ws& ws, int rpt, int K, bool has_spmv, int m_eff,
+                 int tail, int G, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+int launch_axpy_dot(const Ws& ws, int rpt, double* w, const double* a, const double* coef,
+                    const double* v, int tail, int i_col, int q_row, int m_eff, double aux, int G,
+                    hipStream_t s);
+int launch_scale(const Ws& ws, double* v, hipStream_t s);
+int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, hipStream_t s);
+size_t fused_lds_bytes(int rpt, int m);
+
+}  // namespace gmres

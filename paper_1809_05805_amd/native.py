@@ -1,0 +1,254 @@
+"""ctypes binding to libgmres_hip.so (C ABI in include/gmres.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels. The functions carry the C names; ``GmresSolver`` bundles a context
+with the torch tensors (CSR arrays, workspace) it borrows. There is no CPU
+fallback: if the library is not built, loading it raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmres_hip.so")
+
+GMRES_MGS, GMRES_MGS_1R, GMRES_CGS2 = 0, 1, 2
+SCHEMES = {"mgs": GMRES_MGS, "mgs1r": GMRES_MGS_1R, "cgs2": GMRES_CGS2}
+GMRES_OK, GMRES_ERR_ARG, GMRES_ERR_HIP, GMRES_ERR_NONFINITE, GMRES_ERR_WORKSPACE = 0, -1, -2, -3, -4
+GMRES_MAX_RESTART = 256
+
+EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destroy",
+            "gmres_status_string", "gmres_spmv", "gmres_last_cycle", "gmres_basis",
+            "gmres_set_timing", "gmres_get_timing"]
+GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_COUNT = 0, 1, 2
+
+
+class GmresInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("cycles", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("breakdown", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("rel_res_true", ctypes.c_double),
+                ("rel_res_est", ctypes.c_double), ("reductions", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class GmresKernelStat(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("launches", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1809_05805_amd.build_native "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    lib.gmres_workspace_bytes.restype = SZ
+    lib.gmres_workspace_bytes.argtypes = [I64, I32, I32]
+    lib.gmres_create.restype = ctypes.c_int
+    lib.gmres_create.argtypes = [ctypes.POINTER(P), I64, I64, P, P, P, I32, I32, P, SZ, P]
+    lib.gmres_solve.restype = ctypes.c_int
+    lib.gmres_solve.argtypes = [P, P, P, D, I64, ctypes.POINTER(GmresInfo), P]
+    lib.gmres_destroy.restype = ctypes.c_int
+    lib.gmres_destroy.argtypes = [P]
+    lib.gmres_status_string.restype = ctypes.c_char_p
+    lib.gmres_status_string.argtypes = [ctypes.c_int]
+    lib.gmres_spmv.restype = ctypes.c_int
+    lib.gmres_spmv.argtypes = [P, P, P]
+    lib.gmres_last_cycle.restype = ctypes.c_int
+    lib.gmres_last_cycle.argtypes = [P, P, P, P, ctypes.POINTER(I32)]
+    lib.gmres_basis.restype = ctypes.c_int
+    lib.gmres_basis.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(I64)]
+    lib.gmres_set_timing.restype = ctypes.c_int
+    lib.gmres_set_timing.argtypes = [P, ctypes.c_int]
+    lib.gmres_get_timing.restype = ctypes.c_int
+    lib.gmres_get_timing.argtypes = [P, ctypes.POINTER(GmresKernelStat)]
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------- C-named wrappers
+
+def gmres_workspace_bytes(n: int, m: int, scheme: int) -> int:
+    return int(load().gmres_workspace_bytes(n, m, scheme))
+
+
+def gmres_status_string(status: int) -> str:
+    return load().gmres_status_string(status).decode()
+
+
+def gmres_create(n, nnz, row_ptr_ptr, col_idx_ptr, vals_ptr, m, scheme, ws_ptr, ws_bytes,
+                 stream_ptr) -> tuple[int, int | None]:
+    ctx = ctypes.c_void_p()
+    rc = load().gmres_create(ctypes.byref(ctx), n, nnz, row_ptr_ptr, col_idx_ptr, vals_ptr, m,
+                             scheme, ws_ptr, ws_bytes, stream_ptr)
+    return rc, (ctx.value if rc == GMRES_OK else None)
+
+
+def gmres_solve(ctx, b_ptr, x_ptr, rtol, max_iters, hist: np.ndarray | None = None):
+    info = GmresInfo()
+    hp = None if hist is None else hist.ctypes.data_as(ctypes.c_void_p)
+    rc = load().gmres_solve(ctx, b_ptr, x_ptr, float(rtol), int(max_iters), ctypes.byref(info), hp)
+    return rc, info
+
+
+def gmres_destroy(ctx) -> int:
+    return load().gmres_destroy(ctx)
+
+
+def gmres_spmv(ctx, x_ptr, y_ptr) -> int:
+    return load().gmres_spmv(ctx, x_ptr, y_ptr)
+
+
+def gmres_last_cycle(ctx, m: int):
+    H = np.zeros((m, m + 1))
+    T = np.zeros((m + 2, m + 2))
+    g = np.zeros(m + 2)
+    j = ctypes.c_int32(0)
+    rc = load().gmres_last_cycle(ctx, H.ctypes.data_as(ctypes.c_void_p),
+                                 T.ctypes.data_as(ctypes.c_void_p),
+                                 g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(j))
+    return rc, H.T, T.T, g, j.value     # column-major buffers read as their transposes
+
+
+def gmres_basis(ctx):
+    V = ctypes.c_void_p()
+    ld = ctypes.c_int64()
+    rc = load().gmres_basis(ctx, ctypes.byref(V), ctypes.byref(ld))
+    return rc, V.value, ld.value
+
+
+def gmres_set_timing(ctx, enable: bool) -> int:
+    return load().gmres_set_timing(ctx, 1 if enable else 0)
+
+
+def gmres_get_timing(ctx):
+    arr = (GmresKernelStat * GMRES_KSTAT_COUNT)()
+    rc = load().gmres_get_timing(ctx, arr)
+    return rc, [{"ms": a.ms, "bytes": a.bytes, "launches": a.launches} for a in arr]
+
+
+# ----------------------------------------------------------- torch front end
+
+class GmresError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        super().__init__(f"{what}: {gmres_status_string(rc)} ({rc})")
+        self.rc = rc
+
+
+@dataclass
+class SolveResult:
+    status: int
+    iters: int
+    cycles: int
+    converged: bool
+    breakdown: bool
+    rel_res_true: float
+    rel_res_est: float
+    reductions: int
+    hist: np.ndarray | None
+
+
+class GmresSolver:
+    """A context bound to CSR tensors on a GPU and a workspace it allocates with torch."""
+
+    def __init__(self, row_ptr, col_idx, vals, m: int, scheme: str = "mgs1r", stream=None):
+        import torch
+
+        if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32 or vals.dtype != torch.float64:
+            raise TypeError("CSR arrays must be int32, int32, float64")
+        for t in (row_ptr, col_idx, vals):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("CSR arrays must be contiguous device tensors")
+        self.n = int(row_ptr.numel() - 1)
+        self.nnz = int(col_idx.numel())
+        self.m = int(m)
+        self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        self.device = row_ptr.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._keep = (row_ptr, col_idx, vals)
+        nbytes = gmres_workspace_bytes(self.n, self.m, self.scheme)
+        if nbytes == 0:
+            raise GmresError(GMRES_ERR_ARG, "gmres_workspace_bytes")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = self.ws.data_ptr() + off
+        self.ws_bytes = nbytes
+        rc, ctx = gmres_create(self.n, self.nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                               vals.data_ptr() if self.nnz else None, self.m, self.scheme,
+                               self.ws_ptr, nbytes, self.stream.cuda_stream)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_create")
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            gmres_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, x, rtol: float, max_iters: int, hist: bool = False,
+              check: bool = True) -> SolveResult:
+        import torch
+
+        for t in (b, x):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != self.n:
+                raise ValueError("b and x must be contiguous float64 device tensors of length n")
+        h = np.full(max(int(max_iters), 1), np.nan) if hist else None
+        rc, info = gmres_solve(self.ctx, b.data_ptr(), x.data_ptr(), rtol, max_iters, h)
+        if check and rc not in (GMRES_OK, GMRES_ERR_NONFINITE):
+            raise GmresError(rc, "gmres_solve")
+        return SolveResult(rc, info.iters, info.cycles, bool(info.converged), bool(info.breakdown),
+                           info.rel_res_true, info.rel_res_est, info.reductions,
+                           None if h is None else h[: info.iters].copy())
+
+    def spmv(self, x, y):
+        rc = gmres_spmv(self.ctx, x.data_ptr(), y.data_ptr())
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_spmv")
+
+    def last_cycle(self):
+        rc, H, T, g, j = gmres_last_cycle(self.ctx, self.m)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_last_cycle")
+        return H, T, g, j
+
+    def set_timing(self, enable: bool):
+        rc = gmres_set_timing(self.ctx, enable)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_set_timing")
+
+    def timing(self) -> dict:
+        rc, st = gmres_get_timing(self.ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_get_timing")
+        return {"step": st[GMRES_KSTAT_STEP], "maxpy": st[GMRES_KSTAT_MAXPY]}
+
+    def basis(self):
+        """V (n x (m+2)) as a view into the workspace tensor."""
+        import torch
+
+        rc, vptr, ld = gmres_basis(self.ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_basis")
+        off = vptr - self.ws.data_ptr()
+        cols = self.m + 2
+        flat = self.ws[off: off + ld * cols * 8].view(torch.float64)
+        return flat.view(cols, ld)[:, : self.n].t()

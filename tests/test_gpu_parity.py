@@ -1,0 +1,248 @@
+"""GPU-vs-oracle parity of the HIP GMRES library, called through its C ABI.
+
+Tolerance: 1e-10 relative in FP64 for the Hessenberg matrix, the iterate and
+the residual history of a fixed-budget cycle (no early exit), on seeded inputs
+that span many tiles and a ragged last tile. Integer outcomes (columns per
+cycle, iteration counts, reductions, flags) must be equal.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1809_05805_amd import problems as P
+from tests.gpu_util import D, gpu_run, log, oracle_run, rel
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["mgs", "mgs1r", "cgs2"]
+TOL = 1e-10
+
+
+def small_cases():
+    return {
+        "cfg1": P.make_config("cfg1"),                 # 2D 5-point 64^2 (16 tiles)
+        "cfg1_ragged": P.make_config("cfg1", N=37),    # n = 1369: ragged last tile
+        "cfg2_24": P.make_config("cfg2", N=24),        # 3D 7-point, n = 13824
+        "cfg3_12": P.make_config("cfg3", N=12),        # 27-point, rows scaled to kappa ~ 1e8
+        "dense50": P.random_dense(50, seed=3),         # 50 nonzeros per row
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1809_05805_amd import native
+    native.load()
+    yield
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_spmv_matches_oracle(case):
+    import torch
+
+    from paper_1809_05805_amd.native import GmresSolver
+    import oracle
+
+    p = CASES[case]
+    log(f"spmv {case} n={p.n}")
+    rp, ci, va = (torch.from_numpy(a).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
+    s = GmresSolver(rp, ci, va, 4, "mgs1r")
+    x = P.rng(77, 0).standard_normal(p.n)
+    y = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    s.spmv(torch.from_numpy(x).cuda(), y)
+    torch.cuda.synchronize()
+    ref = oracle.spmv(p.row_ptr, p.col_idx, p.vals, x)
+    absA = p.scipy().copy()
+    absA.data = np.abs(absA.data)
+    bound = 64 * np.finfo(float).eps * (absA @ np.abs(x))
+    assert np.all(np.abs(y.cpu().numpy() - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("case", list(CASES))
+def test_fixed_budget_cycle_parity(scheme, case):
+    """One full cycle, no early exit: H, x and |g_k| match the oracle to 1e-10."""
+    p = CASES[case]
+    m = min(p.m, 40)
+    log(f"fixed-budget {scheme} {case} n={p.n} m={m}")
+    g = gpu_run(p, scheme, m=m, rtol=0.0, max_iters=m)
+    o = oracle_run(p, scheme, m=m, rtol=0.0, max_iters=m)
+    r = g["res"]
+    assert r.status == 0 and o.status == 0
+    assert r.iters == o.iters == m and g["j"] == o.j == m
+    assert r.reductions == o.reductions
+    assert rel(g["x"], o.x) <= TOL
+    assert np.max(np.abs(r.hist - o.hist)) <= TOL
+    # Columns formed after the residual reached rounding level are fixed by
+    # rounding noise in any implementation; compare H where the basis is determined.
+    kc = int(np.argmax(o.hist < 1e-11)) if np.any(o.hist < 1e-11) else m
+    assert rel(g["H"][:, :kc], o.H[:, :kc]) <= TOL
+    assert abs(r.rel_res_true - o.rel_res_true) <= TOL * max(o.rel_res_true, 1e-3)
+    if scheme == "mgs1r":
+        assert np.max(np.abs(g["T"][:kc, :kc] - o.T[:kc, :kc])) <= TOL
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_to_tolerance_parity(scheme):
+    """Restarted solve to rtol: same iteration count, both truly converged."""
+    p = CASES["cfg1"]
+    log(f"to-tolerance {scheme} cfg1")
+    g = gpu_run(p, scheme)
+    o = oracle_run(p, scheme, dump=False)
+    r = g["res"]
+    assert r.converged and o.converged
+    assert r.rel_res_true <= p.rtol and o.rel_res_true <= p.rtol
+    assert abs(r.iters - o.iters) <= 1
+    assert r.cycles == o.cycles or abs(r.iters - o.iters) == 1
+    n_common = min(len(r.hist), len(o.hist))
+    assert np.max(np.abs(r.hist[:n_common] - o.hist[:n_common])) <= 1e-8
+    kappa_rtol = 1e4 * p.rtol
+    assert rel(g["x"], p.x_true) <= kappa_rtol
+    assert rel(g["x"], o.x) <= 10 * p.rtol
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_basis_properties(scheme):
+    """The GPU's own basis satisfies the Arnoldi relation and the scheme's orthogonality bound."""
+    p = CASES["cfg3_12"]
+    log(f"basis {scheme} cfg3_12")
+    g = gpu_run(p, scheme, m=60, rtol=0.0, max_iters=60, basis=True)
+    j = g["j"]
+    V = g["V"][:, :j]
+    H = g["H"]
+    A = p.scipy()
+    AV = A @ V[:, : j - 1]
+    E = AV - V[:, :j] @ H[:j, : j - 1]
+    assert np.linalg.norm(E) / (np.linalg.norm(A.data) * j) <= 1e-13
+    loss = D.orth_loss(V)
+    if scheme == "cgs2":
+        assert loss <= 1e-13
+    else:
+        assert loss <= 1e-6
+    if scheme == "mgs1r":
+        T = g["T"][:j, :j]
+        assert np.max(np.abs(T - D.t_from_basis(V))) <= 1e-12 * max(1.0, np.abs(T).max())
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_deterministic(scheme):
+    """The grid reductions sum in a fixed order: repeated solves are bitwise equal."""
+    p = CASES["cfg2_24"]
+    log(f"determinism {scheme}")
+    a = gpu_run(p, scheme, m=30, rtol=0.0, max_iters=60)
+    b = gpu_run(p, scheme, m=30, rtol=0.0, max_iters=60)
+    assert np.array_equal(a["x"], b["x"])
+    assert np.array_equal(a["H"], b["H"])
+    assert np.array_equal(a["res"].hist, b["res"].hist)
+
+
+# ------------------------------------------------------------- special cases
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_cyclic_shift_exact(scheme):
+    n = 12
+    p = P.cyclic_shift(n)
+    log(f"cyclic {scheme}")
+    g = gpu_run(p, scheme, m=n, rtol=0.0, max_iters=n)
+    r = g["res"]
+    assert r.breakdown and g["j"] == n
+    assert np.all(r.hist[: n - 1] == 1.0) and r.hist[n - 1] == 0.0
+    assert np.array_equal(g["x"], p.x_true)
+    assert r.converged and r.rel_res_true == 0.0
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_edge_sizes(scheme):
+    import scipy.sparse as sp
+
+    log(f"edge sizes {scheme}")
+    # n = 1
+    rp, ci, va = P.csr_from_scipy(sp.csr_matrix(np.array([[3.0]])))
+    p = P.Problem("one", rp, ci, va, np.array([6.0]), np.zeros(1), np.array([2.0]), m=1, rtol=1e-12)
+    g = gpu_run(p, scheme)
+    assert g["res"].converged and abs(g["x"][0] - 2.0) <= 1e-15
+    # restart length 1
+    p = P.make_config("cfg1", N=8)
+    g = gpu_run(p, scheme, m=1, rtol=1e-8, max_iters=3000)
+    o = oracle_run(p, scheme, m=1, rtol=1e-8, max_iters=3000, dump=False)
+    assert g["res"].converged and g["res"].iters == o.iters
+    # zero budget
+    g = gpu_run(p, scheme, max_iters=0)
+    assert g["res"].iters == 0 and not g["res"].converged and abs(g["res"].rel_res_true - 1.0) <= 1e-15
+    # zero right-hand side
+    g = gpu_run(p, scheme, b=np.zeros(p.n), x0=np.ones(p.n))
+    assert g["res"].converged and g["res"].iters == 0 and np.all(g["x"] == 0.0)
+    # converged on the first column
+    g = gpu_run(P.make_config("cfg1", N=16), scheme, rtol=0.9, max_iters=50)
+    assert g["res"].converged and g["res"].iters == 1
+    # empty rows are allowed in the structure (a zero row makes A singular)
+    A = sp.random(300, 300, density=0.02, random_state=1, format="csr") + sp.identity(300)
+    A = sp.csr_matrix(A)
+    A.data[A.indptr[5]:A.indptr[6]] = 0.0
+    A.eliminate_zeros()
+    rp, ci, va = P.csr_from_scipy(A)
+    b = P.rng(9, 3).standard_normal(300)
+    p = P.Problem("zero-row", rp, ci, va, b, np.zeros(300), None, m=20, rtol=0.0)
+    g = gpu_run(p, scheme, m=20, rtol=0.0, max_iters=20)
+    o = oracle_run(p, scheme, m=20, rtol=0.0, max_iters=20)
+    assert g["res"].iters == o.iters
+    assert rel(g["H"], o.H) <= TOL
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_error_paths(scheme):
+    import torch
+
+    from paper_1809_05805_amd import native
+    from paper_1809_05805_amd.native import GmresError, GmresSolver
+
+    p = P.make_config("cfg1", N=16)
+    log(f"errors {scheme}")
+    b = p.b.copy()
+    b[7] = np.nan
+    g = gpu_run(p, scheme, b=b)
+    assert g["res"].status == native.GMRES_ERR_NONFINITE
+    v = p.vals.copy()
+    v[11] = np.inf
+    q = P.Problem("inf", p.row_ptr, p.col_idx, v, p.b, p.x0, None, p.m, p.rtol)
+    g = gpu_run(q, scheme)
+    assert g["res"].status == native.GMRES_ERR_NONFINITE
+    assert np.all(np.isfinite(g["x"]))
+    # malformed CSR is refused before any solve
+    bad = p.col_idx.copy()
+    bad[5] = p.n
+    with pytest.raises(GmresError) as e:
+        GmresSolver(torch.from_numpy(p.row_ptr).cuda(), torch.from_numpy(bad).cuda(),
+                    torch.from_numpy(p.vals).cuda(), 10, scheme)
+    assert e.value.rc == native.GMRES_ERR_ARG
+    rp = p.row_ptr.copy()
+    rp[3], rp[4] = rp[4], rp[3]
+    with pytest.raises(GmresError):
+        GmresSolver(torch.from_numpy(rp).cuda(), torch.from_numpy(p.col_idx).cuda(),
+                    torch.from_numpy(p.vals).cuda(), 10, scheme)
+    # workspace too small, restart too long, host pointers
+    d_rp, d_ci, d_va = (torch.from_numpy(a).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
+    need = native.gmres_workspace_bytes(p.n, 10, native.SCHEMES[scheme])
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rc, _ = native.gmres_create(p.n, p.nnz, d_rp.data_ptr(), d_ci.data_ptr(), d_va.data_ptr(), 10,
+                                native.SCHEMES[scheme], ws.data_ptr(), need - 8, None)
+    assert rc == native.GMRES_ERR_WORKSPACE
+    rc, _ = native.gmres_create(p.n, p.nnz, d_rp.data_ptr(), d_ci.data_ptr(), d_va.data_ptr(),
+                                native.GMRES_MAX_RESTART + 1, native.SCHEMES[scheme],
+                                ws.data_ptr(), need, None)
+    assert rc == native.GMRES_ERR_ARG
+    rc, _ = native.gmres_create(p.n, p.nnz, p.row_ptr.ctypes.data, d_ci.data_ptr(), d_va.data_ptr(),
+                                10, native.SCHEMES[scheme], ws.data_ptr(), need, None)
+    assert rc == native.GMRES_ERR_ARG
+    s = GmresSolver(d_rp, d_ci, d_va, 10, scheme)
+    rc, _ = native.gmres_solve(s.ctx, p.b.ctypes.data, d_va.data_ptr(), 1e-8, 10)
+    assert rc == native.GMRES_ERR_ARG
+    x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    bt = torch.from_numpy(p.b).cuda()
+    for rtol in (-1.0, float("nan")):
+        rc, _ = native.gmres_solve(s.ctx, bt.data_ptr(), x.data_ptr(), rtol, 10)
+        assert rc == native.GMRES_ERR_ARG

@@ -1,0 +1,67 @@
+"""The C-ABI library builds, loads without a GPU and exports what include/gmres.h declares.
+
+No compute call is made here: only the pure host functions (workspace sizing,
+status strings) run.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1809_05805_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gmres.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmres_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(native.LIB_PATH):
+        from paper_1809_05805_amd import build_native
+        build_native.build()
+    return native.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert set(names) == set(native.EXPORTED)
+    for name in names:
+        assert isinstance(getattr(lib, name), ctypes._CFuncPtr), name
+
+
+def test_workspace_sizing(lib):
+    assert native.gmres_workspace_bytes(0, 30, 1) == 0
+    assert native.gmres_workspace_bytes(100, 0, 1) == 0
+    assert native.gmres_workspace_bytes(100, native.GMRES_MAX_RESTART + 1, 1) == 0
+    assert native.gmres_workspace_bytes(100, 30, 3) == 0
+    small = native.gmres_workspace_bytes(4096, 30, 1)
+    # the basis alone: n x (m+2) doubles
+    assert small >= 4096 * 32 * 8
+    assert native.gmres_workspace_bytes(2 * 4096, 30, 1) > small
+    assert native.gmres_workspace_bytes(4096, 60, 1) > small
+    big = native.gmres_workspace_bytes(2_097_152, 50, 1)
+    assert 2_097_152 * 52 * 8 <= big <= 2_097_152 * 52 * 8 * 1.1
+    assert native.gmres_workspace_bytes(4096, 30, 0) == native.gmres_workspace_bytes(4096, 30, 2)
+
+
+def test_status_strings(lib):
+    assert native.gmres_status_string(0) == "ok"
+    for rc in (-1, -2, -3, -4):
+        assert native.gmres_status_string(rc) not in ("ok", "unknown status")
+    assert native.gmres_status_string(7) == "unknown status"
+
+
+def test_header_constants_match_binding():
+    src = open(os.path.join(ROOT, "include", "gmres.h")).read()
+    assert int(re.search(r"GMRES_MAX_RESTART (\d+)", src).group(1)) == native.GMRES_MAX_RESTART
+    for name, val in (("GMRES_MGS", 0), ("GMRES_MGS_1R", 1), ("GMRES_CGS2", 2),
+                      ("GMRES_ERR_ARG", -1), ("GMRES_ERR_HIP", -2), ("GMRES_ERR_NONFINITE", -3),
+                      ("GMRES_ERR_WORKSPACE", -4)):
+        assert re.search(rf"{name} = {val}\b", src), name
