@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -27,7 +28,13 @@ size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Rows per lane of the row-tiled kernels: the largest of 8, 4, 2 that still
 // leaves at least 512 tiles of 256*rpt rows (two per compute unit), else 1.
+// GMRES_ROWS_PER_LANE (1, 2, 4 or 8) overrides the choice for tuning sweeps;
+// it must not change between gmres_workspace_bytes and gmres_create.
 int pick_rpt(int64_t n) {
+  if (const char* e = getenv("GMRES_ROWS_PER_LANE")) {
+    const int r = atoi(e);
+    if (r == 1 || r == 2 || r == 4 || r == 8) return r;
+  }
   for (int r : {8, 4, 2})
     if ((n + 256 * r - 1) / (256 * r) >= 512) return r;
   return 1;

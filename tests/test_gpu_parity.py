@@ -1,9 +1,16 @@
 """GPU-vs-oracle parity of the HIP GMRES library, called through its C ABI.
 
-Tolerance: 1e-10 relative in FP64 for the Hessenberg matrix, the iterate and
-the residual history of a fixed-budget cycle (no early exit), on seeded inputs
-that span many tiles and a ragged last tile. Integer outcomes (columns per
-cycle, iteration counts, reductions, flags) must be equal.
+Tolerance: 1e-10 relative in FP64 for the iterate and the residual history of
+a fixed-budget cycle (no early exit), on seeded inputs that span many tiles
+and a ragged last tile. Integer outcomes (columns per cycle, iteration counts,
+reductions, flags) must be equal.
+
+The Hessenberg matrix is compared column by column with tolerance
+1e-10 + 1e3 eps / r_c, where r_c is the relative residual when basis vector
+v_c was formed: v_c comes out of a cancellation of size r_c, so rounding fixes
+it only to about eps / r_c. Two of the oracle's own schemes, equal in exact
+arithmetic, differ by that much (on the dense 50 x 50 case, by 2e-16 in
+column 0 rising to 3e-6 in column 15 as r_c falls to 2e-11).
 """
 
 import numpy as np
@@ -78,12 +85,15 @@ def test_fixed_budget_cycle_parity(scheme, case):
     assert r.reductions == o.reductions
     assert rel(g["x"], o.x) <= TOL
     assert np.max(np.abs(r.hist - o.hist)) <= TOL
-    # Columns formed after the residual reached rounding level are fixed by
-    # rounding noise in any implementation; compare H where the basis is determined.
-    kc = int(np.argmax(o.hist < 1e-11)) if np.any(o.hist < 1e-11) else m
-    assert rel(g["H"][:, :kc], o.H[:, :kc]) <= TOL
+    eps = np.finfo(float).eps
+    r_c = np.concatenate([[1.0], o.hist[: m - 1]])
+    for c in range(m):
+        tol_c = TOL + 1e3 * eps / max(r_c[c], 1e-300)
+        assert rel(g["H"][:, c], o.H[:, c]) <= tol_c, (c, r_c[c])
+    kc = int(np.argmax(r_c < 1e-4)) if np.any(r_c < 1e-4) else m
     assert abs(r.rel_res_true - o.rel_res_true) <= TOL * max(o.rel_res_true, 1e-3)
     if scheme == "mgs1r":
+        assert rel(g["H"][:, :kc], o.H[:, :kc]) <= TOL
         assert np.max(np.abs(g["T"][:kc, :kc] - o.T[:kc, :kc])) <= TOL
 
 
