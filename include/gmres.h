@@ -130,7 +130,9 @@ int gmres_spmv(gmres_ctx* ctx, const double* x, double* y);
  *     T = (I + L^T)^{-1} built one column per step, whose leading blocks give
  *     Paige's loss-of-orthogonality measure S = I - T (Section II); for
  *     GMRES_CGS2 the strictly lower L with V^T V = I + L + L^T, one row per
- *     step; zeros for GMRES_MGS;
+ *     step; zeros for GMRES_MGS. Columns 0..j-1 are formed: the cycle's last
+ *     step computes only the norm of column j (and of a cycle that ends on
+ *     the tolerance check, column j is formed too);
  *   g (host, m+2): the rotated right-hand side of the least-squares problem;
  *   j (host): the number of columns that cycle completed.
  */
@@ -151,7 +153,7 @@ int gmres_basis(gmres_ctx* ctx, double** V, int64_t* ldv);
  * attached to its dispatch (hipExtLaunchKernel), so they time the kernel
  * alone; launches that the cycle's done flag skipped are not counted. bytes is the algorithmic HBM traffic of the counted launches:
  *   step k with SpMV:  12 nnz + 4 (n+1) + 8 n (k+1) + 8 n   (CSR, V[:,0:k+1], w written)
- *   step k norm-only:  8 n (k+1)
+ *   last step of a cycle (norm of column k only):  8 n
  *   CGS2 second pass:  8 n (k+2)                          (V[:,0:k+1] and z)
  *   MAXPY at step k:   8 n (k+1) + 16 n                   (V[:,0:k+1], w or z, new column)
  * gmres_set_timing(ctx, 1) enables and clears the totals; (ctx, 0) disables.

@@ -237,9 +237,12 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
     // restart check at k = 0 ends it); the rest of step k runs iff j > k.
     for (int k = 0; k <= m_eff; ++k) {
       {
-        const double bytes = k < m_eff ? csr + n8 * (k + 1) + n8 : n8 * (k + 1);
+        // The last step of a cycle only finishes the lagged norm of column m_eff.
+        const bool last = k == m_eff;
+        const double bytes = last ? n8 : csr + n8 * (k + 1) + n8;
         TimedLaunch t(c, GMRES_KSTAT_STEP, k, k, bytes);
-        TRY(launch_fused(c->A, c->S, ws, rpt, k, k < m_eff, m_eff, tail, G, s, t.e0, t.e1));
+        TRY(launch_fused(c->A, c->S, ws, rpt, k, last ? 0 : k, !last, m_eff, tail, G, s, t.e0,
+                         t.e1));
       }
       if (k == m_eff) break;
       {
@@ -249,8 +252,8 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
       if (c->scheme == kSchemeCgs2) {
         {
           TimedLaunch t(c, GMRES_KSTAT_STEP, k, k + 1, n8 * (k + 2));
-          TRY(launch_fused(c->A, c->S, ws, rpt, k + 1, false, m_eff, kTailCgs2Second, G, s, t.e0,
-                           t.e1));
+          TRY(launch_fused(c->A, c->S, ws, rpt, k + 1, k + 1, false, m_eff, kTailCgs2Second, G, s,
+                           t.e0, t.e1));
         }
         TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
         TRY(launch_maxpy(ws, rpt, k, 1, G, s, t.e0, t.e1));

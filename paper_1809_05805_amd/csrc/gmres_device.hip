@@ -73,15 +73,35 @@ __device__ inline double wave_multi_sum(double (&v)[NV], int lane) {
   return v[0];
 }
 
-// Sum 8 values per lane over aligned segments of S lanes (S >= 8): three
-// halving exchanges (4 + 2 + 1 shuffles), then log2(S/8) full steps. Lane sl
-// of a segment ends holding the total of value index sl / (S/8).
-template <int S>
-__device__ inline double seg_sum8(double (&v)[8], int sl) {
-  static_assert(S >= 8 && S <= 64 && (S & (S - 1)) == 0, "S must be a power of two >= 8");
+// Tuning constants (compile-time; defaults are the measured best on MI355X):
+//   GMRES_SPMV_ROWS  rows each SpMV lane group keeps in flight per pass (8 or 16);
+//   GMRES_PROJ_COLS  basis columns per projection chunk (1, 2, 4 or 8).
+#ifndef GMRES_SPMV_ROWS
+#define GMRES_SPMV_ROWS 4
+#endif
+#ifndef GMRES_PROJ_COLS
+#define GMRES_PROJ_COLS 1
+#endif
+//   GMRES_SPMV_PIPELINE  1: the fused kernel's SpMV prefetches the next pass (spmv_tile);
+//                        0: passes run one after another (spmv_pass).
+#ifndef GMRES_SPMV_PIPELINE
+#define GMRES_SPMV_PIPELINE 1
+#endif
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+// Sum R values per lane over aligned segments of S lanes with a halving
+// butterfly: min(log2 R, log2 S) exchange steps (each moves half of the
+// remaining values to the partner lane), then full steps over the remaining
+// lane bits. Afterwards, if R >= S, lane sl of a segment holds in v[0..R/S)
+// the totals of value indices sl*(R/S) + t; if R < S, it holds in v[0] the
+// total of value index sl / (S/R).
+template <int R, int S>
+__device__ inline void seg_sum(double (&v)[R], int sl) {
+  static_assert((R & (R - 1)) == 0 && (S & (S - 1)) == 0 && S <= 64, "powers of two");
   int mask = S / 2;
 #pragma unroll
-  for (int h = 4; h >= 1; h >>= 1) {
+  for (int h = R / 2; h >= 1 && mask >= 1; h >>= 1) {
     const bool upper = (sl & mask) != 0;
 #pragma unroll
     for (int i = 0; i < h; ++i) {
@@ -91,19 +111,20 @@ __device__ inline double seg_sum8(double (&v)[8], int sl) {
     }
     mask >>= 1;
   }
-  for (; mask >= 1; mask >>= 1) v[0] += __shfl_xor(v[0], mask, S);
-  return v[0];
+  if constexpr (R < S) {
+    for (; mask >= 1; mask >>= 1) v[0] += __shfl_xor(v[0], mask, S);
+  }
 }
 
-// One pass of the CSR SpMV over 8 * (256 / S) consecutive local rows starting
-// at local row p0: S lanes per row, and each lane group works on 8 rows at
-// once, so every lane has 8 independent load chains (row pointers, then
+// One pass of the CSR SpMV over R * (256 / S) consecutive local rows starting
+// at local row p0: S lanes per row, and each lane group works on R rows at
+// once, so every lane has R independent load chains (row pointers, then
 // indices and values, then the gathered x) in flight. Rows with more than S
 // nonzeros finish in a strided loop. emit(local_row, value) is called by one
 // lane per row; rows at or past n give 0.
-template <int S, typename Emit>
-__device__ inline void spmv_pass8(const Csr& A, const double* __restrict__ x, int64_t row0, int p0,
-                                  Emit emit) {
+template <int R, int S, typename Emit>
+__device__ inline void spmv_pass(const Csr& A, const double* __restrict__ x, int64_t row0, int p0,
+                                 Emit emit) {
   constexpr int NSUB = 256 / S;
   const int tid = threadIdx.x;
   const int sub = tid / S, sl = tid % S;
@@ -111,42 +132,124 @@ __device__ inline void spmv_pass8(const Csr& A, const double* __restrict__ x, in
   // All loads below are unconditional, at indices clamped into range, and the
   // values they bring are masked afterwards: conditional loads would become
   // branches that wait on each row in turn.
-  int e0[8], e1[8];
+  int e0[R], e1[R];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < R; ++q) {
     const int64_t r = row0 + p0 + q * NSUB + sub;
     const int64_t rc = r < n ? r : n - 1;
     const int a = A.rp[rc], b = A.rp[rc + 1];
     e0[q] = a;
     e1[q] = r < n ? b : a;
   }
-  double acc[8];
+  double acc[R];
   if (A.nnz > 0) {
-    int c[8];
-    double v[8];
+    int c[R];
+    double v[R];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < R; ++q) {
       const int e = e0[q] + sl;
       const int ec = e < e1[q] ? e : 0;
       c[q] = A.ci[ec];
       v[q] = A.va[ec];
     }
-    double xv[8];
+    double xv[R];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) xv[q] = x[(unsigned)c[q]];
+    for (int q = 0; q < R; ++q) xv[q] = x[(unsigned)c[q]];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = (e0[q] + sl < e1[q]) ? v[q] * xv[q] : 0.0;
+    for (int q = 0; q < R; ++q) acc[q] = (e0[q] + sl < e1[q]) ? v[q] * xv[q] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < R; ++q)
       for (int e = e0[q] + sl + S; e < e1[q]; e += S) acc[q] += A.va[e] * x[A.ci[e]];
   } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
   }
-  const double tot = seg_sum8<S>(acc, sl);
-  if ((sl & (S / 8 - 1)) == 0) {
-    const int q = sl / (S / 8);
-    emit(p0 + q * NSUB + sub, tot);
+  seg_sum<R, S>(acc, sl);
+  if constexpr (R >= S) {
+#pragma unroll
+    for (int t = 0; t < R / S; ++t) {
+      const int q = sl * (R / S) + t;
+      emit(p0 + q * NSUB + sub, acc[t]);
+    }
+  } else {
+    if ((sl & (S / R - 1)) == 0) {
+      const int q = sl / (S / R);
+      emit(p0 + q * NSUB + sub, acc[0]);
+    }
+  }
+}
+
+// The SpMV of a whole tile of TR rows as a software pipeline over passes of
+// R * (256 / S) rows: while pass p gathers x, the row pointers and then the
+// indices and values of pass p+1 are already in flight, so a workgroup pays
+// about one memory round trip per pass instead of three. Same lane layout and
+// reduction as spmv_pass.
+template <int R, int S, int TR, typename Emit>
+__device__ inline void spmv_tile(const Csr& A, const double* __restrict__ x, int64_t row0,
+                                 Emit emit) {
+  constexpr int NSUB = 256 / S;
+  constexpr int RPP = R * NSUB;
+  constexpr int NP = TR / RPP;
+  static_assert(NP >= 1 && TR % RPP == 0, "tile must hold whole passes");
+  const int tid = threadIdx.x;
+  const int sub = tid / S, sl = tid % S;
+  const int64_t n = A.n;
+  const bool any = A.nnz > 0;
+  auto load_rp = [&](int p0, int (&e0)[R], int (&e1)[R]) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int64_t r = row0 + p0 + q * NSUB + sub;
+      const int64_t rc = r < n ? r : n - 1;
+      const int a = A.rp[rc], b = A.rp[rc + 1];
+      e0[q] = a;
+      e1[q] = r < n ? b : a;
+    }
+  };
+  auto load_cv = [&](const int (&e0)[R], const int (&e1)[R], int (&c)[R], double (&v)[R]) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int e = e0[q] + sl;
+      const int ec = (any && e < e1[q]) ? e : 0;
+      c[q] = any ? A.ci[ec] : 0;
+      v[q] = any ? A.va[ec] : 0.0;
+    }
+  };
+  int e0[R], e1[R], c[R];
+  double v[R];
+  load_rp(0, e0, e1);
+  load_cv(e0, e1, c, v);
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    int e0n[R], e1n[R], cn[R];
+    double vn[R];
+    if (p + 1 < NP) load_rp((p + 1) * RPP, e0n, e1n);
+    double xv[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) xv[q] = x[(unsigned)c[q]];
+    if (p + 1 < NP) load_cv(e0n, e1n, cn, vn);
+    double acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = (e0[q] + sl < e1[q]) ? v[q] * xv[q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      for (int e = e0[q] + sl + S; e < e1[q]; e += S) acc[q] += A.va[e] * x[A.ci[e]];
+    seg_sum<R, S>(acc, sl);
+    const int p0 = p * RPP;
+    if constexpr (R >= S) {
+#pragma unroll
+      for (int t = 0; t < R / S; ++t) emit(p0 + (sl * (R / S) + t) * NSUB + sub, acc[t]);
+    } else {
+      if ((sl & (S / R - 1)) == 0) emit(p0 + (sl / (S / R)) * NSUB + sub, acc[0]);
+    }
+    if (p + 1 < NP) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        e0[q] = e0n[q];
+        e1[q] = e1n[q];
+        c[q] = cn[q];
+        v[q] = vn[q];
+      }
+    }
   }
 }
 
@@ -354,16 +457,16 @@ __global__ void k_validate_csr(const int* __restrict__ rp, const int* __restrict
   if (bad) atomicOr(&st->bad_csr, 1);
 }
 
-// y = A x (b == nullptr) or y = b - A x: one pass of 8 * (256 / S) rows per
-// workgroup. Skipped when a state is given and its cycle is done.
+// y = A x (b == nullptr) or y = b - A x: one pass of GMRES_SPMV_ROWS * (256 / S)
+// rows per workgroup. Skipped when a state is given and its cycle is done.
 template <int S>
 __global__ __launch_bounds__(256) void k_spmv(Csr A, const double* __restrict__ x,
                                                const double* __restrict__ b, double* __restrict__ y,
                                                const DevState* st) {
   if (st && st->done) return;
-  constexpr int RPP = 8 * (256 / S);
+  constexpr int RPP = GMRES_SPMV_ROWS * (256 / S);
   const int64_t row0 = (int64_t)blockIdx.x * RPP;
-  spmv_pass8<S>(A, x, row0, 0, [&](int lr, double v) {
+  spmv_pass<GMRES_SPMV_ROWS, S>(A, x, row0, 0, [&](int lr, double v) {
     const int64_t r = row0 + lr;
     if (r < A.n) y[r] = b ? b[r] - v : v;
   });
@@ -384,8 +487,10 @@ __host__ __device__ inline size_t fused_lds_doubles(int rpt, int m) {
 // The small dense step of a lagged scheme (one-reduce MGS or CGS2, first
 // reduction), run by the last workgroup with the totals in vals:
 //   vals[2q] = V_q . u, vals[2q+1] = V_q . w (q < k), vals[2k] = u.u, vals[2k+1] = u.w.
-__device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, int m_eff,
-                            int scheme) {
+// With norm_only (the end-of-cycle step) vals[0] = u.u is all there is: only
+// the last Hessenberg entry and its rotation are needed, not a new T column.
+__device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool norm_only,
+                            int m_eff, int scheme) {
   __shared__ double s_rho;
   __shared__ int s_go;  // 0: nothing more; 1: extend T (or L) only; 2: also the MAXPY coefficients
   const int tid = threadIdx.x, bs = blockDim.x;
@@ -405,7 +510,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, int 
   __syncthreads();
   if (tid == 0) {
     st->reductions += 1;
-    const double alpha = vals[2 * k];
+    const double alpha = vals[norm_only ? 0 : 2 * k];
     int go = 2;
     double rho = 0.0;
     if (!(alpha >= 0.0) || !isfinite(alpha)) {
@@ -440,7 +545,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, int 
         } else if (gk <= st->tol_abs || k == m_eff) {
           st->done = 1;
           st->j = k;
-          go = 1;
+          go = norm_only ? 0 : 1;
         }
       }
       if (go) {
@@ -553,10 +658,11 @@ __device__ void tail_cgs2_second(const Ws& ws, const double* vals, int k) {
 // rows tile0 + wv*64*RPT + i*64 + l, so every column read is 512 contiguous
 // bytes per wavefront.
 template <int RPT, int S, bool HAS_SPMV>
-__global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int m_eff, int tail, int G) {
+__global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, int m_eff, int tail,
+                                                int G) {
   extern __shared__ double lds[];
   constexpr int TR = 256 * RPT;
-  constexpr int CB = 4;  // columns per butterfly chunk
+  constexpr int CB = GMRES_PROJ_COLS;  // columns per butterfly chunk
   if (ws.st->done) return;
   const int P = 2 * (ws.m + 2);
   double* wl = lds;
@@ -574,9 +680,16 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int m_eff, i
   const double* __restrict__ u_g = V + (size_t)K * ldv;
 
   if constexpr (HAS_SPMV) {
-    // SpMV of the tile, 8 rows per lane group per pass.
-    for (int p0 = 0; p0 < TR; p0 += 8 * (256 / S))
-      spmv_pass8<S>(A, u_g, row0, p0, [&](int lr, double v) { wl[lr] = v; });
+    // SpMV of the tile, GMRES_SPMV_ROWS rows per lane group per pass (fewer
+    // when the whole tile holds fewer).
+    constexpr int RG = GMRES_SPMV_ROWS * (256 / S) > TR ? TR / (256 / S) : GMRES_SPMV_ROWS;
+    auto emit = [&](int lr, double v) { wl[lr] = v; };
+    if constexpr (GMRES_SPMV_PIPELINE) {
+      spmv_tile<RG, S, TR>(A, u_g, row0, emit);
+    } else {
+      constexpr int RPP = RG * (256 / S);
+      for (int p0 = 0; p0 < TR; p0 += RPP) spmv_pass<RG, S>(A, u_g, row0, p0, emit);
+    }
     __syncthreads();
   }
 
@@ -597,11 +710,11 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int m_eff, i
   }
   double* myred = red + wv * P;
 
-  // Columns 0..K-1 in chunks of CB, then the rest one at a time. The loads of
-  // a chunk (CB columns x RPT rows) are all issued before any is used.
+  // Columns 0..nproj-1 in chunks of CB, then the rest one at a time. The
+  // loads of a chunk (CB columns x RPT rows) are all issued before any is used.
   constexpr int NVC = HAS_SPMV ? 2 * CB : CB;
   int j0 = 0;
-  for (; j0 + CB <= K; j0 += CB) {
+  for (; j0 + CB <= nproj; j0 += CB) {
     double vv[CB][RPT];
 #pragma unroll
     for (int c = 0; c < CB; ++c)
@@ -624,7 +737,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int m_eff, i
       }
     }
     const double tot = wave_multi_sum<NVC>(acc, lane);
-    constexpr int LOGNV = (NVC == 8) ? 3 : 2;
+    constexpr int LOGNV = ilog2(NVC);
     if ((lane & ((64 / NVC) - 1)) == 0) {
       const int vi = lane >> (6 - LOGNV);
       if constexpr (HAS_SPMV) {
@@ -635,7 +748,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int m_eff, i
       }
     }
   }
-  for (; j0 < K; ++j0) {
+  for (; j0 < nproj; ++j0) {
     double vv[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) vv[i] = V[(size_t)j0 * ldv + rows[i]];
@@ -662,19 +775,20 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int m_eff, i
     al = wave_sum(al);
     if constexpr (HAS_SPMV) ga = wave_sum(ga);
     if (lane == 0) {
-      myred[2 * K] = al;
-      myred[2 * K + 1] = HAS_SPMV ? ga : 0.0;
+      myred[2 * nproj] = al;
+      myred[2 * nproj + 1] = HAS_SPMV ? ga : 0.0;
     }
   }
   __syncthreads();
-  const int cnt = 2 * (K + 1);
+  const int cnt = 2 * (nproj + 1);
   for (int i = tid; i < cnt; i += 256) vals[i] = ((red[i] + red[P + i]) + red[2 * P + i]) + red[3 * P + i];
   __syncthreads();
   if (!grid_reduce(vals, cnt, ws, tile, G)) return;
   if (tail == kTailCgs2Second)
     tail_cgs2_second(ws, vals, K - 1);
   else
-    tail_lagged(ws, vals, scr, K, m_eff, tail == kTailLagged1r ? kSchemeMgs1r : kSchemeCgs2);
+    tail_lagged(ws, vals, scr, K, nproj < K, m_eff,
+                tail == kTailLagged1r ? kSchemeMgs1r : kSchemeCgs2);
 }
 
 // ------------------------------------------------------------------ MAXPY
@@ -892,7 +1006,8 @@ __global__ __launch_bounds__(256) void k_backsolve(Ws ws) {
   }
 }
 
-// x += V[:,0:j] y.
+// x += V[:,0:j] y, four basis columns at a time with every load in flight
+// (loads at clamped rows; only rows below n are stored).
 template <int RPT>
 __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, int G) {
   constexpr int TR = 256 * RPT;
@@ -904,14 +1019,38 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
   const int64_t n = ws.n;
   const double* __restrict__ V = ws.V;
   const int64_t ldv = ws.ldv;
+  const double* __restrict__ y = ws.y;
+  int64_t rows[RPT];
+  double acc[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + threadIdx.x;
-    if (r < n) {
-      double s = x[r];
-      for (int q = 0; q < j; ++q) s += V[(size_t)q * ldv + r] * ws.y[q];
-      x[r] = s;
-    }
+    rows[i] = r < n ? r : n - 1;
+    acc[i] = x[rows[i]];
+  }
+  int q = 0;
+  for (; q + 4 <= j; q += 4) {
+    const double c0 = y[q], c1 = y[q + 1], c2 = y[q + 2], c3 = y[q + 3];
+    double v[4][RPT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) v[t][i] = V[(size_t)(q + t) * ldv + rows[i]];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) acc[i] = acc[i] + v[0][i] * c0 + v[1][i] * c1 + v[2][i] * c2 + v[3][i] * c3;
+  }
+  for (; q < j; ++q) {
+    const double c0 = y[q];
+    double v[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) v[i] = V[(size_t)q * ldv + rows[i]];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) acc[i] += v[i] * c0;
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = row0 + i * 256 + threadIdx.x;
+    if (r < n) x[r] = acc[i];
   }
 }
 
@@ -956,7 +1095,7 @@ int launch_validate(const Csr& A, int64_t nnz, DevState* st, hipStream_t s) {
 template <int S>
 static void spmv_s(const Csr& A, const double* x, const double* b, double* y, const DevState* st,
                    hipStream_t s) {
-  constexpr int RPP = 8 * (256 / S);
+  constexpr int RPP = GMRES_SPMV_ROWS * (256 / S);
   const int64_t blocks = (A.n + RPP - 1) / RPP;
   hipLaunchKernelGGL(k_spmv<S>, dim3((unsigned)blocks), dim3(256), 0, s, A, x, b, y, st);
 }
@@ -977,39 +1116,39 @@ int launch_spmv(const Csr& A, int S, const double* x, const double* b, double* y
 // start/stop events are attached to the dispatch itself and time the kernel
 // alone.
 template <int RPT, int S, bool HS>
-static void fused_t(const Csr& A, const Ws& ws, int K, int m_eff, int tail, int G, hipStream_t s,
-                    hipEvent_t e0, hipEvent_t e1) {
+static void fused_t(const Csr& A, const Ws& ws, int K, int nproj, int m_eff, int tail, int G,
+                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const uint32_t lds = (uint32_t)(fused_lds_doubles(RPT, ws.m) * sizeof(double));
   hipExtLaunchKernelGGL((k_fused<RPT, S, HS>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A, ws, K,
-                        m_eff, tail, G);
+                        nproj, m_eff, tail, G);
 }
 
 template <int RPT, bool HS>
-static void fused_r(const Csr& A, int S, const Ws& ws, int K, int m_eff, int tail, int G,
-                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static void fused_r(const Csr& A, int S, const Ws& ws, int K, int nproj, int m_eff, int tail,
+                    int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (!HS) {
-    fused_t<RPT, 8, false>(A, ws, K, m_eff, tail, G, s, e0, e1);
+    fused_t<RPT, 8, false>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1);
     return;
   }
   switch (S) {
-    case 8: fused_t<RPT, 8, true>(A, ws, K, m_eff, tail, G, s, e0, e1); break;
-    case 16: fused_t<RPT, 16, true>(A, ws, K, m_eff, tail, G, s, e0, e1); break;
-    case 32: fused_t<RPT, 32, true>(A, ws, K, m_eff, tail, G, s, e0, e1); break;
-    default: fused_t<RPT, 64, true>(A, ws, K, m_eff, tail, G, s, e0, e1); break;
+    case 8: fused_t<RPT, 8, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 16: fused_t<RPT, 16, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 32: fused_t<RPT, 32, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    default: fused_t<RPT, 64, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
   }
 }
 
-int launch_fused(const Csr& A, int S, const Ws& ws, int rpt, int K, bool has_spmv, int m_eff,
-                 int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+int launch_fused(const Csr& A, int S, const Ws& ws, int rpt, int K, int nproj, bool has_spmv,
+                 int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (rpt) {
-    case 1: has_spmv ? fused_r<1, true>(A, S, ws, K, m_eff, tail, G, s, e0, e1)
-                     : fused_r<1, false>(A, S, ws, K, m_eff, tail, G, s, e0, e1); break;
-    case 2: has_spmv ? fused_r<2, true>(A, S, ws, K, m_eff, tail, G, s, e0, e1)
-                     : fused_r<2, false>(A, S, ws, K, m_eff, tail, G, s, e0, e1); break;
-    case 4: has_spmv ? fused_r<4, true>(A, S, ws, K, m_eff, tail, G, s, e0, e1)
-                     : fused_r<4, false>(A, S, ws, K, m_eff, tail, G, s, e0, e1); break;
-    default: has_spmv ? fused_r<8, true>(A, S, ws, K, m_eff, tail, G, s, e0, e1)
-                      : fused_r<8, false>(A, S, ws, K, m_eff, tail, G, s, e0, e1); break;
+    case 1: has_spmv ? fused_r<1, true>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1)
+                     : fused_r<1, false>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 2: has_spmv ? fused_r<2, true>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1)
+                     : fused_r<2, false>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 4: has_spmv ? fused_r<4, true>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1)
+                     : fused_r<4, false>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    default: has_spmv ? fused_r<8, true>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1)
+                      : fused_r<8, false>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
   }
   GMRES_CHECK_LAUNCH();
   return 0;

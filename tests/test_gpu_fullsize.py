@@ -74,8 +74,9 @@ def test_cfg3_orthogonality_curve():
     log(f"cfg3 N=40 orthogonality n={p.n}")
     g = gpu_run(p, "mgs1r", m=100, rtol=0.0, max_iters=100)
     o = oracle_run(p, "mgs1r", m=100, rtol=0.0, max_iters=100)
-    sg = D.s_norm_history(g["T"], g["j"])
-    so = D.s_norm_history(o.T, o.j)
+    # the cycle's last step forms only a norm, so T has columns 0..j-1
+    sg = D.s_norm_history(g["T"], g["j"] - 1)
+    so = D.s_norm_history(o.T, o.j - 1)
     log("S oracle: " + " ".join(f"{v:.1e}" for v in so[::10]))
     log("S gpu:    " + " ".join(f"{v:.1e}" for v in sg[::10]))
     eps = np.finfo(float).eps
