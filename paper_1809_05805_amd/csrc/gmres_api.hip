@@ -60,7 +60,7 @@ int pick_lanes(int64_t n, int64_t nnz) {
 struct Layout {
   int64_t ldv;
   int rpt, G, NG, pstride;
-  size_t V, w, H, R, T, g, gh, cs, sn, coef, coef2, y, partials, gpartials, counters, state, total;
+  size_t V, w, H, R, T, TT, g, gh, cs, sn, coef, coef2, y, partials, gpartials, counters, state, total;
 };
 
 bool make_layout(int64_t n, int m, Layout* L) {
@@ -82,6 +82,7 @@ bool make_layout(int64_t n, int m, Layout* L) {
   L->H = take((size_t)(m + 1) * (size_t)m * d);
   L->R = take((size_t)(m + 1) * (size_t)m * d);
   L->T = take((size_t)(m + 2) * (size_t)(m + 2) * d);
+  L->TT = take((size_t)(m + 2) * (size_t)(m + 2) * d);
   L->g = take((size_t)(m + 2) * d);
   L->gh = take((size_t)(m + 2) * d);
   L->cs = take((size_t)(m + 2) * d);
@@ -328,6 +329,7 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   ws.H = (double*)(base + L.H);
   ws.R = (double*)(base + L.R);
   ws.T = (double*)(base + L.T);
+  ws.TT = (double*)(base + L.TT);
   ws.g = (double*)(base + L.g);
   ws.gh = (double*)(base + L.gh);
   ws.cs = (double*)(base + L.cs);

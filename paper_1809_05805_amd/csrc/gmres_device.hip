@@ -268,7 +268,52 @@ __device__ inline void spmv_tile(const Csr& A, const double* __restrict__ x, int
 // write-back on every workgroup) is needed.
 __device__ inline void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-__device__ bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int nslots) {
+// Sum rows [beg, beg + nrows) of a partials array (row stride ws.pstride),
+// columns [0, cnt), into vals. The workgroup splits the rows into `parts`
+// interleaved subsets so that each thread has at most 8 independent loads in
+// flight, then adds the subsets' sums in a fixed order (so the result does not
+// depend on timing). scratch needs parts * cnt doubles.
+__device__ void sum_rows(const double* rows_base, int pstride, int nrows, int cnt, double* vals,
+                         double* scratch) {
+  const int tid = threadIdx.x, bs = blockDim.x;
+  int parts = bs / cnt;
+  if (parts > (nrows + 7) / 8) parts = (nrows + 7) / 8;
+  if (parts < 1) parts = 1;
+  if (cnt * parts <= bs) {
+    if (tid < cnt * parts) {
+      const int i = tid % cnt, part = tid / cnt;
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = part + t * parts;
+        const int qc = q < nrows ? q : nrows - 1;
+        v[t] = atomic_ld(rows_base + (size_t)qc * pstride + i);
+      }
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc += (part + t * parts < nrows) ? v[t] : 0.0;
+      for (int q = part + 8 * parts; q < nrows; q += parts)
+        acc += atomic_ld(rows_base + (size_t)q * pstride + i);
+      scratch[part * cnt + i] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < cnt; i += bs) {
+      double acc = 0.0;
+      for (int part = 0; part < parts; ++part) acc += scratch[part * cnt + i];
+      vals[i] = acc;
+    }
+  } else {
+    for (int i = tid; i < cnt; i += bs) {
+      double acc = 0.0;
+      for (int q = 0; q < nrows; ++q) acc += atomic_ld(rows_base + (size_t)q * pstride + i);
+      vals[i] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int nslots,
+                            double* scratch) {
   __shared__ int s_last;
   const int tid = threadIdx.x;
   const int bs = blockDim.x;
@@ -285,19 +330,10 @@ __device__ bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int n
   }
   __syncthreads();
   if (!s_last) return false;
-  for (int i = tid; i < cnt; i += bs) {
-    double s = 0.0;
-    for (int q = 0; q < gcnt; ++q) s += atomic_ld(ws.partials + (size_t)(gbeg + q) * ws.pstride + i);
-    if (ng == 1)
-      vals[i] = s;
-    else
-      atomic_st(ws.gpartials + (size_t)grp * ws.pstride + i, s);
-  }
+  sum_rows(ws.partials + (size_t)gbeg * ws.pstride, ws.pstride, gcnt, cnt, vals, scratch);
   if (tid == 0) atomicExch(ws.counters + grp, 0u);
-  if (ng == 1) {
-    __syncthreads();
-    return true;
-  }
+  if (ng == 1) return true;
+  for (int i = tid; i < cnt; i += bs) atomic_st(ws.gpartials + (size_t)grp * ws.pstride + i, vals[i]);
   wait_stores();
   __syncthreads();
   if (tid == 0) {
@@ -306,14 +342,47 @@ __device__ bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int n
   }
   __syncthreads();
   if (!s_last) return false;
-  for (int i = tid; i < cnt; i += bs) {
-    double s = 0.0;
-    for (int q = 0; q < ng; ++q) s += atomic_ld(ws.gpartials + (size_t)q * ws.pstride + i);
-    vals[i] = s;
-  }
+  sum_rows(ws.gpartials, ws.pstride, ng, cnt, vals, scratch);
   if (tid == 0) atomicExch(ws.counters + ng, 0u);
-  __syncthreads();
   return true;
+}
+
+// out[i] = sum over q in [lo(i), hi(i)) of M[i * ld + q] * vec[q], for i in
+// [0, nrows): dot products of contiguous row segments with a vector in LDS.
+// Each wavefront takes 8 rows at a time with its lanes striding over q, so
+// every lane has 8 independent loads in flight, and one halving butterfly
+// reduces the 8 sums. Loads use clamped indices (M must hold nrows rows of ld
+// entries); the values are masked.
+template <typename Lo, typename Hi>
+__device__ void rows_dot(const double* M, int ld, const double* vec, int nrows, int qmax, Lo lo,
+                         Hi hi, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i0 = wv * 8; i0 < nrows; i0 += nw * 8) {
+    double acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+    for (int q0 = 0; q0 < qmax; q0 += 64) {
+      const int q = q0 + lane;
+      const int qc = q < ld ? q : ld - 1;
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int i = i0 + t < nrows ? i0 + t : nrows - 1;
+        v[t] = M[(size_t)i * ld + qc];
+      }
+      const double x = vec[q < qmax ? q : 0];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int i = i0 + t;
+        acc[t] += (i < nrows && q >= lo(i) && q < hi(i)) ? v[t] * x : 0.0;
+      }
+    }
+    wave_multi_sum<8>(acc, lane);
+    if ((lane & 7) == 0) {
+      const int i = i0 + (lane >> 3);
+      if (i < nrows) out[i] = acc[0];
+    }
+  }
 }
 
 // Plane rotation [c s; -s c] taking (a, b) to (r, 0).
@@ -403,11 +472,11 @@ __global__ void k_init(Ws ws, int ncounters) {
 }
 
 // Start of a cycle: clear the flags and the small dense matrices (H, R, T,
-// g, gh), whose untouched entries must read as zero.
+// TT, g, gh), whose untouched entries must read as zero.
 __global__ void k_cycle_begin(Ws ws) {
   const int m = ws.m;
   const size_t nh = (size_t)(m + 1) * m, nt = (size_t)(m + 2) * (m + 2);
-  const size_t tot = 2 * nh + nt + 2 * (size_t)(m + 2);
+  const size_t tot = 2 * nh + 2 * nt + 2 * (size_t)(m + 2);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
        i += (size_t)gridDim.x * blockDim.x) {
     if (i < nh)
@@ -416,10 +485,12 @@ __global__ void k_cycle_begin(Ws ws) {
       ws.R[i - nh] = 0.0;
     else if (i < 2 * nh + nt)
       ws.T[i - 2 * nh] = 0.0;
-    else if (i < 2 * nh + nt + (m + 2))
-      ws.g[i - 2 * nh - nt] = 0.0;
+    else if (i < 2 * nh + 2 * nt)
+      ws.TT[i - 2 * nh - nt] = 0.0;
+    else if (i < 2 * nh + 2 * nt + (m + 2))
+      ws.g[i - 2 * nh - 2 * nt] = 0.0;
     else
-      ws.gh[i - 2 * nh - nt - (m + 2)] = 0.0;
+      ws.gh[i - 2 * nh - 2 * nt - (m + 2)] = 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     DevState* st = ws.st;
@@ -476,12 +547,17 @@ __global__ __launch_bounds__(256) void k_spmv(Csr A, const double* __restrict__ 
 
 // Dynamic LDS layout of k_fused (doubles):
 //   wl[TR]          w = A u for this tile (SpMV phase)
-//   red[4][P]       per-wavefront column sums, P = 2 (m + 2)
+//   red[4][P]       per-wavefront column sums, P = 2 (m + 2) (at least 256
+//                   doubles: it is also the reduction's scratch)
 //   vals[P]         this tile's sums, then the device-wide totals
 //   scr[6 (m + 2)]  scratch for the small dense step
+__host__ __device__ inline int fused_red_doubles(int m) {
+  const int r = 4 * 2 * (m + 2);
+  return r < 256 ? 256 : r;
+}
 __host__ __device__ inline size_t fused_lds_doubles(int rpt, int m) {
   const int P = 2 * (m + 2);
-  return (size_t)256 * rpt + 4 * (size_t)P + P + 6 * (size_t)(m + 2);
+  return (size_t)256 * rpt + (size_t)fused_red_doubles(m) + P + 6 * (size_t)(m + 2);
 }
 
 // The small dense step of a lagged scheme (one-reduce MGS or CGS2, first
@@ -568,54 +644,65 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
   __syncthreads();
   if (scheme == kSchemeMgs1r) {
     // Malard-Paige: T[0:k,k] = -T[0:k,0:k] l, T[k,k] = 1, so T = (I + L^T)^{-1}.
+    // Row i of T (entries i..k-1) is contiguous in the row-major copy TT.
+    rows_dot(ws.TT, ldt, ell, k, k, [](int i) { return i; }, [&](int) { return k; }, tcol);
+    __syncthreads();
     for (int i = tid; i < k; i += bs) {
-      double s = 0.0;
-#pragma unroll 8
-      for (int q = i; q < k; ++q) s += ws.T[(size_t)q * ldt + i] * ell[q];
-      tcol[i] = -s;
-      ws.T[(size_t)k * ldt + i] = -s;
+      const double t = -tcol[i];
+      tcol[i] = t;
+      ws.T[(size_t)k * ldt + i] = t;
+      ws.TT[(size_t)i * ldt + k] = t;
     }
     if (tid == 0) {
       tcol[k] = 1.0;
       ws.T[(size_t)k * ldt + k] = 1.0;
+      ws.TT[(size_t)k * ldt + k] = 1.0;
     }
   } else {
-    for (int q = tid; q < k; q += bs) ws.T[(size_t)q * ldt + k] = ell[q];  // L[k,q]
+    // row k of L, kept row-major in TT for the (I - L) r product and
+    // column-major in T for the diagnostics
+    for (int q = tid; q < k; q += bs) {
+      ws.TT[(size_t)k * ldt + q] = ell[q];
+      ws.T[(size_t)q * ldt + k] = ell[q];
+    }
   }
   if (go == 1) return;
   for (int q = tid; q < k; q += bs) rr[q] = vals[2 * q + 1] / rho;
   if (tid == 0) rr[k] = (vals[2 * k + 1] / rho) / rho;
   __syncthreads();
   __shared__ int s_bad;
+  __shared__ double s_last;
   if (tid == 0) s_bad = 0;
-  __syncthreads();
+  double* hbuf = scr + 3 * (ws.m + 2);  // the Givens staging area is free again
   if (scheme == kSchemeMgs1r) {
-    // h = T^T r = (I + L)^{-1} V^T A v_k: the MGS coefficients.
-    for (int i = tid; i <= k; i += bs) {
-      double s = 0.0;
-      if (i < k) {
-#pragma unroll 8
-        for (int q = 0; q < i; ++q) s += ws.T[(size_t)i * ldt + q] * rr[q];
-      } else {
-        for (int q = 0; q < k; ++q) s += tcol[q] * rr[q];
-      }
-      s += rr[i];
-      ws.coef[i] = s;
-      ws.H[(size_t)k * ws.ldh + i] = s;
-      if (!isfinite(s)) s_bad = 1;
+    // h = T^T r = (I + L)^{-1} V^T A v_k, the MGS coefficients: h_i for i < k
+    // uses column i of T (rows 0..i-1 contiguous in T) plus T[i,i] r_i = r_i;
+    // h_k uses the new column, already in LDS.
+    rows_dot(ws.T, ldt, rr, k, k, [](int) { return 0; }, [](int i) { return i; }, hbuf);
+    if (tid < 64) {
+      double a = 0.0;
+      for (int q = tid; q < k; q += 64) a += tcol[q] * rr[q];
+      a = wave_sum(a);
+      if (tid == 0) s_last = a;
     }
   } else {
-    // CGS2: first-pass coefficients corrected to first order, (I - L) r.
-    for (int i = tid; i <= k; i += bs) {
-      double s = rr[i];
-      if (i < k) {
-        for (int q = 0; q < i; ++q) s -= ws.T[(size_t)q * ldt + i] * rr[q];
-      } else {
-        for (int q = 0; q < k; ++q) s -= ell[q] * rr[q];
-      }
-      ws.coef[i] = s;
-      if (!isfinite(s)) s_bad = 1;
+    // CGS2: first-pass coefficients corrected to first order, (I - L) r, with
+    // row i of L contiguous in TT (row k is the new one, in LDS).
+    rows_dot(ws.TT, ldt, rr, k, k, [](int) { return 0; }, [](int i) { return i; }, hbuf);
+    if (tid < 64) {
+      double a = 0.0;
+      for (int q = tid; q < k; q += 64) a += ell[q] * rr[q];
+      a = wave_sum(a);
+      if (tid == 0) s_last = a;
     }
+  }
+  __syncthreads();
+  for (int i = tid; i <= k; i += bs) {
+    const double dot = i < k ? hbuf[i] : s_last;
+    const double h = scheme == kSchemeMgs1r ? dot + rr[i] : rr[i] - dot;
+    ws.coef[i] = h;
+    if (scheme == kSchemeMgs1r) ws.H[(size_t)k * ws.ldh + i] = h;
+    if (!isfinite(h)) s_bad = 1;
   }
   __syncthreads();
   if (tid == 0 && s_bad) {
@@ -667,7 +754,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
   const int P = 2 * (ws.m + 2);
   double* wl = lds;
   double* red = lds + TR;
-  double* vals = red + 4 * P;
+  double* vals = red + fused_red_doubles(ws.m);
   double* scr = vals + P;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -783,7 +870,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
   const int cnt = 2 * (nproj + 1);
   for (int i = tid; i < cnt; i += 256) vals[i] = ((red[i] + red[P + i]) + red[2 * P + i]) + red[3 * P + i];
   __syncthreads();
-  if (!grid_reduce(vals, cnt, ws, tile, G)) return;
+  if (!grid_reduce(vals, cnt, ws, tile, G, red)) return;
   if (tail == kTailCgs2Second)
     tail_cgs2_second(ws, vals, K - 1);
   else
@@ -869,7 +956,7 @@ __global__ __launch_bounds__(256) void k_axpy_dot(Ws ws, double* wv_,
                                                    const double* v, int tail, int i_col,
                                                    int q_row, int m_eff, double aux, int G) {
   constexpr int TR = 256 * RPT;
-  __shared__ double red[4];
+  __shared__ double red[256];
   __shared__ double vals[2];
   if (tail != kTailBnorm && tail != kTailFinalRes && ws.st->done) return;
   const int tile = tile_of_block(G);
@@ -895,7 +982,7 @@ __global__ __launch_bounds__(256) void k_axpy_dot(Ws ws, double* wv_,
   __syncthreads();
   if (tid == 0) vals[0] = ((red[0] + red[1]) + red[2]) + red[3];
   __syncthreads();
-  if (!grid_reduce(vals, 1, ws, tile, G)) return;
+  if (!grid_reduce(vals, 1, ws, tile, G, red)) return;
   if (tid != 0) return;
   DevState* st = ws.st;
   st->reductions += 1;
@@ -982,26 +1069,35 @@ __global__ __launch_bounds__(256) void k_scale(Ws ws, double* __restrict__ v) {
 // --------------------------------------------------------- end of a cycle
 
 // y = R[0:j,0:j]^{-1} g[0:j] by column-oriented back substitution; a zero
-// pivot (singular A) gives a zero component. One workgroup.
-__global__ __launch_bounds__(256) void k_backsolve(Ws ws) {
-  extern __shared__ double gg[];
+// pivot (singular A) gives a zero component. One workgroup. When the leading
+// j x j block of R fits in the dynamic LDS (ldh * j doubles), it is staged
+// there first with all loads in flight, so the j sequential steps do not each
+// wait on global memory.
+__global__ __launch_bounds__(256) void k_backsolve(Ws ws, int lds_doubles) {
+  extern __shared__ double sm[];
   __shared__ double s_y;
   const DevState* st = ws.st;
   const int j = st->j;
   if (st->status || j <= 0) return;
   const int tid = threadIdx.x, bs = blockDim.x;
+  double* gg = sm;
+  double* Rl = sm + (ws.m + 2);
+  const bool staged = (size_t)(ws.m + 2) + (size_t)ws.ldh * j <= (size_t)lds_doubles;
   for (int i = tid; i < j; i += bs) gg[i] = ws.g[i];
+  if (staged)
+    for (int e = tid; e < ws.ldh * j; e += bs) Rl[e] = ws.R[e];
   __syncthreads();
+  const double* R = staged ? Rl : ws.R;
   for (int i = j - 1; i >= 0; --i) {
     if (tid == 0) {
-      const double piv = ws.R[(size_t)i * ws.ldh + i];
+      const double piv = R[(size_t)i * ws.ldh + i];
       const double yi = piv != 0.0 ? gg[i] / piv : 0.0;
       ws.y[i] = yi;
       s_y = yi;
     }
     __syncthreads();
     const double yi = s_y;
-    for (int t = tid; t < i; t += bs) gg[t] -= ws.R[(size_t)i * ws.ldh + t] * yi;
+    for (int t = tid; t < i; t += bs) gg[t] -= R[(size_t)i * ws.ldh + t] * yi;
     __syncthreads();
   }
 }
@@ -1074,7 +1170,8 @@ int launch_solve_begin(const Ws& ws, hipStream_t s) {
 }
 
 int launch_cycle_begin(const Ws& ws, hipStream_t s) {
-  const size_t tot = 2 * (size_t)(ws.m + 1) * ws.m + (size_t)(ws.m + 2) * (ws.m + 4);
+  const size_t tot = 2 * (size_t)(ws.m + 1) * ws.m + 2 * (size_t)(ws.m + 2) * (ws.m + 2) +
+                    2 * (size_t)(ws.m + 2);
   const unsigned blocks = (unsigned)((tot + 255) / 256 < 64 ? (tot + 255) / 256 : 64);
   hipLaunchKernelGGL(k_cycle_begin, dim3(blocks), dim3(256), 0, s, ws);
   GMRES_CHECK_LAUNCH();
@@ -1188,7 +1285,11 @@ int launch_scale(const Ws& ws, double* v, hipStream_t s) {
 }
 
 int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, hipStream_t s) {
-  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(256), (size_t)(ws.m + 2) * sizeof(double), s, ws);
+  // up to 48 KiB: R's leading block when it fits, g always
+  size_t want = (size_t)(ws.m + 2) + (size_t)(ws.m + 1) * ws.m;
+  const size_t cap = 48 * 1024 / sizeof(double);
+  if (want > cap) want = cap;
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(256), want * sizeof(double), s, ws, (int)want);
   GMRES_CHECK_LAUNCH();
   switch (rpt) {
     case 1: hipLaunchKernelGGL(k_xupdate<1>, dim3(G), dim3(256), 0, s, ws, x, G); break;

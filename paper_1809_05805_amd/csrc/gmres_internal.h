@@ -55,7 +55,8 @@ struct Ws {
   double* w;         // ldv: SpMV output of the current step
   double* H;         // (m+1) x m unrotated Hessenberg matrix, ld = ldh
   double* R;         // (m+1) x m Givens-rotated copy
-  double* T;         // (m+2) x (m+2): Malard-Paige T (one-reduce) or L rows (CGS2), ld = ldt
+  double* T;         // (m+2) x (m+2): Malard-Paige T (one-reduce) or L (CGS2), column-major, ld = ldt
+  double* TT;        // the same matrix row-major (rows contiguous), ld = ldt
   double* g;         // m+2 rotated right-hand side
   double* gh;        // m+2: gh[k] = |g_k| as it stood right after rotation k-1
   double* cs;        // m+1 rotation cosines
