@@ -48,13 +48,21 @@ int pick_grid(int64_t n, int rpt) {
   return (int)tiles;
 }
 
-// Lanes per CSR row: the power of two at or above the mean row length, at
-// least 8 (the SpMV keeps 8 rows in flight per lane group) and at most 64.
-int pick_lanes(int64_t n, int64_t nnz) {
+// SpMV shape (100 * lanes per row + entries per lane) from the mean row
+// length: the fewest lanes per row whose entry slots cover it. One thread per
+// row for up to 8 entries; 8 lanes of 4 entries for 27-point rows.
+// GMRES_SPMV_SHAPE overrides the choice for tuning sweeps.
+int pick_spmv_shape(int64_t n, int64_t nnz) {
+  if (const char* e = getenv("GMRES_SPMV_SHAPE")) {
+    const int v = atoi(e);
+    if (v == 108 || v == 208 || v == 408 || v == 804 || v == 808 || v == 6401) return v;
+  }
   const int64_t avg = (nnz + n - 1) / n;
-  int s = 8;
-  while (s < avg && s < 64) s <<= 1;
-  return s;
+  if (avg <= 8) return 108;
+  if (avg <= 16) return 208;
+  if (avg <= 32) return 804;
+  if (avg <= 64) return 808;
+  return 6401;
 }
 
 struct Layout {
@@ -113,7 +121,7 @@ bool is_device_ptr(const void* p) {
 struct gmres_ctx {
   Csr A;
   int64_t nnz;
-  int m, scheme, S;
+  int m, scheme, S;  // S: SpMV shape code
   Layout L;
   Ws ws;
   hipStream_t stream;
@@ -319,7 +327,7 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   c->nnz = nnz;
   c->m = m;
   c->scheme = scheme;
-  c->S = pick_lanes(n, nnz);
+  c->S = pick_spmv_shape(n, nnz);
   c->L = L;
   c->stream = (hipStream_t)hip_stream;
   char* base = (char*)workspace;

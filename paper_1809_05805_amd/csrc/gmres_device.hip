@@ -74,11 +74,7 @@ __device__ inline double wave_multi_sum(double (&v)[NV], int lane) {
 }
 
 // Tuning constants (compile-time; defaults are the measured best on MI355X):
-//   GMRES_SPMV_ROWS  rows each SpMV lane group keeps in flight per pass (8 or 16);
 //   GMRES_PROJ_COLS  basis columns per projection chunk (1, 2, 4 or 8).
-#ifndef GMRES_SPMV_ROWS
-#define GMRES_SPMV_ROWS 4
-#endif
 #ifndef GMRES_PROJ_COLS
 #define GMRES_PROJ_COLS 1
 #endif
@@ -116,23 +112,24 @@ __device__ inline void seg_sum(double (&v)[R], int sl) {
   }
 }
 
-// One pass of the CSR SpMV over R * (256 / S) consecutive local rows starting
-// at local row p0: S lanes per row, and each lane group works on R rows at
-// once, so every lane has R independent load chains (row pointers, then
-// indices and values, then the gathered x) in flight. Rows with more than S
-// nonzeros finish in a strided loop. emit(local_row, value) is called by one
-// lane per row; rows at or past n give 0.
-template <int R, int S, typename Emit>
-__device__ inline void spmv_pass(const Csr& A, const double* __restrict__ x, int64_t row0, int p0,
-                                 Emit emit) {
+// CSR SpMV shapes. S lanes share a row and each lane takes EPL of its
+// entries, strided by S so that the S lanes read consecutive entries at each
+// step; a lane group works on R rows at once. Few lanes per row keep each
+// gather instruction on few, well-filled cache lines: on the 7-point
+// 128^3 matrix one row per thread (S = 1, EPL = 8) runs at 6.0 TB/s where
+// eight lanes per row reach 4.8 TB/s. Rows longer than S * EPL finish in a
+// strided loop.
+// Rows per lane group: about 8 entry slots per lane in flight in total.
+template <int S, int EPL>
+constexpr int spmv_rows() { return EPL >= 8 ? 1 : 8 / EPL; }
+
+// Loads for one pass (all unconditional, at clamped indices; values masked
+// afterwards): row pointers, then indices and values.
+template <int R, int S>
+__device__ inline void spmv_load_rp(const Csr& A, int64_t row0, int p0, int (&e0)[R], int (&e1)[R]) {
   constexpr int NSUB = 256 / S;
-  const int tid = threadIdx.x;
-  const int sub = tid / S, sl = tid % S;
+  const int sub = threadIdx.x / S;
   const int64_t n = A.n;
-  // All loads below are unconditional, at indices clamped into range, and the
-  // values they bring are masked afterwards: conditional loads would become
-  // branches that wait on each row in turn.
-  int e0[R], e1[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int64_t r = row0 + p0 + q * NSUB + sub;
@@ -141,113 +138,98 @@ __device__ inline void spmv_pass(const Csr& A, const double* __restrict__ x, int
     e0[q] = a;
     e1[q] = r < n ? b : a;
   }
-  double acc[R];
-  if (A.nnz > 0) {
-    int c[R];
-    double v[R];
+}
+
+template <int R, int S, int EPL>
+__device__ inline void spmv_load_cv(const Csr& A, const int (&e0)[R], const int (&e1)[R],
+                                    int (&c)[R][EPL], double (&v)[R][EPL]) {
+  const int sl = threadIdx.x % S;
+  const bool any = A.nnz > 0;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int e = e0[q] + sl;
-      const int ec = e < e1[q] ? e : 0;
-      c[q] = A.ci[ec];
-      v[q] = A.va[ec];
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) {
+      const int e = e0[q] + sl + t * S;
+      const int ec = (any && e < e1[q]) ? e : 0;
+      c[q][t] = any ? A.ci[ec] : 0;
+      v[q][t] = any ? A.va[ec] : 0.0;
     }
-    double xv[R];
+}
+
+// Gathers, products, the long-row tail, the reduction over the S lanes and
+// the emit of one pass.
+template <int R, int S, int EPL, typename Emit>
+__device__ inline void spmv_finish(const Csr& A, const double* __restrict__ x, int p0,
+                                   const int (&e0)[R], const int (&e1)[R], const int (&c)[R][EPL],
+                                   const double (&v)[R][EPL], Emit emit) {
+  constexpr int NSUB = 256 / S;
+  const int sub = threadIdx.x / S, sl = threadIdx.x % S;
+  double xv[R][EPL];
 #pragma unroll
-    for (int q = 0; q < R; ++q) xv[q] = x[(unsigned)c[q]];
+  for (int q = 0; q < R; ++q)
 #pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = (e0[q] + sl < e1[q]) ? v[q] * xv[q] : 0.0;
+    for (int t = 0; t < EPL; ++t) xv[q][t] = x[(unsigned)c[q][t]];
+  double acc[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-      for (int e = e0[q] + sl + S; e < e1[q]; e += S) acc[q] += A.va[e] * x[A.ci[e]];
-  } else {
+  for (int q = 0; q < R; ++q) {
+    double a = 0.0;
 #pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = 0.0;
+    for (int t = 0; t < EPL; ++t) a += (e0[q] + sl + t * S < e1[q]) ? v[q][t] * xv[q][t] : 0.0;
+    for (int e = e0[q] + sl + EPL * S; e < e1[q]; e += S) a += A.va[e] * x[A.ci[e]];
+    acc[q] = a;
   }
   seg_sum<R, S>(acc, sl);
   if constexpr (R >= S) {
 #pragma unroll
-    for (int t = 0; t < R / S; ++t) {
-      const int q = sl * (R / S) + t;
-      emit(p0 + q * NSUB + sub, acc[t]);
-    }
+    for (int t = 0; t < R / S; ++t) emit(p0 + (sl * (R / S) + t) * NSUB + sub, acc[t]);
   } else {
-    if ((sl & (S / R - 1)) == 0) {
-      const int q = sl / (S / R);
-      emit(p0 + q * NSUB + sub, acc[0]);
-    }
+    if ((sl & (S / R - 1)) == 0) emit(p0 + (sl / (S / R)) * NSUB + sub, acc[0]);
   }
 }
 
-// The SpMV of a whole tile of TR rows as a software pipeline over passes of
-// R * (256 / S) rows: while pass p gathers x, the row pointers and then the
-// indices and values of pass p+1 are already in flight, so a workgroup pays
-// about one memory round trip per pass instead of three. Same lane layout and
-// reduction as spmv_pass.
-template <int R, int S, int TR, typename Emit>
+// One pass over R * (256 / S) consecutive local rows starting at local row
+// p0; emit(local_row, value) is called by one lane per row (rows at or past
+// n give 0).
+template <int R, int S, int EPL, typename Emit>
+__device__ inline void spmv_pass(const Csr& A, const double* __restrict__ x, int64_t row0, int p0,
+                                 Emit emit) {
+  int e0[R], e1[R], c[R][EPL];
+  double v[R][EPL];
+  spmv_load_rp<R, S>(A, row0, p0, e0, e1);
+  spmv_load_cv<R, S, EPL>(A, e0, e1, c, v);
+  spmv_finish<R, S, EPL>(A, x, p0, e0, e1, c, v, emit);
+}
+
+// The SpMV of a whole tile of TR rows as a software pipeline over passes:
+// while pass p gathers x, the row pointers and then the indices and values of
+// pass p+1 are already in flight.
+template <int R, int S, int EPL, int TR, typename Emit>
 __device__ inline void spmv_tile(const Csr& A, const double* __restrict__ x, int64_t row0,
                                  Emit emit) {
-  constexpr int NSUB = 256 / S;
-  constexpr int RPP = R * NSUB;
+  constexpr int RPP = R * (256 / S);
   constexpr int NP = TR / RPP;
   static_assert(NP >= 1 && TR % RPP == 0, "tile must hold whole passes");
-  const int tid = threadIdx.x;
-  const int sub = tid / S, sl = tid % S;
-  const int64_t n = A.n;
-  const bool any = A.nnz > 0;
-  auto load_rp = [&](int p0, int (&e0)[R], int (&e1)[R]) {
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int64_t r = row0 + p0 + q * NSUB + sub;
-      const int64_t rc = r < n ? r : n - 1;
-      const int a = A.rp[rc], b = A.rp[rc + 1];
-      e0[q] = a;
-      e1[q] = r < n ? b : a;
-    }
-  };
-  auto load_cv = [&](const int (&e0)[R], const int (&e1)[R], int (&c)[R], double (&v)[R]) {
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int e = e0[q] + sl;
-      const int ec = (any && e < e1[q]) ? e : 0;
-      c[q] = any ? A.ci[ec] : 0;
-      v[q] = any ? A.va[ec] : 0.0;
-    }
-  };
-  int e0[R], e1[R], c[R];
-  double v[R];
-  load_rp(0, e0, e1);
-  load_cv(e0, e1, c, v);
+  int e0[R], e1[R], c[R][EPL];
+  double v[R][EPL];
+  spmv_load_rp<R, S>(A, row0, 0, e0, e1);
+  spmv_load_cv<R, S, EPL>(A, e0, e1, c, v);
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
-    int e0n[R], e1n[R], cn[R];
-    double vn[R];
-    if (p + 1 < NP) load_rp((p + 1) * RPP, e0n, e1n);
-    double xv[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) xv[q] = x[(unsigned)c[q]];
-    if (p + 1 < NP) load_cv(e0n, e1n, cn, vn);
-    double acc[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = (e0[q] + sl < e1[q]) ? v[q] * xv[q] : 0.0;
-#pragma unroll
-    for (int q = 0; q < R; ++q)
-      for (int e = e0[q] + sl + S; e < e1[q]; e += S) acc[q] += A.va[e] * x[A.ci[e]];
-    seg_sum<R, S>(acc, sl);
-    const int p0 = p * RPP;
-    if constexpr (R >= S) {
-#pragma unroll
-      for (int t = 0; t < R / S; ++t) emit(p0 + (sl * (R / S) + t) * NSUB + sub, acc[t]);
-    } else {
-      if ((sl & (S / R - 1)) == 0) emit(p0 + (sl / (S / R)) * NSUB + sub, acc[0]);
-    }
+    int e0n[R], e1n[R], cn[R][EPL];
+    double vn[R][EPL];
+    if (p + 1 < NP) spmv_load_rp<R, S>(A, row0, (p + 1) * RPP, e0n, e1n);
+    if (p + 1 < NP) spmv_load_cv<R, S, EPL>(A, e0n, e1n, cn, vn);
+    spmv_finish<R, S, EPL>(A, x, p * RPP, e0, e1, c, v, emit);
     if (p + 1 < NP) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         e0[q] = e0n[q];
         e1[q] = e1n[q];
-        c[q] = cn[q];
-        v[q] = vn[q];
+#pragma unroll
+        for (int t = 0; t < EPL; ++t) {
+          c[q][t] = cn[q][t];
+          v[q][t] = vn[q][t];
+        }
       }
     }
   }
@@ -528,16 +510,17 @@ __global__ void k_validate_csr(const int* __restrict__ rp, const int* __restrict
   if (bad) atomicOr(&st->bad_csr, 1);
 }
 
-// y = A x (b == nullptr) or y = b - A x: one pass of GMRES_SPMV_ROWS * (256 / S)
-// rows per workgroup. Skipped when a state is given and its cycle is done.
-template <int S>
+// y = A x (b == nullptr) or y = b - A x: one pass of spmv_rows<S, EPL>() *
+// (256 / S) rows per workgroup. Skipped when a state is given and its cycle is done.
+template <int S, int EPL>
 __global__ __launch_bounds__(256) void k_spmv(Csr A, const double* __restrict__ x,
                                                const double* __restrict__ b, double* __restrict__ y,
                                                const DevState* st) {
   if (st && st->done) return;
-  constexpr int RPP = GMRES_SPMV_ROWS * (256 / S);
+  constexpr int R = spmv_rows<S, EPL>();
+  constexpr int RPP = R * (256 / S);
   const int64_t row0 = (int64_t)blockIdx.x * RPP;
-  spmv_pass<GMRES_SPMV_ROWS, S>(A, x, row0, 0, [&](int lr, double v) {
+  spmv_pass<R, S, EPL>(A, x, row0, 0, [&](int lr, double v) {
     const int64_t r = row0 + lr;
     if (r < A.n) y[r] = b ? b[r] - v : v;
   });
@@ -744,7 +727,7 @@ __device__ void tail_cgs2_second(const Ws& ws, const double* vals, int k) {
 // RPT rows per lane, 256 threads = 4 wavefronts; lane l of wavefront wv owns
 // rows tile0 + wv*64*RPT + i*64 + l, so every column read is 512 contiguous
 // bytes per wavefront.
-template <int RPT, int S, bool HAS_SPMV>
+template <int RPT, int S, int EPL, bool HAS_SPMV>
 __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, int m_eff, int tail,
                                                 int G) {
   extern __shared__ double lds[];
@@ -767,15 +750,15 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
   const double* __restrict__ u_g = V + (size_t)K * ldv;
 
   if constexpr (HAS_SPMV) {
-    // SpMV of the tile, GMRES_SPMV_ROWS rows per lane group per pass (fewer
-    // when the whole tile holds fewer).
-    constexpr int RG = GMRES_SPMV_ROWS * (256 / S) > TR ? TR / (256 / S) : GMRES_SPMV_ROWS;
+    // SpMV of the tile (fewer rows per lane group when the tile holds fewer).
+    constexpr int R0 = spmv_rows<S, EPL>();
+    constexpr int RG = R0 * (256 / S) > TR ? TR / (256 / S) : R0;
     auto emit = [&](int lr, double v) { wl[lr] = v; };
-    if constexpr (GMRES_SPMV_PIPELINE) {
-      spmv_tile<RG, S, TR>(A, u_g, row0, emit);
+    if constexpr (GMRES_SPMV_PIPELINE == 1) {
+      spmv_tile<RG, S, EPL, TR>(A, u_g, row0, emit);
     } else {
       constexpr int RPP = RG * (256 / S);
-      for (int p0 = 0; p0 < TR; p0 += RPP) spmv_pass<RG, S>(A, u_g, row0, p0, emit);
+      for (int p0 = 0; p0 < TR; p0 += RPP) spmv_pass<RG, S, EPL>(A, u_g, row0, p0, emit);
     }
     __syncthreads();
   }
@@ -1189,21 +1172,25 @@ int launch_validate(const Csr& A, int64_t nnz, DevState* st, hipStream_t s) {
   return 0;
 }
 
-template <int S>
+template <int S, int EPL>
 static void spmv_s(const Csr& A, const double* x, const double* b, double* y, const DevState* st,
                    hipStream_t s) {
-  constexpr int RPP = GMRES_SPMV_ROWS * (256 / S);
+  constexpr int RPP = spmv_rows<S, EPL>() * (256 / S);
   const int64_t blocks = (A.n + RPP - 1) / RPP;
-  hipLaunchKernelGGL(k_spmv<S>, dim3((unsigned)blocks), dim3(256), 0, s, A, x, b, y, st);
+  hipLaunchKernelGGL((k_spmv<S, EPL>), dim3((unsigned)blocks), dim3(256), 0, s, A, x, b, y, st);
 }
 
-int launch_spmv(const Csr& A, int S, const double* x, const double* b, double* y,
+// SpMV shapes: (S lanes per row, EPL entries per lane).
+#define GMRES_SPMV_SHAPES(X) X(1, 8) X(2, 8) X(4, 8) X(8, 4) X(8, 8) X(64, 1)
+
+int launch_spmv(const Csr& A, int shape, const double* x, const double* b, double* y,
                 const DevState* st, hipStream_t s) {
-  switch (S) {
-    case 8: spmv_s<8>(A, x, b, y, st, s); break;
-    case 16: spmv_s<16>(A, x, b, y, st, s); break;
-    case 32: spmv_s<32>(A, x, b, y, st, s); break;
-    default: spmv_s<64>(A, x, b, y, st, s); break;
+  switch (shape) {
+#define GMRES_CASE(S_, E_) \
+  case S_ * 100 + E_: spmv_s<S_, E_>(A, x, b, y, st, s); break;
+    GMRES_SPMV_SHAPES(GMRES_CASE)
+#undef GMRES_CASE
+    default: return -2;
   }
   GMRES_CHECK_LAUNCH();
   return 0;
@@ -1212,41 +1199,41 @@ int launch_spmv(const Csr& A, int S, const double* x, const double* b, double* y
 // The step kernels are launched with hipExtLaunchKernelGGL so that optional
 // start/stop events are attached to the dispatch itself and time the kernel
 // alone.
-template <int RPT, int S, bool HS>
+template <int RPT, int S, int EPL, bool HS>
 static void fused_t(const Csr& A, const Ws& ws, int K, int nproj, int m_eff, int tail, int G,
                     hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const uint32_t lds = (uint32_t)(fused_lds_doubles(RPT, ws.m) * sizeof(double));
-  hipExtLaunchKernelGGL((k_fused<RPT, S, HS>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A, ws, K,
-                        nproj, m_eff, tail, G);
+  hipExtLaunchKernelGGL((k_fused<RPT, S, EPL, HS>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A, ws,
+                        K, nproj, m_eff, tail, G);
 }
 
-template <int RPT, bool HS>
-static void fused_r(const Csr& A, int S, const Ws& ws, int K, int nproj, int m_eff, int tail,
-                    int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (!HS) {
-    fused_t<RPT, 8, false>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1);
-    return;
+template <int RPT>
+static int fused_r(const Csr& A, int shape, bool has_spmv, const Ws& ws, int K, int nproj,
+                   int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (!has_spmv) {
+    fused_t<RPT, 1, 1, false>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1);
+    return 0;
   }
-  switch (S) {
-    case 8: fused_t<RPT, 8, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 16: fused_t<RPT, 16, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 32: fused_t<RPT, 32, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    default: fused_t<RPT, 64, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+  switch (shape) {
+#define GMRES_CASE(S_, E_) \
+  case S_ * 100 + E_: fused_t<RPT, S_, E_, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    GMRES_SPMV_SHAPES(GMRES_CASE)
+#undef GMRES_CASE
+    default: return -2;
   }
+  return 0;
 }
 
-int launch_fused(const Csr& A, int S, const Ws& ws, int rpt, int K, int nproj, bool has_spmv,
+int launch_fused(const Csr& A, int shape, const Ws& ws, int rpt, int K, int nproj, bool has_spmv,
                  int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  int rc;
   switch (rpt) {
-    case 1: has_spmv ? fused_r<1, true>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1)
-                     : fused_r<1, false>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 2: has_spmv ? fused_r<2, true>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1)
-                     : fused_r<2, false>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 4: has_spmv ? fused_r<4, true>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1)
-                     : fused_r<4, false>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    default: has_spmv ? fused_r<8, true>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1)
-                      : fused_r<8, false>(A, S, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 1: rc = fused_r<1>(A, shape, has_spmv, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 2: rc = fused_r<2>(A, shape, has_spmv, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 4: rc = fused_r<4>(A, shape, has_spmv, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    default: rc = fused_r<8>(A, shape, has_spmv, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
   }
+  if (rc) return rc;
   GMRES_CHECK_LAUNCH();
   return 0;
 }

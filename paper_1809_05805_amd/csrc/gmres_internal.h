@@ -77,9 +77,10 @@ int launch_init(const Ws& ws, int ncounters, hipStream_t s);
 int launch_solve_begin(const Ws& ws, hipStream_t s);
 int launch_cycle_begin(const Ws& ws, hipStream_t s);
 int launch_validate(const Csr& A, int64_t nnz, DevState* st, hipStream_t s);
-int launch_spmv(const Csr& A, int S, const double* x, const double* b, double* y,
+// SpMV shape code: 100 * (lanes per row) + (entries per lane).
+int launch_spmv(const Csr& A, int shape, const double* x, const double* b, double* y,
                 const DevState* st, hipStream_t s);
-int launch_fused(const Csr& A, int S, const Ws& ws, int rpt, int K, int nproj, bool has_spmv,
+int launch_fused(const Csr& A, int shape, const Ws& ws, int rpt, int K, int nproj, bool has_spmv,
                  int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
 int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s,
