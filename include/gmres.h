@@ -148,17 +148,21 @@ int gmres_basis(gmres_ctx* ctx, double** V, int64_t* ldv);
 
 /*
  * Per-kernel timing for measurement (lagged schemes). When enabled, every
- * launch of the fused step kernel (SpMV + projection + device-wide reduction +
- * small dense step) and of the MAXPY kernel carries start/stop HIP events
+ * launch of the step kernel (projection + device-wide reduction + small dense
+ * step, with the SpMV fused in unless it runs as a launch of its own), of the
+ * separate SpMV kernel and of the MAXPY kernel carries start/stop HIP events
  * attached to its dispatch (hipExtLaunchKernel), so they time the kernel
- * alone; launches that the cycle's done flag skipped are not counted. bytes is the algorithmic HBM traffic of the counted launches:
- *   step k with SpMV:  12 nnz + 4 (n+1) + 8 n (k+1) + 8 n   (CSR, V[:,0:k+1], w written)
+ * alone; launches that the cycle's done flag skipped are not counted. bytes is
+ * the algorithmic HBM traffic of the counted launches:
+ *   step k, SpMV fused:     12 nnz + 4 (n+1) + 8 n (k+1) + 8 n   (CSR, V[:,0:k+1], w written)
+ *   step k, SpMV separate:  8 n (k+1) + 8 n                      (V[:,0:k+1], w read)
+ *   separate SpMV:          12 nnz + 4 (n+1) + 16 n              (CSR, u, w written)
  *   last step of a cycle (norm of column k only):  8 n
  *   CGS2 second pass:  8 n (k+2)                          (V[:,0:k+1] and z)
  *   MAXPY at step k:   8 n (k+1) + 16 n                   (V[:,0:k+1], w or z, new column)
  * gmres_set_timing(ctx, 1) enables and clears the totals; (ctx, 0) disables.
  */
-enum { GMRES_KSTAT_STEP = 0, GMRES_KSTAT_MAXPY = 1, GMRES_KSTAT_COUNT = 2 };
+enum { GMRES_KSTAT_STEP = 0, GMRES_KSTAT_MAXPY = 1, GMRES_KSTAT_SPMV = 2, GMRES_KSTAT_COUNT = 3 };
 typedef struct {
   double ms;        /* summed event-to-event time of the counted launches */
   double bytes;     /* summed algorithmic bytes */

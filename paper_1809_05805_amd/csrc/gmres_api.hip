@@ -65,6 +65,16 @@ int pick_spmv_shape(int64_t n, int64_t nnz) {
   return 6401;
 }
 
+// Whether the lagged step computes w = A u in a launch of its own before the
+// projection kernel (which then reads w back) instead of inside it. Fusing
+// saves the write-then-read of w, but the tiles that finish their gathers
+// early start streaming the basis and slow down the gathers still in flight.
+// GMRES_SPLIT_SPMV (0 or 1) overrides the default for tuning sweeps.
+bool pick_split(int64_t, int64_t) {
+  if (const char* e = getenv("GMRES_SPLIT_SPMV")) return atoi(e) != 0;
+  return false;
+}
+
 struct Layout {
   int64_t ldv;
   int rpt, G, NG, pstride;
@@ -122,6 +132,7 @@ struct gmres_ctx {
   Csr A;
   int64_t nnz;
   int m, scheme, S;  // S: SpMV shape code
+  bool split;        // separate SpMV launch in the lagged step
   Layout L;
   Ws ws;
   hipStream_t stream;
@@ -202,7 +213,8 @@ void collect_timing(gmres_ctx* c, int j, bool stopped_at_restart) {
   if (!c->timing) return;
   for (size_t i = 0; i < c->recs.size(); ++i) {
     const auto& r = c->recs[i];
-    const bool ran = stopped_at_restart ? (r.step == 0 && r.cls == GMRES_KSTAT_STEP && r.runs_to == 0)
+    const bool ran = stopped_at_restart ? (r.step == 0 && r.runs_to == 0 &&
+                                           (r.cls == GMRES_KSTAT_STEP || r.cls == GMRES_KSTAT_SPMV))
                                         : j >= r.runs_to;
     if (!ran) continue;
     float ms = 0.f;
@@ -248,9 +260,16 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
       {
         // The last step of a cycle only finishes the lagged norm of column m_eff.
         const bool last = k == m_eff;
-        const double bytes = last ? n8 : csr + n8 * (k + 1) + n8;
+        int wsrc = last ? kWNone : kWSpmv;
+        double bytes = last ? n8 : csr + n8 * (k + 1) + n8;
+        if (!last && c->split) {
+          TimedLaunch t(c, GMRES_KSTAT_SPMV, k, k, csr + 2 * n8);
+          TRY(launch_spmv(c->A, c->S, col(k), nullptr, ws.w, ws.st, s, t.e0, t.e1));
+          wsrc = kWLoad;
+          bytes = n8 * (k + 2);
+        }
         TimedLaunch t(c, GMRES_KSTAT_STEP, k, k, bytes);
-        TRY(launch_fused(c->A, c->S, ws, rpt, k, last ? 0 : k, !last, m_eff, tail, G, s, t.e0,
+        TRY(launch_fused(c->A, c->S, ws, rpt, k, last ? 0 : k, wsrc, m_eff, tail, G, s, t.e0,
                          t.e1));
       }
       if (k == m_eff) break;
@@ -261,7 +280,7 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
       if (c->scheme == kSchemeCgs2) {
         {
           TimedLaunch t(c, GMRES_KSTAT_STEP, k, k + 1, n8 * (k + 2));
-          TRY(launch_fused(c->A, c->S, ws, rpt, k + 1, k + 1, false, m_eff, kTailCgs2Second, G, s,
+          TRY(launch_fused(c->A, c->S, ws, rpt, k + 1, k + 1, kWNone, m_eff, kTailCgs2Second, G, s,
                            t.e0, t.e1));
         }
         TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
@@ -328,6 +347,7 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   c->m = m;
   c->scheme = scheme;
   c->S = pick_spmv_shape(n, nnz);
+  c->split = pick_split(n, nnz);
   c->L = L;
   c->stream = (hipStream_t)hip_stream;
   char* base = (char*)workspace;

@@ -63,8 +63,11 @@ __device__ inline double wave_multi_sum(double (&v)[NV], int lane) {
     const bool upper = (lane & mask) != 0;
 #pragma unroll
     for (int i = 0; i < h; ++i) {
-      const double send = upper ? v[i] : v[i + h];
-      const double keep = upper ? v[i + h] : v[i];
+      // plain values first: a select between array elements can become a
+      // select of addresses, which puts the array in scratch memory
+      const double a = v[i], b = v[i + h];
+      const double send = upper ? a : b;
+      const double keep = upper ? b : a;
       v[i] = keep + __shfl_xor(send, mask, 64);
     }
     mask >>= 1;
@@ -83,6 +86,18 @@ __device__ inline double wave_multi_sum(double (&v)[NV], int lane) {
 #ifndef GMRES_SPMV_PIPELINE
 #define GMRES_SPMV_PIPELINE 1
 #endif
+//   GMRES_MAXPY_COLS  basis columns per MAXPY pass (1, 2 or 4).
+#ifndef GMRES_MAXPY_COLS
+#define GMRES_MAXPY_COLS 2
+#endif
+
+// Load base[boff / 8] with boff an unsigned 32-bit byte offset: with a
+// wave-uniform base this is the scalar-base + 32-bit vector-offset form of a
+// global load, so one offset register per lane serves every column of a tile
+// (a signed or 64-bit index costs a 64-bit address per load instead).
+__device__ inline double ld_at(const double* base, uint32_t boff) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + boff);
+}
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
@@ -101,8 +116,11 @@ __device__ inline void seg_sum(double (&v)[R], int sl) {
     const bool upper = (sl & mask) != 0;
 #pragma unroll
     for (int i = 0; i < h; ++i) {
-      const double send = upper ? v[i] : v[i + h];
-      const double keep = upper ? v[i + h] : v[i];
+      // plain values first: a select between array elements can become a
+      // select of addresses, which puts the array in scratch memory
+      const double a = v[i], b = v[i + h];
+      const double send = upper ? a : b;
+      const double keep = upper ? b : a;
       v[i] = keep + __shfl_xor(send, mask, S);
     }
     mask >>= 1;
@@ -250,33 +268,47 @@ __device__ inline void spmv_tile(const Csr& A, const double* __restrict__ x, int
 // write-back on every workgroup) is needed.
 __device__ inline void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Sum rows [beg, beg + nrows) of a partials array (row stride ws.pstride),
-// columns [0, cnt), into vals. The workgroup splits the rows into `parts`
-// interleaved subsets so that each thread has at most 8 independent loads in
-// flight, then adds the subsets' sums in a fixed order (so the result does not
-// depend on timing). scratch needs parts * cnt doubles.
+// Rows [part, part + B * parts, ...) below nrows of column i, B loads at a
+// time: all B loads of a batch are in flight together (clamped rows, masked
+// values), and the sum runs in row order.
+template <int B>
+__device__ inline double sum_part(const double* rows_base, int pstride, int nrows, int i, int part,
+                                  int parts) {
+  double acc = 0.0;
+  for (int q0 = part; q0 < nrows; q0 += B * parts) {
+    double v[B];
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+      const int q = q0 + t * parts;
+      const int qc = q < nrows ? q : nrows - 1;
+      v[t] = atomic_ld(rows_base + (size_t)qc * pstride + i);
+    }
+#pragma unroll
+    for (int t = 0; t < B; ++t) acc += (q0 + t * parts < nrows) ? v[t] : 0.0;
+  }
+  return acc;
+}
+
+// Sum rows [0, nrows) of a partials array (row stride pstride), columns
+// [0, cnt), into vals. The workgroup splits the rows into `parts` interleaved
+// subsets, one thread per (column, subset), each issuing its rows' loads in
+// batches of 8; then the subsets' sums are added in a fixed order (so the
+// result does not depend on timing). scratch needs parts * cnt doubles.
 __device__ void sum_rows(const double* rows_base, int pstride, int nrows, int cnt, double* vals,
                          double* scratch) {
   const int tid = threadIdx.x, bs = blockDim.x;
   int parts = bs / cnt;
   if (parts > (nrows + 7) / 8) parts = (nrows + 7) / 8;
   if (parts < 1) parts = 1;
+  // Batches of 8: wider ones hold an address and a value per load in VGPRs
+  // and would raise the whole kernel's register allocation.
+  auto part_sum = [&](int i, int part) {
+    return sum_part<8>(rows_base, pstride, nrows, i, part, parts);
+  };
   if (cnt * parts <= bs) {
     if (tid < cnt * parts) {
       const int i = tid % cnt, part = tid / cnt;
-      double v[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int q = part + t * parts;
-        const int qc = q < nrows ? q : nrows - 1;
-        v[t] = atomic_ld(rows_base + (size_t)qc * pstride + i);
-      }
-      double acc = 0.0;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) acc += (part + t * parts < nrows) ? v[t] : 0.0;
-      for (int q = part + 8 * parts; q < nrows; q += parts)
-        acc += atomic_ld(rows_base + (size_t)q * pstride + i);
-      scratch[part * cnt + i] = acc;
+      scratch[part * cnt + i] = part_sum(i, part);
     }
     __syncthreads();
     for (int i = tid; i < cnt; i += bs) {
@@ -285,17 +317,27 @@ __device__ void sum_rows(const double* rows_base, int pstride, int nrows, int cn
       vals[i] = acc;
     }
   } else {
-    for (int i = tid; i < cnt; i += bs) {
-      double acc = 0.0;
-      for (int q = 0; q < nrows; ++q) acc += atomic_ld(rows_base + (size_t)q * pstride + i);
-      vals[i] = acc;
-    }
+    for (int i = tid; i < cnt; i += bs) vals[i] = part_sum(i, 0);
   }
   __syncthreads();
 }
 
+// No work to overlap with the final level of a reduction.
+struct NoPrefetch {
+  __device__ void issue() {}
+  __device__ void commit() {}
+};
+
+// Two-level deterministic device-wide sum of vals[0:cnt] over nslots
+// workgroups: each stores its row of partials; the last of each group of
+// kGroup (by ticket) sums the group's rows, and the last group sums the group
+// rows. Returns true in the one workgroup that holds the totals. That
+// workgroup calls pre.issue() just before the loads of the final level and
+// pre.commit() after them, so the caller's own loads for what follows overlap
+// the final level's.
+template <typename Pre>
 __device__ bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int nslots,
-                            double* scratch) {
+                            double* scratch, Pre& pre) {
   __shared__ int s_last;
   const int tid = threadIdx.x;
   const int bs = blockDim.x;
@@ -312,9 +354,13 @@ __device__ bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int n
   }
   __syncthreads();
   if (!s_last) return false;
+  if (ng == 1) pre.issue();
   sum_rows(ws.partials + (size_t)gbeg * ws.pstride, ws.pstride, gcnt, cnt, vals, scratch);
   if (tid == 0) atomicExch(ws.counters + grp, 0u);
-  if (ng == 1) return true;
+  if (ng == 1) {
+    pre.commit();
+    return true;
+  }
   for (int i = tid; i < cnt; i += bs) atomic_st(ws.gpartials + (size_t)grp * ws.pstride + i, vals[i]);
   wait_stores();
   __syncthreads();
@@ -324,9 +370,17 @@ __device__ bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int n
   }
   __syncthreads();
   if (!s_last) return false;
+  pre.issue();
   sum_rows(ws.gpartials, ws.pstride, ng, cnt, vals, scratch);
   if (tid == 0) atomicExch(ws.counters + ng, 0u);
+  pre.commit();
   return true;
+}
+
+__device__ inline bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot, int nslots,
+                                   double* scratch) {
+  NoPrefetch none;
+  return grid_reduce(vals, cnt, ws, slot, nslots, scratch, none);
 }
 
 // out[i] = sum over q in [lo(i), hi(i)) of M[i * ld + q] * vec[q], for i in
@@ -400,18 +454,20 @@ __device__ double givens_column(const Ws& ws, int col) {
   ws.cs[col] = c;
   ws.sn[col] = s;
   const double gk = ws.g[col];
+  const double gn = -s * gk;
   ws.g[col] = c * gk;
-  ws.g[col + 1] = -s * gk;
-  const double res = fabs(ws.g[col + 1]);
+  ws.g[col + 1] = gn;
+  const double res = fabs(gn);
   ws.gh[col + 1] = res;
   return res;
 }
 
 // The same rotation step with the column, cosines and sines already staged in
-// LDS by the whole workgroup (hc[0..col+1], csl[0..col-1], snl[0..col-1]), so
-// the serial loop does not wait on global memory. Writes R, cs, sn, g, gh.
+// LDS by the whole workgroup (hc[0..col+1], csl[0..col-1], snl[0..col-1]) and
+// gk = g[col] read beforehand, so the serial loop does not wait on global
+// memory. Writes R, cs, sn, g, gh.
 __device__ double givens_column_lds(const Ws& ws, int col, const double* hc, const double* csl,
-                                    const double* snl) {
+                                    const double* snl, double gk) {
   double* Rc = ws.R + (size_t)col * ws.ldh;
   double a = hc[0];
 #pragma unroll 4
@@ -428,10 +484,10 @@ __device__ double givens_column_lds(const Ws& ws, int col, const double* hc, con
   Rc[col + 1] = 0.0;
   ws.cs[col] = c;
   ws.sn[col] = s;
-  const double gk = ws.g[col];
+  const double gn = -s * gk;
   ws.g[col] = c * gk;
-  ws.g[col + 1] = -s * gk;
-  const double res = fabs(ws.g[col + 1]);
+  ws.g[col + 1] = gn;
+  const double res = fabs(gn);
   ws.gh[col + 1] = res;
   return res;
 }
@@ -543,32 +599,94 @@ __host__ __device__ inline size_t fused_lds_doubles(int rpt, int m) {
   return (size_t)256 * rpt + (size_t)fused_red_doubles(m) + P + 6 * (size_t)(m + 2);
 }
 
+// Inputs of the small dense step of lagged step k, loaded by the workgroup
+// that ends up holding the reduction's totals at the same time as the final
+// level's partials, so that their latency overlaps: column k-1 of H and the
+// earlier rotations into LDS, g[k-1] and two state scalars into thread 0's
+// registers, and, when it fits in the SpMV tile buffer, the strictly
+// triangular part of T (one-reduce MGS: tri[i (i-1)/2 + q] = T(q, i), q < i,
+// column i) or of L (CGS2: the same index holds L(i, q), row i).
+template <int NT>
+struct TailPrefetch {
+  const Ws* ws;
+  double* tri;
+  double* hc;
+  double* csl;
+  double* snl;
+  int k, scheme;
+  int ntri;     // entries of tri to load (0: T or L is read from HBM instead)
+  bool active;  // false: this launch's tail needs none of it
+  bool staged;  // tri holds the whole strictly triangular block
+  double tv[NT];
+  double h0, c0, s0;
+  double gprev, tol;
+  int64_t red;
+
+  __device__ void issue() {
+    if (!active) return;
+    const int tid = threadIdx.x;
+    if (k >= 1) {
+      const int i = tid < k ? tid : k - 1;
+      h0 = ws->H[(size_t)(k - 1) * ws->ldh + i];
+      const int j = tid < k - 1 ? tid : 0;
+      c0 = ws->cs[j];
+      s0 = ws->sn[j];
+    }
+    if (tid == 0) {
+      gprev = ws->g[k >= 1 ? k - 1 : 0];
+      tol = ws->st->tol_abs;
+      red = ws->st->reductions;
+    }
+    if (ntri > 0) {
+      const double* src = scheme == kSchemeMgs1r ? ws->T : ws->TT;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int f0 = tid + 256 * t;
+        const int f = f0 < ntri ? f0 : ntri - 1;
+        // row i of the packed triangle holding entry f: i (i-1)/2 <= f < (i+1) i/2
+        int i = (int)((1.0 + sqrt(1.0 + 8.0 * (double)f)) * 0.5);
+        if (i * (i - 1) / 2 > f) --i;
+        if ((i + 1) * i / 2 <= f) ++i;
+        tv[t] = src[(size_t)i * ws->ldt + (f - i * (i - 1) / 2)];
+      }
+    }
+  }
+  __device__ void commit() {
+    if (!active) return;
+    const int tid = threadIdx.x;
+    if (k >= 1) {
+      if (tid < k) hc[tid] = h0;
+      if (tid < k - 1) {
+        csl[tid] = c0;
+        snl[tid] = s0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int f = tid + 256 * t;
+      if (f < ntri) tri[f] = tv[t];
+    }
+    __syncthreads();
+  }
+};
+
 // The small dense step of a lagged scheme (one-reduce MGS or CGS2, first
 // reduction), run by the last workgroup with the totals in vals:
 //   vals[2q] = V_q . u, vals[2q+1] = V_q . w (q < k), vals[2k] = u.u, vals[2k+1] = u.w.
 // With norm_only (the end-of-cycle step) vals[0] = u.u is all there is: only
 // the last Hessenberg entry and its rotation are needed, not a new T column.
+// pf holds the prefetched inputs (H column, rotations, scalars, T or L).
+template <int NT>
 __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool norm_only,
-                            int m_eff, int scheme) {
+                            int m_eff, int scheme, const TailPrefetch<NT>& pf) {
   __shared__ double s_rho;
   __shared__ int s_go;  // 0: nothing more; 1: extend T (or L) only; 2: also the MAXPY coefficients
   const int tid = threadIdx.x, bs = blockDim.x;
   DevState* st = ws.st;
   const int M2 = ws.m + 2;
-  double* hc = scr + 3 * M2;   // column k-1 of H, then rho
-  double* csl = scr + 4 * M2;
-  double* snl = scr + 5 * M2;
-  if (k >= 1) {
-    const double* Hc = ws.H + (size_t)(k - 1) * ws.ldh;
-    for (int i = tid; i < k; i += bs) hc[i] = Hc[i];
-    for (int i = tid; i < k - 1; i += bs) {
-      csl[i] = ws.cs[i];
-      snl[i] = ws.sn[i];
-    }
-  }
-  __syncthreads();
+  double* hc = pf.hc;  // column k-1 of H, then rho
   if (tid == 0) {
-    st->reductions += 1;
+    st->reductions = pf.red + 1;
     const double alpha = vals[norm_only ? 0 : 2 * k];
     int go = 2;
     double rho = 0.0;
@@ -581,7 +699,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
       if (k == 0) {
         st->beta = rho;
         ws.g[0] = rho;
-        if (rho <= st->tol_abs) {
+        if (rho <= pf.tol) {
           st->true_conv = 1;
           st->done = 1;
           st->j = 0;
@@ -590,7 +708,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
       } else {
         ws.H[(size_t)(k - 1) * ws.ldh + k] = rho;
         hc[k] = rho;
-        const double gk = givens_column_lds(ws, k - 1, hc, csl, snl);
+        const double gk = givens_column_lds(ws, k - 1, hc, pf.csl, pf.snl, pf.gprev);
         st->gk = gk;
         if (!isfinite(gk)) {
           st->status = kNonfinite;
@@ -601,7 +719,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
           st->done = 1;
           st->j = k;
           go = 0;
-        } else if (gk <= st->tol_abs || k == m_eff) {
+        } else if (gk <= pf.tol || k == m_eff) {
           st->done = 1;
           st->j = k;
           go = norm_only ? 0 : 1;
@@ -620,15 +738,25 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
   if (go == 0) return;
   const double rho = s_rho;
   const int ldt = ws.ldt;
+  const double* tri = pf.tri;
   double* ell = scr;                 // l = V[:,0:k]^T v_k, the new row of L
-  double* rr = scr + (ws.m + 2);     // r = V[:,0:k+1]^T A v_k
-  double* tcol = scr + 2 * (ws.m + 2);
+  double* rr = scr + M2;             // r = V[:,0:k+1]^T A v_k
+  double* tcol = scr + 2 * M2;
   for (int q = tid; q < k; q += bs) ell[q] = vals[2 * q] / rho;
   __syncthreads();
   if (scheme == kSchemeMgs1r) {
     // Malard-Paige: T[0:k,k] = -T[0:k,0:k] l, T[k,k] = 1, so T = (I + L^T)^{-1}.
-    // Row i of T (entries i..k-1) is contiguous in the row-major copy TT.
-    rows_dot(ws.TT, ldt, ell, k, k, [](int i) { return i; }, [&](int) { return k; }, tcol);
+    if (pf.staged) {
+      // row i of T from the packed columns in LDS (T(i,i) = 1)
+      for (int i = tid; i < k; i += bs) {
+        double a = ell[i];
+        for (int q = i + 1; q < k; ++q) a += tri[q * (q - 1) / 2 + i] * ell[q];
+        tcol[i] = a;
+      }
+    } else {
+      // row i of T (entries i..k-1) is contiguous in the row-major copy TT
+      rows_dot(ws.TT, ldt, ell, k, k, [](int i) { return i; }, [&](int) { return k; }, tcol);
+    }
     __syncthreads();
     for (int i = tid; i < k; i += bs) {
       const double t = -tcol[i];
@@ -656,28 +784,29 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
   __shared__ int s_bad;
   __shared__ double s_last;
   if (tid == 0) s_bad = 0;
-  double* hbuf = scr + 3 * (ws.m + 2);  // the Givens staging area is free again
-  if (scheme == kSchemeMgs1r) {
-    // h = T^T r = (I + L)^{-1} V^T A v_k, the MGS coefficients: h_i for i < k
-    // uses column i of T (rows 0..i-1 contiguous in T) plus T[i,i] r_i = r_i;
-    // h_k uses the new column, already in LDS.
-    rows_dot(ws.T, ldt, rr, k, k, [](int) { return 0; }, [](int i) { return i; }, hbuf);
-    if (tid < 64) {
+  double* hbuf = scr + 3 * M2;  // the Givens staging area is free again
+  // One-reduce MGS: h = T^T r = (I + L)^{-1} V^T A v_k, the MGS coefficients:
+  // h_i for i < k uses column i of T (rows 0..i-1) plus T[i,i] r_i = r_i; h_k
+  // uses the new column, already in LDS. CGS2: the first-pass coefficients
+  // corrected to first order, (I - L) r, with row i of L (row k is the new one).
+  if (pf.staged) {
+    for (int i = tid; i < k; i += bs) {
+      const double* row = tri + i * (i - 1) / 2;
       double a = 0.0;
-      for (int q = tid; q < k; q += 64) a += tcol[q] * rr[q];
-      a = wave_sum(a);
-      if (tid == 0) s_last = a;
+      for (int q = 0; q < i; ++q) a += row[q] * rr[q];
+      hbuf[i] = a;
     }
   } else {
-    // CGS2: first-pass coefficients corrected to first order, (I - L) r, with
-    // row i of L contiguous in TT (row k is the new one, in LDS).
-    rows_dot(ws.TT, ldt, rr, k, k, [](int) { return 0; }, [](int i) { return i; }, hbuf);
-    if (tid < 64) {
-      double a = 0.0;
-      for (int q = tid; q < k; q += 64) a += ell[q] * rr[q];
-      a = wave_sum(a);
-      if (tid == 0) s_last = a;
-    }
+    // column i of T (rows 0..i-1) is contiguous in T; row i of L in TT
+    rows_dot(scheme == kSchemeMgs1r ? ws.T : ws.TT, ldt, rr, k, k, [](int) { return 0; },
+             [](int i) { return i; }, hbuf);
+  }
+  if (tid < 64) {
+    const double* last = scheme == kSchemeMgs1r ? tcol : ell;
+    double a = 0.0;
+    for (int q = tid; q < k; q += 64) a += last[q] * rr[q];
+    a = wave_sum(a);
+    if (tid == 0) s_last = a;
   }
   __syncthreads();
   for (int i = tid; i <= k; i += bs) {
@@ -718,16 +847,16 @@ __device__ void tail_cgs2_second(const Ws& ws, const double* vals, int k) {
 }
 
 // Fused Arnoldi step for the lagged schemes, K = index of the column being
-// normalized (u = V[:,K]):
-//   HAS_SPMV: w = A u for the tile (written to ws.w and kept in LDS);
-//   sums over the tile of V_q . u and V_q . w for q < K, u.u and u.w;
-//   device-wide reduction; the last workgroup runs the tail.
-// Without HAS_SPMV (the norm-only flush, or CGS2's second projection with
-// u = z) w is zero and only the u column sums are formed.
+// normalized (u = V[:,K]). Where w comes from (WSRC):
+//   kWSpmv: w = A u for the tile, computed here (written to ws.w, kept in LDS);
+//   kWLoad: w = A u was written to ws.w by a separate SpMV launch;
+//   kWNone: w = 0 (the norm-only flush, or CGS2's second projection with u = z).
+// Then sums over the tile of V_q . u and V_q . w for q < nproj, u.u and u.w;
+// device-wide reduction; the last workgroup runs the tail.
 // RPT rows per lane, 256 threads = 4 wavefronts; lane l of wavefront wv owns
 // rows tile0 + wv*64*RPT + i*64 + l, so every column read is 512 contiguous
 // bytes per wavefront.
-template <int RPT, int S, int EPL, bool HAS_SPMV>
+template <int RPT, int S, int EPL, int WSRC>
 __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, int m_eff, int tail,
                                                 int G) {
   extern __shared__ double lds[];
@@ -748,8 +877,9 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
   const double* __restrict__ V = ws.V;
   const int64_t ldv = ws.ldv;
   const double* __restrict__ u_g = V + (size_t)K * ldv;
+  constexpr bool HAS_SPMV = WSRC != kWNone;
 
-  if constexpr (HAS_SPMV) {
+  if constexpr (WSRC == kWSpmv) {
     // SpMV of the tile (fewer rows per lane group when the tile holds fewer).
     constexpr int R0 = spmv_rows<S, EPL>();
     constexpr int RG = R0 * (256 / S) > TR ? TR / (256 / S) : R0;
@@ -765,18 +895,30 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
 
   // This lane's rows (clamped into range for loads), its u and w values;
   // rows past n carry u = w = 0 and so add nothing.
+  // Loads take a uniform base rb plus a 32-bit byte offset (rows[i]): rb is
+  // the tile's first row, or row n-1 for a padding tile past the end, so the
+  // clamped rows lie in [rb, rb + TR) and the offsets are never negative.
   double u[RPT], w[RPT];
-  int64_t rows[RPT];
+  uint32_t rows[RPT];
+  const int64_t rb = row0 < n ? row0 : n - 1;
+  const double* __restrict__ Vt = V + rb;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int lr = wv * 64 * RPT + i * 64 + lane;
     const int64_t r = row0 + lr;
     const bool ok = r < n;
-    rows[i] = ok ? r : n - 1;
-    const double uv = u_g[rows[i]];
+    rows[i] = (uint32_t)((ok ? r : n - 1) - rb) * 8u;
+    const double uv = ld_at(u_g + rb, rows[i]);
     u[i] = ok ? uv : 0.0;
-    w[i] = (HAS_SPMV && ok) ? wl[lr] : 0.0;
-    if (HAS_SPMV && ok) ws.w[r] = w[i];
+    if constexpr (WSRC == kWSpmv) {
+      w[i] = ok ? wl[lr] : 0.0;
+      if (ok) ws.w[r] = w[i];
+    } else if constexpr (WSRC == kWLoad) {
+      const double wv_ = ld_at(ws.w + rb, rows[i]);
+      w[i] = ok ? wv_ : 0.0;
+    } else {
+      w[i] = 0.0;
+    }
   }
   double* myred = red + wv * P;
 
@@ -789,7 +931,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) vv[c][i] = V[(size_t)(j0 + c) * ldv + rows[i]];
+      for (int i = 0; i < RPT; ++i) vv[c][i] = ld_at(Vt + (size_t)(j0 + c) * ldv, rows[i]);
     double acc[NVC];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
@@ -821,7 +963,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
   for (; j0 < nproj; ++j0) {
     double vv[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) vv[i] = V[(size_t)j0 * ldv + rows[i]];
+    for (int i = 0; i < RPT; ++i) vv[i] = ld_at(Vt + (size_t)j0 * ldv, rows[i]);
     double p = 0.0, c = 0.0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -853,12 +995,25 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
   const int cnt = 2 * (nproj + 1);
   for (int i = tid; i < cnt; i += 256) vals[i] = ((red[i] + red[P + i]) + red[2 * P + i]) + red[3 * P + i];
   __syncthreads();
-  if (!grid_reduce(vals, cnt, ws, tile, G, red)) return;
+  // The tile buffer wl is free now; the tail's inputs are staged there.
+  const bool norm_only = nproj < K;
+  const int M2 = ws.m + 2;
+  TailPrefetch<RPT> pf;
+  pf.ws = &ws;
+  pf.tri = wl;
+  pf.hc = scr + 3 * M2;
+  pf.csl = scr + 4 * M2;
+  pf.snl = scr + 5 * M2;
+  pf.k = K;
+  pf.scheme = tail == kTailLagged1r ? kSchemeMgs1r : kSchemeCgs2;
+  pf.active = tail != kTailCgs2Second;
+  pf.staged = K * (K - 1) / 2 <= TR;
+  pf.ntri = (pf.active && pf.staged && !norm_only) ? K * (K - 1) / 2 : 0;
+  if (!grid_reduce(vals, cnt, ws, tile, G, red, pf)) return;
   if (tail == kTailCgs2Second)
     tail_cgs2_second(ws, vals, K - 1);
   else
-    tail_lagged(ws, vals, scr, K, nproj < K, m_eff,
-                tail == kTailLagged1r ? kSchemeMgs1r : kSchemeCgs2);
+    tail_lagged(ws, vals, scr, K, norm_only, m_eff, pf.scheme, pf);
 }
 
 // ------------------------------------------------------------------ MAXPY
@@ -879,39 +1034,56 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   const double* __restrict__ cf = mode == 0 ? ws.coef : ws.coef2;
   const double invr = ws.st->inv_rho;
   // Loads at clamped rows (unconditional, so they are all in flight at once);
-  // only rows below n are stored.
+  // only rows below n are stored. Each load is a uniform column base (row rb
+  // of column q: the tile's first row, or n-1 for a padding tile past the
+  // end) plus a per-lane byte offset in [0, 8 TR), so one offset register per
+  // row serves every column.
   double acc[RPT];
-  int64_t rows[RPT];
-  const double* __restrict__ src0 = mode == 0 ? ws.w : V + (size_t)(k + 1) * ldv;
+  uint32_t off[RPT];
+  const int64_t rb = row0 < n ? row0 : n - 1;
+  const double* __restrict__ src0 = (mode == 0 ? ws.w : V + (size_t)(k + 1) * ldv) + rb;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;
-    rows[i] = r < n ? r : n - 1;
-    acc[i] = mode == 0 ? src0[rows[i]] * invr : src0[rows[i]];
+    off[i] = (uint32_t)((r < n ? r : n - 1) - rb) * 8u;
+    acc[i] = mode == 0 ? ld_at(src0, off[i]) * invr : ld_at(src0, off[i]);
   }
+  // GMRES_MAXPY_COLS columns per pass (their loads are in flight together).
+  constexpr int MC = GMRES_MAXPY_COLS;
+  const double* __restrict__ Vt = V + rb;
   int q = 0;
-  for (; q + 4 <= k; q += 4) {
-    const double c0 = cf[q], c1 = cf[q + 1], c2 = cf[q + 2], c3 = cf[q + 3];
-    double v[4][RPT];
+  for (; q + MC <= k; q += MC) {
+    double c[MC];
+    double v[MC][RPT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < MC; ++t) {
+      c[t] = cf[q + t];
+      const double* __restrict__ col = Vt + (size_t)(q + t) * ldv;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) v[t][i] = V[(size_t)(q + t) * ldv + rows[i]];
+      for (int i = 0; i < RPT; ++i) v[t][i] = ld_at(col, off[i]);
+    }
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) acc[i] = acc[i] - v[0][i] * c0 - v[1][i] * c1 - v[2][i] * c2 - v[3][i] * c3;
+    for (int i = 0; i < RPT; ++i) {
+      double a = acc[i];
+#pragma unroll
+      for (int t = 0; t < MC; ++t) a -= v[t][i] * c[t];
+      acc[i] = a;
+    }
   }
   for (; q < k; ++q) {
     const double c0 = cf[q];
+    const double* __restrict__ col = Vt + (size_t)q * ldv;
     double v[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) v[i] = V[(size_t)q * ldv + rows[i]];
+    for (int i = 0; i < RPT; ++i) v[i] = ld_at(col, off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] -= v[i] * c0;
   }
   const double ck = cf[k];
   double vk[RPT];
+  const double* __restrict__ colk = Vt + (size_t)k * ldv;
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) vk[i] = V[(size_t)k * ldv + rows[i]];
+  for (int i = 0; i < RPT; ++i) vk[i] = ld_at(colk, off[i]);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;
@@ -1099,13 +1271,17 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
   const double* __restrict__ V = ws.V;
   const int64_t ldv = ws.ldv;
   const double* __restrict__ y = ws.y;
-  int64_t rows[RPT];
+  // byte offsets from row rb (the tile's first row, or n-1 for a padding
+  // tile past the end), so they lie in [0, 8 TR)
+  const int64_t rb = row0 < n ? row0 : n - 1;
+  const double* __restrict__ Vt = V + rb;
+  uint32_t off[RPT];
   double acc[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + threadIdx.x;
-    rows[i] = r < n ? r : n - 1;
-    acc[i] = x[rows[i]];
+    off[i] = (uint32_t)((r < n ? r : n - 1) - rb) * 8u;
+    acc[i] = ld_at(x + rb, off[i]);
   }
   int q = 0;
   for (; q + 4 <= j; q += 4) {
@@ -1114,7 +1290,7 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) v[t][i] = V[(size_t)(q + t) * ldv + rows[i]];
+      for (int i = 0; i < RPT; ++i) v[t][i] = ld_at(Vt + (size_t)(q + t) * ldv, off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] = acc[i] + v[0][i] * c0 + v[1][i] * c1 + v[2][i] * c2 + v[3][i] * c3;
   }
@@ -1122,7 +1298,7 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
     const double c0 = y[q];
     double v[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) v[i] = V[(size_t)q * ldv + rows[i]];
+    for (int i = 0; i < RPT; ++i) v[i] = ld_at(Vt + (size_t)q * ldv, off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] += v[i] * c0;
   }
@@ -1174,20 +1350,21 @@ int launch_validate(const Csr& A, int64_t nnz, DevState* st, hipStream_t s) {
 
 template <int S, int EPL>
 static void spmv_s(const Csr& A, const double* x, const double* b, double* y, const DevState* st,
-                   hipStream_t s) {
+                   hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   constexpr int RPP = spmv_rows<S, EPL>() * (256 / S);
   const int64_t blocks = (A.n + RPP - 1) / RPP;
-  hipLaunchKernelGGL((k_spmv<S, EPL>), dim3((unsigned)blocks), dim3(256), 0, s, A, x, b, y, st);
+  hipExtLaunchKernelGGL((k_spmv<S, EPL>), dim3((unsigned)blocks), dim3(256), 0u, s, e0, e1, 0u, A,
+                        x, b, y, st);
 }
 
 // SpMV shapes: (S lanes per row, EPL entries per lane).
 #define GMRES_SPMV_SHAPES(X) X(1, 8) X(2, 8) X(4, 8) X(8, 4) X(8, 8) X(64, 1)
 
 int launch_spmv(const Csr& A, int shape, const double* x, const double* b, double* y,
-                const DevState* st, hipStream_t s) {
+                const DevState* st, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (shape) {
 #define GMRES_CASE(S_, E_) \
-  case S_ * 100 + E_: spmv_s<S_, E_>(A, x, b, y, st, s); break;
+  case S_ * 100 + E_: spmv_s<S_, E_>(A, x, b, y, st, s, e0, e1); break;
     GMRES_SPMV_SHAPES(GMRES_CASE)
 #undef GMRES_CASE
     default: return -2;
@@ -1199,24 +1376,27 @@ int launch_spmv(const Csr& A, int shape, const double* x, const double* b, doubl
 // The step kernels are launched with hipExtLaunchKernelGGL so that optional
 // start/stop events are attached to the dispatch itself and time the kernel
 // alone.
-template <int RPT, int S, int EPL, bool HS>
+template <int RPT, int S, int EPL, int WSRC>
 static void fused_t(const Csr& A, const Ws& ws, int K, int nproj, int m_eff, int tail, int G,
                     hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const uint32_t lds = (uint32_t)(fused_lds_doubles(RPT, ws.m) * sizeof(double));
-  hipExtLaunchKernelGGL((k_fused<RPT, S, EPL, HS>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A, ws,
+  hipExtLaunchKernelGGL((k_fused<RPT, S, EPL, WSRC>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A, ws,
                         K, nproj, m_eff, tail, G);
 }
 
 template <int RPT>
-static int fused_r(const Csr& A, int shape, bool has_spmv, const Ws& ws, int K, int nproj,
+static int fused_r(const Csr& A, int shape, int wsrc, const Ws& ws, int K, int nproj,
                    int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (!has_spmv) {
-    fused_t<RPT, 1, 1, false>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1);
+  if (wsrc != kWSpmv) {
+    if (wsrc == kWLoad)
+      fused_t<RPT, 1, 1, kWLoad>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1);
+    else
+      fused_t<RPT, 1, 1, kWNone>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1);
     return 0;
   }
   switch (shape) {
 #define GMRES_CASE(S_, E_) \
-  case S_ * 100 + E_: fused_t<RPT, S_, E_, true>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+  case S_ * 100 + E_: fused_t<RPT, S_, E_, kWSpmv>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
     GMRES_SPMV_SHAPES(GMRES_CASE)
 #undef GMRES_CASE
     default: return -2;
@@ -1224,14 +1404,14 @@ static int fused_r(const Csr& A, int shape, bool has_spmv, const Ws& ws, int K, 
   return 0;
 }
 
-int launch_fused(const Csr& A, int shape, const Ws& ws, int rpt, int K, int nproj, bool has_spmv,
+int launch_fused(const Csr& A, int shape, const Ws& ws, int rpt, int K, int nproj, int wsrc,
                  int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   int rc;
   switch (rpt) {
-    case 1: rc = fused_r<1>(A, shape, has_spmv, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 2: rc = fused_r<2>(A, shape, has_spmv, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 4: rc = fused_r<4>(A, shape, has_spmv, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    default: rc = fused_r<8>(A, shape, has_spmv, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 1: rc = fused_r<1>(A, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 2: rc = fused_r<2>(A, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 4: rc = fused_r<4>(A, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    default: rc = fused_r<8>(A, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
   }
   if (rc) return rc;
   GMRES_CHECK_LAUNCH();

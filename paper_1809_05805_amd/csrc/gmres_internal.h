@@ -79,8 +79,15 @@ int launch_cycle_begin(const Ws& ws, hipStream_t s);
 int launch_validate(const Csr& A, int64_t nnz, DevState* st, hipStream_t s);
 // SpMV shape code: 100 * (lanes per row) + (entries per lane).
 int launch_spmv(const Csr& A, int shape, const double* x, const double* b, double* y,
-                const DevState* st, hipStream_t s);
-int launch_fused(const Csr& A, int shape, const Ws& ws, int rpt, int K, int nproj, bool has_spmv,
+                const DevState* st, hipStream_t s, hipEvent_t e0 = nullptr,
+                hipEvent_t e1 = nullptr);
+// Where the fused step kernel takes w from.
+enum WSource {
+  kWNone = 0,  // w = 0: only the sums over u
+  kWSpmv = 1,  // w = A u computed in the kernel, tile by tile
+  kWLoad = 2   // w read from ws.w, written by a separate SpMV launch
+};
+int launch_fused(const Csr& A, int shape, const Ws& ws, int rpt, int K, int nproj, int wsrc,
                  int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
 int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s,

@@ -25,7 +25,7 @@ GMRES_MAX_RESTART = 256
 EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destroy",
             "gmres_status_string", "gmres_spmv", "gmres_last_cycle", "gmres_basis",
             "gmres_set_timing", "gmres_get_timing"]
-GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_COUNT = 0, 1, 2
+GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
 
 
 class GmresInfo(ctypes.Structure):
@@ -239,7 +239,8 @@ class GmresSolver:
         rc, st = gmres_get_timing(self.ctx)
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_get_timing")
-        return {"step": st[GMRES_KSTAT_STEP], "maxpy": st[GMRES_KSTAT_MAXPY]}
+        return {"step": st[GMRES_KSTAT_STEP], "maxpy": st[GMRES_KSTAT_MAXPY],
+                "spmv": st[GMRES_KSTAT_SPMV]}
 
     def basis(self):
         """V (n x (m+2)) as a view into the workspace tensor."""
