@@ -85,6 +85,16 @@ size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
  * The CSR structure is checked on the device (row_ptr[0] == 0, row_ptr[n] ==
  * nnz, non-decreasing row_ptr, 0 <= col_idx < n); a malformed matrix gives
  * GMRES_ERR_ARG and no context. On success *out holds the context.
+ * Sparse format: when padding every slice of 64 rows to its longest row adds
+ * at most a quarter to nnz (stencil and other regular matrices), the context
+ * keeps its own sliced-ELL copy of A (SELL-64: per slice, entry j of each row
+ * stored column by column; about 12 bytes per padded entry plus 8 per slice,
+ * allocated here on the device and freed by gmres_destroy) and every SpMV
+ * reads the copy, not the caller's arrays: after changing vals (same
+ * structure) call gmres_refresh_matrix. Otherwise, or if that allocation
+ * fails, the SpMV reads the caller's CSR arrays directly. gmres_get_format
+ * tells which. The arithmetic is the same either way: each row's products are
+ * summed in storage order (padding adds exact zeros).
  */
 int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
                  const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
@@ -110,8 +120,28 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
 int gmres_solve(gmres_ctx* ctx, const double* b, double* x, double rtol, int64_t max_iters,
                 gmres_info* info, double* hist_res);
 
-/* Release the context (host memory only; the workspace stays the caller's). */
+/*
+ * Release the context: its host memory and, if it made one, its sliced copy
+ * of A. The workspace and the CSR arrays stay the caller's.
+ */
 int gmres_destroy(gmres_ctx* ctx);
+
+/*
+ * Re-read A's values (and re-check its structure) after the caller changed
+ * vals in place; the structure must be the one given to gmres_create. Blocks
+ * until done. GMRES_ERR_ARG if the structure is malformed or a row no longer
+ * fits its slice of the copy: the context's matrix is then invalid, and
+ * gmres_solve and gmres_spmv return GMRES_ERR_ARG until a later refresh
+ * succeeds.
+ */
+int gmres_refresh_matrix(gmres_ctx* ctx);
+
+enum { GMRES_FORMAT_CSR = 0, GMRES_FORMAT_SELL64 = 1 };
+/*
+ * The SpMV format the context chose (GMRES_FORMAT_*) and the matrix entries
+ * it stores: nnz for CSR, nnz plus padding for SELL64.
+ */
+int gmres_get_format(gmres_ctx* ctx, int32_t* format, int64_t* stored_entries);
 
 /* Static English description of a gmres_status value. */
 const char* gmres_status_string(int status);

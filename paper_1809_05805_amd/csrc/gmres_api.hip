@@ -75,6 +75,22 @@ bool pick_split(int64_t, int64_t) {
   return false;
 }
 
+// Sparse format of the SpMV. The sliced ELL copy (SELL-64, built at create)
+// makes every column-index and value load of a wavefront one contiguous
+// 512-byte block and needs no row pointers; it is used when padding every
+// slice to its longest row costs at most a quarter more entries and no slice
+// is wider than kSellMaxWidth. GMRES_SPMV_FORMAT ("csr" or "sell") overrides
+// the choice for tuning sweeps and tests ("sell" still requires the width cap).
+constexpr int kSellMaxWidth = 4096;
+enum { kFormatCsr = 0, kFormatSell = 1 };
+int format_override() {
+  if (const char* e = getenv("GMRES_SPMV_FORMAT")) {
+    if (!strcmp(e, "csr")) return kFormatCsr;
+    if (!strcmp(e, "sell")) return kFormatSell;
+  }
+  return -1;
+}
+
 struct Layout {
   int64_t ldv;
   int rpt, G, NG, pstride;
@@ -133,6 +149,11 @@ struct gmres_ctx {
   int64_t nnz;
   int m, scheme, S;  // S: SpMV shape code
   bool split;        // separate SpMV launch in the lagged step
+  bool matrix_ok;    // false after a refresh found a bad structure: no more SpMVs
+  int format;        // kFormatCsr or kFormatSell
+  Sell sell;         // the sliced copy (format == kFormatSell)
+  void* sell_mem;    // its device allocation, owned by the context
+  int64_t sell_entries;
   Layout L;
   Ws ws;
   hipStream_t stream;
@@ -226,6 +247,76 @@ void collect_timing(gmres_ctx* c, int j, bool stopped_at_restart) {
   c->recs.clear();
 }
 
+// Build the sliced copy of A when the format choice asks for it (else the
+// context keeps the CSR format): slice widths on the device, offsets on the
+// host, one device allocation for offsets, indices and values, then the copy.
+// An allocation failure leaves the CSR format in place.
+int build_format(gmres_ctx* c) {
+  c->format = kFormatCsr;
+  c->sell = Sell{nullptr, nullptr, nullptr, 0};
+  c->sell_mem = nullptr;
+  c->sell_entries = 0;
+  const int want = format_override();
+  if (want == kFormatCsr || c->nnz == 0) return GMRES_OK;
+  const int64_t ns = (c->A.n + 63) / 64;
+  int* dw = nullptr;
+  if (hipMalloc((void**)&dw, sizeof(int) * (size_t)ns) != hipSuccess) {
+    (void)hipGetLastError();
+    return GMRES_OK;
+  }
+  std::vector<int> wh((size_t)ns);
+  int rc = GMRES_OK;
+  if (launch_sell_width(c->A, ns, dw, c->stream) ||
+      hipMemcpyAsync(wh.data(), dw, sizeof(int) * (size_t)ns, hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    rc = GMRES_ERR_HIP;
+  (void)hipFree(dw);
+  if (rc) return rc;
+  std::vector<int64_t> sp((size_t)ns + 1);
+  sp[0] = 0;
+  int wmax = 0;
+  for (int64_t i = 0; i < ns; ++i) {
+    sp[i + 1] = sp[i] + 64 * (int64_t)wh[i];
+    if (wh[i] > wmax) wmax = wh[i];
+  }
+  const int64_t total = sp[ns];
+  const bool cheap = total * 4 <= c->nnz * 5;
+  if (wmax > kSellMaxWidth || (want != kFormatSell && !cheap)) return GMRES_OK;
+  const size_t o_ci = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
+  const size_t o_va = round_up(o_ci + sizeof(int) * (size_t)total, kAlign);
+  const size_t bytes = o_va + sizeof(double) * (size_t)total;
+  if (hipMalloc(&c->sell_mem, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    c->sell_mem = nullptr;
+    return GMRES_OK;
+  }
+  char* base = (char*)c->sell_mem;
+  c->sell = Sell{(const int64_t*)base, (int*)(base + o_ci), (double*)(base + o_va), ns};
+  if (hipMemcpyAsync(base, sp.data(), sizeof(int64_t) * (size_t)(ns + 1), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      launch_sell_fill(c->A, c->sell, c->ws.st, c->stream))
+    rc = GMRES_ERR_HIP;
+  if (rc == GMRES_OK) rc = sync_state(c, false);
+  if (rc == GMRES_OK && c->h_st->bad_csr) rc = GMRES_ERR_ARG;
+  if (rc != GMRES_OK) {
+    (void)hipFree(c->sell_mem);
+    c->sell_mem = nullptr;
+    c->sell = Sell{nullptr, nullptr, nullptr, 0};
+    return rc;
+  }
+  c->format = kFormatSell;
+  c->sell_entries = total;
+  return GMRES_OK;
+}
+
+// y = A x or y = b - A x in the context's format.
+int spmv(gmres_ctx* c, const double* x, const double* b, double* y, const DevState* st,
+         hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (c->format == kFormatSell) return launch_spmv_sell(c->sell, c->A.n, x, b, y, st, s, e0, e1);
+  return launch_spmv(c->A, c->S, x, b, y, st, s, e0, e1);
+}
+
 // Enqueue one restart cycle with m_eff >= 1 columns at most.
 int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
   const Ws& ws = c->ws;
@@ -235,14 +326,14 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
   const double csr = 12.0 * (double)c->nnz + 4.0 * (double)(c->A.n + 1);
   auto col = [&](int q) { return ws.V + (size_t)q * (size_t)ws.ldv; };
   TRY(launch_cycle_begin(ws, s));
-  TRY(launch_spmv(c->A, c->S, x, b, col(0), nullptr, s));  // V[:,0] = b - A x
+  TRY(spmv(c, x, b, col(0), nullptr, s));  // V[:,0] = b - A x
   if (c->scheme == kSchemeMgs) {
     TRY(launch_axpy_dot(ws, rpt, col(0), nullptr, nullptr, col(0), kTailMgsBeta, 0, 0, m_eff, 0.0,
                         G, s));
     TRY(launch_scale(ws, col(0), s));
     for (int i = 0; i < m_eff; ++i) {
       double* w = col(i + 1);
-      TRY(launch_spmv(c->A, c->S, col(i), nullptr, w, ws.st, s));
+      TRY(spmv(c, col(i), nullptr, w, ws.st, s));
       for (int q = 0; q <= i; ++q) {
         const double* a = q > 0 ? col(q - 1) : nullptr;
         const double* cf = q > 0 ? ws.H + (size_t)i * ws.ldh + (q - 1) : nullptr;
@@ -260,16 +351,16 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
       {
         // The last step of a cycle only finishes the lagged norm of column m_eff.
         const bool last = k == m_eff;
-        int wsrc = last ? kWNone : kWSpmv;
+        int wsrc = last ? kWNone : (c->format == kFormatSell ? kWSell : kWSpmv);
         double bytes = last ? n8 : csr + n8 * (k + 1) + n8;
         if (!last && c->split) {
           TimedLaunch t(c, GMRES_KSTAT_SPMV, k, k, csr + 2 * n8);
-          TRY(launch_spmv(c->A, c->S, col(k), nullptr, ws.w, ws.st, s, t.e0, t.e1));
+          TRY(spmv(c, col(k), nullptr, ws.w, ws.st, s, t.e0, t.e1));
           wsrc = kWLoad;
           bytes = n8 * (k + 2);
         }
         TimedLaunch t(c, GMRES_KSTAT_STEP, k, k, bytes);
-        TRY(launch_fused(c->A, c->S, ws, rpt, k, last ? 0 : k, wsrc, m_eff, tail, G, s, t.e0,
+        TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k, last ? 0 : k, wsrc, m_eff, tail, G, s, t.e0,
                          t.e1));
       }
       if (k == m_eff) break;
@@ -280,7 +371,7 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
       if (c->scheme == kSchemeCgs2) {
         {
           TimedLaunch t(c, GMRES_KSTAT_STEP, k, k + 1, n8 * (k + 2));
-          TRY(launch_fused(c->A, c->S, ws, rpt, k + 1, k + 1, kWNone, m_eff, kTailCgs2Second, G, s,
+          TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k + 1, k + 1, kWNone, m_eff, kTailCgs2Second, G, s,
                            t.e0, t.e1));
         }
         TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
@@ -296,7 +387,7 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
 int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
   const Ws& ws = c->ws;
   TRY(launch_cycle_begin(ws, c->stream));
-  TRY(launch_spmv(c->A, c->S, x, b, ws.w, nullptr, c->stream));
+  TRY(spmv(c, x, b, ws.w, nullptr, c->stream));
   TRY(launch_axpy_dot(ws, c->L.rpt, ws.w, nullptr, nullptr, ws.w, kTailFinalRes, 0, 0, 0, 0.0,
                       c->L.G, c->stream));
   return GMRES_OK;
@@ -395,11 +486,15 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   memset(c->stats, 0, sizeof(c->stats));
 
   int rc = GMRES_OK;
+  c->sell_mem = nullptr;
+  c->matrix_ok = true;
   if (launch_init(ws, L.NG + 1, c->stream) || launch_validate(c->A, nnz, ws.st, c->stream))
     rc = GMRES_ERR_HIP;
   if (rc == GMRES_OK) rc = sync_state(c, false);
   if (rc == GMRES_OK && c->h_st->bad_csr) rc = GMRES_ERR_ARG;
+  if (rc == GMRES_OK) rc = build_format(c);
   if (rc != GMRES_OK) {
+    if (c->sell_mem) (void)hipFree(c->sell_mem);
     (void)hipHostFree(c->pinned);
     delete c;
     return rc;
@@ -412,14 +507,37 @@ int gmres_destroy(gmres_ctx* c) {
   if (!c) return GMRES_ERR_ARG;
   int rc = GMRES_OK;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->sell_mem && hipFree(c->sell_mem) != hipSuccess) rc = GMRES_ERR_HIP;
   if (c->pinned && hipHostFree(c->pinned) != hipSuccess) rc = GMRES_ERR_HIP;
   delete c;
   return rc;
 }
 
+int gmres_refresh_matrix(gmres_ctx* c) {
+  if (!c) return GMRES_ERR_ARG;
+  if (hipMemsetAsync(&c->ws.st->bad_csr, 0, sizeof(int32_t), c->stream) != hipSuccess ||
+      launch_validate(c->A, c->nnz, c->ws.st, c->stream))
+    return GMRES_ERR_HIP;
+  if (c->format == kFormatSell && launch_sell_fill(c->A, c->sell, c->ws.st, c->stream))
+    return GMRES_ERR_HIP;
+  c->matrix_ok = false;
+  const int rc = sync_state(c, false);
+  if (rc != GMRES_OK) return rc;
+  if (c->h_st->bad_csr) return GMRES_ERR_ARG;
+  c->matrix_ok = true;
+  return GMRES_OK;
+}
+
+int gmres_get_format(gmres_ctx* c, int32_t* format, int64_t* stored_entries) {
+  if (!c || !format || !stored_entries) return GMRES_ERR_ARG;
+  *format = c->format == kFormatSell ? GMRES_FORMAT_SELL64 : GMRES_FORMAT_CSR;
+  *stored_entries = c->format == kFormatSell ? c->sell_entries : c->nnz;
+  return GMRES_OK;
+}
+
 int gmres_spmv(gmres_ctx* c, const double* x, double* y) {
-  if (!c || !x || !y || x == y) return GMRES_ERR_ARG;
-  return launch_spmv(c->A, c->S, x, nullptr, y, nullptr, c->stream) ? GMRES_ERR_HIP : GMRES_OK;
+  if (!c || !x || !y || x == y || !c->matrix_ok) return GMRES_ERR_ARG;
+  return spmv(c, x, nullptr, y, nullptr, c->stream) ? GMRES_ERR_HIP : GMRES_OK;
 }
 
 int gmres_basis(gmres_ctx* c, double** V, int64_t* ldv) {
@@ -457,7 +575,7 @@ int gmres_solve(gmres_ctx* c, const double* b, double* x, double rtol, int64_t m
   gmres_info loc;
   memset(&loc, 0, sizeof(loc));
   if (info) *info = loc;
-  if (!c || !b || !x || !(rtol >= 0.0) || max_iters < 0) return GMRES_ERR_ARG;
+  if (!c || !b || !x || !(rtol >= 0.0) || max_iters < 0 || !c->matrix_ok) return GMRES_ERR_ARG;
   if (!is_device_ptr(b) || !is_device_ptr(x)) return GMRES_ERR_ARG;
   const Ws& ws = c->ws;
   hipStream_t s = c->stream;

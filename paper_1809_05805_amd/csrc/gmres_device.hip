@@ -582,6 +582,124 @@ __global__ __launch_bounds__(256) void k_spmv(Csr A, const double* __restrict__ 
   });
 }
 
+// ------------------------------------------------ sliced ELL copy of A
+
+// Width of each slice, max(1, longest row): wavefront per slice, lane per row.
+__global__ __launch_bounds__(256) void k_sell_width(Csr A, int64_t ns, int* __restrict__ width) {
+  const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= ns) return;  // uniform over the wavefront
+  const int64_t r = s * 64 + (threadIdx.x & 63);
+  int len = r < A.n ? A.rp[r + 1] - A.rp[r] : 0;
+  for (int mask = 32; mask >= 1; mask >>= 1) len = max(len, __shfl_xor(len, mask, 64));
+  if ((threadIdx.x & 63) == 0) width[s] = len < 1 ? 1 : len;
+}
+
+// Copy of A into the slices (sp already set), thread per row. A row whose
+// entries are not inside [0, nnz) or that is longer than its slice (a changed
+// structure; the copy can run right behind a structure check on the stream)
+// sets st->bad_csr and is not read.
+__global__ __launch_bounds__(256) void k_sell_fill(Csr A, Sell S, DevState* st) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t s = r >> 6;
+  if (s >= S.ns) return;
+  const int l = (int)(r & 63);
+  const int64_t b = S.sp[s];
+  const int W = (int)((S.sp[s + 1] - b) >> 6);
+  const int64_t e0 = r < A.n ? A.rp[r] : 0;
+  const int64_t e1 = r < A.n ? A.rp[r + 1] : 0;
+  int len = (int)(e1 - e0);
+  if (e0 < 0 || e1 < e0 || e1 > A.nnz || len > W) {
+    atomicOr(&st->bad_csr, 1);
+    len = 0;
+  }
+  const int self = r < A.n ? (int)r : 0;
+  for (int j = 0; j < W; ++j) {
+    const int64_t e = b + (int64_t)j * 64 + l;
+    const bool real = j < len;
+    S.ci[e] = real ? A.ci[e0 + j] : self;
+    S.va[e] = real ? A.va[e0 + j] : 0.0;
+  }
+}
+
+// Entries j0 .. j0+U-1 of lane l's row in the slice at entry offset b, width
+// W (>= 1): indices past W are clamped to W-1 (their products are masked by
+// the caller). Loads are a uniform base plus a 32-bit byte offset.
+template <int U>
+__device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l, int (&c)[U],
+                                 double (&v)[U]) {
+  const int* __restrict__ cb = S.ci + b;
+  const double* __restrict__ vb = S.va + b;
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    const int j = j0 + t < W ? j0 + t : W - 1;
+    const uint32_t e = (uint32_t)(j * 64 + l);
+    c[t] = *reinterpret_cast<const int*>(reinterpret_cast<const char*>(cb) + e * 4u);
+    v[t] = ld_at(vb, e * 8u);
+  }
+}
+
+// out[i] = (A x) at row 64 (s0 + i) + l, i < NS, for the lane's row in NS
+// consecutive slices (slice indices past the last are clamped; the caller
+// drops those rows). U entries per chunk; the column and value loads of the
+// next chunk (of this slice or the next) are issued before the gathers of
+// the current one are consumed, so one memory latency per chunk is hidden.
+template <int NS, int U>
+__device__ inline void sell_slices(const Sell& S, const double* __restrict__ x, int64_t s0, int l,
+                                   double (&out)[NS]) {
+  auto clampslice = [&](int64_t s) { return s < S.ns ? s : S.ns - 1; };
+  int64_t b = S.sp[clampslice(s0)];
+  int W = (int)((S.sp[clampslice(s0) + 1] - b) >> 6);
+  int c[U];
+  double v[U];
+  sell_load<U>(S, b, W, 0, l, c, v);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    int64_t bn = b;
+    int Wn = W;
+    if (i + 1 < NS) {
+      const int64_t sn = clampslice(s0 + i + 1);
+      bn = S.sp[sn];
+      Wn = (int)((S.sp[sn + 1] - bn) >> 6);
+    }
+    double acc = 0.0;
+    for (int j0 = 0; j0 < W; j0 += U) {
+      double xv[U], vv[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        xv[t] = x[c[t]];
+        vv[t] = v[t];
+      }
+      if (j0 + U < W)
+        sell_load<U>(S, b, W, j0 + U, l, c, v);
+      else if (i + 1 < NS)
+        sell_load<U>(S, bn, Wn, 0, l, c, v);
+#pragma unroll
+      for (int t = 0; t < U; ++t) acc += (j0 + t < W) ? vv[t] * xv[t] : 0.0;
+    }
+    out[i] = acc;
+    b = bn;
+    W = Wn;
+  }
+}
+
+// y = A x (b == nullptr) or y = b - A x from the sliced copy: each wavefront
+// takes NS consecutive slices. Skipped when a state is given and its cycle is done.
+template <int NS>
+__global__ __launch_bounds__(256) void k_spmv_sell(Sell S, int64_t n, const double* __restrict__ x,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ y, const DevState* st) {
+  if (st && st->done) return;
+  const int l = threadIdx.x & 63;
+  const int64_t s0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * NS;
+  double out[NS];
+  sell_slices<NS, 8>(S, x, s0, l, out);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const int64_t r = (s0 + i) * 64 + l;
+    if (r < n) y[r] = b ? b[r] - out[i] : out[i];
+  }
+}
+
 // ------------------------------------------------ the fused projection step
 
 // Dynamic LDS layout of k_fused (doubles):
@@ -857,8 +975,8 @@ __device__ void tail_cgs2_second(const Ws& ws, const double* vals, int k) {
 // rows tile0 + wv*64*RPT + i*64 + l, so every column read is 512 contiguous
 // bytes per wavefront.
 template <int RPT, int S, int EPL, int WSRC>
-__global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, int m_eff, int tail,
-                                                int G) {
+__global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int nproj, int m_eff,
+                                                int tail, int G) {
   extern __shared__ double lds[];
   constexpr int TR = 256 * RPT;
   constexpr int CB = GMRES_PROJ_COLS;  // columns per butterfly chunk
@@ -878,6 +996,9 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
   const int64_t ldv = ws.ldv;
   const double* __restrict__ u_g = V + (size_t)K * ldv;
   constexpr bool HAS_SPMV = WSRC != kWNone;
+  // kWSell: the lane's rows are row 64 s + lane of slices s = row0/64 + wv RPT + i
+  double ws_out[RPT];
+  if constexpr (WSRC == kWSell) sell_slices<RPT, 8>(SA, u_g, (row0 >> 6) + wv * RPT, lane, ws_out);
 
   if constexpr (WSRC == kWSpmv) {
     // SpMV of the tile (fewer rows per lane group when the tile holds fewer).
@@ -912,6 +1033,9 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Ws ws, int K, int nproj, i
     u[i] = ok ? uv : 0.0;
     if constexpr (WSRC == kWSpmv) {
       w[i] = ok ? wl[lr] : 0.0;
+      if (ok) ws.w[r] = w[i];
+    } else if constexpr (WSRC == kWSell) {
+      w[i] = ok ? ws_out[i] : 0.0;
       if (ok) ws.w[r] = w[i];
     } else if constexpr (WSRC == kWLoad) {
       const double wv_ = ld_at(ws.w + rb, rows[i]);
@@ -1373,30 +1497,56 @@ int launch_spmv(const Csr& A, int shape, const double* x, const double* b, doubl
   return 0;
 }
 
+int launch_sell_width(const Csr& A, int64_t ns, int* width, hipStream_t s) {
+  const int64_t blocks = (ns + 3) / 4;
+  hipLaunchKernelGGL(k_sell_width, dim3((unsigned)blocks), dim3(256), 0, s, A, ns, width);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s) {
+  const int64_t blocks = (S.ns * 64 + 255) / 256;
+  hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)blocks), dim3(256), 0, s, A, S, st);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+// Two slices per wavefront, four wavefronts per workgroup.
+int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b, double* y,
+                     const DevState* st, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  constexpr int NS = 2;
+  const int64_t blocks = (S.ns + 4 * NS - 1) / (4 * NS);
+  hipExtLaunchKernelGGL(k_spmv_sell<NS>, dim3((unsigned)blocks), dim3(256), 0u, s, e0, e1, 0u, S,
+                        n, x, b, y, st);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
 // The step kernels are launched with hipExtLaunchKernelGGL so that optional
 // start/stop events are attached to the dispatch itself and time the kernel
 // alone.
 template <int RPT, int S, int EPL, int WSRC>
-static void fused_t(const Csr& A, const Ws& ws, int K, int nproj, int m_eff, int tail, int G,
-                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static void fused_t(const Csr& A, const Sell& SA, const Ws& ws, int K, int nproj, int m_eff,
+                    int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const uint32_t lds = (uint32_t)(fused_lds_doubles(RPT, ws.m) * sizeof(double));
-  hipExtLaunchKernelGGL((k_fused<RPT, S, EPL, WSRC>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A, ws,
-                        K, nproj, m_eff, tail, G);
+  hipExtLaunchKernelGGL((k_fused<RPT, S, EPL, WSRC>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A,
+                        SA, ws, K, nproj, m_eff, tail, G);
 }
 
 template <int RPT>
-static int fused_r(const Csr& A, int shape, int wsrc, const Ws& ws, int K, int nproj,
-                   int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (wsrc != kWSpmv) {
-    if (wsrc == kWLoad)
-      fused_t<RPT, 1, 1, kWLoad>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1);
-    else
-      fused_t<RPT, 1, 1, kWNone>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1);
-    return 0;
+static int fused_r(const Csr& A, const Sell& SA, int shape, int wsrc, const Ws& ws, int K,
+                   int nproj, int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0,
+                   hipEvent_t e1) {
+  switch (wsrc) {
+    case kWNone: fused_t<RPT, 1, 1, kWNone>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
+    case kWLoad: fused_t<RPT, 1, 1, kWLoad>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
+    case kWSell: fused_t<RPT, 1, 1, kWSell>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
+    case kWSpmv: break;
+    default: return -2;
   }
   switch (shape) {
 #define GMRES_CASE(S_, E_) \
-  case S_ * 100 + E_: fused_t<RPT, S_, E_, kWSpmv>(A, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+  case S_ * 100 + E_: fused_t<RPT, S_, E_, kWSpmv>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
     GMRES_SPMV_SHAPES(GMRES_CASE)
 #undef GMRES_CASE
     default: return -2;
@@ -1404,14 +1554,15 @@ static int fused_r(const Csr& A, int shape, int wsrc, const Ws& ws, int K, int n
   return 0;
 }
 
-int launch_fused(const Csr& A, int shape, const Ws& ws, int rpt, int K, int nproj, int wsrc,
-                 int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K, int nproj,
+                 int wsrc, int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0,
+                 hipEvent_t e1) {
   int rc;
   switch (rpt) {
-    case 1: rc = fused_r<1>(A, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 2: rc = fused_r<2>(A, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 4: rc = fused_r<4>(A, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    default: rc = fused_r<8>(A, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 1: rc = fused_r<1>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 2: rc = fused_r<2>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 4: rc = fused_r<4>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    default: rc = fused_r<8>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
   }
   if (rc) return rc;
   GMRES_CHECK_LAUNCH();

@@ -49,6 +49,17 @@ struct Csr {
   int64_t nnz;
 };
 
+// Sliced ELL copy of A owned by the library (SELL-64): slice s holds rows
+// 64 s .. 64 s + 63; entry j of row 64 s + l is at sp[s] + 64 j + l, for
+// j < W_s = (sp[s+1] - sp[s]) / 64 (at least 1). Padding entries hold value 0
+// and the row's own index (0 for rows past n).
+struct Sell {
+  const int64_t* sp;  // ns + 1 slice offsets (entries)
+  int* ci;
+  double* va;
+  int64_t ns;         // slices, ceil(n / 64)
+};
+
 // Views into the caller's workspace.
 struct Ws {
   double* V;         // n x (m+2), column-major, leading dimension ldv
@@ -84,11 +95,19 @@ int launch_spmv(const Csr& A, int shape, const double* x, const double* b, doubl
 // Where the fused step kernel takes w from.
 enum WSource {
   kWNone = 0,  // w = 0: only the sums over u
-  kWSpmv = 1,  // w = A u computed in the kernel, tile by tile
-  kWLoad = 2   // w read from ws.w, written by a separate SpMV launch
+  kWSpmv = 1,  // w = A u computed in the kernel from the CSR arrays
+  kWLoad = 2,  // w read from ws.w, written by a separate SpMV launch
+  kWSell = 3   // w = A u computed in the kernel from the sliced ELL copy
 };
-int launch_fused(const Csr& A, int shape, const Ws& ws, int rpt, int K, int nproj, int wsrc,
-                 int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0 = nullptr,
+// Sliced ELL construction: slice widths, then (with sp filled in) the copy;
+// rows longer than their slice's width set st->bad_csr.
+int launch_sell_width(const Csr& A, int64_t ns, int* width, hipStream_t s);
+int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s);
+int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b, double* y,
+                     const DevState* st, hipStream_t s, hipEvent_t e0 = nullptr,
+                     hipEvent_t e1 = nullptr);
+int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K, int nproj,
+                 int wsrc, int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
 int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s,
                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

@@ -24,7 +24,8 @@ GMRES_MAX_RESTART = 256
 
 EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destroy",
             "gmres_status_string", "gmres_spmv", "gmres_last_cycle", "gmres_basis",
-            "gmres_set_timing", "gmres_get_timing"]
+            "gmres_set_timing", "gmres_get_timing", "gmres_refresh_matrix", "gmres_get_format"]
+GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64 = 0, 1
 GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
 
 
@@ -75,6 +76,10 @@ def load() -> ctypes.CDLL:
     lib.gmres_set_timing.argtypes = [P, ctypes.c_int]
     lib.gmres_get_timing.restype = ctypes.c_int
     lib.gmres_get_timing.argtypes = [P, ctypes.POINTER(GmresKernelStat)]
+    lib.gmres_refresh_matrix.restype = ctypes.c_int
+    lib.gmres_refresh_matrix.argtypes = [P]
+    lib.gmres_get_format.restype = ctypes.c_int
+    lib.gmres_get_format.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
     _lib = lib
     return lib
 
@@ -110,6 +115,16 @@ def gmres_destroy(ctx) -> int:
 
 def gmres_spmv(ctx, x_ptr, y_ptr) -> int:
     return load().gmres_spmv(ctx, x_ptr, y_ptr)
+
+
+def gmres_refresh_matrix(ctx) -> int:
+    return load().gmres_refresh_matrix(ctx)
+
+
+def gmres_get_format(ctx):
+    fmt, stored = ctypes.c_int32(), ctypes.c_int64()
+    rc = load().gmres_get_format(ctx, ctypes.byref(fmt), ctypes.byref(stored))
+    return rc, fmt.value, stored.value
 
 
 def gmres_last_cycle(ctx, m: int):
@@ -223,6 +238,19 @@ class GmresSolver:
         rc = gmres_spmv(self.ctx, x.data_ptr(), y.data_ptr())
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_spmv")
+
+    def refresh_matrix(self):
+        """Re-read A's values after they were changed in place (same structure)."""
+        rc = gmres_refresh_matrix(self.ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_refresh_matrix")
+
+    def format(self):
+        """("csr" | "sell64", stored entries) of the context's SpMV."""
+        rc, fmt, stored = gmres_get_format(self.ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_get_format")
+        return ("sell64" if fmt == GMRES_FORMAT_SELL64 else "csr"), stored
 
     def last_cycle(self):
         rc, H, T, g, j = gmres_last_cycle(self.ctx, self.m)

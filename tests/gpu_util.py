@@ -2,6 +2,8 @@
 
 from __future__ import annotations
 
+import contextlib
+import os
 import sys
 
 import numpy as np
@@ -22,8 +24,25 @@ def dev(p):
             torch.from_numpy(p.vals).cuda())
 
 
-def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis=False):
-    """One solve through the C ABI; returns a dict with x, info, hist and the last cycle."""
+@contextlib.contextmanager
+def spmv_format(fmt):
+    """Force the library's SpMV format ("csr" or "sell") for contexts created inside."""
+    old = os.environ.get("GMRES_SPMV_FORMAT")
+    if fmt is not None:
+        os.environ["GMRES_SPMV_FORMAT"] = fmt
+    try:
+        yield
+    finally:
+        if fmt is not None:
+            if old is None:
+                del os.environ["GMRES_SPMV_FORMAT"]
+            else:
+                os.environ["GMRES_SPMV_FORMAT"] = old
+
+
+def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis=False, fmt=None):
+    """One solve through the C ABI; returns a dict with x, info, hist and the last cycle.
+    fmt: None (the library's choice), "csr" or "sell"."""
     import torch
 
     from paper_1809_05805_amd.native import GmresSolver
@@ -32,7 +51,8 @@ def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis
     rtol = p.rtol if rtol is None else rtol
     max_iters = min(10 * p.n, 10**6) if max_iters is None else max_iters
     rp, ci, va = dev(p)
-    s = GmresSolver(rp, ci, va, m, scheme)
+    with spmv_format(fmt):
+        s = GmresSolver(rp, ci, va, m, scheme)
     bt = torch.from_numpy(np.ascontiguousarray(p.b if b is None else b)).cuda()
     xt = torch.from_numpy(np.array(p.x0 if x0 is None else x0, dtype=np.float64)).cuda()
     r = s.solve(bt, xt, rtol, max_iters, hist=True)
@@ -56,4 +76,4 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-__all__ = ["log", "dev", "gpu_run", "oracle_run", "rel", "D"]
+__all__ = ["log", "dev", "gpu_run", "oracle_run", "rel", "spmv_format", "D"]

@@ -1,0 +1,130 @@
+"""The library's SpMV format: which one it picks, and its sliced copy of A.
+
+A context keeps a sliced-ELL copy of A (64 rows per slice, each row padded to
+its slice's longest row) when that costs at most a quarter more entries, and
+otherwise reads the CSR arrays. These tests check the choice on regular and
+irregular matrices, the stored-entry count against a count made here from
+the row lengths, and that gmres_refresh_matrix picks up new values (the solve
+then matches the oracle on the changed matrix) and refuses a structure that
+no longer fits the copy.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1809_05805_amd import problems as P
+from tests.gpu_util import gpu_run, log, oracle_run, rel, spmv_format
+
+pytestmark = pytest.mark.gpu
+
+
+def padded_entries(p):
+    """Entries of the 64-row sliced layout: per slice 64 x max(1, longest row)."""
+    lens = np.diff(p.row_ptr)
+    ns = (p.n + 63) // 64
+    pad = np.zeros(ns * 64, dtype=np.int64)
+    pad[: p.n] = lens
+    return int(64 * np.maximum(pad.reshape(ns, 64).max(axis=1), 1).sum())
+
+
+def solver(p, m=10, scheme="mgs1r", fmt=None):
+    import torch
+
+    from paper_1809_05805_amd.native import GmresSolver
+
+    rp, ci, va = (torch.from_numpy(np.array(a)).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
+    with spmv_format(fmt):
+        s = GmresSolver(rp, ci, va, m, scheme)
+    return s, (rp, ci, va)
+
+
+def test_format_choice():
+    import scipy.sparse as sp
+
+    cases = {
+        "cfg1": (P.make_config("cfg1"), "sell64"),                  # 5-point rows
+        "cfg2_24": (P.make_config("cfg2", N=24), "sell64"),         # 7-point rows
+        "cfg3_12": (P.make_config("cfg3", N=12), "sell64"),         # 27-point rows
+        "dense50": (P.random_dense(50, seed=3), "csr"),             # one slice, 14 padding rows
+    }
+    A = sp.csr_matrix(sp.random(3000, 3000, density=0.003, random_state=4) + sp.identity(3000))
+    rp, ci, va = P.csr_from_scipy(A)
+    cases["irregular"] = (P.Problem("irregular", rp, ci, va, np.ones(3000), np.zeros(3000), None,
+                                    10, 0.0), "csr")
+    for name, (p, want) in cases.items():
+        s, _ = solver(p)
+        fmt, stored = s.format()
+        log(f"format {name}: {fmt} stored={stored} nnz={p.nnz} padded={padded_entries(p)}")
+        assert fmt == want, name
+        assert stored == (padded_entries(p) if fmt == "sell64" else p.nnz)
+        s.close()
+
+
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
+def test_refresh_matrix(fmt):
+    """Scale two rows' values in place: after refresh the solve is the one on the new matrix."""
+    import torch
+
+    p = P.make_config("cfg1", N=40)
+    s, (rp, ci, va) = solver(p, m=20, fmt=fmt)
+    log(f"refresh {fmt}")
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    s.solve(b, x, 0.0, 20)
+    vals2 = p.vals.copy()
+    for r in (3, p.n - 2):
+        vals2[p.row_ptr[r]:p.row_ptr[r + 1]] *= 3.0
+    va.copy_(torch.from_numpy(vals2))
+    s.refresh_matrix()
+    x.zero_()
+    r = s.solve(b, x, 0.0, 20)
+    q = P.Problem("scaled", p.row_ptr, p.col_idx, vals2, p.b, p.x0, None, 20, 0.0)
+    o = oracle_run(q, "mgs1r", m=20, rtol=0.0, max_iters=20, dump=False)
+    assert r.iters == o.iters == 20
+    assert rel(x.cpu().numpy(), o.x) <= 1e-10
+
+
+def test_refresh_refuses_bad_structure():
+    import torch
+
+    from paper_1809_05805_amd import native
+    from paper_1809_05805_amd.native import GmresError
+
+    p = P.make_config("cfg1", N=40)
+    s, (rp, ci, va) = solver(p, fmt="sell")
+    log("refresh bad structure")
+    bad = p.col_idx.copy()
+    bad[9] = p.n
+    ci.copy_(torch.from_numpy(bad))
+    with pytest.raises(GmresError) as e:
+        s.refresh_matrix()
+    assert e.value.rc == native.GMRES_ERR_ARG
+    # the context refuses to run on the refused matrix ...
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(GmresError) as e:
+        s.solve(b, x, 1e-8, 10)
+    assert e.value.rc == native.GMRES_ERR_ARG
+    # ... until the structure is restored and refreshed
+    ci.copy_(torch.from_numpy(p.col_idx))
+    s.refresh_matrix()
+    r = s.solve(b, x, 0.0, 10)
+    assert r.iters == 10
+    s.close()
+
+
+@pytest.mark.parametrize("scheme", ["mgs1r", "cgs2"])
+def test_sell_small_and_one_row(scheme):
+    """The sliced copy on sizes that leave most of the one slice as padding."""
+    import scipy.sparse as sp
+
+    rp, ci, va = P.csr_from_scipy(sp.csr_matrix(np.array([[3.0]])))
+    p = P.Problem("one", rp, ci, va, np.array([6.0]), np.zeros(1), np.array([2.0]), m=1, rtol=1e-12)
+    g = gpu_run(p, scheme, fmt="sell")
+    assert g["solver"].format()[0] == "sell64"
+    assert g["res"].converged and abs(g["x"][0] - 2.0) <= 1e-15
+    p = P.make_config("cfg1", N=5)  # n = 25
+    g = gpu_run(p, scheme, m=10, rtol=0.0, max_iters=10, fmt="sell")
+    o = oracle_run(p, scheme, m=10, rtol=0.0, max_iters=10)
+    assert g["res"].iters == o.iters
+    assert rel(g["x"], o.x) <= 1e-10

@@ -17,11 +17,12 @@ import numpy as np
 import pytest
 
 from paper_1809_05805_amd import problems as P
-from tests.gpu_util import D, gpu_run, log, oracle_run, rel
+from tests.gpu_util import D, gpu_run, log, oracle_run, rel, spmv_format
 
 pytestmark = pytest.mark.gpu
 
 SCHEMES = ["mgs", "mgs1r", "cgs2"]
+FORMATS = ["csr", "sell"]
 TOL = 1e-10
 
 
@@ -48,17 +49,20 @@ def _torch_cuda():
     yield
 
 
+@pytest.mark.parametrize("fmt", FORMATS)
 @pytest.mark.parametrize("case", list(CASES))
-def test_spmv_matches_oracle(case):
+def test_spmv_matches_oracle(case, fmt):
     import torch
 
     from paper_1809_05805_amd.native import GmresSolver
     import oracle
 
     p = CASES[case]
-    log(f"spmv {case} n={p.n}")
+    log(f"spmv {case} {fmt} n={p.n}")
     rp, ci, va = (torch.from_numpy(a).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
-    s = GmresSolver(rp, ci, va, 4, "mgs1r")
+    with spmv_format(fmt):
+        s = GmresSolver(rp, ci, va, 4, "mgs1r")
+    assert s.format()[0] == {"csr": "csr", "sell": "sell64"}[fmt]
     x = P.rng(77, 0).standard_normal(p.n)
     y = torch.empty(p.n, dtype=torch.float64, device="cuda")
     s.spmv(torch.from_numpy(x).cuda(), y)
@@ -70,14 +74,16 @@ def test_spmv_matches_oracle(case):
     assert np.all(np.abs(y.cpu().numpy() - ref) <= bound + 1e-300)
 
 
+@pytest.mark.parametrize("fmt", FORMATS)
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("case", list(CASES))
-def test_fixed_budget_cycle_parity(scheme, case):
-    """One full cycle, no early exit: H, x and |g_k| match the oracle to 1e-10."""
+def test_fixed_budget_cycle_parity(scheme, case, fmt):
+    """One full cycle, no early exit: H, x and |g_k| match the oracle to 1e-10
+    with either SpMV format."""
     p = CASES[case]
     m = min(p.m, 40)
-    log(f"fixed-budget {scheme} {case} n={p.n} m={m}")
-    g = gpu_run(p, scheme, m=m, rtol=0.0, max_iters=m)
+    log(f"fixed-budget {scheme} {case} {fmt} n={p.n} m={m}")
+    g = gpu_run(p, scheme, m=m, rtol=0.0, max_iters=m, fmt=fmt)
     o = oracle_run(p, scheme, m=m, rtol=0.0, max_iters=m)
     r = g["res"]
     assert r.status == 0 and o.status == 0
