@@ -139,7 +139,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    t0 = time.perf_counter()
     s1 = GmresSolver(rp, ci, va, m, "mgs1r")
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    fmt, stored = s1.format()
     dt, iters, res, kt = time_solves(s1, b, x, rtol, args.max_iters, args.steps, args.warmup,
                                      timing=True)
     err = float(torch.linalg.norm(x.cpu() - torch.from_numpy(p.x_true)) / np.linalg.norm(p.x_true))
@@ -176,7 +180,8 @@ def main():
         "config": {"workload": WORKLOAD, "n": n, "nnz": nnz, "m": m, "rtol": rtol,
                    "scheme": "one-reduce lagged compact-WY MGS", "iters_per_solve": iters // args.steps,
                    "converged": bool(res.converged), "rel_res_true": res.rel_res_true,
-                   "reductions_per_solve": res.reductions},
+                   "reductions_per_solve": res.reductions, "spmv_format": fmt,
+                   "stored_matrix_entries": stored, "setup_ms": round(setup_ms, 2)},
         # step-kernel bytes of the instrumented solve over the mean solve time
         "hbm_GBps_arnoldi": round(arnoldi_bytes / (dt / args.steps) / 1e9, 1),
         "roofline": roofline,

@@ -86,15 +86,16 @@ size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
  * nnz, non-decreasing row_ptr, 0 <= col_idx < n); a malformed matrix gives
  * GMRES_ERR_ARG and no context. On success *out holds the context.
  * Sparse format: when padding every slice of 64 rows to its longest row adds
- * at most a quarter to nnz (stencil and other regular matrices), the context
- * keeps its own sliced-ELL copy of A (SELL-64: per slice, entry j of each row
- * stored column by column; about 12 bytes per padded entry plus 8 per slice,
- * allocated here on the device and freed by gmres_destroy) and every SpMV
- * reads the copy, not the caller's arrays: after changing vals (same
- * structure) call gmres_refresh_matrix. Otherwise, or if that allocation
- * fails, the SpMV reads the caller's CSR arrays directly. gmres_get_format
- * tells which. The arithmetic is the same either way: each row's products are
- * summed in storage order (padding adds exact zeros).
+ * at most a quarter to nnz (stencil and other regular matrices) and n < 2^28,
+ * gmres_create plans a sliced-ELL copy of A (SELL-64: per slice, entry j of
+ * each row stored column by column, so a wavefront's index and value loads
+ * are contiguous and no row pointers are read). The library allocates no
+ * device memory: gmres_matrix_storage_bytes gives the size of the copy and
+ * gmres_set_matrix_storage builds it in a caller-owned buffer; from then on
+ * every SpMV reads the copy, not the caller's arrays (after changing vals in
+ * place, call gmres_refresh_matrix). Without that call the SpMV reads the CSR
+ * arrays directly. The slice widths are computed at create in the
+ * workspace's basis region.
  */
 int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
                  const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
@@ -111,6 +112,14 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
  *   max_iters >= 0: cap on Arnoldi columns over all cycles.
  *   info (host, nullable): filled on return.
  *   hist_res (host, nullable, max_iters doubles): |g_k| / ||b|| after each column.
+ *   hist_orth (host, nullable, max_iters doubles): loss of orthogonality per
+ *   column, ||S||_2 with Paige's S = (I + L^T)^{-1} L^T = I - T, L the strictly
+ *   lower part of V^T V: entry i of a cycle covers its basis vectors
+ *   v_0..v_i (the leading (i+1) x (i+1) block of T; 0 for i = 0). Computed on
+ *   the host after each cycle from the T (one-reduce MGS) or L (CGS2) the
+ *   device built, by power iteration to a relative change of 1e-14; NaN for
+ *   GMRES_MGS, which forms neither. It adds host work per cycle; pass NULL
+ *   when timing.
  * Blocks until the solve has finished on the stream. Returns GMRES_OK when the
  * solve ran to convergence or to max_iters (info->converged tells which),
  * GMRES_ERR_NONFINITE if a NaN or Inf appeared (x then holds the last finished
@@ -118,13 +127,32 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
  * zero and the solve reports convergence with no iterations.
  */
 int gmres_solve(gmres_ctx* ctx, const double* b, double* x, double rtol, int64_t max_iters,
-                gmres_info* info, double* hist_res);
+                gmres_info* info, double* hist_res, double* hist_orth);
 
 /*
- * Release the context: its host memory and, if it made one, its sliced copy
- * of A. The workspace and the CSR arrays stay the caller's.
+ * Release the context (host memory only; the workspace, the CSR arrays and
+ * any matrix storage stay the caller's).
  */
 int gmres_destroy(gmres_ctx* ctx);
+
+/*
+ * Device bytes the context's sliced-ELL copy of A needs (0 when no copy is
+ * planned and the SpMV reads the CSR arrays): ceil(n/64) + 1 int64 slice
+ * offsets, then int32 column indices and float64 values for every stored
+ * entry (64 per slice and slice column; padding entries hold value 0), each
+ * part 256-byte aligned.
+ */
+int gmres_matrix_storage_bytes(gmres_ctx* ctx, size_t* bytes /* host */);
+
+/*
+ * Build the sliced copy of A in storage: a caller-owned device buffer of at
+ * least gmres_matrix_storage_bytes bytes, 256-byte aligned, that stays valid
+ * and untouched while the context uses it. Blocks until the copy is built.
+ * storage == NULL goes back to reading the CSR arrays. GMRES_ERR_ARG if no
+ * copy is planned, the buffer is too small, misaligned or not device memory,
+ * or a row no longer fits its slice.
+ */
+int gmres_set_matrix_storage(gmres_ctx* ctx, void* storage, size_t bytes);
 
 /*
  * Re-read A's values (and re-check its structure) after the caller changed
@@ -138,8 +166,10 @@ int gmres_refresh_matrix(gmres_ctx* ctx);
 
 enum { GMRES_FORMAT_CSR = 0, GMRES_FORMAT_SELL64 = 1 };
 /*
- * The SpMV format the context chose (GMRES_FORMAT_*) and the matrix entries
- * it stores: nnz for CSR, nnz plus padding for SELL64.
+ * The SpMV format in use (GMRES_FORMAT_*) and the matrix entries it reads:
+ * nnz for CSR, nnz plus padding for SELL64. The arithmetic is the same
+ * either way: each row's products are summed in storage order (padding adds
+ * exact zeros).
  */
 int gmres_get_format(gmres_ctx* ctx, int32_t* format, int64_t* stored_entries);
 
@@ -183,10 +213,12 @@ int gmres_basis(gmres_ctx* ctx, double** V, int64_t* ldv);
  * separate SpMV kernel and of the MAXPY kernel carries start/stop HIP events
  * attached to its dispatch (hipExtLaunchKernel), so they time the kernel
  * alone; launches that the cycle's done flag skipped are not counted. bytes is
- * the algorithmic HBM traffic of the counted launches:
- *   step k, SpMV fused:     12 nnz + 4 (n+1) + 8 n (k+1) + 8 n   (CSR, V[:,0:k+1], w written)
- *   step k, SpMV separate:  8 n (k+1) + 8 n                      (V[:,0:k+1], w read)
- *   separate SpMV:          12 nnz + 4 (n+1) + 16 n              (CSR, u, w written)
+ * the algorithmic HBM traffic of the counted launches, with A the matrix bytes
+ * of the format in use (CSR: 12 nnz + 4 (n+1); SELL64: 12 per stored entry
+ * plus 8 per slice offset, ceil(n/64) + 1 of them):
+ *   step k, SpMV fused:     A + 8 n (k+1) + 8 n     (A, V[:,0:k+1], w written)
+ *   step k, SpMV separate:  8 n (k+1) + 8 n         (V[:,0:k+1], w read)
+ *   separate SpMV:          A + 16 n                (A, u, w written)
  *   last step of a cycle (norm of column k only):  8 n
  *   CGS2 second pass:  8 n (k+2)                          (V[:,0:k+1] and z)
  *   MAXPY at step k:   8 n (k+1) + 16 n                   (V[:,0:k+1], w or z, new column)

@@ -78,10 +78,11 @@ bool pick_split(int64_t, int64_t) {
 // Sparse format of the SpMV. The sliced ELL copy (SELL-64, built at create)
 // makes every column-index and value load of a wavefront one contiguous
 // 512-byte block and needs no row pointers; it is used when padding every
-// slice to its longest row costs at most a quarter more entries and no slice
-// is wider than kSellMaxWidth. GMRES_SPMV_FORMAT ("csr" or "sell") overrides
+// slice to its longest row costs at most a quarter more entries, no slice is
+// wider than kSellMaxWidth and n < kSellMaxRows. GMRES_SPMV_FORMAT ("csr" or "sell") overrides
 // the choice for tuning sweeps and tests ("sell" still requires the width cap).
 constexpr int kSellMaxWidth = 4096;
+constexpr int64_t kSellMaxRows = (int64_t)1 << 28;  // gathers use 32-bit byte offsets
 enum { kFormatCsr = 0, kFormatSell = 1 };
 int format_override() {
   if (const char* e = getenv("GMRES_SPMV_FORMAT")) {
@@ -151,9 +152,10 @@ struct gmres_ctx {
   bool split;        // separate SpMV launch in the lagged step
   bool matrix_ok;    // false after a refresh found a bad structure: no more SpMVs
   int format;        // kFormatCsr or kFormatSell
-  Sell sell;         // the sliced copy (format == kFormatSell)
-  void* sell_mem;    // its device allocation, owned by the context
-  int64_t sell_entries;
+  Sell sell;         // the sliced copy (format == kFormatSell), in caller memory
+  std::vector<int64_t> sell_sp;  // planned slice offsets (empty: no copy planned)
+  int64_t sell_entries;          // planned stored entries
+  size_t sell_bytes, o_ci, o_va; // planned storage size and its layout
   Layout L;
   Ws ws;
   hipStream_t stream;
@@ -229,6 +231,76 @@ struct TimedLaunch {
   }
 };
 
+// Largest singular value of the K x K matrix S (column-major, leading
+// dimension ld) by power iteration on S^T S, started from x (length K, left
+// holding the final iterate so that the next, larger block can start from it).
+double spectral_norm(const double* S, int K, int ld, std::vector<double>& x) {
+  std::vector<double> y((size_t)K), z((size_t)K);
+  double nx = 0.0;
+  for (int i = 0; i < K; ++i) nx += x[i] * x[i];
+  if (!(nx > 0.0)) {
+    for (int i = 0; i < K; ++i) x[i] = 1.0;
+    nx = K;
+  }
+  for (int i = 0; i < K; ++i) x[i] /= sqrt(nx);
+  double lam = 0.0;
+  for (int iter = 0; iter < 5000; ++iter) {
+    for (int i = 0; i < K; ++i) y[i] = 0.0;
+    for (int col = 0; col < K; ++col)
+      for (int i = 0; i < K; ++i) y[i] += S[(size_t)col * ld + i] * x[col];
+    for (int col = 0; col < K; ++col) {
+      double a = 0.0;
+      for (int i = 0; i < K; ++i) a += S[(size_t)col * ld + i] * y[i];
+      z[col] = a;
+    }
+    double nz = 0.0;
+    for (int i = 0; i < K; ++i) nz += z[i] * z[i];
+    nz = sqrt(nz);
+    if (nz == 0.0) return 0.0;
+    for (int i = 0; i < K; ++i) x[i] = z[i] / nz;
+    const bool done = fabs(nz - lam) <= 1e-14 * nz;
+    lam = nz;
+    if (done) break;
+  }
+  return sqrt(lam);
+}
+
+// ||S||_2 with S = I - (I + L^T)^{-1} (Paige's S for the basis v_0..v_K-1),
+// for the leading K x K blocks, K = 1..j, of the cycle that just ended:
+// one-reduce MGS holds T = (I + L^T)^{-1} itself, CGS2 holds L (its rows are
+// the lagged projections l); plain MGS forms neither, so its entries are NaN.
+void orth_history(gmres_ctx* c, int j, double* out) {
+  if (c->scheme == kSchemeMgs) {
+    for (int q = 0; q < j; ++q) out[q] = NAN;
+    return;
+  }
+  const int ldt = c->m + 2;
+  std::vector<double> S((size_t)j * j, 0.0);  // column-major, ld j
+  if (c->scheme == kSchemeMgs1r) {
+    for (int col = 0; col < j; ++col)
+      for (int i = 0; i < col; ++i) S[(size_t)col * j + i] = -c->h_T[(size_t)col * ldt + i];
+  } else {
+    // U = (I + L^T)^{-1}, unit upper triangular: column col solves
+    // (I + L^T) u = e_col by back substitution; L(t, i) sits at h_T[i * ldt + t]
+    for (int col = 0; col < j; ++col) {
+      std::vector<double> u((size_t)col + 1, 0.0);
+      u[col] = 1.0;
+      for (int i = col - 1; i >= 0; --i) {
+        double a = 0.0;
+        for (int t = i + 1; t <= col; ++t) a += c->h_T[(size_t)i * ldt + t] * u[t];
+        u[i] = -a;
+      }
+      for (int i = 0; i < col; ++i) S[(size_t)col * j + i] = -u[i];
+    }
+  }
+  std::vector<double> x((size_t)j, 0.0);
+  out[0] = 0.0;
+  for (int K = 2; K <= j; ++K) {
+    x[K - 1] = 1.0 / sqrt((double)K);
+    out[K - 1] = spectral_norm(S.data(), K, j, x);
+  }
+}
+
 // After the cycle has finished on the stream: add the launches that ran.
 void collect_timing(gmres_ctx* c, int j, bool stopped_at_restart) {
   if (!c->timing) return;
@@ -247,32 +319,27 @@ void collect_timing(gmres_ctx* c, int j, bool stopped_at_restart) {
   c->recs.clear();
 }
 
-// Build the sliced copy of A when the format choice asks for it (else the
-// context keeps the CSR format): slice widths on the device, offsets on the
-// host, one device allocation for offsets, indices and values, then the copy.
-// An allocation failure leaves the CSR format in place.
-int build_format(gmres_ctx* c) {
+// Plan the sliced copy of A when the format choice asks for it: slice widths
+// on the device (in the basis region of the workspace, which holds nothing
+// before the first solve), offsets on the host. The copy itself is built by
+// gmres_set_matrix_storage in memory the caller provides; until then, or if
+// no copy is planned, the SpMV reads the CSR arrays.
+int plan_format(gmres_ctx* c) {
   c->format = kFormatCsr;
-  c->sell = Sell{nullptr, nullptr, nullptr, 0};
-  c->sell_mem = nullptr;
+  c->sell = Sell{nullptr, nullptr, nullptr, 0, 0};
+  c->sell_sp.clear();
   c->sell_entries = 0;
+  c->sell_bytes = 0;
   const int want = format_override();
-  if (want == kFormatCsr || c->nnz == 0) return GMRES_OK;
+  if (want == kFormatCsr || c->nnz == 0 || c->A.n >= kSellMaxRows) return GMRES_OK;
   const int64_t ns = (c->A.n + 63) / 64;
-  int* dw = nullptr;
-  if (hipMalloc((void**)&dw, sizeof(int) * (size_t)ns) != hipSuccess) {
-    (void)hipGetLastError();
-    return GMRES_OK;
-  }
+  int* dw = reinterpret_cast<int*>(c->ws.V);  // ns ints fit easily in n (m+2) doubles
   std::vector<int> wh((size_t)ns);
-  int rc = GMRES_OK;
   if (launch_sell_width(c->A, ns, dw, c->stream) ||
       hipMemcpyAsync(wh.data(), dw, sizeof(int) * (size_t)ns, hipMemcpyDeviceToHost, c->stream) !=
           hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
-    rc = GMRES_ERR_HIP;
-  (void)hipFree(dw);
-  if (rc) return rc;
+    return GMRES_ERR_HIP;
   std::vector<int64_t> sp((size_t)ns + 1);
   sp[0] = 0;
   int wmax = 0;
@@ -283,30 +350,11 @@ int build_format(gmres_ctx* c) {
   const int64_t total = sp[ns];
   const bool cheap = total * 4 <= c->nnz * 5;
   if (wmax > kSellMaxWidth || (want != kFormatSell && !cheap)) return GMRES_OK;
-  const size_t o_ci = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
-  const size_t o_va = round_up(o_ci + sizeof(int) * (size_t)total, kAlign);
-  const size_t bytes = o_va + sizeof(double) * (size_t)total;
-  if (hipMalloc(&c->sell_mem, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    c->sell_mem = nullptr;
-    return GMRES_OK;
-  }
-  char* base = (char*)c->sell_mem;
-  c->sell = Sell{(const int64_t*)base, (int*)(base + o_ci), (double*)(base + o_va), ns};
-  if (hipMemcpyAsync(base, sp.data(), sizeof(int64_t) * (size_t)(ns + 1), hipMemcpyHostToDevice,
-                     c->stream) != hipSuccess ||
-      launch_sell_fill(c->A, c->sell, c->ws.st, c->stream))
-    rc = GMRES_ERR_HIP;
-  if (rc == GMRES_OK) rc = sync_state(c, false);
-  if (rc == GMRES_OK && c->h_st->bad_csr) rc = GMRES_ERR_ARG;
-  if (rc != GMRES_OK) {
-    (void)hipFree(c->sell_mem);
-    c->sell_mem = nullptr;
-    c->sell = Sell{nullptr, nullptr, nullptr, 0};
-    return rc;
-  }
-  c->format = kFormatSell;
+  c->sell_sp.swap(sp);
   c->sell_entries = total;
+  c->o_ci = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
+  c->o_va = round_up(c->o_ci + sizeof(int) * (size_t)total, kAlign);
+  c->sell_bytes = c->o_va + sizeof(double) * (size_t)total;
   return GMRES_OK;
 }
 
@@ -323,7 +371,10 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
   hipStream_t s = c->stream;
   const int rpt = c->L.rpt, G = c->L.G;
   const double n8 = 8.0 * (double)c->A.n;
-  const double csr = 12.0 * (double)c->nnz + 4.0 * (double)(c->A.n + 1);
+  // bytes of the matrix in the format the SpMV reads
+  const double csr = c->format == kFormatSell
+                         ? 12.0 * (double)c->sell_entries + 8.0 * (double)(c->sell.ns + 1)
+                         : 12.0 * (double)c->nnz + 4.0 * (double)(c->A.n + 1);
   auto col = [&](int q) { return ws.V + (size_t)q * (size_t)ws.ldv; };
   TRY(launch_cycle_begin(ws, s));
   TRY(spmv(c, x, b, col(0), nullptr, s));  // V[:,0] = b - A x
@@ -486,15 +537,13 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   memset(c->stats, 0, sizeof(c->stats));
 
   int rc = GMRES_OK;
-  c->sell_mem = nullptr;
   c->matrix_ok = true;
   if (launch_init(ws, L.NG + 1, c->stream) || launch_validate(c->A, nnz, ws.st, c->stream))
     rc = GMRES_ERR_HIP;
   if (rc == GMRES_OK) rc = sync_state(c, false);
   if (rc == GMRES_OK && c->h_st->bad_csr) rc = GMRES_ERR_ARG;
-  if (rc == GMRES_OK) rc = build_format(c);
+  if (rc == GMRES_OK) rc = plan_format(c);
   if (rc != GMRES_OK) {
-    if (c->sell_mem) (void)hipFree(c->sell_mem);
     (void)hipHostFree(c->pinned);
     delete c;
     return rc;
@@ -507,7 +556,6 @@ int gmres_destroy(gmres_ctx* c) {
   if (!c) return GMRES_ERR_ARG;
   int rc = GMRES_OK;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-  if (c->sell_mem && hipFree(c->sell_mem) != hipSuccess) rc = GMRES_ERR_HIP;
   if (c->pinned && hipHostFree(c->pinned) != hipSuccess) rc = GMRES_ERR_HIP;
   delete c;
   return rc;
@@ -525,6 +573,38 @@ int gmres_refresh_matrix(gmres_ctx* c) {
   if (rc != GMRES_OK) return rc;
   if (c->h_st->bad_csr) return GMRES_ERR_ARG;
   c->matrix_ok = true;
+  return GMRES_OK;
+}
+
+int gmres_matrix_storage_bytes(gmres_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return GMRES_ERR_ARG;
+  *bytes = c->sell_bytes;
+  return GMRES_OK;
+}
+
+int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
+  if (!c) return GMRES_ERR_ARG;
+  if (!storage) {
+    c->format = kFormatCsr;
+    c->sell = Sell{nullptr, nullptr, nullptr, 0, 0};
+    return GMRES_OK;
+  }
+  if (c->sell_bytes == 0 || bytes < c->sell_bytes || ((uintptr_t)storage % kAlign) != 0 ||
+      !is_device_ptr(storage))
+    return GMRES_ERR_ARG;
+  char* base = (char*)storage;
+  const int64_t ns = (int64_t)c->sell_sp.size() - 1;
+  const Sell S{(const int64_t*)base, (int*)(base + c->o_ci), (double*)(base + c->o_va), ns, c->A.n};
+  if (hipMemcpyAsync(base, c->sell_sp.data(), sizeof(int64_t) * (size_t)(ns + 1),
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemsetAsync(&c->ws.st->bad_csr, 0, sizeof(int32_t), c->stream) != hipSuccess ||
+      launch_sell_fill(c->A, S, c->ws.st, c->stream))
+    return GMRES_ERR_HIP;
+  const int rc = sync_state(c, false);  // also keeps the offsets' host copy alive until done
+  if (rc != GMRES_OK) return rc;
+  if (c->h_st->bad_csr) return GMRES_ERR_ARG;
+  c->sell = S;
+  c->format = kFormatSell;
   return GMRES_OK;
 }
 
@@ -571,7 +651,7 @@ int gmres_last_cycle(gmres_ctx* c, double* H, double* T, double* g, int32_t* j) 
 }
 
 int gmres_solve(gmres_ctx* c, const double* b, double* x, double rtol, int64_t max_iters,
-                gmres_info* info, double* hist_res) {
+                gmres_info* info, double* hist_res, double* hist_orth) {
   gmres_info loc;
   memset(&loc, 0, sizeof(loc));
   if (info) *info = loc;
@@ -639,6 +719,7 @@ int gmres_solve(gmres_ctx* c, const double* b, double* x, double rtol, int64_t m
     if (j > 0) {
       if (hist_res)
         for (int q = 0; q < j; ++q) hist_res[it + q] = c->h_gh[q + 1] / bnorm;
+      if (hist_orth) orth_history(c, j, hist_orth + it);
       loc.cycles += 1;
       loc.rel_res_est = fabs(c->h_g[j]) / bnorm;
       memcpy(c->last_H.data(), c->h_H, sizeof(double) * c->last_H.size());

@@ -21,6 +21,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace gmres {
 
 // ---------------------------------------------------------------- helpers
@@ -76,6 +78,32 @@ __device__ inline double wave_multi_sum(double (&v)[NV], int lane) {
   return v[0];
 }
 
+// One data-parallel-primitive (DPP) move of a double: the two 32-bit halves
+// go through the same lane permutation CTRL; lanes with no source (or in rows
+// outside ROWMASK) receive 0.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWMASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a wavefront, valid in lane 63 only: shifts by 1,
+// 2, 4 and 8 lanes within each row of 16 leave the row's total in its last
+// lane, then row_bcast:15 adds row 0 into row 1 and row 2 into row 3, and
+// row_bcast:31 adds rows 0-1 into rows 2-3. All moves are VALU cross-lane
+// operations, with no trip through the LDS unit.
+__device__ inline double wave_sum_last(double v) {
+  v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // Tuning constants (compile-time; defaults are the measured best on MI355X):
 //   GMRES_PROJ_COLS  basis columns per projection chunk (1, 2, 4 or 8).
 #ifndef GMRES_PROJ_COLS
@@ -85,6 +113,15 @@ __device__ inline double wave_multi_sum(double (&v)[NV], int lane) {
 //                        0: passes run one after another (spmv_pass).
 #ifndef GMRES_SPMV_PIPELINE
 #define GMRES_SPMV_PIPELINE 1
+#endif
+//   GMRES_DPP_REDUCE  1: the projection's wavefront sums use DPP row shifts
+//                     and broadcasts; 0: a halving butterfly of lane shuffles.
+#ifndef GMRES_DPP_REDUCE
+#define GMRES_DPP_REDUCE 1
+#endif
+//   GMRES_FUSED_ROWMAP  rows of a lane in the fused step (see k_fused).
+#ifndef GMRES_FUSED_ROWMAP
+#define GMRES_FUSED_ROWMAP 1
 #endif
 //   GMRES_MAXPY_COLS  basis columns per MAXPY pass (1, 2 or 4).
 #ifndef GMRES_MAXPY_COLS
@@ -98,6 +135,42 @@ __device__ inline double wave_multi_sum(double (&v)[NV], int lane) {
 __device__ inline double ld_at(const double* base, uint32_t boff) {
   return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + boff);
 }
+
+// A raw buffer resource over elements [0, nelem) of a wave-uniform array: its
+// descriptor sits in scalar registers, so a load needs only the lane's 32-bit
+// byte offset; offsets at or past the end read 0 instead of memory. The third
+// descriptor word is the gfx9-family raw-buffer format (32-bit data, no
+// swizzle).
+struct BufCol {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ BufCol(const double* base, int64_t nelem) {
+    const int64_t nb = nelem * 8;
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0,
+                                          (int)(nb < 0x7ffffff8 ? nb : 0x7ffffff8), 0x00020000);
+  }
+  __device__ double operator()(uint32_t boff) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)boff, 0, 0));
+  }
+};
+
+// The same interface over a plain global load (scalar base + 32-bit offset);
+// callers keep their offsets inside [0, 8 nelem).
+struct GlbCol {
+  const double* b;
+  __device__ GlbCol(const double* base, int64_t) : b(base) {}
+  __device__ double operator()(uint32_t boff) const { return ld_at(b, boff); }
+};
+
+//   GMRES_PROJ_BUFFER / GMRES_MAXPY_BUFFER  1: the projection's (MAXPY's and
+//   x update's) column loads are buffer loads; 0: global loads.
+#ifndef GMRES_PROJ_BUFFER
+#define GMRES_PROJ_BUFFER 0
+#endif
+#ifndef GMRES_MAXPY_BUFFER
+#define GMRES_MAXPY_BUFFER 0
+#endif
+using ProjCol = std::conditional_t<GMRES_PROJ_BUFFER != 0, BufCol, GlbCol>;
+using MaxpyCol = std::conditional_t<GMRES_MAXPY_BUFFER != 0, BufCol, GlbCol>;
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
@@ -623,30 +696,35 @@ __global__ __launch_bounds__(256) void k_sell_fill(Csr A, Sell S, DevState* st) 
 
 // Entries j0 .. j0+U-1 of lane l's row in the slice at entry offset b, width
 // W (>= 1): indices past W are clamped to W-1 (their products are masked by
-// the caller). Loads are a uniform base plus a 32-bit byte offset.
+// the caller). Buffer loads over the slice's own entries (the descriptors are
+// scalar; a lane supplies a 32-bit byte offset).
 template <int U>
 __device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l, int (&c)[U],
                                  double (&v)[U]) {
-  const int* __restrict__ cb = S.ci + b;
-  const double* __restrict__ vb = S.va + b;
+  const __amdgpu_buffer_rsrc_t rc =
+      __builtin_amdgcn_make_buffer_rsrc(S.ci + b, (short)0, W * 64 * 4, 0x00020000);
+  const BufCol vb(S.va + b, (int64_t)W * 64);
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     const int j = j0 + t < W ? j0 + t : W - 1;
     const uint32_t e = (uint32_t)(j * 64 + l);
-    c[t] = *reinterpret_cast<const int*>(reinterpret_cast<const char*>(cb) + e * 4u);
-    v[t] = ld_at(vb, e * 8u);
+    c[t] = __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(e * 4u), 0, 0);
+    v[t] = vb(e * 8u);
   }
 }
 
-// out[i] = (A x) at row 64 (s0 + i) + l, i < NS, for the lane's row in NS
-// consecutive slices (slice indices past the last are clamped; the caller
-// drops those rows). U entries per chunk; the column and value loads of the
+// out[i] = (A x) at row 64 (s0 + i sstride) + l, i < NS, for the lane's row in
+// NS slices sstride apart (slice indices past the last are clamped; the
+// caller drops those rows). U entries per chunk; the column and value loads of the
 // next chunk (of this slice or the next) are issued before the gathers of
 // the current one are consumed, so one memory latency per chunk is hidden.
 template <int NS, int U>
-__device__ inline void sell_slices(const Sell& S, const double* __restrict__ x, int64_t s0, int l,
-                                   double (&out)[NS]) {
+__device__ inline void sell_slices(const Sell& S, const double* __restrict__ x, int64_t s0,
+                                   int64_t sstride, int l, double (&out)[NS]) {
   auto clampslice = [&](int64_t s) { return s < S.ns ? s : S.ns - 1; };
+  // gathers from x[0, n) by 32-bit byte offset (the sliced format is used only
+  // for n < 2^28)
+  const BufCol xb(x, S.n);
   int64_t b = S.sp[clampslice(s0)];
   int W = (int)((S.sp[clampslice(s0) + 1] - b) >> 6);
   int c[U];
@@ -657,7 +735,7 @@ __device__ inline void sell_slices(const Sell& S, const double* __restrict__ x, 
     int64_t bn = b;
     int Wn = W;
     if (i + 1 < NS) {
-      const int64_t sn = clampslice(s0 + i + 1);
+      const int64_t sn = clampslice(s0 + (i + 1) * sstride);
       bn = S.sp[sn];
       Wn = (int)((S.sp[sn + 1] - bn) >> 6);
     }
@@ -666,7 +744,7 @@ __device__ inline void sell_slices(const Sell& S, const double* __restrict__ x, 
       double xv[U], vv[U];
 #pragma unroll
       for (int t = 0; t < U; ++t) {
-        xv[t] = x[c[t]];
+        xv[t] = xb((uint32_t)c[t] * 8u);
         vv[t] = v[t];
       }
       if (j0 + U < W)
@@ -692,7 +770,7 @@ __global__ __launch_bounds__(256) void k_spmv_sell(Sell S, int64_t n, const doub
   const int l = threadIdx.x & 63;
   const int64_t s0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * NS;
   double out[NS];
-  sell_slices<NS, 8>(S, x, s0, l, out);
+  sell_slices<NS, 8>(S, x, s0, 1, l, out);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int64_t r = (s0 + i) * 64 + l;
@@ -971,9 +1049,12 @@ __device__ void tail_cgs2_second(const Ws& ws, const double* vals, int k) {
 //   kWNone: w = 0 (the norm-only flush, or CGS2's second projection with u = z).
 // Then sums over the tile of V_q . u and V_q . w for q < nproj, u.u and u.w;
 // device-wide reduction; the last workgroup runs the tail.
-// RPT rows per lane, 256 threads = 4 wavefronts; lane l of wavefront wv owns
-// rows tile0 + wv*64*RPT + i*64 + l, so every column read is 512 contiguous
-// bytes per wavefront.
+// RPT rows per lane, 256 threads = 4 wavefronts. Row map (GMRES_FUSED_ROWMAP):
+//   0: lane l of wavefront wv owns rows tile0 + wv*64*RPT + i*64 + l (each
+//      wavefront a contiguous block of 64 RPT rows);
+//   1: rows tile0 + i*256 + wv*64 + l (the four wavefronts' loads of one i
+//      are adjacent, 2 KB contiguous per workgroup).
+// Either way every column read is 512 contiguous bytes per wavefront.
 template <int RPT, int S, int EPL, int WSRC>
 __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int nproj, int m_eff,
                                                 int tail, int G) {
@@ -998,7 +1079,12 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   constexpr bool HAS_SPMV = WSRC != kWNone;
   // kWSell: the lane's rows are row 64 s + lane of slices s = row0/64 + wv RPT + i
   double ws_out[RPT];
-  if constexpr (WSRC == kWSell) sell_slices<RPT, 8>(SA, u_g, (row0 >> 6) + wv * RPT, lane, ws_out);
+  if constexpr (WSRC == kWSell) {
+    if constexpr (GMRES_FUSED_ROWMAP == 1)
+      sell_slices<RPT, 8>(SA, u_g, (row0 >> 6) + wv, 4, lane, ws_out);
+    else
+      sell_slices<RPT, 8>(SA, u_g, (row0 >> 6) + wv * RPT, 1, lane, ws_out);
+  }
 
   if constexpr (WSRC == kWSpmv) {
     // SpMV of the tile (fewer rows per lane group when the tile holds fewer).
@@ -1025,11 +1111,11 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   const double* __restrict__ Vt = V + rb;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int lr = wv * 64 * RPT + i * 64 + lane;
+    const int lr = GMRES_FUSED_ROWMAP == 1 ? i * 256 + wv * 64 + lane : wv * 64 * RPT + i * 64 + lane;
     const int64_t r = row0 + lr;
     const bool ok = r < n;
     rows[i] = (uint32_t)((ok ? r : n - 1) - rb) * 8u;
-    const double uv = ld_at(u_g + rb, rows[i]);
+    const double uv = ProjCol(u_g + rb, n - rb)(rows[i]);
     u[i] = ok ? uv : 0.0;
     if constexpr (WSRC == kWSpmv) {
       w[i] = ok ? wl[lr] : 0.0;
@@ -1038,7 +1124,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
       w[i] = ok ? ws_out[i] : 0.0;
       if (ok) ws.w[r] = w[i];
     } else if constexpr (WSRC == kWLoad) {
-      const double wv_ = ld_at(ws.w + rb, rows[i]);
+      const double wv_ = ProjCol(ws.w + rb, n - rb)(rows[i]);
       w[i] = ok ? wv_ : 0.0;
     } else {
       w[i] = 0.0;
@@ -1047,15 +1133,23 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   double* myred = red + wv * P;
 
   // Columns 0..nproj-1 in chunks of CB, then the rest one at a time. The
-  // loads of a chunk (CB columns x RPT rows) are all issued before any is used.
+  // loads of the next chunk (CB columns x RPT rows) are issued before the
+  // current chunk is reduced, so two chunks' loads are in flight per lane.
+  // The loop is unrolled twice over two fixed buffers: a loop-carried copy of
+  // a loaded register would make the compiler wait for every load at the end
+  // of each iteration. The last chunk's "next" load repeats that chunk (a
+  // cache hit), which keeps the loads free of branches.
   constexpr int NVC = HAS_SPMV ? 2 * CB : CB;
-  int j0 = 0;
-  for (; j0 + CB <= nproj; j0 += CB) {
-    double vv[CB][RPT];
+  const int64_t nvalid = n - rb;  // rows rb .. n-1 of every column
+  auto load_chunk = [&](double (&buf)[CB][RPT], int j) {
 #pragma unroll
-    for (int c = 0; c < CB; ++c)
+    for (int c = 0; c < CB; ++c) {
+      const ProjCol col(Vt + (size_t)(j + c) * ldv, nvalid);
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) vv[c][i] = ld_at(Vt + (size_t)(j0 + c) * ldv, rows[i]);
+      for (int i = 0; i < RPT; ++i) buf[c][i] = col(rows[i]);
+    }
+  };
+  auto reduce_chunk = [&](const double (&vv)[CB][RPT], int j) {
     double acc[NVC];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
@@ -1072,31 +1166,66 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
         acc[c] = p;
       }
     }
-    const double tot = wave_multi_sum<NVC>(acc, lane);
-    constexpr int LOGNV = ilog2(NVC);
-    if ((lane & ((64 / NVC) - 1)) == 0) {
-      const int vi = lane >> (6 - LOGNV);
-      if constexpr (HAS_SPMV) {
-        myred[2 * j0 + vi] = tot;
-      } else {
-        myred[2 * (j0 + vi)] = tot;
-        myred[2 * (j0 + vi) + 1] = 0.0;
+    if constexpr (GMRES_DPP_REDUCE) {
+      // each value summed on its own, total in lane 63
+#pragma unroll
+      for (int t = 0; t < NVC; ++t) acc[t] = wave_sum_last(acc[t]);
+      if (lane == 63) {
+#pragma unroll
+        for (int t = 0; t < NVC; ++t) {
+          if constexpr (HAS_SPMV) {
+            myred[2 * j + t] = acc[t];
+          } else {
+            myred[2 * (j + t)] = acc[t];
+            myred[2 * (j + t) + 1] = 0.0;
+          }
+        }
       }
+    } else {
+      const double tot = wave_multi_sum<NVC>(acc, lane);
+      constexpr int LOGNV = ilog2(NVC);
+      if ((lane & ((64 / NVC) - 1)) == 0) {
+        const int vi = lane >> (6 - LOGNV);
+        if constexpr (HAS_SPMV) {
+          myred[2 * j + vi] = tot;
+        } else {
+          myred[2 * (j + vi)] = tot;
+          myred[2 * (j + vi) + 1] = 0.0;
+        }
+      }
+    }
+  };
+  int j0 = 0;
+  if (nproj >= CB) {
+    double ba[CB][RPT], bb[CB][RPT];
+    load_chunk(ba, 0);
+    for (;;) {
+      // ba holds chunk j0
+      load_chunk(bb, j0 + 2 * CB <= nproj ? j0 + CB : j0);
+      reduce_chunk(ba, j0);
+      j0 += CB;
+      if (j0 + CB > nproj) break;
+      // bb holds chunk j0
+      load_chunk(ba, j0 + 2 * CB <= nproj ? j0 + CB : j0);
+      reduce_chunk(bb, j0);
+      j0 += CB;
+      if (j0 + CB > nproj) break;
     }
   }
   for (; j0 < nproj; ++j0) {
     double vv[RPT];
+    const ProjCol col(Vt + (size_t)j0 * ldv, nvalid);
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) vv[i] = ld_at(Vt + (size_t)j0 * ldv, rows[i]);
+    for (int i = 0; i < RPT; ++i) vv[i] = col(rows[i]);
     double p = 0.0, c = 0.0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       p += vv[i] * u[i];
       if constexpr (HAS_SPMV) c += vv[i] * w[i];
     }
-    p = wave_sum(p);
-    if constexpr (HAS_SPMV) c = wave_sum(c);
-    if (lane == 0) {
+    p = wave_sum_last(p);
+    if constexpr (HAS_SPMV) c = wave_sum_last(c);
+    if (lane == 63) {
       myred[2 * j0] = p;
       myred[2 * j0 + 1] = HAS_SPMV ? c : 0.0;
     }
@@ -1108,9 +1237,9 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
       al += u[i] * u[i];
       if constexpr (HAS_SPMV) ga += u[i] * w[i];
     }
-    al = wave_sum(al);
-    if constexpr (HAS_SPMV) ga = wave_sum(ga);
-    if (lane == 0) {
+    al = wave_sum_last(al);
+    if constexpr (HAS_SPMV) ga = wave_sum_last(ga);
+    if (lane == 63) {
       myred[2 * nproj] = al;
       myred[2 * nproj + 1] = HAS_SPMV ? ga : 0.0;
     }
@@ -1165,12 +1294,13 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   double acc[RPT];
   uint32_t off[RPT];
   const int64_t rb = row0 < n ? row0 : n - 1;
-  const double* __restrict__ src0 = (mode == 0 ? ws.w : V + (size_t)(k + 1) * ldv) + rb;
+  const int64_t nvalid = n - rb;
+  const MaxpyCol src0((mode == 0 ? ws.w : V + (size_t)(k + 1) * ldv) + rb, nvalid);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;
     off[i] = (uint32_t)((r < n ? r : n - 1) - rb) * 8u;
-    acc[i] = mode == 0 ? ld_at(src0, off[i]) * invr : ld_at(src0, off[i]);
+    acc[i] = mode == 0 ? src0(off[i]) * invr : src0(off[i]);
   }
   // GMRES_MAXPY_COLS columns per pass (their loads are in flight together).
   constexpr int MC = GMRES_MAXPY_COLS;
@@ -1182,9 +1312,9 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
 #pragma unroll
     for (int t = 0; t < MC; ++t) {
       c[t] = cf[q + t];
-      const double* __restrict__ col = Vt + (size_t)(q + t) * ldv;
+      const MaxpyCol col(Vt + (size_t)(q + t) * ldv, nvalid);
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) v[t][i] = ld_at(col, off[i]);
+      for (int i = 0; i < RPT; ++i) v[t][i] = col(off[i]);
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -1196,18 +1326,18 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   }
   for (; q < k; ++q) {
     const double c0 = cf[q];
-    const double* __restrict__ col = Vt + (size_t)q * ldv;
+    const MaxpyCol col(Vt + (size_t)q * ldv, nvalid);
     double v[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) v[i] = ld_at(col, off[i]);
+    for (int i = 0; i < RPT; ++i) v[i] = col(off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] -= v[i] * c0;
   }
   const double ck = cf[k];
   double vk[RPT];
-  const double* __restrict__ colk = Vt + (size_t)k * ldv;
+  const MaxpyCol colk(Vt + (size_t)k * ldv, nvalid);
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) vk[i] = ld_at(colk, off[i]);
+  for (int i = 0; i < RPT; ++i) vk[i] = colk(off[i]);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;
@@ -1405,7 +1535,7 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + threadIdx.x;
     off[i] = (uint32_t)((r < n ? r : n - 1) - rb) * 8u;
-    acc[i] = ld_at(x + rb, off[i]);
+    acc[i] = MaxpyCol(x + rb, n - rb)(off[i]);
   }
   int q = 0;
   for (; q + 4 <= j; q += 4) {
@@ -1414,7 +1544,7 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) v[t][i] = ld_at(Vt + (size_t)(q + t) * ldv, off[i]);
+      for (int i = 0; i < RPT; ++i) v[t][i] = MaxpyCol(Vt + (size_t)(q + t) * ldv, n - rb)(off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] = acc[i] + v[0][i] * c0 + v[1][i] * c1 + v[2][i] * c2 + v[3][i] * c3;
   }
@@ -1422,7 +1552,7 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
     const double c0 = y[q];
     double v[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) v[i] = ld_at(Vt + (size_t)q * ldv, off[i]);
+    for (int i = 0; i < RPT; ++i) v[i] = MaxpyCol(Vt + (size_t)q * ldv, n - rb)(off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] += v[i] * c0;
   }

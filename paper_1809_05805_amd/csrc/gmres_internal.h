@@ -58,6 +58,7 @@ struct Sell {
   int* ci;
   double* va;
   int64_t ns;         // slices, ceil(n / 64)
+  int64_t n;          // rows (below 2^28: gathers take 32-bit byte offsets)
 };
 
 // Views into the caller's workspace.

@@ -24,7 +24,8 @@ GMRES_MAX_RESTART = 256
 
 EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destroy",
             "gmres_status_string", "gmres_spmv", "gmres_last_cycle", "gmres_basis",
-            "gmres_set_timing", "gmres_get_timing", "gmres_refresh_matrix", "gmres_get_format"]
+            "gmres_set_timing", "gmres_get_timing", "gmres_refresh_matrix", "gmres_get_format",
+            "gmres_matrix_storage_bytes", "gmres_set_matrix_storage"]
 GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64 = 0, 1
 GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
 
@@ -61,7 +62,7 @@ def load() -> ctypes.CDLL:
     lib.gmres_create.restype = ctypes.c_int
     lib.gmres_create.argtypes = [ctypes.POINTER(P), I64, I64, P, P, P, I32, I32, P, SZ, P]
     lib.gmres_solve.restype = ctypes.c_int
-    lib.gmres_solve.argtypes = [P, P, P, D, I64, ctypes.POINTER(GmresInfo), P]
+    lib.gmres_solve.argtypes = [P, P, P, D, I64, ctypes.POINTER(GmresInfo), P, P]
     lib.gmres_destroy.restype = ctypes.c_int
     lib.gmres_destroy.argtypes = [P]
     lib.gmres_status_string.restype = ctypes.c_char_p
@@ -80,6 +81,10 @@ def load() -> ctypes.CDLL:
     lib.gmres_refresh_matrix.argtypes = [P]
     lib.gmres_get_format.restype = ctypes.c_int
     lib.gmres_get_format.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    lib.gmres_matrix_storage_bytes.restype = ctypes.c_int
+    lib.gmres_matrix_storage_bytes.argtypes = [P, ctypes.POINTER(SZ)]
+    lib.gmres_set_matrix_storage.restype = ctypes.c_int
+    lib.gmres_set_matrix_storage.argtypes = [P, P, SZ]
     _lib = lib
     return lib
 
@@ -102,10 +107,12 @@ def gmres_create(n, nnz, row_ptr_ptr, col_idx_ptr, vals_ptr, m, scheme, ws_ptr, 
     return rc, (ctx.value if rc == GMRES_OK else None)
 
 
-def gmres_solve(ctx, b_ptr, x_ptr, rtol, max_iters, hist: np.ndarray | None = None):
+def gmres_solve(ctx, b_ptr, x_ptr, rtol, max_iters, hist: np.ndarray | None = None,
+                orth: np.ndarray | None = None):
     info = GmresInfo()
     hp = None if hist is None else hist.ctypes.data_as(ctypes.c_void_p)
-    rc = load().gmres_solve(ctx, b_ptr, x_ptr, float(rtol), int(max_iters), ctypes.byref(info), hp)
+    op = None if orth is None else orth.ctypes.data_as(ctypes.c_void_p)
+    rc = load().gmres_solve(ctx, b_ptr, x_ptr, float(rtol), int(max_iters), ctypes.byref(info), hp, op)
     return rc, info
 
 
@@ -119,6 +126,16 @@ def gmres_spmv(ctx, x_ptr, y_ptr) -> int:
 
 def gmres_refresh_matrix(ctx) -> int:
     return load().gmres_refresh_matrix(ctx)
+
+
+def gmres_matrix_storage_bytes(ctx):
+    nb = ctypes.c_size_t()
+    rc = load().gmres_matrix_storage_bytes(ctx, ctypes.byref(nb))
+    return rc, nb.value
+
+
+def gmres_set_matrix_storage(ctx, ptr, nbytes: int) -> int:
+    return load().gmres_set_matrix_storage(ctx, ptr, nbytes)
 
 
 def gmres_get_format(ctx):
@@ -174,6 +191,7 @@ class SolveResult:
     rel_res_est: float
     reductions: int
     hist: np.ndarray | None
+    orth: np.ndarray | None = None
 
 
 class GmresSolver:
@@ -207,6 +225,17 @@ class GmresSolver:
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_create")
         self.ctx = ctx
+        # the sliced copy of A, when the library plans one, lives in a tensor of ours
+        rc, mbytes = gmres_matrix_storage_bytes(ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_matrix_storage_bytes")
+        self.mat = None
+        if mbytes:
+            self.mat = torch.empty(mbytes + 256, dtype=torch.uint8, device=self.device)
+            moff = (-self.mat.data_ptr()) % 256
+            rc = gmres_set_matrix_storage(ctx, self.mat.data_ptr() + moff, mbytes)
+            if rc != GMRES_OK:
+                raise GmresError(rc, "gmres_set_matrix_storage")
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -220,19 +249,21 @@ class GmresSolver:
             pass
 
     def solve(self, b, x, rtol: float, max_iters: int, hist: bool = False,
-              check: bool = True) -> SolveResult:
+              check: bool = True, orth: bool = False) -> SolveResult:
         import torch
 
         for t in (b, x):
             if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != self.n:
                 raise ValueError("b and x must be contiguous float64 device tensors of length n")
         h = np.full(max(int(max_iters), 1), np.nan) if hist else None
-        rc, info = gmres_solve(self.ctx, b.data_ptr(), x.data_ptr(), rtol, max_iters, h)
+        o = np.full(max(int(max_iters), 1), np.nan) if orth else None
+        rc, info = gmres_solve(self.ctx, b.data_ptr(), x.data_ptr(), rtol, max_iters, h, o)
         if check and rc not in (GMRES_OK, GMRES_ERR_NONFINITE):
             raise GmresError(rc, "gmres_solve")
         return SolveResult(rc, info.iters, info.cycles, bool(info.converged), bool(info.breakdown),
                            info.rel_res_true, info.rel_res_est, info.reductions,
-                           None if h is None else h[: info.iters].copy())
+                           None if h is None else h[: info.iters].copy(),
+                           None if o is None else o[: info.iters].copy())
 
     def spmv(self, x, y):
         rc = gmres_spmv(self.ctx, x.data_ptr(), y.data_ptr())

@@ -40,7 +40,8 @@ def spmv_format(fmt):
                 os.environ["GMRES_SPMV_FORMAT"] = old
 
 
-def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis=False, fmt=None):
+def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis=False, fmt=None,
+            orth=False):
     """One solve through the C ABI; returns a dict with x, info, hist and the last cycle.
     fmt: None (the library's choice), "csr" or "sell"."""
     import torch
@@ -55,7 +56,7 @@ def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis
         s = GmresSolver(rp, ci, va, m, scheme)
     bt = torch.from_numpy(np.ascontiguousarray(p.b if b is None else b)).cuda()
     xt = torch.from_numpy(np.array(p.x0 if x0 is None else x0, dtype=np.float64)).cuda()
-    r = s.solve(bt, xt, rtol, max_iters, hist=True)
+    r = s.solve(bt, xt, rtol, max_iters, hist=True, orth=orth)
     torch.cuda.synchronize()
     H, T, g, j = s.last_cycle()
     out = {"res": r, "x": xt.cpu().numpy(), "H": H, "T": T, "g": g, "j": j, "solver": s}

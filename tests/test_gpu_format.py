@@ -128,3 +128,54 @@ def test_sell_small_and_one_row(scheme):
     o = oracle_run(p, scheme, m=10, rtol=0.0, max_iters=10)
     assert g["res"].iters == o.iters
     assert rel(g["x"], o.x) <= 1e-10
+
+
+def test_storage_calls():
+    """The raw entry points: the planned size, CSR until storage is given, and refusals."""
+    import torch
+
+    from paper_1809_05805_amd import native
+
+    p = P.make_config("cfg1", N=33)  # n = 1089: 18 slices, the last one ragged
+    rp, ci, va = (torch.from_numpy(a).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
+    m = 10
+    need = native.gmres_workspace_bytes(p.n, m, native.GMRES_MGS_1R)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    wp = ws.data_ptr() + (-ws.data_ptr()) % 256
+    stream = torch.cuda.current_stream().cuda_stream
+    rc, ctx = native.gmres_create(p.n, p.nnz, rp.data_ptr(), ci.data_ptr(), va.data_ptr(), m,
+                                  native.GMRES_MGS_1R, wp, need, stream)
+    assert rc == native.GMRES_OK
+    try:
+        rc, nb = native.gmres_matrix_storage_bytes(ctx)
+        ns = (p.n + 63) // 64
+        total = padded_entries(p)
+        up = lambda v: (v + 255) // 256 * 256
+        o_ci = up(8 * (ns + 1))
+        o_va = up(o_ci + 4 * total)
+        assert rc == native.GMRES_OK and nb == o_va + 8 * total
+        assert native.gmres_get_format(ctx)[1] == native.GMRES_FORMAT_CSR
+        buf = torch.empty(nb + 512, dtype=torch.uint8, device="cuda")
+        bp = buf.data_ptr() + (-buf.data_ptr()) % 256
+        assert native.gmres_set_matrix_storage(ctx, bp, nb - 8) == native.GMRES_ERR_ARG
+        assert native.gmres_set_matrix_storage(ctx, bp + 8, nb) == native.GMRES_ERR_ARG
+        host = np.zeros(nb // 8 + 64)
+        assert native.gmres_set_matrix_storage(ctx, host.ctypes.data, nb) == native.GMRES_ERR_ARG
+        assert native.gmres_set_matrix_storage(ctx, bp, nb) == native.GMRES_OK
+        rc, fmt, stored = native.gmres_get_format(ctx)
+        assert fmt == native.GMRES_FORMAT_SELL64 and stored == total
+        # the copy gives the same product as the CSR arrays
+        x = torch.from_numpy(P.rng(5, 1).standard_normal(p.n)).cuda()
+        y1 = torch.empty_like(x)
+        y0 = torch.empty_like(x)
+        assert native.gmres_spmv(ctx, x.data_ptr(), y1.data_ptr()) == native.GMRES_OK
+        assert native.gmres_set_matrix_storage(ctx, None, 0) == native.GMRES_OK
+        assert native.gmres_get_format(ctx)[1] == native.GMRES_FORMAT_CSR
+        assert native.gmres_spmv(ctx, x.data_ptr(), y0.data_ptr()) == native.GMRES_OK
+        torch.cuda.synchronize()
+        absA = p.scipy().copy()
+        absA.data = np.abs(absA.data)
+        bound = 8 * np.finfo(float).eps * (absA @ np.abs(x.cpu().numpy()))
+        assert np.all(np.abs((y0 - y1).cpu().numpy()) <= bound)
+    finally:
+        native.gmres_destroy(ctx)

@@ -262,3 +262,43 @@ def test_error_paths(scheme):
     for rtol in (-1.0, float("nan")):
         rc, _ = native.gmres_solve(s.ctx, bt.data_ptr(), x.data_ptr(), rtol, 10)
         assert rc == native.GMRES_ERR_ARG
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_hist_orth(scheme):
+    """||S||_2 per column from the library equals numpy's 2-norm of I - (I + L^T)^{-1} built
+    from the library's own T (or L), and stays within the oracle's level."""
+    p = CASES["cfg3_12"]
+    m = 40
+    log(f"hist_orth {scheme}")
+    g = gpu_run(p, scheme, m=m, rtol=0.0, max_iters=m, orth=True)
+    orth = g["res"].orth
+    assert len(orth) == m
+    if scheme == "mgs":
+        assert np.all(np.isnan(orth))
+        return
+    j = g["j"]
+    T = g["T"][:j, :j]
+    if scheme == "cgs2":
+        T = np.linalg.solve(np.eye(j) + np.tril(T, -1).T, np.eye(j))
+    want = np.array([np.linalg.norm(np.eye(k) - T[:k, :k], 2) for k in range(1, j + 1)])
+    assert orth[0] == 0.0
+    assert np.max(np.abs(orth - want) / np.maximum(want, 1e-300)) <= 1e-8
+    o = oracle_run(p, scheme, m=m, rtol=0.0, max_iters=m)
+    To = o.T[:j, :j]
+    if scheme == "cgs2":
+        To = np.linalg.solve(np.eye(j) + np.tril(To, -1).T, np.eye(j))
+    ref = np.array([np.linalg.norm(np.eye(k) - To[:k, :k], 2) for k in range(1, j + 1)])
+    eps = np.finfo(float).eps
+    assert np.all(orth <= 2.0 * ref + 10 * eps)
+
+
+def test_hist_orth_restarts():
+    """Across restarts each cycle starts again at 0 (its first basis vector)."""
+    p = CASES["cfg1"]
+    log("hist_orth restarts")
+    g = gpu_run(p, "mgs1r", m=10, rtol=1e-8, orth=True)
+    r = g["res"]
+    assert r.cycles >= 3 and len(r.orth) == r.iters
+    assert np.all(r.orth[0::10] == 0.0) and np.all(np.isfinite(r.orth))
+    assert np.all(r.orth[1:10] > 0.0)
