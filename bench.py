@@ -99,6 +99,86 @@ def cpu_baseline(p, m):
                       "sequential FP64 C"}
 
 
+def kernel_table(kt, ms_per_solve):
+    out = {}
+    for name, st in kt.items():
+        if st["launches"]:
+            out[name] = {"launches": st["launches"], "avg_us": st["ms"] / st["launches"] * 1e3,
+                         "avg_bytes": st["bytes"] / st["launches"],
+                         "GBps": st["bytes"] / (st["ms"] * 1e-3) / 1e9,
+                         "time_share": st["ms"] / ms_per_solve}
+    return out
+
+
+def ir32_result(args, p, rp, ci, va, b, x, x64, s64_per_solve, iters64):
+    """The FP32-basis scheme on the same system and tolerance: speed, and its
+    solution's error against the float64 one and against x_true."""
+    import numpy as np
+    import torch
+
+    from paper_1809_05805_amd.native import GmresSolver
+
+    s = GmresSolver(rp, ci, va, p.m, "mgs1r_ir32")
+    k = max(1, min(args.steps, 5))
+    dt, iters, res, kt = time_solves(s, b, x, p.rtol, args.max_iters, k, 1, timing=True)
+    xr = x.cpu().numpy()
+    A = p.scipy()
+    rel_res = float(np.linalg.norm(p.b - A @ xr) / np.linalg.norm(p.b))
+    x64n = x64.cpu().numpy()
+    err64 = float(np.linalg.norm(xr - x64n) / np.linalg.norm(x64n))
+    errt = float(np.linalg.norm(xr - p.x_true) / np.linalg.norm(p.x_true))
+    err64t = float(np.linalg.norm(x64n - p.x_true) / np.linalg.norm(p.x_true))
+    log(f"mgs1r_ir32: {iters / k:.0f} iters/solve, {dt / k * 1e3:.2f} ms/solve, rel_res {rel_res:.2e}, "
+        f"err vs fp64 {err64:.2e}")
+    s.close()
+    return {"scheme": "one-reduce on a float32 basis, float64 refinement at every restart",
+            "m": p.m, "iters_per_s": round(iters / dt, 2), "ms_per_solve": round(dt / k * 1e3, 3),
+            "iters_per_solve": iters // k, "fp64_iters_per_solve": iters64,
+            "speedup_vs_fp64_solve": round(s64_per_solve / (dt / k), 3),
+            "converged": bool(res.converged), "rel_res_true_fp64_recomputed": rel_res,
+            "err_vs_fp64_solution": err64, "err_vs_x_true": errt, "fp64_err_vs_x_true": err64t,
+            "kernels": kernel_table(kt, dt / k * 1e3)}
+
+
+def precision_config(args):
+    """The 256^3 precision workload: float64 one-reduce GMRES(40) vs the
+    FP32-basis scheme at 1e-10, one solve each after a warm-up."""
+    import numpy as np
+    import torch
+
+    from paper_1809_05805_amd import problems
+    from paper_1809_05805_amd.native import GmresSolver
+
+    t0 = time.perf_counter()
+    p = problems.make_config("cfg2", N=args.precision_N)
+    log(f"precision config n={p.n} nnz={p.nnz} built in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (p.row_ptr, p.col_idx, p.vals))
+    b = torch.from_numpy(p.b).to(dev)
+    x = torch.zeros(p.n, dtype=torch.float64, device=dev)
+    out = {"workload": f"3D 7-point upwind convection-diffusion {args.precision_N}^3, GMRES(40) to 1e-10",
+           "n": p.n, "nnz": p.nnz}
+    sols = {}
+    A = p.scipy()
+    for scheme in ("mgs1r", "mgs1r_ir32"):
+        s = GmresSolver(rp, ci, va, 40, scheme)
+        dt, iters, res, kt = time_solves(s, b, x, 1e-10, args.max_iters, 1, 1, timing=True)
+        sols[scheme] = x.cpu().numpy()
+        rel_res = float(np.linalg.norm(p.b - A @ sols[scheme]) / np.linalg.norm(p.b))
+        out[scheme] = {"iters_per_s": round(iters / dt, 2), "ms_per_solve": round(dt * 1e3, 3),
+                       "iters": iters, "converged": bool(res.converged),
+                       "rel_res_true_fp64_recomputed": rel_res,
+                       "err_vs_x_true": float(np.linalg.norm(sols[scheme] - p.x_true) /
+                                              np.linalg.norm(p.x_true)),
+                       "kernels": kernel_table(kt, dt * 1e3)}
+        log(f"precision {scheme}: {iters} iters, {dt * 1e3:.1f} ms, rel_res {rel_res:.2e}")
+        s.close()
+    out["mgs1r_ir32"]["err_vs_fp64_solution"] = float(
+        np.linalg.norm(sols["mgs1r_ir32"] - sols["mgs1r"]) / np.linalg.norm(sols["mgs1r"]))
+    out["speedup_vs_fp64_solve"] = round(out["mgs1r"]["ms_per_solve"] / out["mgs1r_ir32"]["ms_per_solve"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +188,10 @@ def main():
     ap.add_argument("--max-iters", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baselines", action="store_true", help="skip the MGS and CGS2 solves")
+    ap.add_argument("--no-ir32", action="store_true", help="skip the FP32-basis solve")
+    ap.add_argument("--precision-N", type=int, default=0,
+                    help="also run the FP32-basis vs float64 comparison on an N^3 system (256: the "
+                         "precision workload)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a reference kernel "
                          "for hardware byte counters)")
@@ -187,6 +271,11 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
+    x64 = x.clone()
+    if not args.no_ir32:
+        out["fp32_ir"] = ir32_result(args, p, rp, ci, va, b, x, x64, dt / args.steps, res.iters)
+    if args.precision_N:
+        out["fp32_ir_precision_config"] = precision_config(args)
     if not args.no_baselines:
         for scheme in ("mgs", "cgs2"):
             sv = GmresSolver(rp, ci, va, m, scheme)

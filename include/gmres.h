@@ -1,8 +1,9 @@
 /*
- * gmres.h - restarted GMRES(m) on one AMD MI355X (gfx950), FP64, with three
+ * gmres.h - restarted GMRES(m) on one AMD MI355X (gfx950) with three
  * Gram-Schmidt schemes for the Arnoldi process, after Swirydowicz, Langou,
  * Ananthan, Yang, Thomas, "Low synchronization GMRES algorithms"
- * (arXiv:1809.05805):
+ * (arXiv:1809.05805), in FP64, and the one-reduce scheme also on an FP32
+ * basis inside FP64 iterative refinement:
  *
  *   GMRES_MGS_1R  one global reduction per Arnoldi step: the level-2 MGS in
  *                 compact WY form with lagged normalization of R's diagonal
@@ -16,6 +17,20 @@
  *                 i+2 reductions in iteration i.
  *   GMRES_CGS2    two reductions per step: lagged iterated classical
  *                 Gram-Schmidt (Section II, level-2 CGS2 with normalization lag).
+ *   GMRES_MGS_1R_IR32  the GMRES_MGS_1R step on a float32 basis. Every
+ *                 restart computes r = b - A x and ||r|| in float64 from the
+ *                 CSR arrays (the float64 master), checks the tolerance on
+ *                 that true residual, and starts the cycle from
+ *                 float32(r / ||r||). Inside the cycle the basis, the SpMV
+ *                 output, the SpMV (float32 values of the sliced copy of A, or
+ *                 the CSR values with float32 vector entries), the projection
+ *                 products and per-lane sums and the MAXPY are float32; the
+ *                 cross-lane and device-wide sums, the lagged norm, the T
+ *                 matrix, the Hessenberg column, the Givens least squares and
+ *                 the back substitution are float64, and x += ||r|| V y
+ *                 accumulates in float64. Restarted GMRES is then iterative
+ *                 refinement with float32 inner cycles; the precision is not
+ *                 discussed in the paper.
  *
  * The problem is A x = b with residual r = b - A x and initial guess x0
  * (Section III); A is in CSR form (Section V-B); all vectors live in device
@@ -41,7 +56,7 @@ extern "C" {
 
 typedef struct gmres_ctx gmres_ctx; /* opaque */
 
-typedef enum { GMRES_MGS = 0, GMRES_MGS_1R = 1, GMRES_CGS2 = 2 } gmres_scheme;
+typedef enum { GMRES_MGS = 0, GMRES_MGS_1R = 1, GMRES_CGS2 = 2, GMRES_MGS_1R_IR32 = 3 } gmres_scheme;
 
 typedef enum {
   GMRES_OK = 0,
@@ -117,7 +132,8 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
  *   lower part of V^T V: entry i of a cycle covers its basis vectors
  *   v_0..v_i (the leading (i+1) x (i+1) block of T; 0 for i = 0). Computed on
  *   the host after each cycle from the T (one-reduce MGS) or L (CGS2) the
- *   device built, by power iteration to a relative change of 1e-14; NaN for
+ *   device built (T for GMRES_MGS_1R_IR32 too), by power iteration to a
+ *   relative change of 1e-14; NaN for
  *   GMRES_MGS, which forms neither. It adds host work per cycle; pass NULL
  *   when timing.
  * Blocks until the solve has finished on the stream. Returns GMRES_OK when the
@@ -186,23 +202,26 @@ int gmres_spmv(gmres_ctx* ctx, const double* x, double* y);
  * Diagnostics of the last cycle that completed at least one column (host
  * copies, each nullable):
  *   H (host, (m+1) x m, column-major): the unrotated Hessenberg matrix;
- *   T (host, (m+2) x (m+2), column-major): for GMRES_MGS_1R the Malard-Paige
+ *   T (host, (m+2) x (m+2), column-major): for GMRES_MGS_1R (and _IR32) the Malard-Paige
  *     T = (I + L^T)^{-1} built one column per step, whose leading blocks give
  *     Paige's loss-of-orthogonality measure S = I - T (Section II); for
  *     GMRES_CGS2 the strictly lower L with V^T V = I + L + L^T, one row per
  *     step; zeros for GMRES_MGS. Columns 0..j-1 are formed: the cycle's last
  *     step computes only the norm of column j (and of a cycle that ends on
  *     the tolerance check, column j is formed too);
- *   g (host, m+2): the rotated right-hand side of the least-squares problem;
+ *   g (host, m+2): the rotated right-hand side of the least-squares problem
+ *     (for GMRES_MGS_1R_IR32 relative to the cycle's restart residual norm:
+ *     the cycle starts from r / ||r||, and H is that of the float32 basis);
  *   j (host): the number of columns that cycle completed.
  */
 int gmres_last_cycle(gmres_ctx* ctx, double* H, double* T, double* g, int32_t* j);
 
 /*
- * Device pointer to the basis V inside the workspace and its leading
+ * Device pointer to the float64 basis V inside the workspace and its leading
  * dimension (in elements). Columns 0..j-1 of the last cycle hold its
  * orthonormal basis until the next solve, except that a solve that ends by
  * converging overwrites column 0 with the final residual it verified.
+ * GMRES_ERR_ARG for GMRES_MGS_1R_IR32, whose basis is float32.
  */
 int gmres_basis(gmres_ctx* ctx, double** V, int64_t* ldv);
 

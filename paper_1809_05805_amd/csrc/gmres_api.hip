@@ -95,12 +95,16 @@ int format_override() {
 struct Layout {
   int64_t ldv;
   int rpt, G, NG, pstride;
-  size_t V, w, H, R, T, TT, g, gh, cs, sn, coef, coef2, y, partials, gpartials, counters, state, total;
+  size_t V, w, r64, H, R, T, TT, g, gh, cs, sn, coef, coef2, y, partials, gpartials, counters,
+      state, total;
 };
 
-bool make_layout(int64_t n, int m, Layout* L) {
+// The FP64 schemes keep the basis V and the SpMV output w in float64; the
+// FP32-basis scheme keeps them in float32 plus a float64 restart residual.
+// Columns are 64 elements apart at least, so every column starts 256-byte aligned.
+bool make_layout(int64_t n, int m, int scheme, Layout* L) {
   if (n < 1 || m < 1 || m > GMRES_MAX_RESTART) return false;
-  L->ldv = (int64_t)round_up((size_t)n, 32);
+  L->ldv = (int64_t)round_up((size_t)n, 64);
   L->rpt = pick_rpt(n);
   L->G = pick_grid(n, L->rpt);
   L->NG = (L->G + kGroup - 1) / kGroup;
@@ -112,8 +116,10 @@ bool make_layout(int64_t n, int m, Layout* L) {
     return at;
   };
   const size_t d = sizeof(double);
-  L->V = take((size_t)L->ldv * (size_t)(m + 2) * d);
-  L->w = take((size_t)L->ldv * d);
+  const size_t vb = scheme == kSchemeIr32 ? sizeof(float) : d;
+  L->V = take((size_t)L->ldv * (size_t)(m + 2) * vb);
+  L->w = take((size_t)L->ldv * vb);
+  L->r64 = scheme == kSchemeIr32 ? take((size_t)L->ldv * d) : 0;
   L->H = take((size_t)(m + 1) * (size_t)m * d);
   L->R = take((size_t)(m + 1) * (size_t)m * d);
   L->T = take((size_t)(m + 2) * (size_t)(m + 2) * d);
@@ -276,7 +282,7 @@ void orth_history(gmres_ctx* c, int j, double* out) {
   }
   const int ldt = c->m + 2;
   std::vector<double> S((size_t)j * j, 0.0);  // column-major, ld j
-  if (c->scheme == kSchemeMgs1r) {
+  if (c->scheme != kSchemeCgs2) {
     for (int col = 0; col < j; ++col)
       for (int i = 0; i < col; ++i) S[(size_t)col * j + i] = -c->h_T[(size_t)col * ldt + i];
   } else {
@@ -326,14 +332,16 @@ void collect_timing(gmres_ctx* c, int j, bool stopped_at_restart) {
 // no copy is planned, the SpMV reads the CSR arrays.
 int plan_format(gmres_ctx* c) {
   c->format = kFormatCsr;
-  c->sell = Sell{nullptr, nullptr, nullptr, 0, 0};
+  c->sell = Sell{nullptr, nullptr, nullptr, nullptr, 0, 0};
   c->sell_sp.clear();
   c->sell_entries = 0;
   c->sell_bytes = 0;
   const int want = format_override();
   if (want == kFormatCsr || c->nnz == 0 || c->A.n >= kSellMaxRows) return GMRES_OK;
   const int64_t ns = (c->A.n + 63) / 64;
-  int* dw = reinterpret_cast<int*>(c->ws.V);  // ns ints fit easily in n (m+2) doubles
+  // ns ints fit easily in the basis region (n (m+2) doubles, or floats)
+  int* dw = c->scheme == kSchemeIr32 ? reinterpret_cast<int*>(c->ws.Vf)
+                                     : reinterpret_cast<int*>(c->ws.V);
   std::vector<int> wh((size_t)ns);
   if (launch_sell_width(c->A, ns, dw, c->stream) ||
       hipMemcpyAsync(wh.data(), dw, sizeof(int) * (size_t)ns, hipMemcpyDeviceToHost, c->stream) !=
@@ -354,14 +362,18 @@ int plan_format(gmres_ctx* c) {
   c->sell_entries = total;
   c->o_ci = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
   c->o_va = round_up(c->o_ci + sizeof(int) * (size_t)total, kAlign);
-  c->sell_bytes = c->o_va + sizeof(double) * (size_t)total;
+  const size_t vsize = c->scheme == kSchemeIr32 ? sizeof(float) : sizeof(double);
+  c->sell_bytes = c->o_va + vsize * (size_t)total;
   return GMRES_OK;
 }
 
-// y = A x or y = b - A x in the context's format.
+// y = A x or y = b - A x in float64: from the sliced copy when it holds
+// float64 values, else from the CSR arrays (the FP32-basis scheme's copy
+// holds float32 values, so its float64 products read the CSR arrays).
 int spmv(gmres_ctx* c, const double* x, const double* b, double* y, const DevState* st,
          hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  if (c->format == kFormatSell) return launch_spmv_sell(c->sell, c->A.n, x, b, y, st, s, e0, e1);
+  if (c->format == kFormatSell && c->scheme != kSchemeIr32)
+    return launch_spmv_sell(c->sell, c->A.n, x, b, y, st, s, e0, e1);
   return launch_spmv(c->A, c->S, x, b, y, st, s, e0, e1);
 }
 
@@ -370,14 +382,24 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
   const Ws& ws = c->ws;
   hipStream_t s = c->stream;
   const int rpt = c->L.rpt, G = c->L.G;
-  const double n8 = 8.0 * (double)c->A.n;
-  // bytes of the matrix in the format the SpMV reads
+  const bool f32 = c->scheme == kSchemeIr32;
+  const double n8 = (f32 ? 4.0 : 8.0) * (double)c->A.n;  // one basis column
+  // bytes of the matrix in the format the step's SpMV reads
   const double csr = c->format == kFormatSell
-                         ? 12.0 * (double)c->sell_entries + 8.0 * (double)(c->sell.ns + 1)
+                         ? (f32 ? 8.0 : 12.0) * (double)c->sell_entries + 8.0 * (double)(c->sell.ns + 1)
                          : 12.0 * (double)c->nnz + 4.0 * (double)(c->A.n + 1);
   auto col = [&](int q) { return ws.V + (size_t)q * (size_t)ws.ldv; };
   TRY(launch_cycle_begin(ws, s));
-  TRY(spmv(c, x, b, col(0), nullptr, s));  // V[:,0] = b - A x
+  if (f32) {
+    // float64 restart residual and its norm (the restart check), then the
+    // cycle's first basis vector r / ||r|| in float32
+    TRY(spmv(c, x, b, ws.r64, nullptr, s));
+    TRY(launch_axpy_dot(ws, rpt, ws.r64, nullptr, nullptr, ws.r64, kTailIrBeta, 0, 0, m_eff, 0.0,
+                        G, s));
+    TRY(launch_first_f32(ws, s));
+  } else {
+    TRY(spmv(c, x, b, col(0), nullptr, s));  // V[:,0] = b - A x
+  }
   if (c->scheme == kSchemeMgs) {
     TRY(launch_axpy_dot(ws, rpt, col(0), nullptr, nullptr, col(0), kTailMgsBeta, 0, 0, m_eff, 0.0,
                         G, s));
@@ -395,7 +417,7 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
       TRY(launch_scale(ws, w, s));
     }
   } else {
-    const int tail = c->scheme == kSchemeMgs1r ? kTailLagged1r : kTailLaggedCgs2;
+    const int tail = c->scheme == kSchemeCgs2 ? kTailLaggedCgs2 : kTailLagged1r;
     // Step k's fused kernel runs iff the cycle reaches step k (j >= k, or the
     // restart check at k = 0 ends it); the rest of step k runs iff j > k.
     for (int k = 0; k <= m_eff; ++k) {
@@ -404,43 +426,44 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
         const bool last = k == m_eff;
         int wsrc = last ? kWNone : (c->format == kFormatSell ? kWSell : kWSpmv);
         double bytes = last ? n8 : csr + n8 * (k + 1) + n8;
-        if (!last && c->split) {
+        if (!last && c->split && !f32) {
           TimedLaunch t(c, GMRES_KSTAT_SPMV, k, k, csr + 2 * n8);
           TRY(spmv(c, col(k), nullptr, ws.w, ws.st, s, t.e0, t.e1));
           wsrc = kWLoad;
           bytes = n8 * (k + 2);
         }
         TimedLaunch t(c, GMRES_KSTAT_STEP, k, k, bytes);
-        TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k, last ? 0 : k, wsrc, m_eff, tail, G, s, t.e0,
-                         t.e1));
+        TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k, last ? 0 : k, wsrc, m_eff, tail, G, f32, s,
+                         t.e0, t.e1));
       }
       if (k == m_eff) break;
       {
         TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
-        TRY(launch_maxpy(ws, rpt, k, 0, G, s, t.e0, t.e1));
+        TRY(launch_maxpy(ws, rpt, k, 0, G, f32, s, t.e0, t.e1));
       }
       if (c->scheme == kSchemeCgs2) {
         {
           TimedLaunch t(c, GMRES_KSTAT_STEP, k, k + 1, n8 * (k + 2));
-          TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k + 1, k + 1, kWNone, m_eff, kTailCgs2Second, G, s,
-                           t.e0, t.e1));
+          TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k + 1, k + 1, kWNone, m_eff, kTailCgs2Second, G,
+                           false, s, t.e0, t.e1));
         }
         TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
-        TRY(launch_maxpy(ws, rpt, k, 1, G, s, t.e0, t.e1));
+        TRY(launch_maxpy(ws, rpt, k, 1, G, false, s, t.e0, t.e1));
       }
     }
   }
-  TRY(launch_cycle_end(ws, rpt, x, G, s));
+  TRY(launch_cycle_end(ws, rpt, x, G, f32, s));
   return GMRES_OK;
 }
 
 // ||b - A x|| into the state's beta, without touching the basis.
 int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
   const Ws& ws = c->ws;
+  double* r = c->scheme == kSchemeIr32 ? ws.r64 : ws.w;
   TRY(launch_cycle_begin(ws, c->stream));
-  TRY(spmv(c, x, b, ws.w, nullptr, c->stream));
-  TRY(launch_axpy_dot(ws, c->L.rpt, ws.w, nullptr, nullptr, ws.w, kTailFinalRes, 0, 0, 0, 0.0,
-                      c->L.G, c->stream));
+  TRY(spmv(c, x, b, r, nullptr, c->stream));
+  TRY(launch_axpy_dot(ws, c->L.rpt, r, nullptr, nullptr, r, kTailFinalRes, 0, 0, 0, 0.0, c->L.G,
+                      c->stream));
   return GMRES_OK;
 }
 
@@ -449,9 +472,9 @@ int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
 extern "C" {
 
 size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme) {
-  if (scheme < GMRES_MGS || scheme > GMRES_CGS2) return 0;
+  if (scheme < GMRES_MGS || scheme > GMRES_MGS_1R_IR32) return 0;
   Layout L;
-  if (!make_layout(n, m, &L)) return 0;
+  if (!make_layout(n, m, scheme, &L)) return 0;
   return L.total;
 }
 
@@ -472,14 +495,14 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   if (!out) return GMRES_ERR_ARG;
   *out = nullptr;
   if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31) || m < 1 ||
-      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_CGS2)
+      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_MGS_1R_IR32)
     return GMRES_ERR_ARG;
   if (!is_device_ptr(row_ptr) || !is_device_ptr(workspace) ||
       (nnz > 0 && (!is_device_ptr(col_idx) || !is_device_ptr(vals))))
     return GMRES_ERR_ARG;
   if (((uintptr_t)workspace % kAlign) != 0) return GMRES_ERR_ARG;
   Layout L;
-  if (!make_layout(n, m, &L)) return GMRES_ERR_ARG;
+  if (!make_layout(n, m, scheme, &L)) return GMRES_ERR_ARG;
   if (ws_bytes < L.total) return GMRES_ERR_WORKSPACE;
 
   gmres_ctx* c = new (std::nothrow) gmres_ctx();
@@ -494,8 +517,19 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   c->stream = (hipStream_t)hip_stream;
   char* base = (char*)workspace;
   Ws& ws = c->ws;
-  ws.V = (double*)(base + L.V);
-  ws.w = (double*)(base + L.w);
+  if (scheme == kSchemeIr32) {
+    ws.V = nullptr;
+    ws.w = nullptr;
+    ws.Vf = (float*)(base + L.V);
+    ws.wf = (float*)(base + L.w);
+    ws.r64 = (double*)(base + L.r64);
+  } else {
+    ws.V = (double*)(base + L.V);
+    ws.w = (double*)(base + L.w);
+    ws.Vf = nullptr;
+    ws.wf = nullptr;
+    ws.r64 = nullptr;
+  }
   ws.H = (double*)(base + L.H);
   ws.R = (double*)(base + L.R);
   ws.T = (double*)(base + L.T);
@@ -586,7 +620,7 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
   if (!c) return GMRES_ERR_ARG;
   if (!storage) {
     c->format = kFormatCsr;
-    c->sell = Sell{nullptr, nullptr, nullptr, 0, 0};
+    c->sell = Sell{nullptr, nullptr, nullptr, nullptr, 0, 0};
     return GMRES_OK;
   }
   if (c->sell_bytes == 0 || bytes < c->sell_bytes || ((uintptr_t)storage % kAlign) != 0 ||
@@ -594,7 +628,10 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
     return GMRES_ERR_ARG;
   char* base = (char*)storage;
   const int64_t ns = (int64_t)c->sell_sp.size() - 1;
-  const Sell S{(const int64_t*)base, (int*)(base + c->o_ci), (double*)(base + c->o_va), ns, c->A.n};
+  const bool f32 = c->scheme == kSchemeIr32;
+  const Sell S{(const int64_t*)base, (int*)(base + c->o_ci),
+               f32 ? nullptr : (double*)(base + c->o_va), f32 ? (float*)(base + c->o_va) : nullptr,
+               ns, c->A.n};
   if (hipMemcpyAsync(base, c->sell_sp.data(), sizeof(int64_t) * (size_t)(ns + 1),
                      hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemsetAsync(&c->ws.st->bad_csr, 0, sizeof(int32_t), c->stream) != hipSuccess ||
@@ -621,7 +658,7 @@ int gmres_spmv(gmres_ctx* c, const double* x, double* y) {
 }
 
 int gmres_basis(gmres_ctx* c, double** V, int64_t* ldv) {
-  if (!c) return GMRES_ERR_ARG;
+  if (!c || c->scheme == kSchemeIr32) return GMRES_ERR_ARG;
   if (V) *V = c->ws.V;
   if (ldv) *ldv = c->ws.ldv;
   return GMRES_OK;
@@ -717,11 +754,13 @@ int gmres_solve(gmres_ctx* c, const double* b, double* x, double rtol, int64_t m
     }
     const int j = st.j;
     if (j > 0) {
+      // the FP32-basis cycle's g is relative to its restart residual norm
+      const double gs = st.xscale / bnorm;
       if (hist_res)
-        for (int q = 0; q < j; ++q) hist_res[it + q] = c->h_gh[q + 1] / bnorm;
+        for (int q = 0; q < j; ++q) hist_res[it + q] = c->h_gh[q + 1] * gs;
       if (hist_orth) orth_history(c, j, hist_orth + it);
       loc.cycles += 1;
-      loc.rel_res_est = fabs(c->h_g[j]) / bnorm;
+      loc.rel_res_est = fabs(c->h_g[j]) * gs;
       memcpy(c->last_H.data(), c->h_H, sizeof(double) * c->last_H.size());
       memcpy(c->last_T.data(), c->h_T, sizeof(double) * c->last_T.size());
       memcpy(c->last_g.data(), c->h_g, sizeof(double) * c->last_g.size());

@@ -136,29 +136,36 @@ __device__ inline double ld_at(const double* base, uint32_t boff) {
   return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + boff);
 }
 
-// A raw buffer resource over elements [0, nelem) of a wave-uniform array: its
-// descriptor sits in scalar registers, so a load needs only the lane's 32-bit
-// byte offset; offsets at or past the end read 0 instead of memory. The third
-// descriptor word is the gfx9-family raw-buffer format (32-bit data, no
-// swizzle).
+// A raw buffer resource over elements [0, nelem) of a wave-uniform array of T
+// (double or float): its descriptor sits in scalar registers, so a load needs
+// only the lane's 32-bit byte offset; offsets at or past the end read 0
+// instead of memory. The third descriptor word is the gfx9-family raw-buffer
+// format (32-bit data, no swizzle).
+template <typename T>
 struct BufCol {
   __amdgpu_buffer_rsrc_t r;
-  __device__ BufCol(const double* base, int64_t nelem) {
-    const int64_t nb = nelem * 8;
-    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0,
+  __device__ BufCol(const T* base, int64_t nelem) {
+    const int64_t nb = nelem * (int64_t)sizeof(T);
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0,
                                           (int)(nb < 0x7ffffff8 ? nb : 0x7ffffff8), 0x00020000);
   }
-  __device__ double operator()(uint32_t boff) const {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)boff, 0, 0));
+  __device__ T operator()(uint32_t boff) const {
+    if constexpr (sizeof(T) == 8)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)boff, 0, 0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, 0));
   }
 };
 
 // The same interface over a plain global load (scalar base + 32-bit offset);
-// callers keep their offsets inside [0, 8 nelem).
+// callers keep their offsets inside [0, sizeof(T) nelem).
+template <typename T>
 struct GlbCol {
-  const double* b;
-  __device__ GlbCol(const double* base, int64_t) : b(base) {}
-  __device__ double operator()(uint32_t boff) const { return ld_at(b, boff); }
+  const T* b;
+  __device__ GlbCol(const T* base, int64_t) : b(base) {}
+  __device__ T operator()(uint32_t boff) const {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(b) + boff);
+  }
 };
 
 //   GMRES_PROJ_BUFFER / GMRES_MAXPY_BUFFER  1: the projection's (MAXPY's and
@@ -169,8 +176,26 @@ struct GlbCol {
 #ifndef GMRES_MAXPY_BUFFER
 #define GMRES_MAXPY_BUFFER 0
 #endif
-using ProjCol = std::conditional_t<GMRES_PROJ_BUFFER != 0, BufCol, GlbCol>;
-using MaxpyCol = std::conditional_t<GMRES_MAXPY_BUFFER != 0, BufCol, GlbCol>;
+template <typename T>
+using ProjCol = std::conditional_t<GMRES_PROJ_BUFFER != 0, BufCol<T>, GlbCol<T>>;
+template <typename T>
+using MaxpyCol = std::conditional_t<GMRES_MAXPY_BUFFER != 0, BufCol<T>, GlbCol<T>>;
+
+// The basis and SpMV-output arrays of the workspace in the basis type.
+template <typename VT>
+__device__ __host__ inline VT* basis_of(const Ws& ws) {
+  if constexpr (sizeof(VT) == 8)
+    return ws.V;
+  else
+    return ws.Vf;
+}
+template <typename VT>
+__device__ __host__ inline VT* wbuf_of(const Ws& ws) {
+  if constexpr (sizeof(VT) == 8)
+    return ws.w;
+  else
+    return ws.wf;
+}
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
@@ -249,8 +274,8 @@ __device__ inline void spmv_load_cv(const Csr& A, const int (&e0)[R], const int 
 
 // Gathers, products, the long-row tail, the reduction over the S lanes and
 // the emit of one pass.
-template <int R, int S, int EPL, typename Emit>
-__device__ inline void spmv_finish(const Csr& A, const double* __restrict__ x, int p0,
+template <int R, int S, int EPL, typename XT, typename Emit>
+__device__ inline void spmv_finish(const Csr& A, const XT* __restrict__ x, int p0,
                                    const int (&e0)[R], const int (&e1)[R], const int (&c)[R][EPL],
                                    const double (&v)[R][EPL], Emit emit) {
   constexpr int NSUB = 256 / S;
@@ -259,14 +284,14 @@ __device__ inline void spmv_finish(const Csr& A, const double* __restrict__ x, i
 #pragma unroll
   for (int q = 0; q < R; ++q)
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) xv[q][t] = x[(unsigned)c[q][t]];
+    for (int t = 0; t < EPL; ++t) xv[q][t] = (double)x[(unsigned)c[q][t]];
   double acc[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     double a = 0.0;
 #pragma unroll
     for (int t = 0; t < EPL; ++t) a += (e0[q] + sl + t * S < e1[q]) ? v[q][t] * xv[q][t] : 0.0;
-    for (int e = e0[q] + sl + EPL * S; e < e1[q]; e += S) a += A.va[e] * x[A.ci[e]];
+    for (int e = e0[q] + sl + EPL * S; e < e1[q]; e += S) a += A.va[e] * (double)x[A.ci[e]];
     acc[q] = a;
   }
   seg_sum<R, S>(acc, sl);
@@ -281,8 +306,8 @@ __device__ inline void spmv_finish(const Csr& A, const double* __restrict__ x, i
 // One pass over R * (256 / S) consecutive local rows starting at local row
 // p0; emit(local_row, value) is called by one lane per row (rows at or past
 // n give 0).
-template <int R, int S, int EPL, typename Emit>
-__device__ inline void spmv_pass(const Csr& A, const double* __restrict__ x, int64_t row0, int p0,
+template <int R, int S, int EPL, typename XT, typename Emit>
+__device__ inline void spmv_pass(const Csr& A, const XT* __restrict__ x, int64_t row0, int p0,
                                  Emit emit) {
   int e0[R], e1[R], c[R][EPL];
   double v[R][EPL];
@@ -294,8 +319,8 @@ __device__ inline void spmv_pass(const Csr& A, const double* __restrict__ x, int
 // The SpMV of a whole tile of TR rows as a software pipeline over passes:
 // while pass p gathers x, the row pointers and then the indices and values of
 // pass p+1 are already in flight.
-template <int R, int S, int EPL, int TR, typename Emit>
-__device__ inline void spmv_tile(const Csr& A, const double* __restrict__ x, int64_t row0,
+template <int R, int S, int EPL, int TR, typename XT, typename Emit>
+__device__ inline void spmv_tile(const Csr& A, const XT* __restrict__ x, int64_t row0,
                                  Emit emit) {
   constexpr int RPP = R * (256 / S);
   constexpr int NP = TR / RPP;
@@ -579,6 +604,8 @@ __global__ void k_init(Ws ws, int ncounters) {
     st->bad_csr = 0;
     st->reductions = 0;
     st->bnorm = st->tol_abs = st->beta = st->rho = st->inv_rho = st->gk = 0.0;
+    st->tol_cycle = 0.0;
+    st->xscale = 1.0;
   }
 }
 
@@ -609,6 +636,7 @@ __global__ void k_cycle_begin(Ws ws) {
     st->j = 0;
     st->true_conv = 0;
     st->breakdown = 0;
+    st->xscale = 1.0;
   }
 }
 
@@ -667,11 +695,14 @@ __global__ __launch_bounds__(256) void k_sell_width(Csr A, int64_t ns, int* __re
   if ((threadIdx.x & 63) == 0) width[s] = len < 1 ? 1 : len;
 }
 
-// Copy of A into the slices (sp already set), thread per row. A row whose
-// entries are not inside [0, nnz) or that is longer than its slice (a changed
-// structure; the copy can run right behind a structure check on the stream)
-// sets st->bad_csr and is not read.
-__global__ __launch_bounds__(256) void k_sell_fill(Csr A, Sell S, DevState* st) {
+// Copy of A into the slices (sp already set), thread per row, with values in
+// SVT (float64, or float32 for the FP32-basis scheme: rounded to nearest). A
+// row whose entries are not inside [0, nnz) or that is longer than its slice
+// (a changed structure; the copy can run right behind a structure check on
+// the stream) sets st->bad_csr and is not read.
+template <typename SVT>
+__global__ __launch_bounds__(256) void k_sell_fill(Csr A, Sell S, SVT* __restrict__ va,
+                                                    DevState* st) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t s = r >> 6;
   if (s >= S.ns) return;
@@ -690,46 +721,57 @@ __global__ __launch_bounds__(256) void k_sell_fill(Csr A, Sell S, DevState* st) 
     const int64_t e = b + (int64_t)j * 64 + l;
     const bool real = j < len;
     S.ci[e] = real ? A.ci[e0 + j] : self;
-    S.va[e] = real ? A.va[e0 + j] : 0.0;
+    va[e] = real ? (SVT)A.va[e0 + j] : (SVT)0;
   }
+}
+
+// The sliced copy's values in SVT.
+template <typename SVT>
+__device__ inline const SVT* sell_vals(const Sell& S) {
+  if constexpr (sizeof(SVT) == 8)
+    return S.va;
+  else
+    return S.vaf;
 }
 
 // Entries j0 .. j0+U-1 of lane l's row in the slice at entry offset b, width
 // W (>= 1): indices past W are clamped to W-1 (their products are masked by
 // the caller). Buffer loads over the slice's own entries (the descriptors are
 // scalar; a lane supplies a 32-bit byte offset).
-template <int U>
+template <int U, typename SVT>
 __device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l, int (&c)[U],
-                                 double (&v)[U]) {
+                                 SVT (&v)[U]) {
   const __amdgpu_buffer_rsrc_t rc =
       __builtin_amdgcn_make_buffer_rsrc(S.ci + b, (short)0, W * 64 * 4, 0x00020000);
-  const BufCol vb(S.va + b, (int64_t)W * 64);
+  const BufCol<SVT> vb(sell_vals<SVT>(S) + b, (int64_t)W * 64);
 #pragma unroll
   for (int t = 0; t < U; ++t) {
     const int j = j0 + t < W ? j0 + t : W - 1;
     const uint32_t e = (uint32_t)(j * 64 + l);
     c[t] = __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(e * 4u), 0, 0);
-    v[t] = vb(e * 8u);
+    v[t] = vb(e * (uint32_t)sizeof(SVT));
   }
 }
 
 // out[i] = (A x) at row 64 (s0 + i sstride) + l, i < NS, for the lane's row in
 // NS slices sstride apart (slice indices past the last are clamped; the
-// caller drops those rows). U entries per chunk; the column and value loads of the
-// next chunk (of this slice or the next) are issued before the gathers of
-// the current one are consumed, so one memory latency per chunk is hidden.
-template <int NS, int U>
-__device__ inline void sell_slices(const Sell& S, const double* __restrict__ x, int64_t s0,
-                                   int64_t sstride, int l, double (&out)[NS]) {
+// caller drops those rows). Values, x and the sums are in T (float64, or
+// float32 for the FP32-basis scheme). U entries per chunk; the column and
+// value loads of the next chunk (of this slice or the next) are issued before
+// the gathers of the current one are consumed, so one memory latency per
+// chunk is hidden.
+template <int NS, int U, typename T>
+__device__ inline void sell_slices(const Sell& S, const T* __restrict__ x, int64_t s0,
+                                   int64_t sstride, int l, T (&out)[NS]) {
   auto clampslice = [&](int64_t s) { return s < S.ns ? s : S.ns - 1; };
   // gathers from x[0, n) by 32-bit byte offset (the sliced format is used only
   // for n < 2^28)
-  const BufCol xb(x, S.n);
+  const BufCol<T> xb(x, S.n);
   int64_t b = S.sp[clampslice(s0)];
   int W = (int)((S.sp[clampslice(s0) + 1] - b) >> 6);
   int c[U];
-  double v[U];
-  sell_load<U>(S, b, W, 0, l, c, v);
+  T v[U];
+  sell_load<U, T>(S, b, W, 0, l, c, v);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     int64_t bn = b;
@@ -739,20 +781,20 @@ __device__ inline void sell_slices(const Sell& S, const double* __restrict__ x, 
       bn = S.sp[sn];
       Wn = (int)((S.sp[sn + 1] - bn) >> 6);
     }
-    double acc = 0.0;
+    T acc = (T)0;
     for (int j0 = 0; j0 < W; j0 += U) {
-      double xv[U], vv[U];
+      T xv[U], vv[U];
 #pragma unroll
       for (int t = 0; t < U; ++t) {
-        xv[t] = xb((uint32_t)c[t] * 8u);
+        xv[t] = xb((uint32_t)c[t] * (uint32_t)sizeof(T));
         vv[t] = v[t];
       }
       if (j0 + U < W)
-        sell_load<U>(S, b, W, j0 + U, l, c, v);
+        sell_load<U, T>(S, b, W, j0 + U, l, c, v);
       else if (i + 1 < NS)
-        sell_load<U>(S, bn, Wn, 0, l, c, v);
+        sell_load<U, T>(S, bn, Wn, 0, l, c, v);
 #pragma unroll
-      for (int t = 0; t < U; ++t) acc += (j0 + t < W) ? vv[t] * xv[t] : 0.0;
+      for (int t = 0; t < U; ++t) acc += (j0 + t < W) ? vv[t] * xv[t] : (T)0;
     }
     out[i] = acc;
     b = bn;
@@ -770,12 +812,24 @@ __global__ __launch_bounds__(256) void k_spmv_sell(Sell S, int64_t n, const doub
   const int l = threadIdx.x & 63;
   const int64_t s0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * NS;
   double out[NS];
-  sell_slices<NS, 8>(S, x, s0, 1, l, out);
+  sell_slices<NS, 8, double>(S, x, s0, 1, l, out);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int64_t r = (s0 + i) * 64 + l;
     if (r < n) y[r] = b ? b[r] - out[i] : out[i];
   }
+}
+
+// First basis vector of an FP32-basis cycle: Vf[:,0] = float(r64 / ||r64||)
+// (inv_rho holds 1 / ||r64|| from the restart reduction), skipped once the
+// restart check ended the cycle.
+__global__ __launch_bounds__(256) void k_first_f32(Ws ws) {
+  const DevState* st = ws.st;
+  if (st->done) return;
+  const double s = st->inv_rho;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ws.n; r += stride)
+    ws.Vf[r] = (float)(ws.r64[r] * s);
 }
 
 // ------------------------------------------------ the fused projection step
@@ -830,7 +884,7 @@ struct TailPrefetch {
     }
     if (tid == 0) {
       gprev = ws->g[k >= 1 ? k - 1 : 0];
-      tol = ws->st->tol_abs;
+      tol = ws->st->tol_cycle;
       red = ws->st->reductions;
     }
     if (ntri > 0) {
@@ -1055,7 +1109,7 @@ __device__ void tail_cgs2_second(const Ws& ws, const double* vals, int k) {
 //   1: rows tile0 + i*256 + wv*64 + l (the four wavefronts' loads of one i
 //      are adjacent, 2 KB contiguous per workgroup).
 // Either way every column read is 512 contiguous bytes per wavefront.
-template <int RPT, int S, int EPL, int WSRC>
+template <int RPT, int S, int EPL, int WSRC, typename VT>
 __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int nproj, int m_eff,
                                                 int tail, int G) {
   extern __shared__ double lds[];
@@ -1073,17 +1127,18 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   const int tile = tile_of_block(G);
   const int64_t row0 = (int64_t)tile * TR;
   const int64_t n = A.n;
-  const double* __restrict__ V = ws.V;
+  const VT* __restrict__ V = basis_of<VT>(ws);
+  VT* __restrict__ wout = wbuf_of<VT>(ws);
   const int64_t ldv = ws.ldv;
-  const double* __restrict__ u_g = V + (size_t)K * ldv;
+  const VT* __restrict__ u_g = V + (size_t)K * ldv;
   constexpr bool HAS_SPMV = WSRC != kWNone;
   // kWSell: the lane's rows are row 64 s + lane of slices s = row0/64 + wv RPT + i
-  double ws_out[RPT];
+  VT ws_out[RPT];
   if constexpr (WSRC == kWSell) {
     if constexpr (GMRES_FUSED_ROWMAP == 1)
-      sell_slices<RPT, 8>(SA, u_g, (row0 >> 6) + wv, 4, lane, ws_out);
+      sell_slices<RPT, 8, VT>(SA, u_g, (row0 >> 6) + wv, 4, lane, ws_out);
     else
-      sell_slices<RPT, 8>(SA, u_g, (row0 >> 6) + wv * RPT, 1, lane, ws_out);
+      sell_slices<RPT, 8, VT>(SA, u_g, (row0 >> 6) + wv * RPT, 1, lane, ws_out);
   }
 
   if constexpr (WSRC == kWSpmv) {
@@ -1105,29 +1160,31 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   // Loads take a uniform base rb plus a 32-bit byte offset (rows[i]): rb is
   // the tile's first row, or row n-1 for a padding tile past the end, so the
   // clamped rows lie in [rb, rb + TR) and the offsets are never negative.
-  double u[RPT], w[RPT];
+  // Products and per-lane sums are in VT (the basis type); the sums become
+  // float64 for the cross-lane and device-wide reduction.
+  VT u[RPT], w[RPT];
   uint32_t rows[RPT];
   const int64_t rb = row0 < n ? row0 : n - 1;
-  const double* __restrict__ Vt = V + rb;
+  const VT* __restrict__ Vt = V + rb;
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int lr = GMRES_FUSED_ROWMAP == 1 ? i * 256 + wv * 64 + lane : wv * 64 * RPT + i * 64 + lane;
     const int64_t r = row0 + lr;
     const bool ok = r < n;
-    rows[i] = (uint32_t)((ok ? r : n - 1) - rb) * 8u;
-    const double uv = ProjCol(u_g + rb, n - rb)(rows[i]);
-    u[i] = ok ? uv : 0.0;
+    rows[i] = (uint32_t)((ok ? r : n - 1) - rb) * (uint32_t)sizeof(VT);
+    const VT uv = ProjCol<VT>(u_g + rb, n - rb)(rows[i]);
+    u[i] = ok ? uv : (VT)0;
     if constexpr (WSRC == kWSpmv) {
-      w[i] = ok ? wl[lr] : 0.0;
-      if (ok) ws.w[r] = w[i];
+      w[i] = ok ? (VT)wl[lr] : (VT)0;
+      if (ok) wout[r] = w[i];
     } else if constexpr (WSRC == kWSell) {
-      w[i] = ok ? ws_out[i] : 0.0;
-      if (ok) ws.w[r] = w[i];
+      w[i] = ok ? ws_out[i] : (VT)0;
+      if (ok) wout[r] = w[i];
     } else if constexpr (WSRC == kWLoad) {
-      const double wv_ = ProjCol(ws.w + rb, n - rb)(rows[i]);
-      w[i] = ok ? wv_ : 0.0;
+      const VT wv_ = ProjCol<VT>(wout + rb, n - rb)(rows[i]);
+      w[i] = ok ? wv_ : (VT)0;
     } else {
-      w[i] = 0.0;
+      w[i] = (VT)0;
     }
   }
   double* myred = red + wv * P;
@@ -1141,29 +1198,29 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   // cache hit), which keeps the loads free of branches.
   constexpr int NVC = HAS_SPMV ? 2 * CB : CB;
   const int64_t nvalid = n - rb;  // rows rb .. n-1 of every column
-  auto load_chunk = [&](double (&buf)[CB][RPT], int j) {
+  auto load_chunk = [&](VT (&buf)[CB][RPT], int j) {
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      const ProjCol col(Vt + (size_t)(j + c) * ldv, nvalid);
+      const ProjCol<VT> col(Vt + (size_t)(j + c) * ldv, nvalid);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) buf[c][i] = col(rows[i]);
     }
   };
-  auto reduce_chunk = [&](const double (&vv)[CB][RPT], int j) {
+  auto reduce_chunk = [&](const VT (&vv)[CB][RPT], int j) {
     double acc[NVC];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      double p = 0.0, q = 0.0;
+      VT p = (VT)0, q = (VT)0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         p += vv[c][i] * u[i];
         if constexpr (HAS_SPMV) q += vv[c][i] * w[i];
       }
       if constexpr (HAS_SPMV) {
-        acc[2 * c] = p;
-        acc[2 * c + 1] = q;
+        acc[2 * c] = (double)p;
+        acc[2 * c + 1] = (double)q;
       } else {
-        acc[c] = p;
+        acc[c] = (double)p;
       }
     }
     if constexpr (GMRES_DPP_REDUCE) {
@@ -1197,7 +1254,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   };
   int j0 = 0;
   if (nproj >= CB) {
-    double ba[CB][RPT], bb[CB][RPT];
+    VT ba[CB][RPT], bb[CB][RPT];
     load_chunk(ba, 0);
     for (;;) {
       // ba holds chunk j0
@@ -1213,35 +1270,35 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     }
   }
   for (; j0 < nproj; ++j0) {
-    double vv[RPT];
-    const ProjCol col(Vt + (size_t)j0 * ldv, nvalid);
+    VT vv[RPT];
+    const ProjCol<VT> col(Vt + (size_t)j0 * ldv, nvalid);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) vv[i] = col(rows[i]);
-    double p = 0.0, c = 0.0;
+    VT pl = (VT)0, cl = (VT)0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      p += vv[i] * u[i];
-      if constexpr (HAS_SPMV) c += vv[i] * w[i];
+      pl += vv[i] * u[i];
+      if constexpr (HAS_SPMV) cl += vv[i] * w[i];
     }
-    p = wave_sum_last(p);
-    if constexpr (HAS_SPMV) c = wave_sum_last(c);
+    const double p = wave_sum_last((double)pl);
+    const double c = HAS_SPMV ? wave_sum_last((double)cl) : 0.0;
     if (lane == 63) {
       myred[2 * j0] = p;
-      myred[2 * j0 + 1] = HAS_SPMV ? c : 0.0;
+      myred[2 * j0 + 1] = c;
     }
   }
   {
-    double al = 0.0, ga = 0.0;
+    VT all = (VT)0, gal = (VT)0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      al += u[i] * u[i];
-      if constexpr (HAS_SPMV) ga += u[i] * w[i];
+      all += u[i] * u[i];
+      if constexpr (HAS_SPMV) gal += u[i] * w[i];
     }
-    al = wave_sum_last(al);
-    if constexpr (HAS_SPMV) ga = wave_sum_last(ga);
+    const double al = wave_sum_last((double)all);
+    const double ga = HAS_SPMV ? wave_sum_last((double)gal) : 0.0;
     if (lane == 63) {
       myred[2 * nproj] = al;
-      myred[2 * nproj + 1] = HAS_SPMV ? ga : 0.0;
+      myred[2 * nproj + 1] = ga;
     }
   }
   __syncthreads();
@@ -1274,7 +1331,9 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
 // mode 0 (lagged step k): V[:,k] = u / rho and V[:,k+1] = w / rho - V[:,0:k+1] coef,
 //   where column k enters already normalized;
 // mode 1 (CGS2 second pass): V[:,k+1] -= V[:,0:k+1] coef2.
-template <int RPT>
+// VT is the basis type; for float32 the coefficients and 1/rho are rounded
+// to float32 and the sums run in float32.
+template <int RPT, typename VT>
 __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   constexpr int TR = 256 * RPT;
   if (ws.st->done) return;
@@ -1282,67 +1341,67 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   const int64_t row0 = (int64_t)tile * TR;
   const int64_t n = ws.n;
   const int tid = threadIdx.x;
-  double* __restrict__ V = ws.V;
+  VT* __restrict__ V = basis_of<VT>(ws);
   const int64_t ldv = ws.ldv;
   const double* __restrict__ cf = mode == 0 ? ws.coef : ws.coef2;
-  const double invr = ws.st->inv_rho;
+  const VT invr = (VT)ws.st->inv_rho;
   // Loads at clamped rows (unconditional, so they are all in flight at once);
   // only rows below n are stored. Each load is a uniform column base (row rb
   // of column q: the tile's first row, or n-1 for a padding tile past the
   // end) plus a per-lane byte offset in [0, 8 TR), so one offset register per
   // row serves every column.
-  double acc[RPT];
+  VT acc[RPT];
   uint32_t off[RPT];
   const int64_t rb = row0 < n ? row0 : n - 1;
   const int64_t nvalid = n - rb;
-  const MaxpyCol src0((mode == 0 ? ws.w : V + (size_t)(k + 1) * ldv) + rb, nvalid);
+  const MaxpyCol<VT> src0((mode == 0 ? wbuf_of<VT>(ws) : V + (size_t)(k + 1) * ldv) + rb, nvalid);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;
-    off[i] = (uint32_t)((r < n ? r : n - 1) - rb) * 8u;
+    off[i] = (uint32_t)((r < n ? r : n - 1) - rb) * (uint32_t)sizeof(VT);
     acc[i] = mode == 0 ? src0(off[i]) * invr : src0(off[i]);
   }
   // GMRES_MAXPY_COLS columns per pass (their loads are in flight together).
   constexpr int MC = GMRES_MAXPY_COLS;
-  const double* __restrict__ Vt = V + rb;
+  const VT* __restrict__ Vt = V + rb;
   int q = 0;
   for (; q + MC <= k; q += MC) {
-    double c[MC];
-    double v[MC][RPT];
+    VT c[MC];
+    VT v[MC][RPT];
 #pragma unroll
     for (int t = 0; t < MC; ++t) {
-      c[t] = cf[q + t];
-      const MaxpyCol col(Vt + (size_t)(q + t) * ldv, nvalid);
+      c[t] = (VT)cf[q + t];
+      const MaxpyCol<VT> col(Vt + (size_t)(q + t) * ldv, nvalid);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) v[t][i] = col(off[i]);
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      double a = acc[i];
+      VT a = acc[i];
 #pragma unroll
       for (int t = 0; t < MC; ++t) a -= v[t][i] * c[t];
       acc[i] = a;
     }
   }
   for (; q < k; ++q) {
-    const double c0 = cf[q];
-    const MaxpyCol col(Vt + (size_t)q * ldv, nvalid);
-    double v[RPT];
+    const VT c0 = (VT)cf[q];
+    const MaxpyCol<VT> col(Vt + (size_t)q * ldv, nvalid);
+    VT v[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) v[i] = col(off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] -= v[i] * c0;
   }
-  const double ck = cf[k];
-  double vk[RPT];
-  const MaxpyCol colk(Vt + (size_t)k * ldv, nvalid);
+  const VT ck = (VT)cf[k];
+  VT vk[RPT];
+  const MaxpyCol<VT> colk(Vt + (size_t)k * ldv, nvalid);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) vk[i] = colk(off[i]);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;
     if (r < n) {
-      double x = vk[i];
+      VT x = vk[i];
       if (mode == 0) {
         x *= invr;
         V[(size_t)k * ldv + r] = x;
@@ -1401,6 +1460,7 @@ __global__ __launch_bounds__(256) void k_axpy_dot(Ws ws, double* wv_,
       const double bn = sqrt(d);
       st->bnorm = bn;
       st->tol_abs = aux * bn;
+      st->tol_cycle = st->tol_abs;
       if (!isfinite(bn)) st->status = kNonfinite;
       break;
     }
@@ -1423,6 +1483,26 @@ __global__ __launch_bounds__(256) void k_axpy_dot(Ws ws, double* wv_,
         st->j = 0;
       } else {
         st->inv_rho = 1.0 / beta;
+      }
+      break;
+    }
+    case kTailIrBeta: {
+      // FP32-basis cycle: ||r|| of the FP64 restart residual is the restart
+      // check; the cycle then works on r / ||r||, so its |g_k| are relative
+      // to ||r||, and x is updated by ||r|| V y.
+      const double beta = sqrt(d);
+      st->beta = beta;
+      if (!isfinite(beta)) {
+        st->status = kNonfinite;
+        st->done = 1;
+      } else if (beta <= st->tol_abs) {
+        st->true_conv = 1;
+        st->done = 1;
+        st->j = 0;
+      } else {
+        st->inv_rho = 1.0 / beta;
+        st->tol_cycle = st->tol_abs / beta;
+        st->xscale = beta;
       }
       break;
     }
@@ -1511,9 +1591,11 @@ __global__ __launch_bounds__(256) void k_backsolve(Ws ws, int lds_doubles) {
   }
 }
 
-// x += V[:,0:j] y, four basis columns at a time with every load in flight
-// (loads at clamped rows; only rows below n are stored).
-template <int RPT>
+// x += xscale V[:,0:j] y, with each pass's loads all in flight (loads at
+// clamped rows; only rows below n are stored). The sums run
+// in float64 whatever the basis type VT; xscale (1 for the FP64 schemes, the
+// restart residual norm for the FP32-basis scheme) is folded into y.
+template <int RPT, typename VT>
 __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, int G) {
   constexpr int TR = 256 * RPT;
   const DevState* st = ws.st;
@@ -1522,37 +1604,49 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
   const int tile = tile_of_block(G);
   const int64_t row0 = (int64_t)tile * TR;
   const int64_t n = ws.n;
-  const double* __restrict__ V = ws.V;
+  const VT* __restrict__ V = basis_of<VT>(ws);
   const int64_t ldv = ws.ldv;
   const double* __restrict__ y = ws.y;
+  const double xs = st->xscale;
   // byte offsets from row rb (the tile's first row, or n-1 for a padding
-  // tile past the end), so they lie in [0, 8 TR)
+  // tile past the end), so they lie in [0, sizeof(VT) TR)
   const int64_t rb = row0 < n ? row0 : n - 1;
-  const double* __restrict__ Vt = V + rb;
-  uint32_t off[RPT];
+  const VT* __restrict__ Vt = V + rb;
+  uint32_t off[RPT];  // byte offsets into the basis columns
   double acc[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + threadIdx.x;
-    off[i] = (uint32_t)((r < n ? r : n - 1) - rb) * 8u;
-    acc[i] = MaxpyCol(x + rb, n - rb)(off[i]);
+    const uint32_t e = (uint32_t)((r < n ? r : n - 1) - rb);
+    off[i] = e * (uint32_t)sizeof(VT);
+    acc[i] = MaxpyCol<double>(x + rb, n - rb)(e * 8u);
   }
+  // GMRES_MAXPY_COLS columns per pass, as in the MAXPY
+  constexpr int MC = GMRES_MAXPY_COLS;
   int q = 0;
-  for (; q + 4 <= j; q += 4) {
-    const double c0 = y[q], c1 = y[q + 1], c2 = y[q + 2], c3 = y[q + 3];
-    double v[4][RPT];
+  for (; q + MC <= j; q += MC) {
+    double c[MC];
+    VT v[MC][RPT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < MC; ++t) {
+      c[t] = xs * y[q + t];
+      const MaxpyCol<VT> col(Vt + (size_t)(q + t) * ldv, n - rb);
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) v[t][i] = MaxpyCol(Vt + (size_t)(q + t) * ldv, n - rb)(off[i]);
+      for (int i = 0; i < RPT; ++i) v[t][i] = col(off[i]);
+    }
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) acc[i] = acc[i] + v[0][i] * c0 + v[1][i] * c1 + v[2][i] * c2 + v[3][i] * c3;
+    for (int i = 0; i < RPT; ++i) {
+      double a = acc[i];
+#pragma unroll
+      for (int t = 0; t < MC; ++t) a += (double)v[t][i] * c[t];
+      acc[i] = a;
+    }
   }
   for (; q < j; ++q) {
-    const double c0 = y[q];
+    const double c0 = xs * y[q];
     double v[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) v[i] = MaxpyCol(Vt + (size_t)q * ldv, n - rb)(off[i]);
+    for (int i = 0; i < RPT; ++i) v[i] = (double)MaxpyCol<VT>(Vt + (size_t)q * ldv, n - rb)(off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] += v[i] * c0;
   }
@@ -1636,7 +1730,18 @@ int launch_sell_width(const Csr& A, int64_t ns, int* width, hipStream_t s) {
 
 int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s) {
   const int64_t blocks = (S.ns * 64 + 255) / 256;
-  hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)blocks), dim3(256), 0, s, A, S, st);
+  if (S.vaf)
+    hipLaunchKernelGGL(k_sell_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.vaf, st);
+  else
+    hipLaunchKernelGGL(k_sell_fill<double>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.va, st);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_first_f32(const Ws& ws, hipStream_t s) {
+  int64_t blocks = (ws.n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_first_f32, dim3((unsigned)blocks), dim3(256), 0, s, ws);
   GMRES_CHECK_LAUNCH();
   return 0;
 }
@@ -1655,28 +1760,28 @@ int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b,
 // The step kernels are launched with hipExtLaunchKernelGGL so that optional
 // start/stop events are attached to the dispatch itself and time the kernel
 // alone.
-template <int RPT, int S, int EPL, int WSRC>
+template <int RPT, int S, int EPL, int WSRC, typename VT>
 static void fused_t(const Csr& A, const Sell& SA, const Ws& ws, int K, int nproj, int m_eff,
                     int tail, int G, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const uint32_t lds = (uint32_t)(fused_lds_doubles(RPT, ws.m) * sizeof(double));
-  hipExtLaunchKernelGGL((k_fused<RPT, S, EPL, WSRC>), dim3(G), dim3(256), lds, s, e0, e1, 0u, A,
-                        SA, ws, K, nproj, m_eff, tail, G);
+  hipExtLaunchKernelGGL((k_fused<RPT, S, EPL, WSRC, VT>), dim3(G), dim3(256), lds, s, e0, e1, 0u,
+                        A, SA, ws, K, nproj, m_eff, tail, G);
 }
 
-template <int RPT>
+template <int RPT, typename VT>
 static int fused_r(const Csr& A, const Sell& SA, int shape, int wsrc, const Ws& ws, int K,
                    int nproj, int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0,
                    hipEvent_t e1) {
   switch (wsrc) {
-    case kWNone: fused_t<RPT, 1, 1, kWNone>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
-    case kWLoad: fused_t<RPT, 1, 1, kWLoad>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
-    case kWSell: fused_t<RPT, 1, 1, kWSell>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
+    case kWNone: fused_t<RPT, 1, 1, kWNone, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
+    case kWLoad: fused_t<RPT, 1, 1, kWLoad, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
+    case kWSell: fused_t<RPT, 1, 1, kWSell, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
     case kWSpmv: break;
     default: return -2;
   }
   switch (shape) {
 #define GMRES_CASE(S_, E_) \
-  case S_ * 100 + E_: fused_t<RPT, S_, E_, kWSpmv>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+  case S_ * 100 + E_: fused_t<RPT, S_, E_, kWSpmv, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
     GMRES_SPMV_SHAPES(GMRES_CASE)
 #undef GMRES_CASE
     default: return -2;
@@ -1684,29 +1789,45 @@ static int fused_r(const Csr& A, const Sell& SA, int shape, int wsrc, const Ws& 
   return 0;
 }
 
-int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K, int nproj,
-                 int wsrc, int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0,
-                 hipEvent_t e1) {
-  int rc;
+template <typename VT>
+static int fused_v(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K,
+                   int nproj, int wsrc, int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0,
+                   hipEvent_t e1) {
   switch (rpt) {
-    case 1: rc = fused_r<1>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 2: rc = fused_r<2>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    case 4: rc = fused_r<4>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
-    default: rc = fused_r<8>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1); break;
+    case 1: return fused_r<1, VT>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1);
+    case 2: return fused_r<2, VT>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1);
+    case 4: return fused_r<4, VT>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1);
+    default: return fused_r<8, VT>(A, SA, shape, wsrc, ws, K, nproj, m_eff, tail, G, s, e0, e1);
   }
+}
+
+int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K, int nproj,
+                 int wsrc, int m_eff, int tail, int G, bool f32, hipStream_t s, hipEvent_t e0,
+                 hipEvent_t e1) {
+  const int rc = f32 ? fused_v<float>(A, SA, shape, ws, rpt, K, nproj, wsrc, m_eff, tail, G, s, e0, e1)
+                     : fused_v<double>(A, SA, shape, ws, rpt, K, nproj, wsrc, m_eff, tail, G, s, e0, e1);
   if (rc) return rc;
   GMRES_CHECK_LAUNCH();
   return 0;
 }
 
-int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s, hipEvent_t e0,
-                 hipEvent_t e1) {
+template <typename VT>
+static void maxpy_v(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s, hipEvent_t e0,
+                    hipEvent_t e1) {
   switch (rpt) {
-    case 1: hipExtLaunchKernelGGL(k_maxpy<1>, dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
-    case 2: hipExtLaunchKernelGGL(k_maxpy<2>, dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
-    case 4: hipExtLaunchKernelGGL(k_maxpy<4>, dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
-    default: hipExtLaunchKernelGGL(k_maxpy<8>, dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+    case 1: hipExtLaunchKernelGGL((k_maxpy<1, VT>), dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+    case 2: hipExtLaunchKernelGGL((k_maxpy<2, VT>), dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+    case 4: hipExtLaunchKernelGGL((k_maxpy<4, VT>), dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+    default: hipExtLaunchKernelGGL((k_maxpy<8, VT>), dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
   }
+}
+
+int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, bool f32, hipStream_t s,
+                 hipEvent_t e0, hipEvent_t e1) {
+  if (f32)
+    maxpy_v<float>(ws, rpt, k, mode, G, s, e0, e1);
+  else
+    maxpy_v<double>(ws, rpt, k, mode, G, s, e0, e1);
   GMRES_CHECK_LAUNCH();
   return 0;
 }
@@ -1732,19 +1853,27 @@ int launch_scale(const Ws& ws, double* v, hipStream_t s) {
   return 0;
 }
 
-int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, hipStream_t s) {
+template <typename VT>
+static void xupdate_v(const Ws& ws, int rpt, double* x, int G, hipStream_t s) {
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL((k_xupdate<1, VT>), dim3(G), dim3(256), 0, s, ws, x, G); break;
+    case 2: hipLaunchKernelGGL((k_xupdate<2, VT>), dim3(G), dim3(256), 0, s, ws, x, G); break;
+    case 4: hipLaunchKernelGGL((k_xupdate<4, VT>), dim3(G), dim3(256), 0, s, ws, x, G); break;
+    default: hipLaunchKernelGGL((k_xupdate<8, VT>), dim3(G), dim3(256), 0, s, ws, x, G); break;
+  }
+}
+
+int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, bool f32, hipStream_t s) {
   // up to 48 KiB: R's leading block when it fits, g always
   size_t want = (size_t)(ws.m + 2) + (size_t)(ws.m + 1) * ws.m;
   const size_t cap = 48 * 1024 / sizeof(double);
   if (want > cap) want = cap;
   hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(256), want * sizeof(double), s, ws, (int)want);
   GMRES_CHECK_LAUNCH();
-  switch (rpt) {
-    case 1: hipLaunchKernelGGL(k_xupdate<1>, dim3(G), dim3(256), 0, s, ws, x, G); break;
-    case 2: hipLaunchKernelGGL(k_xupdate<2>, dim3(G), dim3(256), 0, s, ws, x, G); break;
-    case 4: hipLaunchKernelGGL(k_xupdate<4>, dim3(G), dim3(256), 0, s, ws, x, G); break;
-    default: hipLaunchKernelGGL(k_xupdate<8>, dim3(G), dim3(256), 0, s, ws, x, G); break;
-  }
+  if (f32)
+    xupdate_v<float>(ws, rpt, x, G, s);
+  else
+    xupdate_v<double>(ws, rpt, x, G, s);
   GMRES_CHECK_LAUNCH();
   return 0;
 }

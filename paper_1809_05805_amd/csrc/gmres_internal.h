@@ -14,6 +14,7 @@ constexpr int kGroup = 32;  // tiles per first-level group of the grid reduction
 constexpr int kSchemeMgs = 0;
 constexpr int kSchemeMgs1r = 1;
 constexpr int kSchemeCgs2 = 2;
+constexpr int kSchemeIr32 = 3;  // one-reduce MGS cycles on an FP32 basis, FP64 refinement
 
 constexpr int kNonfinite = -3;
 
@@ -26,7 +27,8 @@ enum Tail {
   kTailFinalRes = 5,    // ||b - A x|| at exit
   kTailMgsBeta = 6,     // level-1 MGS restart norm
   kTailMgsH = 7,        // level-1 MGS coefficient h_{q,i}
-  kTailMgsNorm = 8      // level-1 MGS h_{i+1,i}, Givens, flags
+  kTailMgsNorm = 8,     // level-1 MGS h_{i+1,i}, Givens, flags
+  kTailIrBeta = 9       // FP32-basis cycle: ||r|| of the FP64 restart residual, check, scales
 };
 
 // Per-solve state in device memory; the host reads it once per cycle.
@@ -39,6 +41,8 @@ struct DevState {
   int32_t bad_csr;    // set by the structure check
   int64_t reductions; // device-wide reductions completed
   double bnorm, tol_abs, beta, rho, inv_rho, gk;
+  double tol_cycle;   // what |g_k| is compared with inside a cycle (tol_abs, or tol_abs / beta for IR)
+  double xscale;      // x += xscale V y at the end of a cycle (1, or beta for IR)
 };
 
 struct Csr {
@@ -56,15 +60,19 @@ struct Csr {
 struct Sell {
   const int64_t* sp;  // ns + 1 slice offsets (entries)
   int* ci;
-  double* va;
+  double* va;         // float64 values (the FP64 schemes) ...
+  float* vaf;         // ... or float32 values (the FP32-basis scheme)
   int64_t ns;         // slices, ceil(n / 64)
   int64_t n;          // rows (below 2^28: gathers take 32-bit byte offsets)
 };
 
 // Views into the caller's workspace.
 struct Ws {
-  double* V;         // n x (m+2), column-major, leading dimension ldv
-  double* w;         // ldv: SpMV output of the current step
+  double* V;         // n x (m+2), column-major, leading dimension ldv (FP64 schemes)
+  double* w;         // ldv: SpMV output of the current step (FP64 schemes)
+  float* Vf;         // the same two in float32 (the FP32-basis scheme)
+  float* wf;
+  double* r64;       // ldv: the FP64 restart residual (the FP32-basis scheme)
   double* H;         // (m+1) x m unrotated Hessenberg matrix, ld = ldh
   double* R;         // (m+1) x m Givens-rotated copy
   double* T;         // (m+2) x (m+2): Malard-Paige T (one-reduce) or L (CGS2), column-major, ld = ldt
@@ -107,16 +115,19 @@ int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s);
 int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b, double* y,
                      const DevState* st, hipStream_t s, hipEvent_t e0 = nullptr,
                      hipEvent_t e1 = nullptr);
+// f32: the FP32-basis variant (ws.Vf, ws.wf; float32 values in the sliced copy).
 int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K, int nproj,
-                 int wsrc, int m_eff, int tail, int G, hipStream_t s, hipEvent_t e0 = nullptr,
-                 hipEvent_t e1 = nullptr);
-int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s,
+                 int wsrc, int m_eff, int tail, int G, bool f32, hipStream_t s,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, bool f32, hipStream_t s,
                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int launch_axpy_dot(const Ws& ws, int rpt, double* w, const double* a, const double* coef,
                     const double* v, int tail, int i_col, int q_row, int m_eff, double aux, int G,
                     hipStream_t s);
 int launch_scale(const Ws& ws, double* v, hipStream_t s);
-int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, hipStream_t s);
+int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, bool f32, hipStream_t s);
+// FP32-basis cycle start: Vf[:,0] = float(r64 * inv_rho).
+int launch_first_f32(const Ws& ws, hipStream_t s);
 size_t fused_lds_bytes(int rpt, int m);
 
 }  // namespace gmres
