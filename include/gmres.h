@@ -252,6 +252,134 @@ typedef struct {
 int gmres_set_timing(gmres_ctx* ctx, int enable);
 int gmres_get_timing(gmres_ctx* ctx, gmres_kernel_stat* stats /* host, GMRES_KSTAT_COUNT */);
 
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent systems in one persistent launch.
+ *
+ * The systems are the diagonal blocks of one block-diagonal CSR matrix:
+ * system i owns rows (and columns) [row_off[i], row_off[i+1]) of A and the
+ * same entries of b and x. Each is solved by restarted one-reduce GMRES(m)
+ * (the GMRES_MGS_1R step of Section III, or its GMRES_MGS_1R_IR32 form) with
+ * its own restart cycles, lagged normalization state, T matrix, Givens
+ * rotations and stopping test ||b_i - A_i x_i|| <= rtol ||b_i||. One kernel
+ * launch solves the whole batch: a fixed number of workgroups take systems
+ * from a device-side queue, in the chosen order, until it is empty, and each
+ * workgroup runs its system's entire solve with workgroup-level reductions
+ * in place of the single-system device-wide ones (the paper maps its
+ * reductions onto SIMD lanes on the CPU and onto all of the GPU for one
+ * system, Section V-B; here the batch fills the GPU instead).
+ * gmres_batch_solve_async makes no host synchronization, memset or
+ * allocation, so it can be captured into a HIP graph;
+ * gmres_batch_capture / gmres_batch_replay do that inside the library.
+ * ------------------------------------------------------------------------ */
+typedef struct gmres_batch gmres_batch; /* opaque */
+
+/* Per-system result, written by the device (the same 32-byte layout there). */
+typedef struct {
+  int64_t iters;       /* Arnoldi columns completed over all cycles                 */
+  int32_t cycles;      /* restart cycles that ran at least one Arnoldi step         */
+  int32_t converged;   /* 1 if ||b_i - A_i x_i|| <= rtol ||b_i|| was verified       */
+  int32_t status;      /* GMRES_OK or GMRES_ERR_NONFINITE for this system           */
+  int32_t breakdown;   /* 1 if a cycle ended on an exact breakdown, rho == 0        */
+  double rel_res_true; /* ||b_i - A_i x_i|| / ||b_i|| at exit, from a residual the
+                          device computed in float64 (0 when ||b_i|| == 0)           */
+} gmres_batch_info;
+
+enum { GMRES_BATCH_ORDER_NATURAL = 0, GMRES_BATCH_ORDER_LARGEST_FIRST = 1 };
+
+/*
+ * Device workspace bytes for nsys systems with row offsets row_off (host,
+ * int64[nsys+1], row_off[0] = 0, strictly increasing, every system below
+ * 2^28 rows, total below 2^31), restart m (1..GMRES_MAX_RESTART) and scheme
+ * GMRES_MGS_1R or GMRES_MGS_1R_IR32; 0 if the arguments are invalid. Per
+ * system: the basis (m+1 columns of n_i rounded up to 64, float64 or
+ * float32), the Hessenberg, T and Givens arrays and a state record; for the
+ * batch: the SpMV output, a float64 copy of x for the autotuner, and for
+ * GMRES_MGS_1R_IR32 the float64 restart residual.
+ */
+size_t gmres_batch_workspace_bytes(int32_t nsys, const int64_t* row_off, int32_t m, int32_t scheme);
+
+/*
+ * Bind a block-diagonal CSR matrix (device arrays as for gmres_create, n =
+ * row_off[nsys] rows) and a workspace (device, 256-byte aligned,
+ * ws_bytes >= gmres_batch_workspace_bytes) to a new batch context. Checks the
+ * CSR structure and that every column index of a system's rows lies in the
+ * system's own range; GMRES_ERR_ARG otherwise. Blocks until the checks are
+ * done. The initial configuration is 256-thread workgroups, as many as the
+ * GPU holds at once (at most nsys), systems largest first.
+ */
+int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, int64_t nnz,
+                       const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
+                       int32_t m, int32_t scheme, void* workspace, size_t ws_bytes,
+                       void* hip_stream);
+
+/* Release the context and any captured graph (host resources only). */
+int gmres_batch_destroy(gmres_batch* bt);
+
+/* Change the stream later work is enqueued on. */
+int gmres_batch_set_stream(gmres_batch* bt, void* hip_stream);
+
+/*
+ * Enqueue one batched solve and return without waiting.
+ *   b, x: float64[n] (x: initial guesses in, solutions out); rtol >= 0;
+ *   max_iters >= 0: cap on Arnoldi columns per system;
+ *   info: device array of nsys gmres_batch_info, or NULL for the context's
+ *   own (read it with gmres_batch_read_info).
+ * Only null pointers and negative values are refused here; the device
+ * pointers are the caller's to get right.
+ */
+int gmres_batch_solve_async(gmres_batch* bt, const double* b, double* x, double rtol,
+                            int64_t max_iters, gmres_batch_info* info);
+
+/*
+ * The same, then wait: info (host, nullable, nsys entries) receives the
+ * results. Returns GMRES_ERR_NONFINITE if any system met a NaN or Inf (the
+ * others are still solved), else GMRES_OK.
+ */
+int gmres_batch_solve(gmres_batch* bt, const double* b, double* x, double rtol, int64_t max_iters,
+                      gmres_batch_info* info);
+
+/* Copy the context's own result array to info (host, nsys entries); waits. */
+int gmres_batch_read_info(gmres_batch* bt, gmres_batch_info* info);
+
+/*
+ * Launch configuration: block_size 256, 512 or 1024 threads per workgroup;
+ * grid >= 1 persistent workgroups (0: as many as the GPU holds at once, at
+ * most nsys); order GMRES_BATCH_ORDER_*. The results do not depend on it
+ * (each system's arithmetic is fixed by its workgroup size: the per-wavefront
+ * sums are combined in a fixed order), only the time.
+ */
+int gmres_batch_set_config(gmres_batch* bt, int32_t block_size, int32_t grid, int32_t order);
+int gmres_batch_get_config(gmres_batch* bt, int32_t* block_size, int32_t* grid, int32_t* order);
+
+typedef struct {
+  int32_t block_size, grid, order;
+  float ms; /* event-timed duration of the solve */
+} gmres_batch_trial;
+
+/*
+ * Time one solve of (b, x, rtol, max_iters) under each candidate
+ * configuration (block sizes 256, 512, 1024; grids of one workgroup per
+ * compute unit and of as many as the GPU holds; both orders) after one
+ * warm-up solve, keep the fastest, and leave x as it was on entry (it is
+ * restored from the workspace's copy before every trial). trials (host,
+ * nullable, max_trials entries) and ntrials (host, nullable) report what was
+ * timed. Blocks.
+ */
+int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rtol,
+                         int64_t max_iters, gmres_batch_trial* trials, int32_t max_trials,
+                         int32_t* ntrials);
+
+/*
+ * Capture one gmres_batch_solve_async(b, x, rtol, max_iters, NULL) with the
+ * current configuration into a HIP graph held by the context (replacing any
+ * earlier one); gmres_batch_replay launches it on the context's stream
+ * without waiting. The graph keeps the pointers it was captured with: refill
+ * b and x in place between replays. Results go to the context's own array.
+ */
+int gmres_batch_capture(gmres_batch* bt, const double* b, double* x, double rtol,
+                        int64_t max_iters);
+int gmres_batch_replay(gmres_batch* bt);
+
 #ifdef __cplusplus
 }
 #endif

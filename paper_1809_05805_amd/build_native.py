@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgmres_hip.so")
-SOURCES = ["gmres_device.hip", "gmres_api.hip"]
+SOURCES = ["gmres_device.hip", "gmres_api.hip", "gmres_batch.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

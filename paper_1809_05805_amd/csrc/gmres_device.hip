@@ -1878,6 +1878,514 @@ int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, bool f32, hipStrea
   return 0;
 }
 
+// ---------------------------------------------------- batched persistent solver
+//
+// A batch is a block-diagonal matrix: system i owns rows [r0, r0 + n) and its
+// columns lie in the same range. One persistent kernel solves all of them:
+// each workgroup takes the next system from a device-side queue (in the given
+// order; largest first by default) and runs that system's whole restarted
+// one-reduce GMRES on its own, with workgroup-level reductions where the
+// single-system path has its device-wide one. No workgroup ever waits for
+// another, so the launch needs no co-residency and ends when the queue is
+// empty.
+
+// Block-diagonal check: every column index of system i's rows lies in
+// [r0, r0 + n). One thread per row; the system is found by bisection.
+__global__ __launch_bounds__(256) void k_batch_validate(Csr A, const BatchSys* __restrict__ sys,
+                                                         int nsys, DevState* st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < A.n; r += stride) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sys[mid].r0 <= r) lo = mid; else hi = mid - 1;
+    }
+    const int64_t r0 = sys[lo].r0, r1 = r0 + sys[lo].n;
+    bool bad = false;
+    for (int e = A.rp[r]; e < A.rp[r + 1]; ++e) {
+      const int c = A.ci[e];
+      if (c < r0 || c >= r1) bad = true;
+    }
+    if (bad) atomicOr(&st->bad_csr, 1);
+  }
+}
+
+// Start of a batched solve: the queue position and every system's result.
+__global__ void k_batch_reset(Batch B) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) *B.queue = 0u;
+  for (int i = t; i < B.nsys; i += gridDim.x * blockDim.x) {
+    BatchOut o;
+    o.iters = 0;
+    o.cycles = o.converged = o.status = o.breakdown = 0;
+    o.rel_res_true = 0.0;
+    B.out[i] = o;
+  }
+}
+
+// Sum of v over the workgroup, returned to every thread (red: NW doubles).
+template <int BS>
+__device__ inline double block_sum(double v, double* red) {
+  __shared__ double s_tot;
+  v = wave_sum_last(v);
+  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int w = 0; w < BS / 64; ++w) a += red[w];
+    s_tot = a;
+  }
+  __syncthreads();
+  const double t = s_tot;
+  __syncthreads();
+  return t;
+}
+
+// Row r (local) of A x for one system: the CSR row sum with x indexed locally.
+template <typename XT>
+__device__ inline double batch_row(const Csr& A, int64_t r0, int64_t r, const XT* __restrict__ x) {
+  double a = 0.0;
+  const int e1 = A.rp[r0 + r + 1];
+  for (int e = A.rp[r0 + r]; e < e1; ++e) a += A.va[e] * (double)x[A.ci[e] - r0];
+  return a;
+}
+
+// The whole solve of system i by one workgroup of BS threads.
+template <int BS, typename VT>
+__device__ void batch_system(const Batch& B, int i, double* red, double* vals, double* scr) {
+  constexpr int NW = BS / 64;
+  constexpr int RB = 8;  // rows per thread per row block
+  constexpr bool F32 = sizeof(VT) == 4;
+  __shared__ int s_flag[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = B.m;
+  const int P = 2 * (m + 2);
+  // i is uniform, so the system's sizes and pointers stay in scalar registers
+  const BatchSys S = B.sys[i];
+  const int64_t n = S.n, r0 = S.r0;
+  Ws ws{};
+  {
+    double* sm = B.small + S.soff;
+    if constexpr (F32) {
+      ws.Vf = (float*)B.Vb + S.voff;
+      ws.wf = (float*)B.wb + r0;
+      ws.r64 = B.r64 + r0;
+    } else {
+      ws.V = (double*)B.Vb + S.voff;
+      ws.w = (double*)B.wb + r0;
+    }
+    ws.H = sm;
+    ws.R = ws.H + (size_t)(m + 1) * m;
+    ws.T = ws.R + (size_t)(m + 1) * m;
+    ws.TT = ws.T + (size_t)(m + 2) * (m + 2);
+    ws.g = ws.TT + (size_t)(m + 2) * (m + 2);
+    ws.gh = ws.g + (m + 2);
+    ws.cs = ws.gh + (m + 2);
+    ws.sn = ws.cs + (m + 2);
+    ws.coef = ws.sn + (m + 2);
+    ws.coef2 = ws.coef + (m + 2);
+    ws.y = ws.coef2 + (m + 2);
+    ws.st = B.st + i;
+    ws.n = n;
+    ws.ldv = S.ldv;
+    ws.ldh = m + 1;
+    ws.ldt = m + 2;
+    ws.m = m;
+  }
+  DevState* st = ws.st;
+  VT* __restrict__ V = basis_of<VT>(ws);
+  VT* __restrict__ wv_ = wbuf_of<VT>(ws);
+  const int64_t ldv = ws.ldv;
+  const double* __restrict__ b = B.b + r0;
+  double* __restrict__ x = B.x + r0;
+  const int64_t nblk = (n + (int64_t)BS * RB - 1) / ((int64_t)BS * RB);
+
+  // ||b|| and the tolerance
+  double sb = 0.0;
+  for (int64_t r = tid; r < n; r += BS) sb += b[r] * b[r];
+  const double bnorm = sqrt(block_sum<BS>(sb, red));
+  if (tid == 0) {
+    st->done = st->j = st->true_conv = st->breakdown = st->status = 0;
+    st->reductions = 1;
+    st->bnorm = bnorm;
+    st->tol_abs = B.rtol * bnorm;
+    st->tol_cycle = st->tol_abs;
+    st->xscale = 1.0;
+  }
+  __syncthreads();
+  BatchOut out;
+  out.iters = 0;
+  out.cycles = out.converged = out.status = out.breakdown = 0;
+  out.rel_res_true = 0.0;
+  if (!isfinite(bnorm)) {
+    out.status = kNonfinite;
+  } else if (bnorm == 0.0) {
+    for (int64_t r = tid; r < n; r += BS) x[r] = 0.0;
+    out.converged = 1;
+  } else {
+    const double tol_abs = B.rtol * bnorm;
+    int64_t it = 0;
+    for (;;) {
+      const int64_t left = B.max_iters - it;
+      const int m_eff = left < (int64_t)m ? (int)left : m;
+      if (m_eff == 0) {
+        // the iteration budget is spent: the true residual of the final x
+        double sr = 0.0;
+        for (int64_t r = tid; r < n; r += BS) {
+          const double d = b[r] - batch_row(B.A, r0, r, x);
+          sr += d * d;
+        }
+        const double rn = sqrt(block_sum<BS>(sr, red));
+        out.rel_res_true = rn / bnorm;
+        out.converged = rn <= tol_abs;
+        if (!isfinite(rn)) out.status = kNonfinite;
+        break;
+      }
+      // cycle start: clear the small dense matrices and the flags
+      {
+        const size_t tot = 2 * (size_t)(m + 1) * m + 2 * (size_t)(m + 2) * (m + 2) + 2 * (size_t)(m + 2);
+        for (size_t e = tid; e < tot; e += BS) ws.H[e] = 0.0;  // H, R, T, TT, g, gh are contiguous
+        if (tid == 0) {
+          st->done = st->j = st->true_conv = st->breakdown = 0;
+          st->xscale = 1.0;
+          st->tol_cycle = tol_abs;
+        }
+      }
+      __syncthreads();
+      // restart residual
+      double beta_cycle = 0.0;
+      if constexpr (F32) {
+        double sr = 0.0;
+        for (int64_t r = tid; r < n; r += BS) {
+          const double d = b[r] - batch_row(B.A, r0, r, x);
+          ws.r64[r] = d;
+          sr += d * d;
+        }
+        const double beta = sqrt(block_sum<BS>(sr, red));
+        if (!isfinite(beta)) {
+          out.status = kNonfinite;
+          break;
+        }
+        if (beta <= tol_abs) {
+          out.converged = 1;
+          out.rel_res_true = beta / bnorm;
+          break;
+        }
+        const double inv = 1.0 / beta;
+        for (int64_t r = tid; r < n; r += BS) V[r] = (VT)(ws.r64[r] * inv);
+        // the float64 check above is the restart test: the normalized float32
+        // start vector is not tested again (tol_cycle 0 for step 0)
+        if (tid == 0) {
+          st->reductions += 1;
+          st->tol_cycle = 0.0;
+          st->xscale = beta;
+        }
+        beta_cycle = beta;
+      } else {
+        for (int64_t r = tid; r < n; r += BS) V[r] = (VT)(b[r] - batch_row(B.A, r0, r, x));
+      }
+      __syncthreads();
+      for (int k = 0; k <= m_eff; ++k) {
+        const bool last = k == m_eff;
+        const int nproj = last ? 0 : k;
+        const int cnt = 2 * (nproj + 1);
+        for (int c = lane; c < cnt; c += 64) red[wv * P + c] = 0.0;
+        const VT* __restrict__ u_g = V + (size_t)k * ldv;
+        for (int64_t blk = 0; blk < nblk; ++blk) {
+          // this thread's rows of the block: clamped loads, masked values
+          VT u[RB], w[RB];
+          uint32_t off[RB];
+#pragma unroll
+          for (int t = 0; t < RB; ++t) {
+            const int64_t r = blk * BS * RB + (int64_t)t * BS + tid;
+            const bool ok = r < n;
+            const int64_t rc = ok ? r : n - 1;
+            off[t] = (uint32_t)rc * (uint32_t)sizeof(VT);
+            u[t] = ok ? u_g[rc] : (VT)0;
+            if (!last) {
+              const double a = ok ? batch_row(B.A, r0, rc, u_g) : 0.0;
+              w[t] = (VT)a;
+              if (ok) wv_[r] = w[t];
+            } else {
+              w[t] = (VT)0;
+            }
+          }
+          // projection over columns 0..nproj-1, the next column's loads in flight
+          auto load_col = [&](VT (&buf)[RB], int j) {
+            const GlbCol<VT> col(V + (size_t)j * ldv, n);
+#pragma unroll
+            for (int t = 0; t < RB; ++t) buf[t] = col(off[t]);
+          };
+          auto reduce_col = [&](const VT (&vv)[RB], int j) {
+            VT p = (VT)0, q = (VT)0;
+#pragma unroll
+            for (int t = 0; t < RB; ++t) {
+              p += vv[t] * u[t];
+              q += vv[t] * w[t];
+            }
+            const double ps = wave_sum_last((double)p);
+            const double qs = wave_sum_last((double)q);
+            if (lane == 63) {
+              red[wv * P + 2 * j] += ps;
+              red[wv * P + 2 * j + 1] += qs;
+            }
+          };
+          if (nproj > 0) {
+            VT ba[RB], bb[RB];
+            load_col(ba, 0);
+            int j = 0;
+            for (;;) {
+              load_col(bb, j + 1 < nproj ? j + 1 : j);
+              reduce_col(ba, j);
+              if (++j >= nproj) break;
+              load_col(ba, j + 1 < nproj ? j + 1 : j);
+              reduce_col(bb, j);
+              if (++j >= nproj) break;
+            }
+          }
+          VT al = (VT)0, ga = (VT)0;
+#pragma unroll
+          for (int t = 0; t < RB; ++t) {
+            al += u[t] * u[t];
+            ga += u[t] * w[t];
+          }
+          const double als = wave_sum_last((double)al);
+          const double gas = wave_sum_last((double)ga);
+          if (lane == 63) {
+            red[wv * P + 2 * nproj] += als;
+            red[wv * P + 2 * nproj + 1] += gas;
+          }
+        }
+        __syncthreads();
+        for (int c = tid; c < cnt; c += BS) {
+          double a = 0.0;
+          for (int w2 = 0; w2 < NW; ++w2) a += red[w2 * P + c];
+          vals[c] = a;
+        }
+        __syncthreads();
+        // the small dense step (H column, T column, Givens, flags, MAXPY coefficients)
+        TailPrefetch<1> pf;
+        pf.ws = &ws;
+        pf.tri = nullptr;
+        pf.hc = scr + 3 * (m + 2);
+        pf.csl = scr + 4 * (m + 2);
+        pf.snl = scr + 5 * (m + 2);
+        pf.k = k;
+        pf.scheme = kSchemeMgs1r;
+        pf.active = true;
+        pf.staged = false;
+        pf.ntri = 0;
+        pf.issue();
+        pf.commit();
+        tail_lagged(ws, vals, scr, k, last, m_eff, kSchemeMgs1r, pf);
+        if (F32 && k == 0 && tid == 0) st->tol_cycle = tol_abs / beta_cycle;
+        __syncthreads();
+        if (tid == 0) {
+          s_flag[0] = st->done;
+          s_flag[1] = st->j;
+        }
+        double* cl = scr;  // the MAXPY coefficients (the tail's LDS scratch is free again)
+        for (int q = tid; q <= k; q += BS) cl[q] = ws.coef[q];
+        __syncthreads();
+        if (s_flag[0]) break;
+        // MAXPY: V[:,k] = u / rho, V[:,k+1] = w / rho - V[:,0:k+1] h
+        const VT invr = (VT)st->inv_rho;
+        for (int64_t blk = 0; blk < nblk; ++blk) {
+          VT acc[RB], vk[RB];
+          uint32_t off[RB];
+#pragma unroll
+          for (int t = 0; t < RB; ++t) {
+            const int64_t r = blk * BS * RB + (int64_t)t * BS + tid;
+            const int64_t rc = r < n ? r : n - 1;
+            off[t] = (uint32_t)rc * (uint32_t)sizeof(VT);
+            acc[t] = wv_[rc] * invr;
+            vk[t] = V[(size_t)k * ldv + rc] * invr;
+          }
+          auto load_col = [&](VT (&buf)[RB], int j) {
+            const GlbCol<VT> col(V + (size_t)j * ldv, n);
+#pragma unroll
+            for (int t = 0; t < RB; ++t) buf[t] = col(off[t]);
+          };
+          auto axpy_col = [&](const VT (&vv)[RB], int j) {
+            const VT c = (VT)cl[j];
+#pragma unroll
+            for (int t = 0; t < RB; ++t) acc[t] -= vv[t] * c;
+          };
+          if (k > 0) {
+            VT ba[RB], bb[RB];
+            load_col(ba, 0);
+            int j = 0;
+            for (;;) {
+              load_col(bb, j + 1 < k ? j + 1 : j);
+              axpy_col(ba, j);
+              if (++j >= k) break;
+              load_col(ba, j + 1 < k ? j + 1 : j);
+              axpy_col(bb, j);
+              if (++j >= k) break;
+            }
+          }
+          const VT ck = (VT)cl[k];
+#pragma unroll
+          for (int t = 0; t < RB; ++t) {
+            const int64_t r = blk * BS * RB + (int64_t)t * BS + tid;
+            if (r < n) {
+              V[(size_t)k * ldv + r] = vk[t];
+              V[(size_t)(k + 1) * ldv + r] = acc[t] - vk[t] * ck;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        s_flag[1] = st->j;
+        s_flag[2] = st->status;
+        s_flag[3] = st->true_conv | (st->breakdown << 1);
+      }
+      __syncthreads();
+      const int j = s_flag[1];
+      if (s_flag[2]) {
+        out.status = s_flag[2];
+        break;
+      }
+      if (s_flag[3] & 1) {
+        // the restart check of this cycle's first step passed (float64 schemes)
+        out.converged = 1;
+        out.rel_res_true = st->beta / bnorm;
+        break;
+      }
+      if (s_flag[3] & 2) out.breakdown = 1;
+      // back substitution R y = g, then x += xscale V y
+      double* yl = scr;
+      if (tid == 0) {
+        const double xs = st->xscale;
+        for (int q = j - 1; q >= 0; --q) {
+          double a = ws.g[q];
+          for (int t = q + 1; t < j; ++t) a -= ws.R[(size_t)t * ws.ldh + q] * ws.y[t];
+          const double piv = ws.R[(size_t)q * ws.ldh + q];
+          const double yq = piv != 0.0 ? a / piv : 0.0;
+          ws.y[q] = yq;
+          yl[q] = xs * yq;
+        }
+      }
+      __syncthreads();
+      for (int64_t r = tid; r < n; r += BS) {
+        double a = x[r];
+        for (int q = 0; q < j; ++q) a += (double)V[(size_t)q * ldv + r] * yl[q];
+        x[r] = a;
+      }
+      __syncthreads();
+      it += j;
+      out.cycles += 1;
+      if (j == 0) break;
+    }
+    out.iters = it;
+  }
+  if (tid == 0) {
+    if (out.status == 0 && st->status) out.status = st->status;
+    B.out[i] = out;
+  }
+  __syncthreads();
+}
+
+template <int BS, typename VT>
+__global__ __launch_bounds__(BS) void k_batch(Batch B) {
+  extern __shared__ double lds[];
+  __shared__ int s_pos;
+  constexpr int NW = BS / 64;
+  const int P = 2 * (B.m + 2);
+  double* red = lds;              // NW x P per-wavefront sums (also block_sum's scratch)
+  double* vals = red + NW * P;    // P totals
+  double* scr = vals + P;         // 6 (m + 2) for the small dense step
+  for (;;) {
+    if (threadIdx.x == 0) s_pos = (int)atomicAdd(B.queue, 1u);
+    __syncthreads();
+    const int pos = __builtin_amdgcn_readfirstlane(s_pos);
+    __syncthreads();
+    if (pos >= B.nsys) break;
+    batch_system<BS, VT>(B, __builtin_amdgcn_readfirstlane(B.order[pos]), red, vals, scr);
+  }
+}
+
+size_t batch_lds_bytes(int bs, int m) {
+  const size_t P = 2 * (size_t)(m + 2);
+  return ((size_t)(bs / 64) * P + P + 6 * (size_t)(m + 2)) * sizeof(double);
+}
+
+int launch_batch_validate(const Csr& A, const BatchSys* sys, int nsys, DevState* st, hipStream_t s) {
+  int64_t blocks = (A.n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_batch_validate, dim3((unsigned)blocks), dim3(256), 0, s, A, sys, nsys, st);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int launch_batch_reset(const Batch& B, hipStream_t s) {
+  const int blocks = (B.nsys + 255) / 256;
+  hipLaunchKernelGGL(k_batch_reset, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, B);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+template <int BS, typename VT>
+void batch_launch_one(const Batch& B, int grid, uint32_t lds, hipStream_t s, hipEvent_t e0,
+                      hipEvent_t e1) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL((k_batch<BS, VT>), dim3(grid), dim3(BS), lds, s, e0, e1, 0u, B);
+  else
+    hipLaunchKernelGGL((k_batch<BS, VT>), dim3(grid), dim3(BS), lds, s, B);
+}
+
+int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipEvent_t e0,
+                 hipEvent_t e1) {
+  if (grid < 1) return -1;
+  const uint32_t lds = (uint32_t)batch_lds_bytes(bs, B.m);
+  switch (bs) {
+    case 256:
+      f32 ? batch_launch_one<256, float>(B, grid, lds, s, e0, e1)
+          : batch_launch_one<256, double>(B, grid, lds, s, e0, e1);
+      break;
+    case 512:
+      f32 ? batch_launch_one<512, float>(B, grid, lds, s, e0, e1)
+          : batch_launch_one<512, double>(B, grid, lds, s, e0, e1);
+      break;
+    case 1024:
+      f32 ? batch_launch_one<1024, float>(B, grid, lds, s, e0, e1)
+          : batch_launch_one<1024, double>(B, grid, lds, s, e0, e1);
+      break;
+    default:
+      return -1;
+  }
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
+int batch_resident_blocks(int bs, int m, bool f32) {
+  const size_t lds = batch_lds_bytes(bs, m);
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (bs) {
+    case 256:
+      e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<256, float>, 256, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<256, double>, 256, lds);
+      break;
+    case 512:
+      e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<512, float>, 512, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<512, double>, 512, lds);
+      break;
+    case 1024:
+      e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<1024, float>, 1024, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<1024, double>, 1024, lds);
+      break;
+    default:
+      break;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
 size_t fused_lds_bytes(int rpt, int m) { return fused_lds_doubles(rpt, m) * sizeof(double); }
 
 }  // namespace gmres

@@ -93,6 +93,59 @@ struct Ws {
   int ldh, ldt, pstride, m;
 };
 
+// One system of a batch: rows [r0, r0 + n) of the block-diagonal matrix and
+// of the concatenated vectors; its basis at voff (leading dimension ldv) in
+// the batch's basis array and its small workspace at soff (doubles).
+struct BatchSys {
+  int64_t r0, n, voff, ldv, soff;
+};
+
+// Per-system result of a batched solve (the layout of gmres_batch_info).
+struct BatchOut {
+  int64_t iters;
+  int32_t cycles, converged, status, breakdown;
+  double rel_res_true;
+};
+
+// Everything the persistent batched kernel needs.
+struct Batch {
+  Csr A;                 // block-diagonal CSR over all systems (global column indices)
+  const BatchSys* sys;   // nsys records
+  const int* order;      // order in which the systems are taken from the queue
+  int nsys, m;
+  void* Vb;              // bases (float64, or float32 for the FP32-basis scheme)
+  void* wb;              // SpMV outputs, by global row (same type)
+  double* r64;           // float64 restart residuals by global row (FP32-basis only)
+  double* small;         // small workspaces, batch_small_doubles(m) each
+  DevState* st;          // nsys states
+  unsigned* queue;       // next queue position
+  BatchOut* out;         // nsys results
+  const double* b;
+  double* x;
+  double rtol;
+  int64_t max_iters;
+};
+
+// Doubles of one system's small workspace: H and R ((m+1) m each), T and TT
+// ((m+2)^2 each), g, gh, cs, sn, coef, coef2, y ((m+2) each).
+constexpr size_t batch_small_doubles(int m) {
+  return 2 * (size_t)(m + 1) * m + 2 * (size_t)(m + 2) * (m + 2) + 7 * (size_t)(m + 2);
+}
+
+// Sets st->bad_csr when a row of system i has a column outside its rows (the
+// CSR arrays must already have passed launch_validate).
+int launch_batch_validate(const Csr& A, const BatchSys* sys, int nsys, DevState* st, hipStream_t s);
+// Clears the queue position and every system's result (a kernel, so a
+// captured graph holds no memset node).
+int launch_batch_reset(const Batch& B, hipStream_t s);
+// The persistent solve: grid workgroups of bs threads (256, 512 or 1024)
+// take systems from the queue until it is empty. f32: float32 basis.
+int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipEvent_t e0 = nullptr,
+                 hipEvent_t e1 = nullptr);
+// Workgroups of k_batch that one compute unit holds at once (0 on error).
+int batch_resident_blocks(int bs, int m, bool f32);
+size_t batch_lds_bytes(int bs, int m);
+
 int launch_init(const Ws& ws, int ncounters, hipStream_t s);
 int launch_solve_begin(const Ws& ws, hipStream_t s);
 int launch_cycle_begin(const Ws& ws, hipStream_t s);

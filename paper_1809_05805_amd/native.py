@@ -26,7 +26,12 @@ GMRES_MAX_RESTART = 256
 EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destroy",
             "gmres_status_string", "gmres_spmv", "gmres_last_cycle", "gmres_basis",
             "gmres_set_timing", "gmres_get_timing", "gmres_refresh_matrix", "gmres_get_format",
-            "gmres_matrix_storage_bytes", "gmres_set_matrix_storage"]
+            "gmres_matrix_storage_bytes", "gmres_set_matrix_storage",
+            "gmres_batch_workspace_bytes", "gmres_batch_create", "gmres_batch_destroy",
+            "gmres_batch_set_stream", "gmres_batch_solve_async", "gmres_batch_solve",
+            "gmres_batch_read_info", "gmres_batch_set_config", "gmres_batch_get_config",
+            "gmres_batch_autotune", "gmres_batch_capture", "gmres_batch_replay"]
+GMRES_BATCH_ORDER_NATURAL, GMRES_BATCH_ORDER_LARGEST_FIRST = 0, 1
 GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64 = 0, 1
 GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
 
@@ -43,6 +48,17 @@ class GmresInfo(ctypes.Structure):
 
 class GmresKernelStat(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("launches", ctypes.c_int64)]
+
+
+class GmresBatchInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("cycles", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("breakdown", ctypes.c_int32), ("rel_res_true", ctypes.c_double)]
+
+
+class GmresBatchTrial(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 _lib = None
@@ -86,6 +102,22 @@ def load() -> ctypes.CDLL:
     lib.gmres_matrix_storage_bytes.argtypes = [P, ctypes.POINTER(SZ)]
     lib.gmres_set_matrix_storage.restype = ctypes.c_int
     lib.gmres_set_matrix_storage.argtypes = [P, P, SZ]
+    lib.gmres_batch_workspace_bytes.restype = SZ
+    lib.gmres_batch_workspace_bytes.argtypes = [I32, P, I32, I32]
+    lib.gmres_batch_create.restype = ctypes.c_int
+    lib.gmres_batch_create.argtypes = [ctypes.POINTER(P), I32, P, I64, P, P, P, I32, I32, P, SZ, P]
+    for name, args in (("gmres_batch_destroy", [P]), ("gmres_batch_set_stream", [P, P]),
+                       ("gmres_batch_solve_async", [P, P, P, D, I64, P]),
+                       ("gmres_batch_solve", [P, P, P, D, I64, P]),
+                       ("gmres_batch_read_info", [P, P]),
+                       ("gmres_batch_set_config", [P, I32, I32, I32]),
+                       ("gmres_batch_get_config", [P, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                                   ctypes.POINTER(I32)]),
+                       ("gmres_batch_autotune", [P, P, P, D, I64, P, I32, ctypes.POINTER(I32)]),
+                       ("gmres_batch_capture", [P, P, P, D, I64]),
+                       ("gmres_batch_replay", [P])):
+        getattr(lib, name).restype = ctypes.c_int
+        getattr(lib, name).argtypes = args
     _lib = lib
     return lib
 
@@ -171,6 +203,70 @@ def gmres_get_timing(ctx):
     arr = (GmresKernelStat * GMRES_KSTAT_COUNT)()
     rc = load().gmres_get_timing(ctx, arr)
     return rc, [{"ms": a.ms, "bytes": a.bytes, "launches": a.launches} for a in arr]
+
+
+def gmres_batch_workspace_bytes(row_off: np.ndarray, m: int, scheme: int) -> int:
+    ro = np.ascontiguousarray(row_off, dtype=np.int64)
+    return int(load().gmres_batch_workspace_bytes(len(ro) - 1, ro.ctypes.data, m, scheme))
+
+
+def gmres_batch_create(row_off: np.ndarray, nnz, row_ptr_ptr, col_idx_ptr, vals_ptr, m, scheme,
+                       ws_ptr, ws_bytes, stream_ptr) -> tuple[int, int | None]:
+    ro = np.ascontiguousarray(row_off, dtype=np.int64)
+    ctx = ctypes.c_void_p()
+    rc = load().gmres_batch_create(ctypes.byref(ctx), len(ro) - 1, ro.ctypes.data, nnz, row_ptr_ptr,
+                                   col_idx_ptr, vals_ptr, m, scheme, ws_ptr, ws_bytes, stream_ptr)
+    return rc, (ctx.value if rc == GMRES_OK else None)
+
+
+def gmres_batch_destroy(ctx) -> int:
+    return load().gmres_batch_destroy(ctx)
+
+
+def gmres_batch_set_stream(ctx, stream_ptr) -> int:
+    return load().gmres_batch_set_stream(ctx, stream_ptr)
+
+
+def gmres_batch_solve_async(ctx, b_ptr, x_ptr, rtol, max_iters, info_ptr=None) -> int:
+    return load().gmres_batch_solve_async(ctx, b_ptr, x_ptr, float(rtol), int(max_iters), info_ptr)
+
+
+def gmres_batch_solve(ctx, b_ptr, x_ptr, rtol, max_iters, nsys: int):
+    info = (GmresBatchInfo * nsys)()
+    rc = load().gmres_batch_solve(ctx, b_ptr, x_ptr, float(rtol), int(max_iters), info)
+    return rc, info
+
+
+def gmres_batch_read_info(ctx, nsys: int):
+    info = (GmresBatchInfo * nsys)()
+    rc = load().gmres_batch_read_info(ctx, info)
+    return rc, info
+
+
+def gmres_batch_set_config(ctx, block_size: int, grid: int, order: int) -> int:
+    return load().gmres_batch_set_config(ctx, block_size, grid, order)
+
+
+def gmres_batch_get_config(ctx):
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    rc = load().gmres_batch_get_config(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return rc, a.value, b.value, c.value
+
+
+def gmres_batch_autotune(ctx, b_ptr, x_ptr, rtol, max_iters, max_trials: int = 32):
+    trials = (GmresBatchTrial * max(max_trials, 1))()
+    nt = ctypes.c_int32()
+    rc = load().gmres_batch_autotune(ctx, b_ptr, x_ptr, float(rtol), int(max_iters), trials,
+                                     max_trials, ctypes.byref(nt))
+    return rc, [(t.block_size, t.grid, t.order, t.ms) for t in trials[: nt.value]]
+
+
+def gmres_batch_capture(ctx, b_ptr, x_ptr, rtol, max_iters) -> int:
+    return load().gmres_batch_capture(ctx, b_ptr, x_ptr, float(rtol), int(max_iters))
+
+
+def gmres_batch_replay(ctx) -> int:
+    return load().gmres_batch_replay(ctx)
 
 
 # ----------------------------------------------------------- torch front end
@@ -313,3 +409,113 @@ class GmresSolver:
         cols = self.m + 2
         flat = self.ws[off: off + ld * cols * 8].view(torch.float64)
         return flat.view(cols, ld)[:, : self.n].t()
+
+
+def batch_info_arrays(info) -> dict:
+    """Per-system fields of a gmres_batch_info array as numpy arrays."""
+    return {k: np.array([getattr(o, k) for o in info]) for k, _ in GmresBatchInfo._fields_}
+
+
+class BatchSolver:
+    """A batch context over a block-diagonal CSR matrix on a GPU, workspace allocated with torch.
+
+    row_off: host int64[nsys+1] system boundaries. scheme "mgs1r" or "mgs1r_ir32".
+    """
+
+    def __init__(self, row_off, row_ptr, col_idx, vals, m: int, scheme: str = "mgs1r", stream=None):
+        import torch
+
+        if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32 or vals.dtype != torch.float64:
+            raise TypeError("CSR arrays must be int32, int32, float64")
+        for t in (row_ptr, col_idx, vals):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("CSR arrays must be contiguous device tensors")
+        self.row_off = np.ascontiguousarray(row_off, dtype=np.int64)
+        self.nsys = len(self.row_off) - 1
+        self.n = int(row_ptr.numel() - 1)
+        self.m = int(m)
+        self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        self.device = row_ptr.device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._keep = (row_ptr, col_idx, vals)
+        nbytes = gmres_batch_workspace_bytes(self.row_off, self.m, self.scheme)
+        if nbytes == 0:
+            raise GmresError(GMRES_ERR_ARG, "gmres_batch_workspace_bytes")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        self.ws_bytes = nbytes
+        nnz = int(col_idx.numel())
+        rc, ctx = gmres_batch_create(self.row_off, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                     vals.data_ptr() if nnz else None, self.m, self.scheme,
+                                     self.ws_ptr, nbytes, self.stream.cuda_stream)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_create")
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            gmres_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, b, x):
+        import torch
+
+        for t in (b, x):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != self.n:
+                raise ValueError("b and x must be contiguous float64 device tensors of length n")
+
+    def solve(self, b, x, rtol: float, max_iters: int, check: bool = True):
+        """Solve every system; returns (status, dict of per-system numpy arrays)."""
+        self._check(b, x)
+        rc, info = gmres_batch_solve(self.ctx, b.data_ptr(), x.data_ptr(), rtol, max_iters, self.nsys)
+        if check and rc not in (GMRES_OK, GMRES_ERR_NONFINITE):
+            raise GmresError(rc, "gmres_batch_solve")
+        return rc, batch_info_arrays(info)
+
+    def solve_async(self, b, x, rtol: float, max_iters: int, info=None):
+        self._check(b, x)
+        rc = gmres_batch_solve_async(self.ctx, b.data_ptr(), x.data_ptr(), rtol, max_iters,
+                                     None if info is None else info.data_ptr())
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_solve_async")
+
+    def read_info(self) -> dict:
+        rc, info = gmres_batch_read_info(self.ctx, self.nsys)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_read_info")
+        return batch_info_arrays(info)
+
+    def set_config(self, block_size: int = 256, grid: int = 0, order: int = GMRES_BATCH_ORDER_LARGEST_FIRST):
+        rc = gmres_batch_set_config(self.ctx, block_size, grid, order)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_set_config")
+
+    def config(self):
+        rc, bs, grid, order = gmres_batch_get_config(self.ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_get_config")
+        return {"block_size": bs, "grid": grid, "order": order}
+
+    def autotune(self, b, x, rtol: float, max_iters: int):
+        self._check(b, x)
+        rc, trials = gmres_batch_autotune(self.ctx, b.data_ptr(), x.data_ptr(), rtol, max_iters)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_autotune")
+        return trials
+
+    def capture(self, b, x, rtol: float, max_iters: int):
+        self._check(b, x)
+        rc = gmres_batch_capture(self.ctx, b.data_ptr(), x.data_ptr(), rtol, max_iters)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_capture")
+
+    def replay(self):
+        rc = gmres_batch_replay(self.ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_replay")

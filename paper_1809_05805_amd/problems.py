@@ -19,9 +19,13 @@ same row structure (7 and 27 nonzeros per row) and the same physics family
 * ``simonici``: the diagonal test matrix of Section V-A,
   diag(1e-8, 2, 3, ..., 100) with a normalized random right-hand side.
 
+* ``make_batch``: many independent 2D convection-diffusion systems of uneven
+  sizes, the diagonal blocks of one block-diagonal CSR matrix.
+
 Random numbers come from ``numpy.random.PCG64`` seeded by
 ``SeedSequence([config_id, stream, seed])``; stream 0 draws x_true, stream 1
-off-diagonal values, stream 2 row scales, stream 3 right-hand sides.
+off-diagonal values, stream 2 row scales, stream 3 right-hand sides (of the
+batch: the per-system grid sides, Peclet numbers and wind angles).
 """
 
 from __future__ import annotations
@@ -42,6 +46,8 @@ __all__ = [
     "cyclic_shift",
     "random_dense",
     "make_config",
+    "BatchProblem",
+    "make_batch",
 ]
 
 
@@ -226,3 +232,87 @@ def make_config(name: str, seed: int = 0, N: int | None = None) -> Problem:
     return Problem(name, rp, ci, va, np.ascontiguousarray(b), np.zeros(n), x_true, m, rtol,
                    meta={"N": N, "config_id": cid})
 
+
+
+@dataclass
+class BatchProblem:
+    """Independent systems as the diagonal blocks of one CSR matrix.
+
+    System i owns rows and columns [row_off[i], row_off[i+1]); ``sides``,
+    ``peclet`` and ``angle`` are its grid side, Peclet number and wind angle.
+    """
+
+    name: str
+    row_off: np.ndarray
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    vals: np.ndarray
+    b: np.ndarray
+    x0: np.ndarray
+    x_true: np.ndarray
+    m: int
+    rtol: float
+    sides: np.ndarray
+    peclet: np.ndarray
+    angle: np.ndarray
+
+    @property
+    def nsys(self) -> int:
+        return int(self.row_off.shape[0] - 1)
+
+    @property
+    def n(self) -> int:
+        return int(self.row_off[-1])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.shape[0])
+
+    def system(self, i: int) -> Problem:
+        """System i as a stand-alone Problem (local row and column indices)."""
+        r0, r1 = int(self.row_off[i]), int(self.row_off[i + 1])
+        e0, e1 = int(self.row_ptr[r0]), int(self.row_ptr[r1])
+        rp = (self.row_ptr[r0: r1 + 1] - e0).astype(np.int32)
+        ci = (self.col_idx[e0:e1] - r0).astype(np.int32)
+        return Problem(f"{self.name}[{i}]", rp, ci, self.vals[e0:e1].copy(), self.b[r0:r1].copy(),
+                       self.x0[r0:r1].copy(), self.x_true[r0:r1].copy(), self.m, self.rtol,
+                       meta={"N": int(self.sides[i]), "peclet": float(self.peclet[i]),
+                             "angle": float(self.angle[i])})
+
+
+def make_batch(nsys: int = 512, seed: int = 0, side_lo: int = 32, side_hi: int = 256,
+               m: int = 30, rtol: float = 1e-10) -> BatchProblem:
+    """Batch of 2D 5-point upwind convection-diffusion systems (config id 5).
+
+    Per system: grid side N ~ U{side_lo..side_hi} (n = N^2), Peclet ~ U(1, 100)
+    and wind (cos t, sin t) with t ~ U(0, 2 pi), all from stream 3;
+    x_true ~ U(-1, 1) over the whole batch from stream 0; b = A x_true, x0 = 0.
+    """
+    if nsys < 1 or side_lo < 1 or side_hi < side_lo:
+        raise ValueError("need nsys >= 1 and 1 <= side_lo <= side_hi")
+    cid = 5
+    g = rng(cid, 3, seed)
+    sides = g.integers(side_lo, side_hi + 1, size=nsys)
+    peclet = g.uniform(1.0, 100.0, size=nsys)
+    angle = g.uniform(0.0, 2.0 * np.pi, size=nsys)
+    sizes = sides.astype(np.int64) ** 2
+    row_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(row_off[-1])
+    rps, cis, vas = [], [], []
+    nnz = 0
+    for i in range(nsys):
+        A = convdiff(int(sides[i]), 2, (np.cos(angle[i]), np.sin(angle[i])), float(peclet[i]))
+        rp, ci, va = csr_from_scipy(A)
+        rps.append(rp[:-1].astype(np.int64) + nnz)
+        cis.append(ci.astype(np.int64) + row_off[i])
+        vas.append(va)
+        nnz += int(rp[-1])
+    if nnz >= 2**31 or n >= 2**31:
+        raise ValueError("batch too large for int32 CSR indices")
+    row_ptr = np.concatenate(rps + [np.array([nnz])]).astype(np.int32)
+    col_idx = np.concatenate(cis).astype(np.int32)
+    vals = np.concatenate(vas)
+    x_true = rng(cid, 0, seed).uniform(-1.0, 1.0, n)
+    b = sp.csr_matrix((vals, col_idx, row_ptr), shape=(n, n)) @ x_true
+    return BatchProblem(f"batch{nsys}", row_off, row_ptr, col_idx, vals, np.ascontiguousarray(b),
+                        np.zeros(n), x_true, m, rtol, sides, peclet, angle)

@@ -1,0 +1,289 @@
+"""Batched persistent solver (gmres_batch_*) against the oracle, system by system.
+
+Every system of a batch is an independent restarted one-reduce GMRES(m)
+solve, so each is compared with the oracle's GMRES_MGS_1R solve of that
+system alone, with the tolerances of the single-system parity tests: after a
+fixed budget (no early exit) the iterate within 1e-10 relative; to tolerance,
+equal iteration counts up to one and both truly converged. The float32-basis
+batch is held to the float64 stopping test and its iterate compared with the
+float64 oracle within 10 kappa_est rtol (as for the single-system float32
+scheme). Results must not depend on the grid or the queue order, and a
+captured graph must reproduce the eager solve bit for bit on every replay.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1809_05805_amd import problems as P
+from tests.gpu_util import log, oracle_run, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1809_05805_amd import native
+    native.load()
+    yield
+
+
+def small_batch(nsys=24, seed=1, lo=6, hi=40):
+    # sides 6..40: n from 36 (most of a 256-thread workgroup idle) to 1600
+    # (several row blocks of 2048 and a ragged last one)
+    return P.make_batch(nsys=nsys, seed=seed, side_lo=lo, side_hi=hi, m=30, rtol=TOL)
+
+
+SMALL = small_batch()
+
+
+def tensors(bp):
+    import torch
+
+    return (torch.from_numpy(bp.row_ptr).cuda(), torch.from_numpy(bp.col_idx).cuda(),
+            torch.from_numpy(bp.vals).cuda())
+
+
+def solver(bp, scheme="mgs1r", m=None, stream=None):
+    from paper_1809_05805_amd.native import BatchSolver
+
+    rp, ci, va = tensors(bp)
+    return BatchSolver(bp.row_off, rp, ci, va, bp.m if m is None else m, scheme, stream=stream)
+
+
+def run(bp, scheme="mgs1r", rtol=TOL, max_iters=20000, b=None, x0=None, config=None, m=None):
+    import torch
+
+    s = solver(bp, scheme, m)
+    if config:
+        s.set_config(*config)
+    bt = torch.from_numpy(np.ascontiguousarray(bp.b if b is None else b)).cuda()
+    xt = torch.from_numpy(np.array(bp.x0 if x0 is None else x0, dtype=np.float64)).cuda()
+    rc, info = s.solve(bt, xt, rtol, max_iters)
+    torch.cuda.synchronize()
+    return rc, info, xt.cpu().numpy(), s
+
+
+def true_rel(bp, i, x):
+    p = bp.system(i)
+    nb = np.linalg.norm(p.b)
+    return float(np.linalg.norm(p.b - p.scipy() @ x[bp.row_off[i]: bp.row_off[i + 1]]) / nb)
+
+
+@pytest.mark.parametrize("bs", [256, 512, 1024])
+def test_fixed_budget_parity(bs):
+    """45 Arnoldi steps per system (one full cycle and half of the next), rtol 0."""
+    bp = SMALL
+    log(f"batch fixed budget bs={bs}")
+    rc, info, x, _ = run(bp, rtol=0.0, max_iters=45, config=(bs, 0, 1))
+    assert rc == 0
+    worst = 0.0
+    for i in range(bp.nsys):
+        p = bp.system(i)
+        o = oracle_run(p, "mgs1r", m=30, rtol=0.0, max_iters=45, dump=False)
+        xi = x[bp.row_off[i]: bp.row_off[i + 1]]
+        assert info["iters"][i] == o.iters, i
+        assert info["cycles"][i] == o.cycles, i
+        assert info["status"][i] == 0
+        e = rel(xi, o.x)
+        worst = max(worst, e)
+        assert e <= TOL, (i, p.n, e)
+        assert abs(info["rel_res_true"][i] - o.rel_res_true) <= TOL * max(o.rel_res_true, 1e-3)
+    log(f"  worst |x - x_oracle| / |x_oracle| = {worst:.2e}")
+
+
+def test_to_tolerance_parity():
+    bp = SMALL
+    log("batch to tolerance fp64")
+    rc, info, x, _ = run(bp)
+    assert rc == 0
+    for i in range(bp.nsys):
+        p = bp.system(i)
+        o = oracle_run(p, "mgs1r", m=30, rtol=TOL, dump=False)
+        xi = x[bp.row_off[i]: bp.row_off[i + 1]]
+        assert o.converged and info["converged"][i] == 1, i
+        assert abs(int(info["iters"][i]) - o.iters) <= 1, (i, info["iters"][i], o.iters)
+        r = true_rel(bp, i, x)
+        assert r <= TOL * (1 + 1e-6), (i, r)
+        assert abs(info["rel_res_true"][i] - r) <= 1e-3 * r + 1e-16
+        assert rel(xi, o.x) <= 10 * 1e4 * TOL
+
+
+def test_fp32_basis_to_tolerance():
+    bp = SMALL
+    log("batch to tolerance fp32 basis")
+    rc, info, x, _ = run(bp, "mgs1r_ir32")
+    _, info64, x64, _ = run(bp)
+    assert rc == 0
+    errs = []
+    for i in range(bp.nsys):
+        p = bp.system(i)
+        o = oracle_run(p, "mgs1r", m=30, rtol=TOL, dump=False)
+        xi = x[bp.row_off[i]: bp.row_off[i + 1]]
+        assert info["converged"][i] == 1 and info["status"][i] == 0, i
+        r = true_rel(bp, i, x)
+        assert r <= TOL * (1 + 1e-6), (i, r)
+        kappa = max(rel(o.x, p.x_true) / TOL, 1.0)
+        e = rel(xi, o.x)
+        errs.append(e)
+        assert e <= 10 * kappa * TOL, (i, e, kappa)
+        assert info["iters"][i] <= int(np.ceil(1.34 * info64["iters"][i])) + 30
+    log(f"  fp32 basis: iters {int(info['iters'].sum())} (fp64 {int(info64['iters'].sum())}), "
+        f"max |x - x_oracle| / |x_oracle| {max(errs):.2e}")
+
+
+def test_config_invariance():
+    """Grid and queue order change the schedule, not the arithmetic."""
+    bp = SMALL
+    log("batch config invariance")
+    _, i0, x0, _ = run(bp, rtol=TOL, config=(256, 0, 1))
+    for cfg in [(256, 1, 1), (256, 7, 0), (256, 1000, 0)]:
+        _, i1, x1, _ = run(bp, rtol=TOL, config=cfg)
+        assert np.array_equal(x0, x1), cfg
+        assert np.array_equal(i0["iters"], i1["iters"])
+
+
+def test_graph_replay():
+    """Capture once, replay three times with eager work in between: every replay equals eager."""
+    import torch
+
+    bp = SMALL
+    log("batch graph capture")
+    stream = torch.cuda.Stream()
+    s = solver(bp, stream=stream)
+    bt = torch.from_numpy(bp.b).cuda()
+    x_e = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        rc, info_e = s.solve(bt, x_e, TOL, 20000)
+    torch.cuda.synchronize()
+    x = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    s.capture(bt, x, TOL, 20000)
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            x.zero_()
+            s.replay()
+        stream.synchronize()
+        info = s.read_info()
+        assert torch.equal(x, x_e), rep
+        assert np.array_equal(info["iters"], info_e["iters"])
+        # eager work between replays
+        y = (x_e * 2.0).sum().item()
+        assert np.isfinite(y)
+
+
+def test_autotune():
+    import torch
+
+    bp = SMALL
+    log("batch autotune")
+    s = solver(bp)
+    bt = torch.from_numpy(bp.b).cuda()
+    x = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+    trials = s.autotune(bt, x, TOL, 20000)
+    assert len(trials) >= 6 and all(t[3] > 0 for t in trials)
+    best = min(trials, key=lambda t: t[3])
+    cfg = s.config()
+    assert (cfg["block_size"], cfg["grid"], cfg["order"]) == best[:3]
+    assert torch.count_nonzero(x).item() == 0  # x restored
+    rc, info = s.solve(bt, x, TOL, 20000)
+    assert rc == 0 and np.all(info["converged"] == 1)
+    log("  trials: " + ", ".join(f"{t[0]}/{t[1]}/{t[2]}:{t[3]:.2f}ms" for t in trials))
+
+
+def test_edges():
+    """Zero right-hand side, a NaN in one system, max_iters 0, one-row systems."""
+    import scipy.sparse as sp
+
+    from paper_1809_05805_amd import native
+
+    bp = small_batch(nsys=6, seed=3, lo=3, hi=12)
+    log("batch edges")
+    b = bp.b.copy()
+    b[bp.row_off[1]: bp.row_off[2]] = 0.0
+    b[bp.row_off[3] + 2] = np.nan
+    x0 = np.ones(bp.n)
+    rc, info, x, _ = run(bp, b=b, x0=x0)
+    assert rc == native.GMRES_ERR_NONFINITE
+    assert info["status"][3] == native.GMRES_ERR_NONFINITE
+    assert info["converged"][1] == 1 and info["iters"][1] == 0
+    assert np.all(x[bp.row_off[1]: bp.row_off[2]] == 0.0)
+    for i in (0, 2, 4, 5):
+        assert info["status"][i] == 0 and info["converged"][i] == 1
+        assert true_rel(bp, i, x) <= TOL * (1 + 1e-6)
+    rc, info, x, _ = run(bp, max_iters=0)
+    assert np.all(info["iters"] == 0) and np.all(np.abs(info["rel_res_true"] - 1.0) <= 1e-15)
+    # one-row systems next to a larger one
+    blocks = [sp.csr_matrix(np.array([[4.0]])), sp.csr_matrix(np.array([[2.0]])),
+              P.convdiff(9, 2, (1.0, 0.0), 5.0)]
+    A = sp.block_diag(blocks, format="csr")
+    rp, ci, va = P.csr_from_scipy(A)
+    n = A.shape[0]
+    xt = np.linspace(-1.0, 1.0, n)
+    one = P.BatchProblem("ones", np.array([0, 1, 2, n]), rp, ci, va, A @ xt, np.zeros(n), xt, 5,
+                         1e-12, np.array([1, 1, 9]), np.ones(3), np.zeros(3))
+    rc, info, x, _ = run(one, rtol=1e-12)
+    assert rc == 0 and np.all(info["converged"] == 1)
+    assert abs(x[0] - xt[0]) <= 1e-15 and abs(x[1] - xt[1]) <= 1e-15
+    assert rel(x[2:], xt[2:]) <= 1e-8
+
+
+def test_create_refusals():
+    import torch
+
+    from paper_1809_05805_amd import native
+    from paper_1809_05805_amd.native import BatchSolver, GmresError
+
+    bp = small_batch(nsys=4, seed=2, lo=4, hi=8)
+    rp, ci, va = tensors(bp)
+    log("batch create refusals")
+    # a column of system 1 pointing into system 0
+    bad = bp.col_idx.copy()
+    bad[bp.row_ptr[bp.row_off[1]]] = 0
+    with pytest.raises(GmresError) as e:
+        BatchSolver(bp.row_off, rp, torch.from_numpy(bad).cuda(), va, 10)
+    assert e.value.rc == native.GMRES_ERR_ARG
+    # row offsets that do not increase, and the schemes without a batched form
+    ro = bp.row_off.copy()
+    ro[2] = ro[1]
+    with pytest.raises(GmresError):
+        BatchSolver(ro, rp, ci, va, 10)
+    for scheme in ("mgs", "cgs2"):
+        with pytest.raises(GmresError):
+            BatchSolver(bp.row_off, rp, ci, va, 10, scheme)
+    s = BatchSolver(bp.row_off, rp, ci, va, 10)
+    with pytest.raises(GmresError):
+        s.set_config(128, 0, 0)
+    with pytest.raises(GmresError):
+        s.set_config(256, -1, 0)
+
+
+@pytest.mark.parametrize("scheme", ["mgs1r", "mgs1r_ir32"])
+def test_full_batch(scheme):
+    """512 systems, sides 32..256, Peclet 1..100, m=30, rtol 1e-10: every system truly
+    converged (residuals recomputed here), the three smallest against the oracle."""
+    bp = P.make_batch()
+    log(f"full batch {scheme}: n={bp.n} nnz={bp.nnz}")
+    rc, info, x, _ = run(bp, scheme)
+    assert rc == 0
+    assert np.all(info["status"] == 0) and np.all(info["converged"] == 1)
+    A = None
+    worst = 0.0
+    for i in range(bp.nsys):
+        r = true_rel(bp, i, x)
+        worst = max(worst, r)
+        assert r <= TOL * (1 + 1e-6), (i, r)
+    log(f"  iters total {int(info['iters'].sum())}, max {int(info['iters'].max())}, "
+        f"worst true rel res {worst:.2e}")
+    for i in np.argsort(bp.row_off[1:] - bp.row_off[:-1], kind="stable")[:3]:
+        p = bp.system(int(i))
+        o = oracle_run(p, "mgs1r", m=30, rtol=TOL, dump=False)
+        xi = x[bp.row_off[i]: bp.row_off[i + 1]]
+        if scheme == "mgs1r":
+            assert abs(int(info["iters"][i]) - o.iters) <= 1
+        assert rel(xi, o.x) <= 10 * 1e4 * TOL
+    del A

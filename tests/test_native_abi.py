@@ -69,3 +69,37 @@ def test_header_constants_match_binding():
                       ("GMRES_ERR_ARG", -1), ("GMRES_ERR_HIP", -2), ("GMRES_ERR_NONFINITE", -3),
                       ("GMRES_ERR_WORKSPACE", -4)):
         assert re.search(rf"{name} = {val}\b", src), name
+
+
+def test_batch_workspace_sizing(lib):
+    import numpy as np
+
+    ro = np.array([0, 1000, 1100, 5196], dtype=np.int64)
+    m = 30
+    f64 = native.gmres_batch_workspace_bytes(ro, m, native.GMRES_MGS_1R)
+    f32 = native.gmres_batch_workspace_bytes(ro, m, native.GMRES_MGS_1R_IR32)
+    # bases: (m+1) columns of n_i rounded up to 64
+    ld = [1024, 128, 4096]
+    basis = sum(ld) * (m + 1)
+    small = 2 * (m + 1) * m + 2 * (m + 2) ** 2 + 7 * (m + 2)
+    assert f64 >= 8 * basis + 3 * 8 * small + 8 * 5196 * 2
+    assert f64 <= 8 * basis + 3 * 8 * small + 8 * 5196 * 2 + 3 * 400 + 12 * 256
+    assert f32 >= 4 * basis + 3 * 8 * small + 4 * 5196 + 2 * 8 * 5196
+    assert f32 < f64
+    # refusals: empty systems, a bad first offset, the schemes with no batched form, m out of range
+    assert native.gmres_batch_workspace_bytes(np.array([0, 10, 10]), m, 1) == 0
+    assert native.gmres_batch_workspace_bytes(np.array([1, 10]), m, 1) == 0
+    assert native.gmres_batch_workspace_bytes(ro, m, native.GMRES_MGS) == 0
+    assert native.gmres_batch_workspace_bytes(ro, m, native.GMRES_CGS2) == 0
+    assert native.gmres_batch_workspace_bytes(ro, 0, 1) == 0
+    assert native.gmres_batch_workspace_bytes(ro, native.GMRES_MAX_RESTART + 1, 1) == 0
+    assert native.gmres_batch_workspace_bytes(np.array([0, 2**28]), m, 1) == 0
+    assert native.gmres_batch_workspace_bytes(np.array([0, 2**28 - 1]), m, 1) > 0
+
+
+def test_batch_info_layout():
+    assert ctypes.sizeof(native.GmresBatchInfo) == 32
+    assert native.GmresBatchInfo.rel_res_true.offset == 24
+    src = open(os.path.join(ROOT, "include", "gmres.h")).read()
+    for name, val in (("GMRES_BATCH_ORDER_NATURAL", 0), ("GMRES_BATCH_ORDER_LARGEST_FIRST", 1)):
+        assert re.search(rf"{name} = {val}\b", src), name
