@@ -179,6 +179,114 @@ def precision_config(args):
     return out
 
 
+BATCH_WORKLOAD = ("512 independent 2D 5-point upwind convection-diffusion systems, grid side "
+                  "U{32..256} (n 1,024-65,536), Peclet U(1,100), wind angle U(0,2pi), GMRES(30) to 1e-10")
+
+
+def batch_bytes(info, sizes, nnz_sys, m, vb):
+    """Algorithmic HBM bytes of a batched solve from each system's iteration and
+    cycle counts (cycles taken full but the last). Per Arnoldi step k: A, the
+    projection's read of V[:,0:k+1], w written; MAXPY's read of V[:,0:k+1] and w
+    and its two column writes; per cycle the norm-only step, the x update and
+    the restart residual. vb: bytes per basis entry (8 or 4)."""
+    import numpy as np
+
+    total = 0.0
+    for it, cyc, n, nnz in zip(info["iters"], info["cycles"], sizes, nnz_sys):
+        A = 12.0 * nnz + 4.0 * (n + 1)
+        full = max(int(cyc) - 1, 0)
+        js = [m] * full + [int(it) - m * full] if cyc else []
+        for j in js:
+            k = np.arange(j)
+            total += j * A + vb * n * float(np.sum(2 * (k + 1) + 4))       # steps
+            total += vb * n + 8.0 * n * j + 16.0 * n + A + 24.0 * n        # norm step, x update, restart
+        total += A + 24.0 * n                                              # the final residual check
+    return total
+
+
+def batch_result(args):
+    """The batched form: one persistent launch per solve of the whole batch,
+    float64 and float32 basis, each with the autotuned launch configuration,
+    against single-system float64 solves of a stratified sample run one by one."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    from paper_1809_05805_amd import problems
+    from paper_1809_05805_amd.native import BatchSolver, GmresSolver
+
+    t0 = time.perf_counter()
+    bp = problems.make_batch(nsys=args.batch_systems)
+    log(f"batch: {bp.nsys} systems, n={bp.n} nnz={bp.nnz}, built in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (bp.row_ptr, bp.col_idx, bp.vals))
+    b = torch.from_numpy(bp.b).to(dev)
+    A = sp.csr_matrix((bp.vals, bp.col_idx, bp.row_ptr), shape=(bp.n, bp.n))
+    sizes = np.diff(bp.row_off)
+    nnz_sys = bp.row_ptr[bp.row_off[1:]].astype(np.int64) - bp.row_ptr[bp.row_off[:-1]]
+    bnorm = np.sqrt(np.add.reduceat(bp.b ** 2, bp.row_off[:-1]))
+    out = {"workload": BATCH_WORKLOAD if args.batch_systems == 512 else f"{bp.nsys} systems",
+           "systems": bp.nsys, "rows": bp.n, "nnz": bp.nnz, "m": bp.m, "rtol": bp.rtol}
+    for scheme, key, vb in (("mgs1r", "fp64", 8), ("mgs1r_ir32", "fp32_basis", 4)):
+        s = BatchSolver(bp.row_off, rp, ci, va, bp.m, scheme)
+        x = torch.zeros(bp.n, dtype=torch.float64, device=dev)
+        trials = []
+        if not args.no_batch_autotune:
+            trials = s.autotune(b, x, bp.rtol, args.max_iters)
+        cfg = s.config()
+        times = []
+        for rep in range(1 + args.batch_steps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rc, info = s.solve(b, x, bp.rtol, args.max_iters)
+            times.append(time.perf_counter() - t)
+        dt = float(np.mean(times[1:]))
+        xs = x.cpu().numpy()
+        res = np.sqrt(np.add.reduceat((bp.b - A @ xs) ** 2, bp.row_off[:-1])) / bnorm
+        iters = int(info["iters"].sum())
+        nbytes = batch_bytes(info, sizes, nnz_sys, bp.m, vb)
+        out[key] = {"iters_per_s": round(iters / dt, 1), "ms_per_solve": round(dt * 1e3, 2),
+                    "iters": iters, "max_iters_one_system": int(info["iters"].max()),
+                    "all_converged": bool(np.all(info["converged"] == 1)) and rc == 0,
+                    "worst_rel_res_true_fp64_recomputed": float(res.max()),
+                    "algorithmic_GBps": round(nbytes / dt / 1e9, 1),
+                    "config": cfg,
+                    "autotune_trials": [{"block_size": t[0], "grid": t[1],
+                                         "order": "largest_first" if t[2] else "natural",
+                                         "ms": round(t[3], 2)} for t in trials]}
+        log(f"batch {scheme}: {iters} iters in {dt * 1e3:.1f} ms ({iters / dt:.0f} it/s), cfg {cfg}, "
+            f"worst rel res {res.max():.2e}")
+        s.close()
+        del x
+    # single-system float64 solves, one after another, on systems spread over the sizes
+    order = np.argsort(sizes, kind="stable")
+    sample = order[np.linspace(0, bp.nsys - 1, min(16, bp.nsys)).astype(int)]
+    it_s, t_s = 0, 0.0
+    for i in sample:
+        p = bp.system(int(i))
+        r2, c2, v2 = (torch.from_numpy(a).to(dev) for a in (p.row_ptr, p.col_idx, p.vals))
+        g = GmresSolver(r2, c2, v2, bp.m, "mgs1r")
+        bb = torch.from_numpy(p.b).to(dev)
+        xx = torch.zeros(p.n, dtype=torch.float64, device=dev)
+        g.solve(bb, xx, bp.rtol, args.max_iters)
+        xx.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = g.solve(bb, xx, bp.rtol, args.max_iters)
+        t_s += time.perf_counter() - t
+        it_s += r.iters
+        g.close()
+    seq = it_s / t_s
+    out["sequential_fp64"] = {"iters_per_s": round(seq, 1), "iters": it_s, "seconds": round(t_s, 3),
+                              "sample": f"{len(sample)} systems evenly spread over the sorted sizes, "
+                                        "each solved alone by the single-system float64 path"}
+    out["fp64_speedup_vs_sequential"] = round(out["fp64"]["iters_per_s"] / seq, 2)
+    out["fp32_basis_speedup_vs_sequential"] = round(out["fp32_basis"]["iters_per_s"] / seq, 2)
+    log(f"batch: sequential sample {seq:.0f} it/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +303,11 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a reference kernel "
                          "for hardware byte counters)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-solver section")
+    ap.add_argument("--no-batch-autotune", action="store_true",
+                    help="batched solves with the default launch configuration")
+    ap.add_argument("--batch-systems", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed batched solves per scheme")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver is built and measured for a single "
@@ -289,6 +402,8 @@ def main():
             log(f"{scheme}: {it2 / k2:.0f} iters/solve, {dt2 / k2 * 1e3:.2f} ms/solve")
             sv.close()
         out["speedup_vs_mgs"] = round(out["value"] / out["mgs_baseline"]["iters_per_s"], 3)
+    if not args.no_batch:
+        out["batch"] = batch_result(args)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, one restart cycle ...")
         out["cpu_baseline"] = cpu_baseline(p, m)

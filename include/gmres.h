@@ -261,12 +261,13 @@ int gmres_get_timing(gmres_ctx* ctx, gmres_kernel_stat* stats /* host, GMRES_KST
  * (the GMRES_MGS_1R step of Section III, or its GMRES_MGS_1R_IR32 form) with
  * its own restart cycles, lagged normalization state, T matrix, Givens
  * rotations and stopping test ||b_i - A_i x_i|| <= rtol ||b_i||. One kernel
- * launch solves the whole batch: a fixed number of workgroups take systems
- * from a device-side queue, in the chosen order, until it is empty, and each
- * workgroup runs its system's entire solve with workgroup-level reductions
- * in place of the single-system device-wide ones (the paper maps its
- * reductions onto SIMD lanes on the CPU and onto all of the GPU for one
- * system, Section V-B; here the batch fills the GPU instead).
+ * launch solves the whole batch: a fixed number of workgroups take entries
+ * from a device-side queue until it is empty. An entry is a whole system, or
+ * one row part of a larger system: such a team of workgroups (up to 16) adds
+ * its parts' sums through global memory once per step, where a one-part
+ * system reduces within its workgroup and the single-system path across the
+ * GPU (the paper maps its reductions onto SIMD lanes on the CPU and onto the
+ * whole GPU for one system, Section V-B; here the batch fills the GPU).
  * gmres_batch_solve_async makes no host synchronization, memset or
  * allocation, so it can be captured into a HIP graph;
  * gmres_batch_capture / gmres_batch_replay do that inside the library.
@@ -278,7 +279,9 @@ typedef struct {
   int64_t iters;       /* Arnoldi columns completed over all cycles                 */
   int32_t cycles;      /* restart cycles that ran at least one Arnoldi step         */
   int32_t converged;   /* 1 if ||b_i - A_i x_i|| <= rtol ||b_i|| was verified       */
-  int32_t status;      /* GMRES_OK or GMRES_ERR_NONFINITE for this system           */
+  int32_t status;      /* GMRES_OK, GMRES_ERR_NONFINITE, or GMRES_ERR_HIP if the
+                          parts of this system's team did not all run at once
+                          (each waits about half a minute at most, then gives up) */
   int32_t breakdown;   /* 1 if a cycle ended on an exact breakdown, rho == 0        */
   double rel_res_true; /* ||b_i - A_i x_i|| / ||b_i|| at exit, from a residual the
                           device computed in float64 (0 when ||b_i|| == 0)           */
@@ -305,7 +308,7 @@ size_t gmres_batch_workspace_bytes(int32_t nsys, const int64_t* row_off, int32_t
  * CSR structure and that every column index of a system's rows lies in the
  * system's own range; GMRES_ERR_ARG otherwise. Blocks until the checks are
  * done. The initial configuration is 256-thread workgroups, as many as the
- * GPU holds at once (at most nsys), systems largest first.
+ * GPU holds at once, systems largest first, parts of 8192 rows.
  */
 int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, int64_t nnz,
                        const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
@@ -332,8 +335,9 @@ int gmres_batch_solve_async(gmres_batch* bt, const double* b, double* x, double 
 
 /*
  * The same, then wait: info (host, nullable, nsys entries) receives the
- * results. Returns GMRES_ERR_NONFINITE if any system met a NaN or Inf (the
- * others are still solved), else GMRES_OK.
+ * results. Returns GMRES_ERR_HIP if a team could not assemble,
+ * GMRES_ERR_NONFINITE if any system met a NaN or Inf (the others are still
+ * solved), else GMRES_OK.
  */
 int gmres_batch_solve(gmres_batch* bt, const double* b, double* x, double rtol, int64_t max_iters,
                       gmres_batch_info* info);
@@ -344,26 +348,34 @@ int gmres_batch_read_info(gmres_batch* bt, gmres_batch_info* info);
 /*
  * Launch configuration: block_size 256, 512 or 1024 threads per workgroup;
  * grid >= 1 persistent workgroups (0: as many as the GPU holds at once, at
- * most nsys); order GMRES_BATCH_ORDER_*. The results do not depend on it
- * (each system's arithmetic is fixed by its workgroup size: the per-wavefront
- * sums are combined in a fixed order), only the time.
+ * most the number of queue entries); order GMRES_BATCH_ORDER_*; part_rows:
+ * system i is split into ceil(n_i / part_rows) parts (0: never split), but
+ * at most 16, at most one per 256 rows, and at most the grid or what the GPU
+ * holds at once. Blocks (the queue is uploaded). Each system's arithmetic is
+ * fixed by the block size and its number of parts; the grid and the order
+ * change only the time. get_config reports the grid in use and the largest
+ * team (host pointers, each nullable).
  */
-int gmres_batch_set_config(gmres_batch* bt, int32_t block_size, int32_t grid, int32_t order);
-int gmres_batch_get_config(gmres_batch* bt, int32_t* block_size, int32_t* grid, int32_t* order);
+int gmres_batch_set_config(gmres_batch* bt, int32_t block_size, int32_t grid, int32_t order,
+                           int64_t part_rows);
+int gmres_batch_get_config(gmres_batch* bt, int32_t* block_size, int32_t* grid, int32_t* order,
+                           int64_t* part_rows, int32_t* max_parts);
 
 typedef struct {
   int32_t block_size, grid, order;
   float ms; /* event-timed duration of the solve */
+  int64_t part_rows;
 } gmres_batch_trial;
 
 /*
- * Time one solve of (b, x, rtol, max_iters) under each candidate
- * configuration (block sizes 256, 512, 1024; grids of one workgroup per
- * compute unit and of as many as the GPU holds; both orders) after one
- * warm-up solve, keep the fastest, and leave x as it was on entry (it is
- * restored from the workspace's copy before every trial). trials (host,
- * nullable, max_trials entries) and ntrials (host, nullable) report what was
- * timed. Blocks.
+ * Time one solve of (b, x, rtol, max_iters) under candidate configurations
+ * after one warm-up solve: block sizes 256, 512 and 1024 with parts of
+ * 16384, 8192 or 4096 rows or no split (largest first, as many workgroups as
+ * the GPU holds), then for the fastest a grid of one workgroup per compute
+ * unit and the natural order. Keeps the fastest and leaves x as it was on
+ * entry (it is restored from the workspace's copy before every trial).
+ * trials (host, nullable, max_trials entries) and ntrials (host, nullable)
+ * report what was timed. Blocks.
  */
 int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rtol,
                          int64_t max_iters, gmres_batch_trial* trials, int32_t max_trials,

@@ -45,15 +45,27 @@ bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// A system is split into at most kTeamMax parts of at least kMinPartRows
+// rows each; every possible part has a slot (small workspace, state record,
+// reduction partials) reserved at create.
+constexpr int kTeamMax = 16;
+constexpr int64_t kDefaultPartRows = 8192;
+constexpr int64_t kMinPartRows = 256;
+
+int team_cap(int64_t n) {
+  const int64_t c = (n + kMinPartRows - 1) / kMinPartRows;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kTeamMax, c));
+}
+
 struct BatchLayout {
   std::vector<BatchSys> sys;
   int64_t n;
-  size_t o_sys, o_nat, o_lpt, o_st, o_queue, o_out, o_small, o_V, o_w, o_r64, o_xsave, total;
+  int slots;
+  size_t o_sys, o_tk, o_st, o_part, o_bar, o_queue, o_out, o_small, o_V, o_w, o_r64, o_xsave, total;
 };
 
 // Every system's basis starts 256-byte aligned with a leading dimension that
-// is a multiple of 64 elements; the small dense arrays of all systems form
-// one block of batch_small_doubles(m) doubles each.
+// is a multiple of 64 elements.
 bool batch_layout(int32_t nsys, const int64_t* row_off, int32_t m, int32_t scheme, BatchLayout* L) {
   if (nsys < 1 || !row_off || m < 1 || m > GMRES_MAX_RESTART) return false;
   if (scheme != GMRES_MGS_1R && scheme != GMRES_MGS_1R_IR32) return false;
@@ -61,7 +73,7 @@ bool batch_layout(int32_t nsys, const int64_t* row_off, int32_t m, int32_t schem
   const size_t vb = scheme == GMRES_MGS_1R_IR32 ? sizeof(float) : sizeof(double);
   const size_t small = batch_small_doubles(m);
   L->sys.resize((size_t)nsys);
-  int64_t voff = 0;
+  int64_t voff = 0, slots = 0;
   for (int32_t i = 0; i < nsys; ++i) {
     const int64_t n = row_off[i + 1] - row_off[i];
     if (n < 1 || n >= kMaxSysRows) return false;
@@ -70,11 +82,12 @@ bool batch_layout(int32_t nsys, const int64_t* row_off, int32_t m, int32_t schem
     s.n = n;
     s.ldv = (int64_t)round_up((size_t)n, 64);
     s.voff = voff;
-    s.soff = (int64_t)((size_t)i * small);
     voff += s.ldv * (m + 1);
+    slots += team_cap(n);
   }
   L->n = row_off[nsys];
-  if (L->n >= ((int64_t)1 << 31)) return false;
+  if (L->n >= ((int64_t)1 << 31) || slots >= ((int64_t)1 << 30)) return false;
+  L->slots = (int)slots;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -82,12 +95,13 @@ bool batch_layout(int32_t nsys, const int64_t* row_off, int32_t m, int32_t schem
     return at;
   };
   L->o_sys = take(sizeof(BatchSys) * (size_t)nsys);
-  L->o_nat = take(sizeof(int) * (size_t)nsys);
-  L->o_lpt = take(sizeof(int) * (size_t)nsys);
-  L->o_st = take(sizeof(DevState) * (size_t)nsys);
+  L->o_tk = take(sizeof(BatchTicket) * (size_t)slots);
+  L->o_st = take(sizeof(DevState) * (size_t)slots);
+  L->o_part = take(sizeof(double) * 4 * (size_t)(m + 2) * (size_t)slots);
+  L->o_bar = take(sizeof(unsigned) * (size_t)nsys);
   L->o_queue = take(sizeof(unsigned));
   L->o_out = take(sizeof(BatchOut) * (size_t)nsys);
-  L->o_small = take(sizeof(double) * small * (size_t)nsys);
+  L->o_small = take(sizeof(double) * small * (size_t)slots);
   L->o_V = take(vb * (size_t)voff);
   L->o_w = take(vb * (size_t)L->n);
   L->o_r64 = scheme == GMRES_MGS_1R_IR32 ? take(sizeof(double) * (size_t)L->n) : 0;
@@ -99,13 +113,15 @@ bool batch_layout(int32_t nsys, const int64_t* row_off, int32_t m, int32_t schem
 }  // namespace
 
 struct gmres_batch {
-  Batch B;            // device view; b, x, rtol, max_iters, out and order set per solve
-  int nsys, m, scheme;
+  Batch B;            // device view; b, x, rtol, max_iters and out set per solve
+  int nsys, m, scheme, slots;
   int64_t n;
-  int bs, grid, order;  // grid 0: as many as the GPU holds
+  int bs, grid, order;  // grid 0: as many workgroups as the GPU holds
+  int64_t part_rows;    // rows per part of a team (0: one workgroup per system)
+  int grid_eff;         // the grid of the current queue
   int num_cu;
-  const int* order_nat;
-  const int* order_lpt;
+  BatchTicket* tickets_d;
+  std::vector<BatchTicket> tickets;
   BatchOut* out_ws;
   double* xsave;
   hipStream_t stream;
@@ -116,12 +132,42 @@ struct gmres_batch {
 
 namespace {
 
-int effective_grid(const gmres_batch* bt, int bs) {
-  if (bt->grid > 0) return bt->grid;
+// Team sizes, queue order and grid for a configuration; uploads the queue
+// (blocking). Parts of a system: ceil(n / part_rows), at most kTeamMax, one per
+// kMinPartRows rows, and no more than the grid or what the GPU holds at once,
+// so that every team can assemble.
+int apply_config(gmres_batch* bt, int bs, int grid, int order, int64_t part_rows) {
   const int per_cu = batch_resident_blocks(bs, bt->m, bt->scheme == GMRES_MGS_1R_IR32);
-  int64_t g = (int64_t)std::max(per_cu, 1) * bt->num_cu;
-  if (g > bt->nsys) g = bt->nsys;
-  return (int)std::max<int64_t>(g, 1);
+  if (per_cu < 1) return GMRES_ERR_HIP;
+  const int64_t resident = (int64_t)per_cu * bt->num_cu;
+  const int64_t cap = std::min<int64_t>(resident, grid > 0 ? grid : resident);
+  std::vector<int> seq((size_t)bt->nsys);
+  std::iota(seq.begin(), seq.end(), 0);
+  if (order == GMRES_BATCH_ORDER_LARGEST_FIRST)
+    std::stable_sort(seq.begin(), seq.end(),
+                     [&](int a, int b) { return bt->sizes[(size_t)a] > bt->sizes[(size_t)b]; });
+  std::vector<BatchTicket> tk;
+  tk.reserve((size_t)bt->slots);
+  for (int i : seq) {
+    const int64_t n = bt->sizes[(size_t)i];
+    int64_t T = part_rows > 0 ? (n + part_rows - 1) / part_rows : 1;
+    T = std::max<int64_t>(1, std::min<int64_t>({T, (int64_t)team_cap(n), cap}));
+    const int base = (int)tk.size();
+    for (int p = 0; p < (int)T; ++p) tk.push_back(BatchTicket{i, p, (int)T, base});
+  }
+  if ((int)tk.size() > bt->slots) return GMRES_ERR_ARG;  // cannot happen: T <= team_cap
+  if (hipMemcpyAsync(bt->tickets_d, tk.data(), sizeof(BatchTicket) * tk.size(), hipMemcpyHostToDevice,
+                     bt->stream) != hipSuccess ||
+      hipStreamSynchronize(bt->stream) != hipSuccess)
+    return GMRES_ERR_HIP;
+  bt->tickets.swap(tk);
+  bt->B.ntickets = (int)bt->tickets.size();
+  bt->bs = bs;
+  bt->grid = grid;
+  bt->order = order;
+  bt->part_rows = part_rows;
+  bt->grid_eff = grid > 0 ? grid : (int)std::max<int64_t>(1, std::min<int64_t>(resident, bt->B.ntickets));
+  return GMRES_OK;
 }
 
 int enqueue(gmres_batch* bt, const double* b, double* x, double rtol, int64_t max_iters,
@@ -132,10 +178,8 @@ int enqueue(gmres_batch* bt, const double* b, double* x, double rtol, int64_t ma
   B.rtol = rtol;
   B.max_iters = max_iters;
   B.out = info ? reinterpret_cast<BatchOut*>(info) : bt->out_ws;
-  B.order = bt->order == GMRES_BATCH_ORDER_NATURAL ? bt->order_nat : bt->order_lpt;
   if (launch_batch_reset(B, bt->stream)) return GMRES_ERR_HIP;
-  if (launch_batch(B, bt->bs, effective_grid(bt, bt->bs), bt->scheme == GMRES_MGS_1R_IR32,
-                   bt->stream, e0, e1))
+  if (launch_batch(B, bt->bs, bt->grid_eff, bt->scheme == GMRES_MGS_1R_IR32, bt->stream, e0, e1))
     return GMRES_ERR_HIP;
   return GMRES_OK;
 }
@@ -182,25 +226,26 @@ int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, 
   Batch& B = bt->B;
   B.A = Csr{row_ptr, col_idx, vals, L.n, nnz};
   B.sys = (const BatchSys*)(base + L.o_sys);
+  B.tickets = (const BatchTicket*)(base + L.o_tk);
   B.nsys = nsys;
+  B.ntickets = 0;
   B.m = m;
   B.Vb = base + L.o_V;
   B.wb = base + L.o_w;
   B.r64 = scheme == GMRES_MGS_1R_IR32 ? (double*)(base + L.o_r64) : nullptr;
   B.small = (double*)(base + L.o_small);
   B.st = (DevState*)(base + L.o_st);
+  B.partials = (double*)(base + L.o_part);
+  B.bar = (unsigned*)(base + L.o_bar);
   B.queue = (unsigned*)(base + L.o_queue);
   B.out = (BatchOut*)(base + L.o_out);
   bt->nsys = nsys;
   bt->m = m;
   bt->scheme = scheme;
+  bt->slots = L.slots;
   bt->n = L.n;
-  bt->bs = 256;
-  bt->grid = 0;
-  bt->order = GMRES_BATCH_ORDER_LARGEST_FIRST;
   bt->num_cu = ncu;
-  bt->order_nat = (const int*)(base + L.o_nat);
-  bt->order_lpt = (const int*)(base + L.o_lpt);
+  bt->tickets_d = (BatchTicket*)(base + L.o_tk);
   bt->out_ws = (BatchOut*)(base + L.o_out);
   bt->xsave = (double*)(base + L.o_xsave);
   bt->stream = (hipStream_t)hip_stream;
@@ -209,23 +254,12 @@ int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, 
   bt->sizes.resize((size_t)nsys);
   for (int i = 0; i < nsys; ++i) bt->sizes[(size_t)i] = L.sys[(size_t)i].n;
 
-  // The two queue orders: as given, and by decreasing size (longest-processing-
-  // time first; the size stands in for the unknown iteration count), ties by index.
-  std::vector<int> nat((size_t)nsys), lpt((size_t)nsys);
-  std::iota(nat.begin(), nat.end(), 0);
-  lpt = nat;
-  std::stable_sort(lpt.begin(), lpt.end(),
-                   [&](int a, int b) { return L.sys[(size_t)a].n > L.sys[(size_t)b].n; });
   DevState st0;
   int rc = GMRES_OK;
   hipStream_t s = bt->stream;
   if (hipMemcpyAsync(base + L.o_sys, L.sys.data(), sizeof(BatchSys) * (size_t)nsys,
                      hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(base + L.o_nat, nat.data(), sizeof(int) * (size_t)nsys, hipMemcpyHostToDevice,
-                     s) != hipSuccess ||
-      hipMemcpyAsync(base + L.o_lpt, lpt.data(), sizeof(int) * (size_t)nsys, hipMemcpyHostToDevice,
-                     s) != hipSuccess ||
-      hipMemsetAsync(B.st, 0, sizeof(DevState) * (size_t)nsys, s) != hipSuccess ||
+      hipMemsetAsync(B.st, 0, sizeof(DevState), s) != hipSuccess ||
       launch_validate(B.A, nnz, B.st, s) ||
       hipMemcpyAsync(&st0, B.st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
@@ -239,6 +273,8 @@ int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, 
        hipStreamSynchronize(s) != hipSuccess))
     rc = GMRES_ERR_HIP;
   if (rc == GMRES_OK && st0.bad_csr) rc = GMRES_ERR_ARG;
+  if (rc == GMRES_OK)
+    rc = apply_config(bt, 256, 0, GMRES_BATCH_ORDER_LARGEST_FIRST, kDefaultPartRows);
   if (rc != GMRES_OK) {
     delete bt;
     return rc;
@@ -285,28 +321,36 @@ int gmres_batch_solve(gmres_batch* bt, const double* b, double* x, double rtol, 
   rc = gmres_batch_read_info(bt, h.data());
   if (rc) return rc;
   if (info) memcpy(info, h.data(), sizeof(gmres_batch_info) * h.size());
-  for (const auto& o : h)
-    if (o.status) return GMRES_ERR_NONFINITE;
-  return GMRES_OK;
+  int worst = GMRES_OK;
+  for (const auto& o : h) {
+    if (o.status == GMRES_ERR_HIP) return GMRES_ERR_HIP;
+    if (o.status) worst = GMRES_ERR_NONFINITE;
+  }
+  return worst;
 }
 
-int gmres_batch_set_config(gmres_batch* bt, int32_t block_size, int32_t grid, int32_t order) {
+int gmres_batch_set_config(gmres_batch* bt, int32_t block_size, int32_t grid, int32_t order,
+                           int64_t part_rows) {
   if (!bt) return GMRES_ERR_ARG;
   if (block_size != 256 && block_size != 512 && block_size != 1024) return GMRES_ERR_ARG;
-  if (grid < 0) return GMRES_ERR_ARG;
+  if (grid < 0 || part_rows < 0) return GMRES_ERR_ARG;
   if (order != GMRES_BATCH_ORDER_NATURAL && order != GMRES_BATCH_ORDER_LARGEST_FIRST)
     return GMRES_ERR_ARG;
-  bt->bs = block_size;
-  bt->grid = grid;
-  bt->order = order;
-  return GMRES_OK;
+  return apply_config(bt, block_size, grid, order, part_rows);
 }
 
-int gmres_batch_get_config(gmres_batch* bt, int32_t* block_size, int32_t* grid, int32_t* order) {
+int gmres_batch_get_config(gmres_batch* bt, int32_t* block_size, int32_t* grid, int32_t* order,
+                           int64_t* part_rows, int32_t* max_parts) {
   if (!bt) return GMRES_ERR_ARG;
   if (block_size) *block_size = bt->bs;
-  if (grid) *grid = effective_grid(bt, bt->bs);
+  if (grid) *grid = bt->grid_eff;
   if (order) *order = bt->order;
+  if (part_rows) *part_rows = bt->part_rows;
+  if (max_parts) {
+    int mp = 1;
+    for (const auto& t : bt->tickets) mp = std::max(mp, t.nparts);
+    *max_parts = mp;
+  }
   return GMRES_OK;
 }
 
@@ -321,55 +365,55 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
   hipStream_t s = bt->stream;
   struct Cand {
     int bs, grid, order;
+    int64_t part_rows;
   };
-  std::vector<Cand> cands;
-  for (int bs : {256, 512, 1024}) {
-    const int per_cu = batch_resident_blocks(bs, bt->m, bt->scheme == GMRES_MGS_1R_IR32);
-    if (per_cu < 1) continue;
-    std::vector<int> grids = {std::min(bt->nsys, per_cu * bt->num_cu), std::min(bt->nsys, bt->num_cu)};
-    if (grids[1] == grids[0]) grids.pop_back();
-    for (int g : grids)
-      for (int order : {GMRES_BATCH_ORDER_LARGEST_FIRST, GMRES_BATCH_ORDER_NATURAL})
-        cands.push_back({bs, g, order});
-  }
-  if (cands.empty()) return GMRES_ERR_HIP;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return GMRES_ERR_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return GMRES_ERR_HIP;
   }
-  const int save_bs = bt->bs, save_grid = bt->grid, save_order = bt->order;
+  const Cand saved{bt->bs, bt->grid, bt->order, bt->part_rows};
   int rc = hipMemcpyAsync(bt->xsave, x, xb, hipMemcpyDeviceToDevice, s) == hipSuccess
                ? GMRES_OK
                : GMRES_ERR_HIP;
-  float best = -1.0f;
-  Cand pick = cands[0];
   int nt = 0;
-  // one warm-up solve (code objects loaded, caches in a steady state), then each candidate once
-  for (int t = -1; rc == GMRES_OK && t < (int)cands.size(); ++t) {
-    const Cand c = cands[(size_t)(t < 0 ? 0 : t)];
-    bt->bs = c.bs;
-    bt->grid = c.grid;
-    bt->order = c.order;
+  float best = -1.0f;
+  Cand pick = saved;
+  // One solve under configuration c from the saved x; its event-timed duration.
+  auto trial = [&](const Cand& c, bool record) -> int {
+    int r = apply_config(bt, c.bs, c.grid, c.order, c.part_rows);
+    if (r) return r;
     if (hipMemcpyAsync(x, bt->xsave, xb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipEventRecord(e0, s) != hipSuccess) {
-      rc = GMRES_ERR_HIP;
-      break;
-    }
-    rc = enqueue(bt, b, x, rtol, max_iters, nullptr, nullptr, nullptr);
+        hipEventRecord(e0, s) != hipSuccess)
+      return GMRES_ERR_HIP;
+    r = enqueue(bt, b, x, rtol, max_iters, nullptr, nullptr, nullptr);
+    if (r) return r;
     float ms = 0.0f;
-    if (rc == GMRES_OK &&
-        (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-      rc = GMRES_ERR_HIP;
-    if (rc != GMRES_OK || t < 0) continue;
-    if (nt < max_trials) trials[nt] = gmres_batch_trial{c.bs, c.grid, c.order, ms};
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return GMRES_ERR_HIP;
+    if (!record) return GMRES_OK;
+    if (nt < max_trials)
+      trials[nt] = gmres_batch_trial{c.bs, bt->grid_eff, c.order, ms, c.part_rows};
     ++nt;
     if (best < 0.0f || ms < best) {
       best = ms;
       pick = c;
     }
+    return GMRES_OK;
+  };
+  // first the workgroup size and the team split (largest systems first, as
+  // many workgroups as the GPU holds), then the grid and the order for the best
+  const Cand first{256, 0, GMRES_BATCH_ORDER_LARGEST_FIRST, kDefaultPartRows};
+  if (rc == GMRES_OK) rc = trial(first, false);  // warm-up
+  for (int bs : {256, 512, 1024})
+    for (int64_t pr : {(int64_t)0, (int64_t)16384, (int64_t)8192, (int64_t)4096})
+      if (rc == GMRES_OK) rc = trial(Cand{bs, 0, GMRES_BATCH_ORDER_LARGEST_FIRST, pr}, true);
+  if (rc == GMRES_OK) {
+    const Cand top = pick;
+    rc = trial(Cand{top.bs, std::min(bt->num_cu, bt->B.ntickets), top.order, top.part_rows}, true);
+    if (rc == GMRES_OK) rc = trial(Cand{top.bs, 0, GMRES_BATCH_ORDER_NATURAL, top.part_rows}, true);
   }
   if (rc == GMRES_OK &&
       (hipMemcpyAsync(x, bt->xsave, xb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -377,15 +421,10 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
     rc = GMRES_ERR_HIP;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (rc != GMRES_OK) {
-    bt->bs = save_bs;
-    bt->grid = save_grid;
-    bt->order = save_order;
-    return rc;
-  }
-  bt->bs = pick.bs;
-  bt->grid = pick.grid;
-  bt->order = pick.order;
+  const Cand keep = rc == GMRES_OK ? pick : saved;
+  const int rc2 = apply_config(bt, keep.bs, keep.grid, keep.order, keep.part_rows);
+  if (rc != GMRES_OK) return rc;
+  if (rc2 != GMRES_OK) return rc2;
   if (ntrials) *ntrials = std::min(nt, max_trials);
   return GMRES_OK;
 }
@@ -396,18 +435,13 @@ int gmres_batch_capture(gmres_batch* bt, const double* b, double* x, double rtol
     return GMRES_ERR_ARG;
   if (!bt->stream) return GMRES_ERR_ARG;  // the legacy default stream cannot be captured
   drop_graph(bt);
-  // the occupancy query behind the default grid is made before capture starts
-  const int grid = effective_grid(bt, bt->bs);
-  const int save_grid = bt->grid;
-  bt->grid = grid;
-  if (hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-    bt->grid = save_grid;
+  // the queue and the grid were set up by the last configuration call; the
+  // capture records only the reset kernel and the persistent launch
+  if (hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return GMRES_ERR_HIP;
-  }
   const int rc = enqueue(bt, b, x, rtol, max_iters, nullptr, nullptr, nullptr);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(bt->stream, &g);
-  bt->grid = save_grid;
   if (rc != GMRES_OK || ec != hipSuccess || !g) {
     if (g) (void)hipGraphDestroy(g);
     (void)hipGetLastError();

@@ -1881,13 +1881,25 @@ int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, bool f32, hipStrea
 // ---------------------------------------------------- batched persistent solver
 //
 // A batch is a block-diagonal matrix: system i owns rows [r0, r0 + n) and its
-// columns lie in the same range. One persistent kernel solves all of them:
-// each workgroup takes the next system from a device-side queue (in the given
-// order; largest first by default) and runs that system's whole restarted
-// one-reduce GMRES on its own, with workgroup-level reductions where the
-// single-system path has its device-wide one. No workgroup ever waits for
-// another, so the launch needs no co-residency and ends when the queue is
-// empty.
+// columns lie in the same range. One persistent kernel solves all of them.
+// Its workgroups take entries from a device-side queue; an entry is a system,
+// or one of the row parts of a larger system. A workgroup runs its entry's
+// whole restarted one-reduce GMRES: where the single-system path has one
+// device-wide reduction per step, a one-part system reduces within its
+// workgroup, and a system of several parts (a team) adds its parts' sums
+// through global memory with a team barrier. Every part then runs the small
+// dense step itself on identical totals (so all parts take the same
+// decisions, with no broadcast), and updates its own rows. Rows that other
+// parts read (the SpMV's gathers across a part boundary, of the newest basis
+// column and of x) are stored and gathered with device-coherent accesses;
+// two team barriers per step order them.
+//
+// Queue order and team assembly: a system's parts are consecutive queue
+// entries, and entries are taken in queue order, so at any time only the
+// system whose parts were taken last can be waiting for a partner, and every
+// earlier team is complete and finishes, freeing workgroups for the missing
+// parts. The host keeps every team within what the GPU holds at once, so a
+// team always assembles.
 
 // Block-diagonal check: every column index of system i's rows lies in
 // [r0, r0 + n). One thread per row; the system is found by bisection.
@@ -1910,7 +1922,8 @@ __global__ __launch_bounds__(256) void k_batch_validate(Csr A, const BatchSys* _
   }
 }
 
-// Start of a batched solve: the queue position and every system's result.
+// Start of a batched solve: the queue position, the team barriers and every
+// system's result.
 __global__ void k_batch_reset(Batch B) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) *B.queue = 0u;
@@ -1920,52 +1933,183 @@ __global__ void k_batch_reset(Batch B) {
     o.cycles = o.converged = o.status = o.breakdown = 0;
     o.rel_res_true = 0.0;
     B.out[i] = o;
+    B.bar[i] = 0u;
   }
 }
 
-// Sum of v over the workgroup, returned to every thread (red: NW doubles).
+// Device-coherent (agent-scope) loads and stores of basis and solution
+// entries that another workgroup of the team reads or wrote.
+template <typename T>
+__device__ inline T coh_ld(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ inline void coh_st(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One workgroup's view of its queue entry.
+struct Team {
+  unsigned* bar;     // the system's barrier counter
+  double* rows;      // partial rows: slot base + p, 2 buffers of P doubles each
+  unsigned target;   // barrier count this part waits for next
+  int nparts, part, P, buf;
+  bool failed;       // a wait ran out: the solve of this entry is abandoned
+  int64_t lo, hi;    // own rows (local indices)
+};
+
+// All parts of the team have arrived: every store made before it by any
+// part (completed, agent-scope where another part reads it) is visible.
+// The wait is bounded (short sleeps first, then long ones, at least about
+// half a minute in all): a team that cannot assemble ends its solve with a
+// failure instead of holding the GPU. Returns false (and sets failed, the
+// same in every thread) when the wait ran out or failed was already set.
+__device__ inline bool team_sync(Team& tm) {
+  __shared__ int s_ok;
+  if (tm.nparts == 1) {
+    __syncthreads();
+    return true;
+  }
+  if (tm.failed) return false;
+  wait_stores();
+  __syncthreads();
+  tm.target += (unsigned)tm.nparts;
+  if (threadIdx.x == 0) {
+    atomicAdd(tm.bar, 1u);
+    int ok = 1;
+    for (uint32_t spin = 0;; ++spin) {
+      if (__hip_atomic_load(tm.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= tm.target) break;
+      if (spin < 4096) {
+        __builtin_amdgcn_s_sleep(1);
+      } else if (spin < (1u << 23)) {
+        __builtin_amdgcn_s_sleep(127);
+      } else {
+        ok = 0;
+        break;
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  const bool ok = s_ok != 0;
+  __syncthreads();
+  if (!ok) tm.failed = true;
+  return ok;
+}
+
+// vals[0:cnt] = the team's totals of loc[0:cnt] (LDS), added over the parts
+// in part order (loc is returned unchanged for a one-part team). The two
+// buffers alternate, so a buffer is rewritten only after a later barrier
+// that every part passes after reading it.
+__device__ inline void team_reduce(Team& tm, const double* loc, double* vals, int cnt) {
+  const int tid = threadIdx.x, bs = blockDim.x;
+  if (tm.nparts == 1) {
+    for (int c = tid; c < cnt; c += bs) vals[c] = loc[c];
+    __syncthreads();
+    return;
+  }
+  double* mine = tm.rows + ((size_t)tm.part * 2 + tm.buf) * tm.P;
+  for (int c = tid; c < cnt; c += bs) atomic_st(mine + c, loc[c]);
+  if (!team_sync(tm)) {
+    for (int c = tid; c < cnt; c += bs) vals[c] = 0.0;
+    __syncthreads();
+    return;
+  }
+  for (int c = tid; c < cnt; c += bs) {
+    double a = 0.0;
+    for (int q = 0; q < tm.nparts; ++q) a += atomic_ld(tm.rows + ((size_t)q * 2 + tm.buf) * tm.P + c);
+    vals[c] = a;
+  }
+  tm.buf ^= 1;
+  __syncthreads();
+}
+
+// The team total of one value per thread (loc: NW + 1 doubles of LDS).
 template <int BS>
-__device__ inline double block_sum(double v, double* red) {
-  __shared__ double s_tot;
+__device__ inline double team_sum(Team& tm, double v, double* loc) {
   v = wave_sum_last(v);
-  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 63) == 63) loc[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0.0;
-    for (int w = 0; w < BS / 64; ++w) a += red[w];
-    s_tot = a;
+    for (int w = 0; w < BS / 64; ++w) a += loc[w];
+    loc[BS / 64] = a;
   }
   __syncthreads();
-  const double t = s_tot;
+  double* tot = loc + BS / 64 + 1;
+  team_reduce(tm, loc + BS / 64, tot, 1);
+  const double t = tot[0];
   __syncthreads();
   return t;
 }
 
-// Row r (local) of A x for one system: the CSR row sum with x indexed locally.
+// Row r (local) of A x for one system, x indexed locally. With COH, entries
+// outside [lo, hi) (another part's rows) are gathered with coherent loads.
 template <typename XT>
-__device__ inline double batch_row(const Csr& A, int64_t r0, int64_t r, const XT* __restrict__ x) {
+__device__ inline double batch_row(const Csr& A, int64_t r0, int64_t r, const XT* __restrict__ x,
+                                   bool COH, int64_t lo, int64_t hi) {
   double a = 0.0;
   const int e1 = A.rp[r0 + r + 1];
-  for (int e = A.rp[r0 + r]; e < e1; ++e) a += A.va[e] * (double)x[A.ci[e] - r0];
+  for (int e = A.rp[r0 + r]; e < e1; ++e) {
+    const int64_t c = A.ci[e] - r0;
+    XT v;
+    if (COH && (c < lo || c >= hi))
+      v = coh_ld(x + c);
+    else
+      v = x[c];
+    a += A.va[e] * (double)v;
+  }
   return a;
 }
 
-// The whole solve of system i by one workgroup of BS threads.
+template <typename T>
+__device__ inline void put(bool coh, T* p, T v) {
+  if (coh)
+    coh_st(p, v);
+  else
+    *p = v;
+}
+
+// The solve of one queue entry (a system, or one part of a team) by one
+// workgroup of BS threads. Team and ticket values are uniform.
 template <int BS, typename VT>
-__device__ void batch_system(const Batch& B, int i, double* red, double* vals, double* scr) {
+__device__ void batch_part(const Batch& B, const BatchTicket K, double* red, double* vals,
+                           double* scr) {
   constexpr int NW = BS / 64;
-  constexpr int RB = 8;  // rows per thread per row block
+  // rows per thread per row block (fewer for 1024 threads, whose 128
+  // registers per lane the deeper unrolling would overflow)
+  constexpr int RB = BS >= 1024 ? 4 : 8;
   constexpr bool F32 = sizeof(VT) == 4;
   __shared__ int s_flag[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m = B.m;
   const int P = 2 * (m + 2);
-  // i is uniform, so the system's sizes and pointers stay in scalar registers
-  const BatchSys S = B.sys[i];
+  const BatchSys S = B.sys[K.sys];
   const int64_t n = S.n, r0 = S.r0;
+  const int slot = K.base + K.part;
+  Team tm;
+  tm.bar = B.bar + K.sys;
+  tm.rows = B.partials + (size_t)K.base * 2 * P;
+  tm.target = 0;
+  tm.nparts = K.nparts;
+  tm.part = K.part;
+  tm.P = P;
+  tm.buf = 0;
+  tm.failed = false;
+  {
+    const int64_t per = (n + K.nparts - 1) / K.nparts;
+    const int64_t chunk = (per + 63) / 64 * 64;
+    tm.lo = chunk * K.part < n ? chunk * K.part : n;
+    tm.hi = tm.lo + chunk < n ? tm.lo + chunk : n;
+  }
+  const int64_t lo = tm.lo, hi = tm.hi;
+  // coherent gathers across part boundaries and coherent stores of what
+  // other parts gather: only in a real team
+  const bool coh = K.nparts > 1;
+  const bool cst = coh;
   Ws ws{};
   {
-    double* sm = B.small + S.soff;
+    double* sm = B.small + (size_t)slot * batch_small_doubles(m);
     if constexpr (F32) {
       ws.Vf = (float*)B.Vb + S.voff;
       ws.wf = (float*)B.wb + r0;
@@ -1985,7 +2129,7 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
     ws.coef = ws.sn + (m + 2);
     ws.coef2 = ws.coef + (m + 2);
     ws.y = ws.coef2 + (m + 2);
-    ws.st = B.st + i;
+    ws.st = B.st + slot;
     ws.n = n;
     ws.ldv = S.ldv;
     ws.ldh = m + 1;
@@ -1998,12 +2142,14 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
   const int64_t ldv = ws.ldv;
   const double* __restrict__ b = B.b + r0;
   double* __restrict__ x = B.x + r0;
-  const int64_t nblk = (n + (int64_t)BS * RB - 1) / ((int64_t)BS * RB);
+  const int64_t nrow = hi - lo;
+  const int64_t nblk = (nrow + (int64_t)BS * RB - 1) / ((int64_t)BS * RB);
+  double* loc = vals + P;  // team_sum's LDS (NW + 2 doubles after vals)
 
   // ||b|| and the tolerance
   double sb = 0.0;
-  for (int64_t r = tid; r < n; r += BS) sb += b[r] * b[r];
-  const double bnorm = sqrt(block_sum<BS>(sb, red));
+  for (int64_t r = lo + tid; r < hi; r += BS) sb += b[r] * b[r];
+  const double bnorm = sqrt(team_sum<BS>(tm, sb, loc));
   if (tid == 0) {
     st->done = st->j = st->true_conv = st->breakdown = st->status = 0;
     st->reductions = 1;
@@ -2017,25 +2163,30 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
   out.iters = 0;
   out.cycles = out.converged = out.status = out.breakdown = 0;
   out.rel_res_true = 0.0;
-  if (!isfinite(bnorm)) {
+  if (tm.failed) {
+    out.status = kTeamStall;
+  } else if (!isfinite(bnorm)) {
     out.status = kNonfinite;
   } else if (bnorm == 0.0) {
-    for (int64_t r = tid; r < n; r += BS) x[r] = 0.0;
+    for (int64_t r = lo + tid; r < hi; r += BS) x[r] = 0.0;
     out.converged = 1;
   } else {
     const double tol_abs = B.rtol * bnorm;
     int64_t it = 0;
     for (;;) {
+      // x of the previous cycle is complete on every part before it is gathered
+      if (!team_sync(tm)) break;
       const int64_t left = B.max_iters - it;
       const int m_eff = left < (int64_t)m ? (int)left : m;
       if (m_eff == 0) {
         // the iteration budget is spent: the true residual of the final x
         double sr = 0.0;
-        for (int64_t r = tid; r < n; r += BS) {
-          const double d = b[r] - batch_row(B.A, r0, r, x);
+        for (int64_t r = lo + tid; r < hi; r += BS) {
+          const double d = b[r] - batch_row(B.A, r0, r, x, coh, lo, hi);
           sr += d * d;
         }
-        const double rn = sqrt(block_sum<BS>(sr, red));
+        const double rn = sqrt(team_sum<BS>(tm, sr, loc));
+        if (tm.failed) break;
         out.rel_res_true = rn / bnorm;
         out.converged = rn <= tol_abs;
         if (!isfinite(rn)) out.status = kNonfinite;
@@ -2056,12 +2207,13 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
       double beta_cycle = 0.0;
       if constexpr (F32) {
         double sr = 0.0;
-        for (int64_t r = tid; r < n; r += BS) {
-          const double d = b[r] - batch_row(B.A, r0, r, x);
+        for (int64_t r = lo + tid; r < hi; r += BS) {
+          const double d = b[r] - batch_row(B.A, r0, r, x, coh, lo, hi);
           ws.r64[r] = d;
           sr += d * d;
         }
-        const double beta = sqrt(block_sum<BS>(sr, red));
+        const double beta = sqrt(team_sum<BS>(tm, sr, loc));
+        if (tm.failed) break;
         if (!isfinite(beta)) {
           out.status = kNonfinite;
           break;
@@ -2072,7 +2224,7 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
           break;
         }
         const double inv = 1.0 / beta;
-        for (int64_t r = tid; r < n; r += BS) V[r] = (VT)(ws.r64[r] * inv);
+        for (int64_t r = lo + tid; r < hi; r += BS) put(cst, V + r, (VT)(ws.r64[r] * inv));
         // the float64 check above is the restart test: the normalized float32
         // start vector is not tested again (tol_cycle 0 for step 0)
         if (tid == 0) {
@@ -2082,10 +2234,12 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
         }
         beta_cycle = beta;
       } else {
-        for (int64_t r = tid; r < n; r += BS) V[r] = (VT)(b[r] - batch_row(B.A, r0, r, x));
+        for (int64_t r = lo + tid; r < hi; r += BS)
+          put(cst, V + r, (VT)(b[r] - batch_row(B.A, r0, r, x, coh, lo, hi)));
       }
-      __syncthreads();
       for (int k = 0; k <= m_eff; ++k) {
+        // column k is complete on every part before the SpMV gathers it
+        if (!team_sync(tm)) break;
         const bool last = k == m_eff;
         const int nproj = last ? 0 : k;
         const int cnt = 2 * (nproj + 1);
@@ -2097,13 +2251,13 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
           uint32_t off[RB];
 #pragma unroll
           for (int t = 0; t < RB; ++t) {
-            const int64_t r = blk * BS * RB + (int64_t)t * BS + tid;
-            const bool ok = r < n;
-            const int64_t rc = ok ? r : n - 1;
+            const int64_t r = lo + blk * BS * RB + (int64_t)t * BS + tid;
+            const bool ok = r < hi;
+            const int64_t rc = ok ? r : hi - 1;
             off[t] = (uint32_t)rc * (uint32_t)sizeof(VT);
             u[t] = ok ? u_g[rc] : (VT)0;
             if (!last) {
-              const double a = ok ? batch_row(B.A, r0, rc, u_g) : 0.0;
+              const double a = ok ? batch_row(B.A, r0, rc, u_g, coh, lo, hi) : 0.0;
               w[t] = (VT)a;
               if (ok) wv_[r] = w[t];
             } else {
@@ -2157,13 +2311,17 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
           }
         }
         __syncthreads();
+        // the workgroup's sums (in scr), then the team's totals in vals
         for (int c = tid; c < cnt; c += BS) {
           double a = 0.0;
           for (int w2 = 0; w2 < NW; ++w2) a += red[w2 * P + c];
-          vals[c] = a;
+          scr[c] = a;
         }
         __syncthreads();
-        // the small dense step (H column, T column, Givens, flags, MAXPY coefficients)
+        team_reduce(tm, scr, vals, cnt);
+        if (tm.failed) break;
+        // the small dense step (H column, T column, Givens, flags, MAXPY
+        // coefficients), run by every part on the same totals
         TailPrefetch<1> pf;
         pf.ws = &ws;
         pf.tri = nullptr;
@@ -2195,8 +2353,8 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
           uint32_t off[RB];
 #pragma unroll
           for (int t = 0; t < RB; ++t) {
-            const int64_t r = blk * BS * RB + (int64_t)t * BS + tid;
-            const int64_t rc = r < n ? r : n - 1;
+            const int64_t r = lo + blk * BS * RB + (int64_t)t * BS + tid;
+            const int64_t rc = r < hi ? r : hi - 1;
             off[t] = (uint32_t)rc * (uint32_t)sizeof(VT);
             acc[t] = wv_[rc] * invr;
             vk[t] = V[(size_t)k * ldv + rc] * invr;
@@ -2227,15 +2385,15 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
           const VT ck = (VT)cl[k];
 #pragma unroll
           for (int t = 0; t < RB; ++t) {
-            const int64_t r = blk * BS * RB + (int64_t)t * BS + tid;
-            if (r < n) {
+            const int64_t r = lo + blk * BS * RB + (int64_t)t * BS + tid;
+            if (r < hi) {
               V[(size_t)k * ldv + r] = vk[t];
-              V[(size_t)(k + 1) * ldv + r] = acc[t] - vk[t] * ck;
+              put(cst, V + (size_t)(k + 1) * ldv + r, acc[t] - vk[t] * ck);
             }
           }
         }
-        __syncthreads();
       }
+      if (tm.failed) break;
       if (tid == 0) {
         s_flag[1] = st->j;
         s_flag[2] = st->status;
@@ -2254,7 +2412,7 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
         break;
       }
       if (s_flag[3] & 2) out.breakdown = 1;
-      // back substitution R y = g, then x += xscale V y
+      // back substitution R y = g, then x += xscale V y on the own rows
       double* yl = scr;
       if (tid == 0) {
         const double xs = st->xscale;
@@ -2268,10 +2426,10 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
         }
       }
       __syncthreads();
-      for (int64_t r = tid; r < n; r += BS) {
+      for (int64_t r = lo + tid; r < hi; r += BS) {
         double a = x[r];
         for (int q = 0; q < j; ++q) a += (double)V[(size_t)q * ldv + r] * yl[q];
-        x[r] = a;
+        put(cst, x + r, a);
       }
       __syncthreads();
       it += j;
@@ -2279,10 +2437,11 @@ __device__ void batch_system(const Batch& B, int i, double* red, double* vals, d
       if (j == 0) break;
     }
     out.iters = it;
+    if (tm.failed) out.status = kTeamStall;
   }
-  if (tid == 0) {
+  if (tid == 0 && K.part == 0) {
     if (out.status == 0 && st->status) out.status = st->status;
-    B.out[i] = out;
+    B.out[K.sys] = out;
   }
   __syncthreads();
 }
@@ -2293,22 +2452,27 @@ __global__ __launch_bounds__(BS) void k_batch(Batch B) {
   __shared__ int s_pos;
   constexpr int NW = BS / 64;
   const int P = 2 * (B.m + 2);
-  double* red = lds;              // NW x P per-wavefront sums (also block_sum's scratch)
-  double* vals = red + NW * P;    // P totals
-  double* scr = vals + P;         // 6 (m + 2) for the small dense step
+  double* red = lds;              // NW x P per-wavefront sums
+  double* vals = red + NW * P;    // P totals, then team_sum's NW + 2
+  double* scr = vals + P + NW + 2; // 6 (m + 2) for the small dense step
   for (;;) {
     if (threadIdx.x == 0) s_pos = (int)atomicAdd(B.queue, 1u);
     __syncthreads();
     const int pos = __builtin_amdgcn_readfirstlane(s_pos);
     __syncthreads();
-    if (pos >= B.nsys) break;
-    batch_system<BS, VT>(B, __builtin_amdgcn_readfirstlane(B.order[pos]), red, vals, scr);
+    if (pos >= B.ntickets) break;
+    BatchTicket K = B.tickets[pos];
+    K.sys = __builtin_amdgcn_readfirstlane(K.sys);
+    K.part = __builtin_amdgcn_readfirstlane(K.part);
+    K.nparts = __builtin_amdgcn_readfirstlane(K.nparts);
+    K.base = __builtin_amdgcn_readfirstlane(K.base);
+    batch_part<BS, VT>(B, K, red, vals, scr);
   }
 }
 
 size_t batch_lds_bytes(int bs, int m) {
   const size_t P = 2 * (size_t)(m + 2);
-  return ((size_t)(bs / 64) * P + P + 6 * (size_t)(m + 2)) * sizeof(double);
+  return ((size_t)(bs / 64) * P + P + (size_t)(bs / 64) + 2 + 6 * (size_t)(m + 2)) * sizeof(double);
 }
 
 int launch_batch_validate(const Csr& A, const BatchSys* sys, int nsys, DevState* st, hipStream_t s) {

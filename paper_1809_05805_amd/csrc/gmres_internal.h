@@ -17,6 +17,7 @@ constexpr int kSchemeCgs2 = 2;
 constexpr int kSchemeIr32 = 3;  // one-reduce MGS cycles on an FP32 basis, FP64 refinement
 
 constexpr int kNonfinite = -3;
+constexpr int kTeamStall = -2;  // a team's parts did not all arrive (GMRES_ERR_HIP)
 
 // Tail selectors: what the last workgroup of a reduction does with the totals.
 enum Tail {
@@ -94,10 +95,20 @@ struct Ws {
 };
 
 // One system of a batch: rows [r0, r0 + n) of the block-diagonal matrix and
-// of the concatenated vectors; its basis at voff (leading dimension ldv) in
-// the batch's basis array and its small workspace at soff (doubles).
+// of the concatenated vectors, and its basis at voff (leading dimension ldv)
+// in the batch's basis array.
 struct BatchSys {
-  int64_t r0, n, voff, ldv, soff;
+  int64_t r0, n, voff, ldv;
+};
+
+// One entry of the work queue: part `part` of `nparts` of system `sys`. A
+// system's parts are consecutive in the queue; part p owns its rows
+// [p c, min(n, (p+1) c)) with c = the part size rounded up to 64 rows. Each
+// entry has its own slot (its queue position) for the small workspace, the
+// state record and two rows of reduction partials; `base` is the slot of
+// part 0.
+struct BatchTicket {
+  int32_t sys, part, nparts, base;
 };
 
 // Per-system result of a batched solve (the layout of gmres_batch_info).
@@ -109,17 +120,19 @@ struct BatchOut {
 
 // Everything the persistent batched kernel needs.
 struct Batch {
-  Csr A;                 // block-diagonal CSR over all systems (global column indices)
-  const BatchSys* sys;   // nsys records
-  const int* order;      // order in which the systems are taken from the queue
-  int nsys, m;
-  void* Vb;              // bases (float64, or float32 for the FP32-basis scheme)
-  void* wb;              // SpMV outputs, by global row (same type)
-  double* r64;           // float64 restart residuals by global row (FP32-basis only)
-  double* small;         // small workspaces, batch_small_doubles(m) each
-  DevState* st;          // nsys states
-  unsigned* queue;       // next queue position
-  BatchOut* out;         // nsys results
+  Csr A;                     // block-diagonal CSR over all systems (global column indices)
+  const BatchSys* sys;       // nsys records
+  const BatchTicket* tickets;// ntickets queue entries
+  int nsys, ntickets, m;
+  void* Vb;                  // bases (float64, or float32 for the FP32-basis scheme)
+  void* wb;                  // SpMV outputs, by global row (same type)
+  double* r64;               // float64 restart residuals by global row (FP32-basis only)
+  double* small;             // small workspaces, batch_small_doubles(m) per slot
+  DevState* st;              // one state per slot
+  double* partials;          // 2 rows of 2 (m + 2) doubles per slot
+  unsigned* bar;             // nsys team barrier counters
+  unsigned* queue;           // next queue position
+  BatchOut* out;             // nsys results
   const double* b;
   double* x;
   double rtol;
@@ -135,11 +148,13 @@ constexpr size_t batch_small_doubles(int m) {
 // Sets st->bad_csr when a row of system i has a column outside its rows (the
 // CSR arrays must already have passed launch_validate).
 int launch_batch_validate(const Csr& A, const BatchSys* sys, int nsys, DevState* st, hipStream_t s);
-// Clears the queue position and every system's result (a kernel, so a
-// captured graph holds no memset node).
+// Clears the queue position, the team barrier counters and every system's
+// result (a kernel, so a captured graph holds no memset node).
 int launch_batch_reset(const Batch& B, hipStream_t s);
 // The persistent solve: grid workgroups of bs threads (256, 512 or 1024)
-// take systems from the queue until it is empty. f32: float32 basis.
+// take queue entries until the queue is empty. f32: float32 basis. A system
+// split into several parts needs all of them running at once: the caller
+// keeps every nparts within what the GPU holds concurrently.
 int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
 // Workgroups of k_batch that one compute unit holds at once (0 on error).

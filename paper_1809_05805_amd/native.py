@@ -58,7 +58,7 @@ class GmresBatchInfo(ctypes.Structure):
 
 class GmresBatchTrial(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("ms", ctypes.c_float)]
+                ("order", ctypes.c_int32), ("ms", ctypes.c_float), ("part_rows", ctypes.c_int64)]
 
 
 _lib = None
@@ -110,8 +110,9 @@ def load() -> ctypes.CDLL:
                        ("gmres_batch_solve_async", [P, P, P, D, I64, P]),
                        ("gmres_batch_solve", [P, P, P, D, I64, P]),
                        ("gmres_batch_read_info", [P, P]),
-                       ("gmres_batch_set_config", [P, I32, I32, I32]),
+                       ("gmres_batch_set_config", [P, I32, I32, I32, I64]),
                        ("gmres_batch_get_config", [P, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                                   ctypes.POINTER(I32), ctypes.POINTER(I64),
                                                    ctypes.POINTER(I32)]),
                        ("gmres_batch_autotune", [P, P, P, D, I64, P, I32, ctypes.POINTER(I32)]),
                        ("gmres_batch_capture", [P, P, P, D, I64]),
@@ -243,14 +244,16 @@ def gmres_batch_read_info(ctx, nsys: int):
     return rc, info
 
 
-def gmres_batch_set_config(ctx, block_size: int, grid: int, order: int) -> int:
-    return load().gmres_batch_set_config(ctx, block_size, grid, order)
+def gmres_batch_set_config(ctx, block_size: int, grid: int, order: int, part_rows: int) -> int:
+    return load().gmres_batch_set_config(ctx, block_size, grid, order, part_rows)
 
 
 def gmres_batch_get_config(ctx):
-    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    rc = load().gmres_batch_get_config(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
-    return rc, a.value, b.value, c.value
+    a, b, c, mp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    pr = ctypes.c_int64()
+    rc = load().gmres_batch_get_config(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                       ctypes.byref(pr), ctypes.byref(mp))
+    return rc, a.value, b.value, c.value, pr.value, mp.value
 
 
 def gmres_batch_autotune(ctx, b_ptr, x_ptr, rtol, max_iters, max_trials: int = 32):
@@ -258,7 +261,7 @@ def gmres_batch_autotune(ctx, b_ptr, x_ptr, rtol, max_iters, max_trials: int = 3
     nt = ctypes.c_int32()
     rc = load().gmres_batch_autotune(ctx, b_ptr, x_ptr, float(rtol), int(max_iters), trials,
                                      max_trials, ctypes.byref(nt))
-    return rc, [(t.block_size, t.grid, t.order, t.ms) for t in trials[: nt.value]]
+    return rc, [(t.block_size, t.grid, t.order, t.ms, t.part_rows) for t in trials[: nt.value]]
 
 
 def gmres_batch_capture(ctx, b_ptr, x_ptr, rtol, max_iters) -> int:
@@ -491,16 +494,17 @@ class BatchSolver:
             raise GmresError(rc, "gmres_batch_read_info")
         return batch_info_arrays(info)
 
-    def set_config(self, block_size: int = 256, grid: int = 0, order: int = GMRES_BATCH_ORDER_LARGEST_FIRST):
-        rc = gmres_batch_set_config(self.ctx, block_size, grid, order)
+    def set_config(self, block_size: int = 256, grid: int = 0,
+                   order: int = GMRES_BATCH_ORDER_LARGEST_FIRST, part_rows: int = 8192):
+        rc = gmres_batch_set_config(self.ctx, block_size, grid, order, part_rows)
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_batch_set_config")
 
     def config(self):
-        rc, bs, grid, order = gmres_batch_get_config(self.ctx)
+        rc, bs, grid, order, pr, mp = gmres_batch_get_config(self.ctx)
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_batch_get_config")
-        return {"block_size": bs, "grid": grid, "order": order}
+        return {"block_size": bs, "grid": grid, "order": order, "part_rows": pr, "max_parts": mp}
 
     def autotune(self, b, x, rtol: float, max_iters: int):
         self._check(b, x)

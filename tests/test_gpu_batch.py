@@ -7,8 +7,10 @@ fixed budget (no early exit) the iterate within 1e-10 relative; to tolerance,
 equal iteration counts up to one and both truly converged. The float32-basis
 batch is held to the float64 stopping test and its iterate compared with the
 float64 oracle within 10 kappa_est rtol (as for the single-system float32
-scheme). Results must not depend on the grid or the queue order, and a
-captured graph must reproduce the eager solve bit for bit on every replay.
+scheme). Systems split over a team of workgroups (parts of 256 rows here, so
+that the small systems form teams of up to 6) are held to the same bounds.
+Results must not depend on the grid or the queue order, and a captured graph
+must reproduce the eager solve bit for bit on every replay.
 """
 
 import numpy as np
@@ -74,12 +76,14 @@ def true_rel(bp, i, x):
     return float(np.linalg.norm(p.b - p.scipy() @ x[bp.row_off[i]: bp.row_off[i + 1]]) / nb)
 
 
-@pytest.mark.parametrize("bs", [256, 512, 1024])
-def test_fixed_budget_parity(bs):
+@pytest.mark.parametrize("bs,part_rows", [(256, 0), (512, 0), (1024, 0), (256, 256), (1024, 256)])
+def test_fixed_budget_parity(bs, part_rows):
     """45 Arnoldi steps per system (one full cycle and half of the next), rtol 0."""
     bp = SMALL
-    log(f"batch fixed budget bs={bs}")
-    rc, info, x, _ = run(bp, rtol=0.0, max_iters=45, config=(bs, 0, 1))
+    log(f"batch fixed budget bs={bs} part_rows={part_rows}")
+    rc, info, x, s = run(bp, rtol=0.0, max_iters=45, config=(bs, 0, 1, part_rows))
+    if part_rows:
+        assert s.config()["max_parts"] == 6
     assert rc == 0
     worst = 0.0
     for i in range(bp.nsys):
@@ -96,10 +100,11 @@ def test_fixed_budget_parity(bs):
     log(f"  worst |x - x_oracle| / |x_oracle| = {worst:.2e}")
 
 
-def test_to_tolerance_parity():
+@pytest.mark.parametrize("part_rows", [0, 256])
+def test_to_tolerance_parity(part_rows):
     bp = SMALL
-    log("batch to tolerance fp64")
-    rc, info, x, _ = run(bp)
+    log(f"batch to tolerance fp64 part_rows={part_rows}")
+    rc, info, x, _ = run(bp, config=(256, 0, 1, part_rows))
     assert rc == 0
     for i in range(bp.nsys):
         p = bp.system(i)
@@ -113,11 +118,12 @@ def test_to_tolerance_parity():
         assert rel(xi, o.x) <= 10 * 1e4 * TOL
 
 
-def test_fp32_basis_to_tolerance():
+@pytest.mark.parametrize("part_rows", [0, 256])
+def test_fp32_basis_to_tolerance(part_rows):
     bp = SMALL
-    log("batch to tolerance fp32 basis")
-    rc, info, x, _ = run(bp, "mgs1r_ir32")
-    _, info64, x64, _ = run(bp)
+    log(f"batch to tolerance fp32 basis part_rows={part_rows}")
+    rc, info, x, _ = run(bp, "mgs1r_ir32", config=(256, 0, 1, part_rows))
+    _, info64, x64, _ = run(bp, config=(256, 0, 1, part_rows))
     assert rc == 0
     errs = []
     for i in range(bp.nsys):
@@ -136,14 +142,17 @@ def test_fp32_basis_to_tolerance():
         f"max |x - x_oracle| / |x_oracle| {max(errs):.2e}")
 
 
-def test_config_invariance():
-    """Grid and queue order change the schedule, not the arithmetic."""
+@pytest.mark.parametrize("part_rows", [0, 256])
+def test_config_invariance(part_rows):
+    """Grid and queue order change the schedule, not the arithmetic (grids of at
+    least the largest team, 6 parts, keep every team whole)."""
     bp = SMALL
-    log("batch config invariance")
-    _, i0, x0, _ = run(bp, rtol=TOL, config=(256, 0, 1))
-    for cfg in [(256, 1, 1), (256, 7, 0), (256, 1000, 0)]:
-        _, i1, x1, _ = run(bp, rtol=TOL, config=cfg)
-        assert np.array_equal(x0, x1), cfg
+    log(f"batch config invariance part_rows={part_rows}")
+    _, i0, x0, _ = run(bp, rtol=TOL, config=(256, 0, 1, part_rows))
+    grids = [(6, 1), (9, 0), (1000, 0)] + ([(1, 1)] if part_rows == 0 else [])
+    for grid, order in grids:
+        _, i1, x1, _ = run(bp, rtol=TOL, config=(256, grid, order, part_rows))
+        assert np.array_equal(x0, x1), (grid, order)
         assert np.array_equal(i0["iters"], i1["iters"])
 
 
@@ -188,11 +197,11 @@ def test_autotune():
     assert len(trials) >= 6 and all(t[3] > 0 for t in trials)
     best = min(trials, key=lambda t: t[3])
     cfg = s.config()
-    assert (cfg["block_size"], cfg["grid"], cfg["order"]) == best[:3]
+    assert (cfg["block_size"], cfg["grid"], cfg["order"], cfg["part_rows"]) == (*best[:3], best[4])
     assert torch.count_nonzero(x).item() == 0  # x restored
     rc, info = s.solve(bt, x, TOL, 20000)
     assert rc == 0 and np.all(info["converged"] == 1)
-    log("  trials: " + ", ".join(f"{t[0]}/{t[1]}/{t[2]}:{t[3]:.2f}ms" for t in trials))
+    log("  trials: " + ", ".join(f"{t[0]}/{t[1]}/{t[2]}/{t[4]}:{t[3]:.2f}ms" for t in trials))
 
 
 def test_edges():
@@ -260,6 +269,10 @@ def test_create_refusals():
         s.set_config(128, 0, 0)
     with pytest.raises(GmresError):
         s.set_config(256, -1, 0)
+    with pytest.raises(GmresError):
+        s.set_config(256, 0, 0, -1)
+    with pytest.raises(GmresError):
+        s.set_config(256, 0, 2)
 
 
 @pytest.mark.parametrize("scheme", ["mgs1r", "mgs1r_ir32"])

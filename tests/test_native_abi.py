@@ -81,10 +81,13 @@ def test_batch_workspace_sizing(lib):
     # bases: (m+1) columns of n_i rounded up to 64
     ld = [1024, 128, 4096]
     basis = sum(ld) * (m + 1)
+    # one slot per possible part of a team: ceil(n_i / 256) parts, at most 16
+    slots = 4 + 1 + 16
     small = 2 * (m + 1) * m + 2 * (m + 2) ** 2 + 7 * (m + 2)
-    assert f64 >= 8 * basis + 3 * 8 * small + 8 * 5196 * 2
-    assert f64 <= 8 * basis + 3 * 8 * small + 8 * 5196 * 2 + 3 * 400 + 12 * 256
-    assert f32 >= 4 * basis + 3 * 8 * small + 4 * 5196 + 2 * 8 * 5196
+    per_slot = 8 * small + 8 * 4 * (m + 2) + 16 + 128      # small arrays, partials, ticket, state
+    assert f64 >= 8 * basis + slots * (8 * small + 8 * 4 * (m + 2)) + 8 * 5196 * 2
+    assert f64 <= 8 * basis + slots * per_slot + 8 * 5196 * 2 + 3 * 64 + 14 * 256
+    assert f32 >= 4 * basis + slots * (8 * small) + 4 * 5196 + 2 * 8 * 5196
     assert f32 < f64
     # refusals: empty systems, a bad first offset, the schemes with no batched form, m out of range
     assert native.gmres_batch_workspace_bytes(np.array([0, 10, 10]), m, 1) == 0
