@@ -231,7 +231,9 @@ def batch_result(args):
         s = BatchSolver(bp.row_off, rp, ci, va, bp.m, scheme)
         x = torch.zeros(bp.n, dtype=torch.float64, device=dev)
         trials = []
-        if not args.no_batch_autotune:
+        if args.batch_config:
+            s.set_config(*(int(v) for v in args.batch_config.split(",")))
+        elif not args.no_batch_autotune:
             trials = s.autotune(b, x, bp.rtol, args.max_iters)
         cfg = s.config()
         times = []
@@ -254,7 +256,7 @@ def batch_result(args):
                     "config": cfg,
                     "autotune_trials": [{"block_size": t[0], "grid": t[1],
                                          "order": "largest_first" if t[2] else "natural",
-                                         "ms": round(t[3], 2)} for t in trials]}
+                                         "part_rows": t[4], "ms": round(t[3], 2)} for t in trials]}
         log(f"batch {scheme}: {iters} iters in {dt * 1e3:.1f} ms ({iters / dt:.0f} it/s), cfg {cfg}, "
             f"worst rel res {res.max():.2e}")
         s.close()
@@ -307,6 +309,8 @@ def main():
     ap.add_argument("--no-batch-autotune", action="store_true",
                     help="batched solves with the default launch configuration")
     ap.add_argument("--batch-systems", type=int, default=512)
+    ap.add_argument("--batch-config", type=str, default="",
+                    help="block_size,grid,order,part_rows for the batched solves instead of autotuning")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed batched solves per scheme")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
