@@ -110,15 +110,16 @@ def kernel_table(kt, ms_per_solve):
     return out
 
 
-def ir32_result(args, p, rp, ci, va, b, x, x64, s64_per_solve, iters64):
-    """The FP32-basis scheme on the same system and tolerance: speed, and its
-    solution's error against the float64 one and against x_true."""
+def ir32_result(args, p, rp, ci, va, b, x, x64, s64_per_solve, iters64, scheme="mgs1r_ir32"):
+    """A reduced-precision-basis scheme (float32, or the bfloat16 experiment)
+    on the same system and tolerance: speed, and its solution's error against
+    the float64 one and against x_true."""
     import numpy as np
     import torch
 
     from paper_1809_05805_amd.native import GmresSolver
 
-    s = GmresSolver(rp, ci, va, p.m, "mgs1r_ir32")
+    s = GmresSolver(rp, ci, va, p.m, scheme)
     k = max(1, min(args.steps, 5))
     dt, iters, res, kt = time_solves(s, b, x, p.rtol, args.max_iters, k, 1, timing=True)
     xr = x.cpu().numpy()
@@ -128,10 +129,11 @@ def ir32_result(args, p, rp, ci, va, b, x, x64, s64_per_solve, iters64):
     err64 = float(np.linalg.norm(xr - x64n) / np.linalg.norm(x64n))
     errt = float(np.linalg.norm(xr - p.x_true) / np.linalg.norm(p.x_true))
     err64t = float(np.linalg.norm(x64n - p.x_true) / np.linalg.norm(p.x_true))
-    log(f"mgs1r_ir32: {iters / k:.0f} iters/solve, {dt / k * 1e3:.2f} ms/solve, rel_res {rel_res:.2e}, "
+    log(f"{scheme}: {iters / k:.0f} iters/solve, {dt / k * 1e3:.2f} ms/solve, rel_res {rel_res:.2e}, "
         f"err vs fp64 {err64:.2e}")
     s.close()
-    return {"scheme": "one-reduce on a float32 basis, float64 refinement at every restart",
+    basis = "float32" if scheme == "mgs1r_ir32" else "bfloat16 (float32 arithmetic)"
+    return {"scheme": f"one-reduce on a {basis} basis, float64 refinement at every restart",
             "m": p.m, "iters_per_s": round(iters / dt, 2), "ms_per_solve": round(dt / k * 1e3, 3),
             "iters_per_solve": iters // k, "fp64_iters_per_solve": iters64,
             "speedup_vs_fp64_solve": round(s64_per_solve / (dt / k), 3),
@@ -160,7 +162,7 @@ def precision_config(args):
            "n": p.n, "nnz": p.nnz}
     sols = {}
     A = p.scipy()
-    for scheme in ("mgs1r", "mgs1r_ir32"):
+    for scheme in ("mgs1r", "mgs1r_ir32", "mgs1r_ir16"):
         s = GmresSolver(rp, ci, va, 40, scheme)
         dt, iters, res, kt = time_solves(s, b, x, 1e-10, args.max_iters, 1, 1, timing=True)
         sols[scheme] = x.cpu().numpy()
@@ -175,7 +177,10 @@ def precision_config(args):
         s.close()
     out["mgs1r_ir32"]["err_vs_fp64_solution"] = float(
         np.linalg.norm(sols["mgs1r_ir32"] - sols["mgs1r"]) / np.linalg.norm(sols["mgs1r"]))
+    out["mgs1r_ir16"]["err_vs_fp64_solution"] = float(
+        np.linalg.norm(sols["mgs1r_ir16"] - sols["mgs1r"]) / np.linalg.norm(sols["mgs1r"]))
     out["speedup_vs_fp64_solve"] = round(out["mgs1r"]["ms_per_solve"] / out["mgs1r_ir32"]["ms_per_solve"], 3)
+    out["bf16_speedup_vs_fp64_solve"] = round(out["mgs1r"]["ms_per_solve"] / out["mgs1r_ir16"]["ms_per_solve"], 3)
     return out
 
 
@@ -391,6 +396,8 @@ def main():
     x64 = x.clone()
     if not args.no_ir32:
         out["fp32_ir"] = ir32_result(args, p, rp, ci, va, b, x, x64, dt / args.steps, res.iters)
+        out["bf16_ir"] = ir32_result(args, p, rp, ci, va, b, x, x64, dt / args.steps, res.iters,
+                                     scheme="mgs1r_ir16")
     if args.precision_N:
         out["fp32_ir_precision_config"] = precision_config(args)
     if not args.no_baselines:

@@ -31,6 +31,12 @@
  *                 accumulates in float64. Restarted GMRES is then iterative
  *                 refinement with float32 inner cycles; the precision is not
  *                 discussed in the paper.
+ *   GMRES_MGS_1R_IR16  an experiment: the same refinement with the basis and
+ *                 the SpMV output stored in bfloat16 (8-bit significand,
+ *                 round to nearest even). Every product and per-lane sum runs
+ *                 in float32 on values widened from bfloat16; the sliced copy
+ *                 of A keeps float32 values; everything the float32-basis
+ *                 scheme keeps in float64 stays float64.
  *
  * The problem is A x = b with residual r = b - A x and initial guess x0
  * (Section III); A is in CSR form (Section V-B); all vectors live in device
@@ -56,7 +62,13 @@ extern "C" {
 
 typedef struct gmres_ctx gmres_ctx; /* opaque */
 
-typedef enum { GMRES_MGS = 0, GMRES_MGS_1R = 1, GMRES_CGS2 = 2, GMRES_MGS_1R_IR32 = 3 } gmres_scheme;
+typedef enum {
+  GMRES_MGS = 0,
+  GMRES_MGS_1R = 1,
+  GMRES_CGS2 = 2,
+  GMRES_MGS_1R_IR32 = 3,
+  GMRES_MGS_1R_IR16 = 4
+} gmres_scheme;
 
 typedef enum {
   GMRES_OK = 0,
@@ -132,7 +144,7 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
  *   lower part of V^T V: entry i of a cycle covers its basis vectors
  *   v_0..v_i (the leading (i+1) x (i+1) block of T; 0 for i = 0). Computed on
  *   the host after each cycle from the T (one-reduce MGS) or L (CGS2) the
- *   device built (T for GMRES_MGS_1R_IR32 too), by power iteration to a
+ *   device built (T for GMRES_MGS_1R_IR32 and _IR16 too), by power iteration to a
  *   relative change of 1e-14; NaN for
  *   GMRES_MGS, which forms neither. It adds host work per cycle; pass NULL
  *   when timing.
@@ -202,7 +214,7 @@ int gmres_spmv(gmres_ctx* ctx, const double* x, double* y);
  * Diagnostics of the last cycle that completed at least one column (host
  * copies, each nullable):
  *   H (host, (m+1) x m, column-major): the unrotated Hessenberg matrix;
- *   T (host, (m+2) x (m+2), column-major): for GMRES_MGS_1R (and _IR32) the Malard-Paige
+ *   T (host, (m+2) x (m+2), column-major): for GMRES_MGS_1R (and _IR32, _IR16) the Malard-Paige
  *     T = (I + L^T)^{-1} built one column per step, whose leading blocks give
  *     Paige's loss-of-orthogonality measure S = I - T (Section II); for
  *     GMRES_CGS2 the strictly lower L with V^T V = I + L + L^T, one row per
@@ -210,8 +222,8 @@ int gmres_spmv(gmres_ctx* ctx, const double* x, double* y);
  *     step computes only the norm of column j (and of a cycle that ends on
  *     the tolerance check, column j is formed too);
  *   g (host, m+2): the rotated right-hand side of the least-squares problem
- *     (for GMRES_MGS_1R_IR32 relative to the cycle's restart residual norm:
- *     the cycle starts from r / ||r||, and H is that of the float32 basis);
+ *     (for GMRES_MGS_1R_IR32 and _IR16 relative to the cycle's restart residual norm:
+ *     the cycle starts from r / ||r||, and H is that of the reduced-precision basis);
  *   j (host): the number of columns that cycle completed.
  */
 int gmres_last_cycle(gmres_ctx* ctx, double* H, double* T, double* g, int32_t* j);
@@ -221,7 +233,7 @@ int gmres_last_cycle(gmres_ctx* ctx, double* H, double* T, double* g, int32_t* j
  * dimension (in elements). Columns 0..j-1 of the last cycle hold its
  * orthonormal basis until the next solve, except that a solve that ends by
  * converging overwrites column 0 with the final residual it verified.
- * GMRES_ERR_ARG for GMRES_MGS_1R_IR32, whose basis is float32.
+ * GMRES_ERR_ARG for GMRES_MGS_1R_IR32 and _IR16, whose basis is float32 or bfloat16.
  */
 int gmres_basis(gmres_ctx* ctx, double** V, int64_t* ldv);
 
@@ -233,8 +245,10 @@ int gmres_basis(gmres_ctx* ctx, double** V, int64_t* ldv);
  * attached to its dispatch (hipExtLaunchKernel), so they time the kernel
  * alone; launches that the cycle's done flag skipped are not counted. bytes is
  * the algorithmic HBM traffic of the counted launches, with A the matrix bytes
- * of the format in use (CSR: 12 nnz + 4 (n+1); SELL64: 12 per stored entry
- * plus 8 per slice offset, ceil(n/64) + 1 of them):
+ * of the format in use (CSR: 12 nnz + 4 (n+1); SELL64: 12 per stored entry,
+ * 8 for the float32 values of the refinement schemes, plus 8 per slice
+ * offset, ceil(n/64) + 1 of them). The figures below are for a float64
+ * basis; for the float32 (bfloat16) basis every 8 n is 4 n (2 n):
  *   step k, SpMV fused:     A + 8 n (k+1) + 8 n     (A, V[:,0:k+1], w written)
  *   step k, SpMV separate:  8 n (k+1) + 8 n         (V[:,0:k+1], w read)
  *   separate SpMV:          A + 16 n                (A, u, w written)

@@ -92,6 +92,16 @@ int format_override() {
   return -1;
 }
 
+// The refinement schemes: one-reduce cycles on a reduced-precision basis
+// (float32 or bfloat16) inside float64 refinement.
+bool ir_scheme(int scheme) { return scheme == kSchemeIr32 || scheme == kSchemeIr16; }
+int basis_type(int scheme) {
+  return scheme == kSchemeIr32 ? kBasisF32 : scheme == kSchemeIr16 ? kBasisBf16 : kBasisF64;
+}
+size_t basis_bytes(int scheme) {
+  return scheme == kSchemeIr32 ? sizeof(float) : scheme == kSchemeIr16 ? 2 : sizeof(double);
+}
+
 struct Layout {
   int64_t ldv;
   int rpt, G, NG, pstride;
@@ -116,10 +126,10 @@ bool make_layout(int64_t n, int m, int scheme, Layout* L) {
     return at;
   };
   const size_t d = sizeof(double);
-  const size_t vb = scheme == kSchemeIr32 ? sizeof(float) : d;
+  const size_t vb = basis_bytes(scheme);
   L->V = take((size_t)L->ldv * (size_t)(m + 2) * vb);
   L->w = take((size_t)L->ldv * vb);
-  L->r64 = scheme == kSchemeIr32 ? take((size_t)L->ldv * d) : 0;
+  L->r64 = ir_scheme(scheme) ? take((size_t)L->ldv * d) : 0;
   L->H = take((size_t)(m + 1) * (size_t)m * d);
   L->R = take((size_t)(m + 1) * (size_t)m * d);
   L->T = take((size_t)(m + 2) * (size_t)(m + 2) * d);
@@ -340,8 +350,8 @@ int plan_format(gmres_ctx* c) {
   if (want == kFormatCsr || c->nnz == 0 || c->A.n >= kSellMaxRows) return GMRES_OK;
   const int64_t ns = (c->A.n + 63) / 64;
   // ns ints fit easily in the basis region (n (m+2) doubles, or floats)
-  int* dw = c->scheme == kSchemeIr32 ? reinterpret_cast<int*>(c->ws.Vf)
-                                     : reinterpret_cast<int*>(c->ws.V);
+  int* dw = ir_scheme(c->scheme) ? reinterpret_cast<int*>(c->ws.Vf)
+                                 : reinterpret_cast<int*>(c->ws.V);
   std::vector<int> wh((size_t)ns);
   if (launch_sell_width(c->A, ns, dw, c->stream) ||
       hipMemcpyAsync(wh.data(), dw, sizeof(int) * (size_t)ns, hipMemcpyDeviceToHost, c->stream) !=
@@ -362,7 +372,7 @@ int plan_format(gmres_ctx* c) {
   c->sell_entries = total;
   c->o_ci = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
   c->o_va = round_up(c->o_ci + sizeof(int) * (size_t)total, kAlign);
-  const size_t vsize = c->scheme == kSchemeIr32 ? sizeof(float) : sizeof(double);
+  const size_t vsize = ir_scheme(c->scheme) ? sizeof(float) : sizeof(double);
   c->sell_bytes = c->o_va + vsize * (size_t)total;
   return GMRES_OK;
 }
@@ -372,7 +382,7 @@ int plan_format(gmres_ctx* c) {
 // holds float32 values, so its float64 products read the CSR arrays).
 int spmv(gmres_ctx* c, const double* x, const double* b, double* y, const DevState* st,
          hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  if (c->format == kFormatSell && c->scheme != kSchemeIr32)
+  if (c->format == kFormatSell && !ir_scheme(c->scheme))
     return launch_spmv_sell(c->sell, c->A.n, x, b, y, st, s, e0, e1);
   return launch_spmv(c->A, c->S, x, b, y, st, s, e0, e1);
 }
@@ -382,8 +392,9 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
   const Ws& ws = c->ws;
   hipStream_t s = c->stream;
   const int rpt = c->L.rpt, G = c->L.G;
-  const bool f32 = c->scheme == kSchemeIr32;
-  const double n8 = (f32 ? 4.0 : 8.0) * (double)c->A.n;  // one basis column
+  const bool f32 = ir_scheme(c->scheme);       // a reduced-precision basis
+  const int bt = basis_type(c->scheme);
+  const double n8 = (double)basis_bytes(c->scheme) * (double)c->A.n;  // one basis column
   // bytes of the matrix in the format the step's SpMV reads
   const double csr = c->format == kFormatSell
                          ? (f32 ? 8.0 : 12.0) * (double)c->sell_entries + 8.0 * (double)(c->sell.ns + 1)
@@ -396,7 +407,7 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
     TRY(spmv(c, x, b, ws.r64, nullptr, s));
     TRY(launch_axpy_dot(ws, rpt, ws.r64, nullptr, nullptr, ws.r64, kTailIrBeta, 0, 0, m_eff, 0.0,
                         G, s));
-    TRY(launch_first_f32(ws, s));
+    TRY(launch_first_vector(ws, bt, s));
   } else {
     TRY(spmv(c, x, b, col(0), nullptr, s));  // V[:,0] = b - A x
   }
@@ -433,33 +444,33 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
           bytes = n8 * (k + 2);
         }
         TimedLaunch t(c, GMRES_KSTAT_STEP, k, k, bytes);
-        TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k, last ? 0 : k, wsrc, m_eff, tail, G, f32, s,
+        TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k, last ? 0 : k, wsrc, m_eff, tail, G, bt, s,
                          t.e0, t.e1));
       }
       if (k == m_eff) break;
       {
         TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
-        TRY(launch_maxpy(ws, rpt, k, 0, G, f32, s, t.e0, t.e1));
+        TRY(launch_maxpy(ws, rpt, k, 0, G, bt, s, t.e0, t.e1));
       }
       if (c->scheme == kSchemeCgs2) {
         {
           TimedLaunch t(c, GMRES_KSTAT_STEP, k, k + 1, n8 * (k + 2));
           TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, k + 1, k + 1, kWNone, m_eff, kTailCgs2Second, G,
-                           false, s, t.e0, t.e1));
+                           kBasisF64, s, t.e0, t.e1));
         }
         TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
-        TRY(launch_maxpy(ws, rpt, k, 1, G, false, s, t.e0, t.e1));
+        TRY(launch_maxpy(ws, rpt, k, 1, G, kBasisF64, s, t.e0, t.e1));
       }
     }
   }
-  TRY(launch_cycle_end(ws, rpt, x, G, f32, s));
+  TRY(launch_cycle_end(ws, rpt, x, G, bt, s));
   return GMRES_OK;
 }
 
 // ||b - A x|| into the state's beta, without touching the basis.
 int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
   const Ws& ws = c->ws;
-  double* r = c->scheme == kSchemeIr32 ? ws.r64 : ws.w;
+  double* r = ir_scheme(c->scheme) ? ws.r64 : ws.w;
   TRY(launch_cycle_begin(ws, c->stream));
   TRY(spmv(c, x, b, r, nullptr, c->stream));
   TRY(launch_axpy_dot(ws, c->L.rpt, r, nullptr, nullptr, r, kTailFinalRes, 0, 0, 0, 0.0, c->L.G,
@@ -472,7 +483,7 @@ int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
 extern "C" {
 
 size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme) {
-  if (scheme < GMRES_MGS || scheme > GMRES_MGS_1R_IR32) return 0;
+  if (scheme < GMRES_MGS || scheme > GMRES_MGS_1R_IR16) return 0;
   Layout L;
   if (!make_layout(n, m, scheme, &L)) return 0;
   return L.total;
@@ -495,7 +506,7 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   if (!out) return GMRES_ERR_ARG;
   *out = nullptr;
   if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31) || m < 1 ||
-      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_MGS_1R_IR32)
+      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_MGS_1R_IR16)
     return GMRES_ERR_ARG;
   if (!is_device_ptr(row_ptr) || !is_device_ptr(workspace) ||
       (nnz > 0 && (!is_device_ptr(col_idx) || !is_device_ptr(vals))))
@@ -517,7 +528,7 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   c->stream = (hipStream_t)hip_stream;
   char* base = (char*)workspace;
   Ws& ws = c->ws;
-  if (scheme == kSchemeIr32) {
+  if (ir_scheme(scheme)) {
     ws.V = nullptr;
     ws.w = nullptr;
     ws.Vf = (float*)(base + L.V);
@@ -628,7 +639,7 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
     return GMRES_ERR_ARG;
   char* base = (char*)storage;
   const int64_t ns = (int64_t)c->sell_sp.size() - 1;
-  const bool f32 = c->scheme == kSchemeIr32;
+  const bool f32 = ir_scheme(c->scheme);  // float32 values for the reduced-precision bases
   const Sell S{(const int64_t*)base, (int*)(base + c->o_ci),
                f32 ? nullptr : (double*)(base + c->o_va), f32 ? (float*)(base + c->o_va) : nullptr,
                ns, c->A.n};
@@ -658,7 +669,7 @@ int gmres_spmv(gmres_ctx* c, const double* x, double* y) {
 }
 
 int gmres_basis(gmres_ctx* c, double** V, int64_t* ldv) {
-  if (!c || c->scheme == kSchemeIr32) return GMRES_ERR_ARG;
+  if (!c || ir_scheme(c->scheme)) return GMRES_ERR_ARG;
   if (V) *V = c->ws.V;
   if (ldv) *ldv = c->ws.ldv;
   return GMRES_OK;

@@ -152,8 +152,10 @@ struct BufCol {
   __device__ T operator()(uint32_t boff) const {
     if constexpr (sizeof(T) == 8)
       return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)boff, 0, 0));
-    else
+    else if constexpr (sizeof(T) == 4)
       return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, 0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)boff, 0, 0));
   }
 };
 
@@ -181,20 +183,38 @@ using ProjCol = std::conditional_t<GMRES_PROJ_BUFFER != 0, BufCol<T>, GlbCol<T>>
 template <typename T>
 using MaxpyCol = std::conditional_t<GMRES_MAXPY_BUFFER != 0, BufCol<T>, GlbCol<T>>;
 
-// The basis and SpMV-output arrays of the workspace in the basis type.
+// Basis element types: float64, float32, and bfloat16 (storage only). The
+// arithmetic type of a basis type: its own, and float32 for bfloat16. The
+// sliced copy's value type: float64 for the float64 basis, float32 otherwise.
+template <typename VT>
+struct ArithOf {
+  using type = VT;
+};
+template <>
+struct ArithOf<__bf16> {
+  using type = float;
+};
+template <typename VT>
+using arith_t = typename ArithOf<VT>::type;
+template <typename VT>
+using sval_t = std::conditional_t<sizeof(VT) == 8, double, float>;
+
+// The basis and SpMV-output arrays of the workspace in the basis type (the
+// reduced-precision bases share the float32 pointers; the workspace layout
+// sizes them by element size).
 template <typename VT>
 __device__ __host__ inline VT* basis_of(const Ws& ws) {
   if constexpr (sizeof(VT) == 8)
     return ws.V;
   else
-    return ws.Vf;
+    return reinterpret_cast<VT*>(ws.Vf);
 }
 template <typename VT>
 __device__ __host__ inline VT* wbuf_of(const Ws& ws) {
   if constexpr (sizeof(VT) == 8)
     return ws.w;
   else
-    return ws.wf;
+    return reinterpret_cast<VT*>(ws.wf);
 }
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
@@ -755,23 +775,26 @@ __device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l,
 
 // out[i] = (A x) at row 64 (s0 + i sstride) + l, i < NS, for the lane's row in
 // NS slices sstride apart (slice indices past the last are clamped; the
-// caller drops those rows). Values, x and the sums are in T (float64, or
-// float32 for the FP32-basis scheme). U entries per chunk; the column and
+// caller drops those rows). x is in the basis type XT; values are float64 for
+// the float64 basis and float32 otherwise, and the products and sums are in
+// XT's arithmetic type. U entries per chunk; the column and
 // value loads of the next chunk (of this slice or the next) are issued before
 // the gathers of the current one are consumed, so one memory latency per
 // chunk is hidden.
-template <int NS, int U, typename T>
-__device__ inline void sell_slices(const Sell& S, const T* __restrict__ x, int64_t s0,
-                                   int64_t sstride, int l, T (&out)[NS]) {
+template <int NS, int U, typename XT>
+__device__ inline void sell_slices(const Sell& S, const XT* __restrict__ x, int64_t s0,
+                                   int64_t sstride, int l, arith_t<XT> (&out)[NS]) {
+  using T = arith_t<XT>;
+  using SVT = sval_t<XT>;
   auto clampslice = [&](int64_t s) { return s < S.ns ? s : S.ns - 1; };
   // gathers from x[0, n) by 32-bit byte offset (the sliced format is used only
   // for n < 2^28)
-  const BufCol<T> xb(x, S.n);
+  const BufCol<XT> xb(x, S.n);
   int64_t b = S.sp[clampslice(s0)];
   int W = (int)((S.sp[clampslice(s0) + 1] - b) >> 6);
   int c[U];
-  T v[U];
-  sell_load<U, T>(S, b, W, 0, l, c, v);
+  SVT v[U];
+  sell_load<U, SVT>(S, b, W, 0, l, c, v);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     int64_t bn = b;
@@ -786,13 +809,13 @@ __device__ inline void sell_slices(const Sell& S, const T* __restrict__ x, int64
       T xv[U], vv[U];
 #pragma unroll
       for (int t = 0; t < U; ++t) {
-        xv[t] = xb((uint32_t)c[t] * (uint32_t)sizeof(T));
-        vv[t] = v[t];
+        xv[t] = (T)xb((uint32_t)c[t] * (uint32_t)sizeof(XT));
+        vv[t] = (T)v[t];
       }
       if (j0 + U < W)
-        sell_load<U, T>(S, b, W, j0 + U, l, c, v);
+        sell_load<U, SVT>(S, b, W, j0 + U, l, c, v);
       else if (i + 1 < NS)
-        sell_load<U, T>(S, bn, Wn, 0, l, c, v);
+        sell_load<U, SVT>(S, bn, Wn, 0, l, c, v);
 #pragma unroll
       for (int t = 0; t < U; ++t) acc += (j0 + t < W) ? vv[t] * xv[t] : (T)0;
     }
@@ -820,16 +843,19 @@ __global__ __launch_bounds__(256) void k_spmv_sell(Sell S, int64_t n, const doub
   }
 }
 
-// First basis vector of an FP32-basis cycle: Vf[:,0] = float(r64 / ||r64||)
-// (inv_rho holds 1 / ||r64|| from the restart reduction), skipped once the
-// restart check ended the cycle.
-__global__ __launch_bounds__(256) void k_first_f32(Ws ws) {
+// First basis vector of a reduced-precision-basis cycle: V[:,0] = r64 / ||r64||
+// rounded to float32, and from there to bfloat16 for that basis (inv_rho
+// holds 1 / ||r64|| from the restart reduction); skipped once the restart
+// check ended the cycle.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_first_vector(Ws ws) {
   const DevState* st = ws.st;
   if (st->done) return;
   const double s = st->inv_rho;
+  VT* __restrict__ V = basis_of<VT>(ws);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ws.n; r += stride)
-    ws.Vf[r] = (float)(ws.r64[r] * s);
+    V[r] = (VT)(float)(ws.r64[r] * s);
 }
 
 // ------------------------------------------------ the fused projection step
@@ -1131,9 +1157,10 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   VT* __restrict__ wout = wbuf_of<VT>(ws);
   const int64_t ldv = ws.ldv;
   const VT* __restrict__ u_g = V + (size_t)K * ldv;
+  using CT = arith_t<VT>;  // arithmetic type of the basis
   constexpr bool HAS_SPMV = WSRC != kWNone;
   // kWSell: the lane's rows are row 64 s + lane of slices s = row0/64 + wv RPT + i
-  VT ws_out[RPT];
+  CT ws_out[RPT];
   if constexpr (WSRC == kWSell) {
     if constexpr (GMRES_FUSED_ROWMAP == 1)
       sell_slices<RPT, 8, VT>(SA, u_g, (row0 >> 6) + wv, 4, lane, ws_out);
@@ -1160,9 +1187,9 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   // Loads take a uniform base rb plus a 32-bit byte offset (rows[i]): rb is
   // the tile's first row, or row n-1 for a padding tile past the end, so the
   // clamped rows lie in [rb, rb + TR) and the offsets are never negative.
-  // Products and per-lane sums are in VT (the basis type); the sums become
-  // float64 for the cross-lane and device-wide reduction.
-  VT u[RPT], w[RPT];
+  // Products and per-lane sums are in CT (the basis type's arithmetic type);
+  // the sums become float64 for the cross-lane and device-wide reduction.
+  CT u[RPT], w[RPT];
   uint32_t rows[RPT];
   const int64_t rb = row0 < n ? row0 : n - 1;
   const VT* __restrict__ Vt = V + rb;
@@ -1172,19 +1199,19 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     const int64_t r = row0 + lr;
     const bool ok = r < n;
     rows[i] = (uint32_t)((ok ? r : n - 1) - rb) * (uint32_t)sizeof(VT);
-    const VT uv = ProjCol<VT>(u_g + rb, n - rb)(rows[i]);
-    u[i] = ok ? uv : (VT)0;
+    const CT uv = (CT)ProjCol<VT>(u_g + rb, n - rb)(rows[i]);
+    u[i] = ok ? uv : (CT)0;
     if constexpr (WSRC == kWSpmv) {
-      w[i] = ok ? (VT)wl[lr] : (VT)0;
-      if (ok) wout[r] = w[i];
+      w[i] = ok ? (CT)wl[lr] : (CT)0;
+      if (ok) wout[r] = (VT)w[i];
     } else if constexpr (WSRC == kWSell) {
-      w[i] = ok ? ws_out[i] : (VT)0;
-      if (ok) wout[r] = w[i];
+      w[i] = ok ? ws_out[i] : (CT)0;
+      if (ok) wout[r] = (VT)w[i];
     } else if constexpr (WSRC == kWLoad) {
-      const VT wv_ = ProjCol<VT>(wout + rb, n - rb)(rows[i]);
-      w[i] = ok ? wv_ : (VT)0;
+      const CT wv_ = (CT)ProjCol<VT>(wout + rb, n - rb)(rows[i]);
+      w[i] = ok ? wv_ : (CT)0;
     } else {
-      w[i] = (VT)0;
+      w[i] = (CT)0;
     }
   }
   double* myred = red + wv * P;
@@ -1210,11 +1237,11 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     double acc[NVC];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      VT p = (VT)0, q = (VT)0;
+      CT p = (CT)0, q = (CT)0;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        p += vv[c][i] * u[i];
-        if constexpr (HAS_SPMV) q += vv[c][i] * w[i];
+        p += (CT)vv[c][i] * u[i];
+        if constexpr (HAS_SPMV) q += (CT)vv[c][i] * w[i];
       }
       if constexpr (HAS_SPMV) {
         acc[2 * c] = (double)p;
@@ -1274,11 +1301,11 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     const ProjCol<VT> col(Vt + (size_t)j0 * ldv, nvalid);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) vv[i] = col(rows[i]);
-    VT pl = (VT)0, cl = (VT)0;
+    CT pl = (CT)0, cl = (CT)0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      pl += vv[i] * u[i];
-      if constexpr (HAS_SPMV) cl += vv[i] * w[i];
+      pl += (CT)vv[i] * u[i];
+      if constexpr (HAS_SPMV) cl += (CT)vv[i] * w[i];
     }
     const double p = wave_sum_last((double)pl);
     const double c = HAS_SPMV ? wave_sum_last((double)cl) : 0.0;
@@ -1288,7 +1315,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     }
   }
   {
-    VT all = (VT)0, gal = (VT)0;
+    CT all = (CT)0, gal = (CT)0;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       all += u[i] * u[i];
@@ -1344,13 +1371,14 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   VT* __restrict__ V = basis_of<VT>(ws);
   const int64_t ldv = ws.ldv;
   const double* __restrict__ cf = mode == 0 ? ws.coef : ws.coef2;
-  const VT invr = (VT)ws.st->inv_rho;
+  using CT = arith_t<VT>;  // arithmetic type of the basis
+  const CT invr = (CT)ws.st->inv_rho;
   // Loads at clamped rows (unconditional, so they are all in flight at once);
   // only rows below n are stored. Each load is a uniform column base (row rb
   // of column q: the tile's first row, or n-1 for a padding tile past the
   // end) plus a per-lane byte offset in [0, 8 TR), so one offset register per
   // row serves every column.
-  VT acc[RPT];
+  CT acc[RPT];
   uint32_t off[RPT];
   const int64_t rb = row0 < n ? row0 : n - 1;
   const int64_t nvalid = n - rb;
@@ -1359,40 +1387,40 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;
     off[i] = (uint32_t)((r < n ? r : n - 1) - rb) * (uint32_t)sizeof(VT);
-    acc[i] = mode == 0 ? src0(off[i]) * invr : src0(off[i]);
+    acc[i] = mode == 0 ? (CT)src0(off[i]) * invr : (CT)src0(off[i]);
   }
   // GMRES_MAXPY_COLS columns per pass (their loads are in flight together).
   constexpr int MC = GMRES_MAXPY_COLS;
   const VT* __restrict__ Vt = V + rb;
   int q = 0;
   for (; q + MC <= k; q += MC) {
-    VT c[MC];
+    CT c[MC];
     VT v[MC][RPT];
 #pragma unroll
     for (int t = 0; t < MC; ++t) {
-      c[t] = (VT)cf[q + t];
+      c[t] = (CT)cf[q + t];
       const MaxpyCol<VT> col(Vt + (size_t)(q + t) * ldv, nvalid);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) v[t][i] = col(off[i]);
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      VT a = acc[i];
+      CT a = acc[i];
 #pragma unroll
-      for (int t = 0; t < MC; ++t) a -= v[t][i] * c[t];
+      for (int t = 0; t < MC; ++t) a -= (CT)v[t][i] * c[t];
       acc[i] = a;
     }
   }
   for (; q < k; ++q) {
-    const VT c0 = (VT)cf[q];
+    const CT c0 = (CT)cf[q];
     const MaxpyCol<VT> col(Vt + (size_t)q * ldv, nvalid);
     VT v[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) v[i] = col(off[i]);
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) acc[i] -= v[i] * c0;
+    for (int i = 0; i < RPT; ++i) acc[i] -= (CT)v[i] * c0;
   }
-  const VT ck = (VT)cf[k];
+  const CT ck = (CT)cf[k];
   VT vk[RPT];
   const MaxpyCol<VT> colk(Vt + (size_t)k * ldv, nvalid);
 #pragma unroll
@@ -1401,12 +1429,12 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;
     if (r < n) {
-      VT x = vk[i];
+      CT x = (CT)vk[i];
       if (mode == 0) {
         x *= invr;
-        V[(size_t)k * ldv + r] = x;
+        V[(size_t)k * ldv + r] = (VT)x;
       }
-      V[(size_t)(k + 1) * ldv + r] = acc[i] - x * ck;
+      V[(size_t)(k + 1) * ldv + r] = (VT)(acc[i] - x * ck);
     }
   }
 }
@@ -1738,10 +1766,13 @@ int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s) {
   return 0;
 }
 
-int launch_first_f32(const Ws& ws, hipStream_t s) {
+int launch_first_vector(const Ws& ws, int bt, hipStream_t s) {
   int64_t blocks = (ws.n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_first_f32, dim3((unsigned)blocks), dim3(256), 0, s, ws);
+  if (bt == kBasisBf16)
+    hipLaunchKernelGGL(k_first_vector<__bf16>, dim3((unsigned)blocks), dim3(256), 0, s, ws);
+  else
+    hipLaunchKernelGGL(k_first_vector<float>, dim3((unsigned)blocks), dim3(256), 0, s, ws);
   GMRES_CHECK_LAUNCH();
   return 0;
 }
@@ -1802,10 +1833,12 @@ static int fused_v(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rp
 }
 
 int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K, int nproj,
-                 int wsrc, int m_eff, int tail, int G, bool f32, hipStream_t s, hipEvent_t e0,
+                 int wsrc, int m_eff, int tail, int G, int bt, hipStream_t s, hipEvent_t e0,
                  hipEvent_t e1) {
-  const int rc = f32 ? fused_v<float>(A, SA, shape, ws, rpt, K, nproj, wsrc, m_eff, tail, G, s, e0, e1)
-                     : fused_v<double>(A, SA, shape, ws, rpt, K, nproj, wsrc, m_eff, tail, G, s, e0, e1);
+  const int rc =
+      bt == kBasisF32    ? fused_v<float>(A, SA, shape, ws, rpt, K, nproj, wsrc, m_eff, tail, G, s, e0, e1)
+      : bt == kBasisBf16 ? fused_v<__bf16>(A, SA, shape, ws, rpt, K, nproj, wsrc, m_eff, tail, G, s, e0, e1)
+                         : fused_v<double>(A, SA, shape, ws, rpt, K, nproj, wsrc, m_eff, tail, G, s, e0, e1);
   if (rc) return rc;
   GMRES_CHECK_LAUNCH();
   return 0;
@@ -1822,10 +1855,12 @@ static void maxpy_v(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s
   }
 }
 
-int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, bool f32, hipStream_t s,
+int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, int bt, hipStream_t s,
                  hipEvent_t e0, hipEvent_t e1) {
-  if (f32)
+  if (bt == kBasisF32)
     maxpy_v<float>(ws, rpt, k, mode, G, s, e0, e1);
+  else if (bt == kBasisBf16)
+    maxpy_v<__bf16>(ws, rpt, k, mode, G, s, e0, e1);
   else
     maxpy_v<double>(ws, rpt, k, mode, G, s, e0, e1);
   GMRES_CHECK_LAUNCH();
@@ -1863,15 +1898,17 @@ static void xupdate_v(const Ws& ws, int rpt, double* x, int G, hipStream_t s) {
   }
 }
 
-int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, bool f32, hipStream_t s) {
+int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, int bt, hipStream_t s) {
   // up to 48 KiB: R's leading block when it fits, g always
   size_t want = (size_t)(ws.m + 2) + (size_t)(ws.m + 1) * ws.m;
   const size_t cap = 48 * 1024 / sizeof(double);
   if (want > cap) want = cap;
   hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(256), want * sizeof(double), s, ws, (int)want);
   GMRES_CHECK_LAUNCH();
-  if (f32)
+  if (bt == kBasisF32)
     xupdate_v<float>(ws, rpt, x, G, s);
+  else if (bt == kBasisBf16)
+    xupdate_v<__bf16>(ws, rpt, x, G, s);
   else
     xupdate_v<double>(ws, rpt, x, G, s);
   GMRES_CHECK_LAUNCH();

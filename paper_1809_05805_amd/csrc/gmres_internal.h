@@ -15,6 +15,9 @@ constexpr int kSchemeMgs = 0;
 constexpr int kSchemeMgs1r = 1;
 constexpr int kSchemeCgs2 = 2;
 constexpr int kSchemeIr32 = 3;  // one-reduce MGS cycles on an FP32 basis, FP64 refinement
+constexpr int kSchemeIr16 = 4;  // the same on a bfloat16 basis (float32 arithmetic)
+// Basis element types of the step kernels.
+enum BasisType { kBasisF64 = 0, kBasisF32 = 1, kBasisBf16 = 2 };
 
 constexpr int kNonfinite = -3;
 constexpr int kTeamStall = -2;  // a team's parts did not all arrive (GMRES_ERR_HIP)
@@ -185,17 +188,17 @@ int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b,
                      hipEvent_t e1 = nullptr);
 // f32: the FP32-basis variant (ws.Vf, ws.wf; float32 values in the sliced copy).
 int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K, int nproj,
-                 int wsrc, int m_eff, int tail, int G, bool f32, hipStream_t s,
+                 int wsrc, int m_eff, int tail, int G, int bt, hipStream_t s,
                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, bool f32, hipStream_t s,
+int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, int bt, hipStream_t s,
                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int launch_axpy_dot(const Ws& ws, int rpt, double* w, const double* a, const double* coef,
                     const double* v, int tail, int i_col, int q_row, int m_eff, double aux, int G,
                     hipStream_t s);
 int launch_scale(const Ws& ws, double* v, hipStream_t s);
-int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, bool f32, hipStream_t s);
+int launch_cycle_end(const Ws& ws, int rpt, double* x, int G, int bt, hipStream_t s);
 // FP32-basis cycle start: Vf[:,0] = float(r64 * inv_rho).
-int launch_first_f32(const Ws& ws, hipStream_t s);
+int launch_first_vector(const Ws& ws, int bt, hipStream_t s);
 size_t fused_lds_bytes(int rpt, int m);
 
 }  // namespace gmres

@@ -40,11 +40,14 @@ def test_workspace_sizing(lib):
     assert native.gmres_workspace_bytes(0, 30, 1) == 0
     assert native.gmres_workspace_bytes(100, 0, 1) == 0
     assert native.gmres_workspace_bytes(100, native.GMRES_MAX_RESTART + 1, 1) == 0
-    assert native.gmres_workspace_bytes(100, 30, 4) == 0
     # the FP32-basis scheme: a float32 basis and SpMV output plus a float64 residual
     f64 = native.gmres_workspace_bytes(2_097_152, 50, 1)
     f32 = native.gmres_workspace_bytes(2_097_152, 50, native.GMRES_MGS_1R_IR32)
     assert 2_097_152 * 53 * 4 + 2_097_152 * 8 <= f32 < 0.6 * f64
+    # the bfloat16 experiment: a 2-byte basis and SpMV output plus the float64 residual
+    f16 = native.gmres_workspace_bytes(2_097_152, 50, native.GMRES_MGS_1R_IR16)
+    assert 2_097_152 * 53 * 2 + 2_097_152 * 8 <= f16 < 0.6 * f32
+    assert native.gmres_workspace_bytes(100, 30, 5) == 0
     small = native.gmres_workspace_bytes(4096, 30, 1)
     # the basis alone: n x (m+2) doubles
     assert small >= 4096 * 32 * 8
@@ -66,6 +69,7 @@ def test_header_constants_match_binding():
     src = open(os.path.join(ROOT, "include", "gmres.h")).read()
     assert int(re.search(r"GMRES_MAX_RESTART (\d+)", src).group(1)) == native.GMRES_MAX_RESTART
     for name, val in (("GMRES_MGS", 0), ("GMRES_MGS_1R", 1), ("GMRES_CGS2", 2), ("GMRES_MGS_1R_IR32", 3),
+                      ("GMRES_MGS_1R_IR16", 4),
                       ("GMRES_ERR_ARG", -1), ("GMRES_ERR_HIP", -2), ("GMRES_ERR_NONFINITE", -3),
                       ("GMRES_ERR_WORKSPACE", -4)):
         assert re.search(rf"{name} = {val}\b", src), name
