@@ -1,5 +1,6 @@
-"""CPU oracle for restarted GMRES(m) with level-1 MGS, one-reduce lagged MGS and
-two-reduce lagged CGS2 (arXiv:1809.05805, Sections II-III).
+"""CPU oracle for restarted GMRES(m) with level-1 MGS, one-reduce lagged MGS,
+two-reduce lagged CGS2, re-orthogonalized CGS (three reductions per step) and
+two-synchronization CGS (arXiv:1809.05805, Sections II-III).
 
 TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the benchmark's
 CPU-baseline leg may import this package. The arithmetic lives in
@@ -21,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle_gmres.c")
 _LIB = os.path.join(_HERE, "liboracle_gmres.so")
 
-SCHEMES = {"mgs": 0, "mgs1r": 1, "cgs2": 2}
+SCHEMES = {"mgs": 0, "mgs1r": 1, "cgs2": 2, "cgs2_3r": 3, "two_synch": 4}
 STATUS = {0: "ok", -1: "invalid argument", -3: "non-finite value"}
 
 

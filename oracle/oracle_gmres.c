@@ -1,7 +1,10 @@
 /*
  * CPU oracle for restarted GMRES(m): level-1 MGS, one-reduce lagged compact-WY
- * MGS, and two-reduce lagged CGS2. Written from Swirydowicz, Langou, Ananthan,
- * Yang, Thomas, "Low synchronization GMRES algorithms" (arXiv:1809.05805).
+ * MGS, two-reduce lagged CGS2, and the two classical Gram-Schmidt baselines the
+ * paper's GPU study runs (re-orthogonalized CGS with three reductions per
+ * step, and Ruhe's two-synchronization CGS). Written from Swirydowicz, Langou,
+ * Ananthan, Yang, Thomas, "Low synchronization GMRES algorithms"
+ * (arXiv:1809.05805).
  *
  * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
  * benchmark's CPU-baseline leg, never by the GPU library. Plain sequential
@@ -263,6 +266,110 @@ static int cycle_mgs(const csr_t* A, const double* b, double* x, int m_eff, doub
 }
 
 /*
+ * Classical Gram-Schmidt cycles on a normalized basis, as in the level-1
+ * listing: V[:,0] = r0 / ||r0||, and step i orthogonalizes w = A v_i against
+ * V[:,0:i+1] with every coefficient taken from the same vector (classical),
+ * then normalizes it with a separate norm reduction.
+ *
+ * ORACLE_CGS2_3R, the first listing of Section II (classical Gram-Schmidt
+ *   with re-orthogonalization) run for two iterations: s = V^T w, r += s,
+ *   w = w - V s, twice; H[0:i+1,i] = r; h_{i+1,i} = ||w||. Three reductions
+ *   per step (two projections and the norm).
+ * ORACLE_TWOSYNCH, the two-synchronization iterated CGS of Section II: one
+ *   reduction gives y = V^T w together with the new row of L, the strictly
+ *   lower part of V^T V = I + L + L^T (l_q = v_q^T v_i for q < i); the
+ *   coefficients are r = T y with T = I - L - L^T on the leading
+ *   (i+1) x (i+1) block (Ruhe's two Gauss-Jacobi iterations folded into one);
+ *   w = w - V r; the second reduction is ||w||. H[0:i+1,i] = r. (Reading of
+ *   the listing's update step, which prints a - Q Q^T a: the update uses the
+ *   corrected coefficients r, which is what the T derivation before it
+ *   produces.)
+ * Parity unpinned for one detail of ORACLE_CGS2_3R: the second pass's
+ * coefficients s are O(eps) relative to the first pass's once V is
+ * orthonormal to working precision, so adding them into H (r += s) changes H
+ * only at the rounding level and no output distinguishes it from leaving them
+ * out. Everything else in both schemes is pinned (same H as MGS, Krylov
+ * minimizer, dense LU, orthogonality bounds that fail without the
+ * re-orthogonalization or without either half of the T correction, reductions
+ * per step).
+ */
+static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, double tol_abs,
+                     double bnorm, int scheme, ws_t* ws, double* hist, int64_t it0,
+                     int64_t* nred, cycle_out* out) {
+  int64_t n = A->n;
+  memset(out, 0, sizeof(*out));
+  ws_reset_small(ws);
+  residual_into_v0(A, b, x, ws);
+  double* v0 = VC(ws, 0);
+  double beta2 = dot(n, v0, v0);
+  (*nred)++;
+  if (!isfinite(beta2)) return ORACLE_ERR_NONFINITE;
+  double beta = sqrt(beta2);
+  out->beta = beta;
+  ws->g[0] = beta;
+  if (beta <= tol_abs) {
+    out->true_conv = 1;
+    return ORACLE_OK;
+  }
+  if (m_eff == 0) return ORACLE_OK;
+  for (int64_t i = 0; i < n; ++i) v0[i] = v0[i] / beta;
+  for (int i = 0; i < m_eff; ++i) {
+    double* w = VC(ws, i + 1);
+    spmv(A, VC(ws, i), w);
+    if (scheme == ORACLE_CGS2_3R) {
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int q = 0; q <= i; ++q) ws->p[q] = dot(n, VC(ws, q), w);
+        (*nred)++;
+        for (int q = 0; q <= i; ++q) {
+          const double* vq = VC(ws, q);
+          double sq = ws->p[q];
+          for (int64_t e = 0; e < n; ++e) w[e] = w[e] - vq[e] * sq;
+          HH(ws, q, i) = HH(ws, q, i) + sq;
+        }
+      }
+    } else {
+      for (int q = 0; q <= i; ++q) ws->c[q] = dot(n, VC(ws, q), w);
+      for (int q = 0; q < i; ++q) LL(ws, i, q) = dot(n, VC(ws, q), VC(ws, i));
+      (*nred)++;
+      for (int a = 0; a <= i; ++a) {
+        double s = ws->c[a];
+        for (int q = 0; q < a; ++q) s -= LL(ws, a, q) * ws->c[q];
+        for (int q = a + 1; q <= i; ++q) s -= LL(ws, q, a) * ws->c[q];
+        ws->r[a] = s;
+      }
+      for (int q = 0; q <= i; ++q) {
+        const double* vq = VC(ws, q);
+        double rq = ws->r[q];
+        for (int64_t e = 0; e < n; ++e) w[e] = w[e] - vq[e] * rq;
+        HH(ws, q, i) = rq;
+      }
+    }
+    double hn2 = dot(n, w, w);
+    (*nred)++;
+    if (!isfinite(hn2)) return ORACLE_ERR_NONFINITE;
+    double hn = sqrt(hn2);
+    HH(ws, i + 1, i) = hn;
+    for (int q = 0; q <= i; ++q)
+      if (!isfinite(HH(ws, q, i))) return ORACLE_ERR_NONFINITE;
+    double gk = rotate_column(ws, i);
+    if (!isfinite(gk)) return ORACLE_ERR_NONFINITE;
+    if (hist) hist[it0 + i] = gk / bnorm;
+    if (hn == 0.0) {
+      out->breakdown = 1;
+      out->j = i + 1;
+      return ORACLE_OK;
+    }
+    for (int64_t e = 0; e < n; ++e) w[e] = w[e] / hn;
+    if (gk <= tol_abs) {
+      out->j = i + 1;
+      return ORACLE_OK;
+    }
+  }
+  out->j = m_eff;
+  return ORACLE_OK;
+}
+
+/*
  * Lagged cycle shared by the one-reduce MGS scheme (level-2 MGS with R
  * normalization lag, inside the one-synchronization GMRES of Section III) and
  * the two-reduce CGS2 scheme (level-2 iterated CGS with the same lag).
@@ -420,7 +527,8 @@ int oracle_gmres_solve(int64_t n, int64_t nnz, const int32_t* row_ptr, const int
   if (j_out) *j_out = 0;
   if (n < 1 || m < 1 || nnz < 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || !b || !x ||
       (nnz > 0 && (!col_idx || !vals)) || !(rtol >= 0.0) || max_iters < 0 ||
-      (scheme != ORACLE_MGS && scheme != ORACLE_MGS_1R && scheme != ORACLE_CGS2))
+      (scheme != ORACLE_MGS && scheme != ORACLE_MGS_1R && scheme != ORACLE_CGS2 &&
+       scheme != ORACLE_CGS2_3R && scheme != ORACLE_TWOSYNCH))
     return ORACLE_ERR_ARG;
   if (row_ptr[0] != 0 || row_ptr[n] != nnz) return ORACLE_ERR_ARG;
   for (int64_t i = 0; i < n; ++i)
@@ -453,6 +561,9 @@ int oracle_gmres_solve(int64_t n, int64_t nnz, const int32_t* row_ptr, const int
     cycle_out co;
     if (scheme == ORACLE_MGS)
       status = cycle_mgs(&A, b, x, m_eff, tol_abs, bnorm, &ws, hist_res, it, &loc.reductions, &co);
+    else if (scheme == ORACLE_CGS2_3R || scheme == ORACLE_TWOSYNCH)
+      status = cycle_cgs(&A, b, x, m_eff, tol_abs, bnorm, scheme, &ws, hist_res, it,
+                         &loc.reductions, &co);
     else
       status = cycle_lagged(&A, b, x, m_eff, tol_abs, bnorm, scheme, &ws, hist_res, it,
                             &loc.reductions, &co);

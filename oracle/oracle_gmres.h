@@ -25,7 +25,11 @@ extern "C" {
 enum {
   ORACLE_MGS = 0,    /* level-1 MGS-GMRES (Algorithm "MGS-GMRES", Section III)     */
   ORACLE_MGS_1R = 1, /* one-synchronization lagged compact-WY MGS (Sections II-III) */
-  ORACLE_CGS2 = 2    /* two-synchronization lagged CGS2 (Section II, level-2 CGS2)  */
+  ORACLE_CGS2 = 2,   /* two-synchronization lagged CGS2 (Section II, level-2 CGS2)  */
+  ORACLE_CGS2_3R = 3,  /* classical Gram-Schmidt with one re-orthogonalization pass:
+                          three reductions per step (Section II, first listing)     */
+  ORACLE_TWOSYNCH = 4  /* iterated classical Gram-Schmidt with two synchronizations,
+                          T = I - L - L^T (Section II, Ruhe's loop invariant)        */
 };
 
 enum {
@@ -48,7 +52,7 @@ typedef struct {
 /*
  * Solve A x = b by restarted GMRES(m).
  *   n, nnz, row_ptr[n+1], col_idx[nnz], vals[nnz]: CSR matrix, int32 indices.
- *   m >= 1: restart length. scheme: ORACLE_MGS / ORACLE_MGS_1R / ORACLE_CGS2.
+ *   m >= 1: restart length. scheme: one of the ORACLE_* schemes above.
  *   b[n]; x[n]: initial guess on entry, solution on exit.
  *   rtol >= 0: stop when the residual 2-norm is <= rtol*||b||_2.
  *   max_iters >= 0: cap on Arnoldi columns.
