@@ -82,7 +82,7 @@ class OracleResult:
     j: int = 0                # columns of the last cycle that completed any
     V: np.ndarray | None = None   # n x (m+2), basis of that cycle
     H: np.ndarray | None = None   # (m+1) x m, unrotated Hessenberg matrix
-    T: np.ndarray | None = None   # (m+2) x (m+2), Malard-Paige T (one-reduce only)
+    T: np.ndarray | None = None   # (m+2) x (m+2), Malard-Paige T (one-reduce), L (cgs2, two_synch)
     g: np.ndarray | None = None   # rotated right-hand side
     S2: np.ndarray | None = None  # (m+1) x m, CGS2 second-pass coefficients
 

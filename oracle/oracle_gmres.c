@@ -505,13 +505,14 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
   }
 }
 
-static void dump_cycle(const ws_t* ws, int j, double* V_out, double* H_out, double* T_out,
-                       double* g_out, double* S2_out, int32_t* j_out) {
+static void dump_cycle(const ws_t* ws, int scheme, int j, double* V_out, double* H_out,
+                       double* T_out, double* g_out, double* S2_out, int32_t* j_out) {
   int m = ws->m;
+  const double* tri = (scheme == ORACLE_CGS2 || scheme == ORACLE_TWOSYNCH) ? ws->L : ws->T;
   if (S2_out) memcpy(S2_out, ws->S2, sizeof(double) * (size_t)(m + 1) * (size_t)m);
   if (V_out) memcpy(V_out, ws->V, sizeof(double) * (size_t)ws->n * (size_t)(m + 2));
   if (H_out) memcpy(H_out, ws->H, sizeof(double) * (size_t)(m + 1) * (size_t)m);
-  if (T_out) memcpy(T_out, ws->T, sizeof(double) * (size_t)(m + 2) * (size_t)(m + 2));
+  if (T_out) memcpy(T_out, tri, sizeof(double) * (size_t)(m + 2) * (size_t)(m + 2));
   if (g_out) memcpy(g_out, ws->g, sizeof(double) * (size_t)(m + 2));
   if (j_out) *j_out = j;
 }
@@ -572,7 +573,7 @@ int oracle_gmres_solve(int64_t n, int64_t nnz, const int32_t* row_ptr, const int
       update_solution(&ws, co.j, x);
       loc.cycles++;
       loc.rel_res_est = fabs(ws.g[co.j]) / bnorm;
-      dump_cycle(&ws, co.j, V_out, H_out, T_out, g_out, S2_out, j_out);
+      dump_cycle(&ws, scheme, co.j, V_out, H_out, T_out, g_out, S2_out, j_out);
     }
     it += co.j;
     if (co.breakdown) loc.breakdown = 1;

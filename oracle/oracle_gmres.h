@@ -61,7 +61,9 @@ typedef struct {
  *   Dump of the last cycle (each nullable):
  *     V_out  n x (m+2), column-major, ld = n: the basis;
  *     H_out  (m+1) x m, column-major, ld = m+1: the unrotated Hessenberg matrix;
- *     T_out  (m+2) x (m+2), column-major: Malard-Paige T (one-reduce only);
+ *     T_out  (m+2) x (m+2), column-major: Malard-Paige T (one-reduce), the
+ *            strictly lower L of V^T V = I + L + L^T (lagged CGS2 and the
+ *            two-synchronization CGS), zero for the other schemes;
  *     g_out  m+2: the rotated right-hand side;
  *     S2_out (m+1) x m, column-major: CGS2's second-pass coefficients s
  *            (zero for the other schemes);

@@ -204,8 +204,8 @@ def test_p7_same_hessenberg_as_mgs(scheme):
 
 
 # ------------------------------------------------- P8 Simonici, Section V-A
-def _s_history(r):
-    if r.T is not None and np.any(r.T):
+def _s_history(r, scheme):
+    if scheme == "mgs1r":
         return D.s_norm_history(r.T, r.j)
     V = r.V[:, : r.j + 1]
     return np.array([D.paige_s_norm(D.t_from_basis(V[:, :k])) for k in range(1, r.j + 2)])
@@ -216,7 +216,7 @@ def test_p8_simonici_bands():
     p = P.simonici(seed=0)
     out = {s: run(p, s, m=100, rtol=0.0, max_iters=100, dump=True) for s in SCHEMES}
     for s in ("mgs", "mgs1r"):
-        S = _s_history(out[s])
+        S = _s_history(out[s], s)
         cross = int(np.argmax(S > 0.5))
         lo, hi = gold["mgs_s_half_crossing_iter"]
         assert lo <= cross <= hi, (s, cross)
@@ -224,7 +224,7 @@ def test_p8_simonici_bands():
         stall = out[s].hist[85:].min()
         lo, hi = gold["mgs_stall_implicit_residual"]
         assert lo <= stall <= hi, (s, stall)
-    S = _s_history(out["cgs2"])
+    S = _s_history(out["cgs2"], "cgs2")
     assert S[:100].max() <= gold["cgs2_s_max_through_iter_100"]
     assert abs(out["cgs2"].hist[-1]) <= gold["cgs2_final_implicit_residual_max"]
     # the two MGS variants behave identically until orthogonality is lost
@@ -252,6 +252,18 @@ def test_p10_malard_paige_t_matches_explicit_gram():
         T_exp = D.t_from_basis(r.V[:, :k])
         assert np.max(np.abs(r.T[:k, :k] - T_exp)) <= 1e-14 * max(1.0, np.abs(T_exp).max())
         assert abs(D.paige_s_norm(r.T[:k, :k]) - D.paige_s_norm(T_exp)) <= 1e-14
+
+
+@pytest.mark.parametrize("scheme", ["cgs2", "two_synch"])
+def test_p10_l_matches_explicit_gram(scheme):
+    """The L the CGS schemes build one row per step is the strictly lower part of
+    the explicit V^T V of their basis (Section II: V^T V = I + L + L^T)."""
+    for p, m in ((P.make_config("cfg1"), 30), (P.make_config("cfg3", N=12), 60)):
+        r = run(p, scheme, m=m, rtol=0.0, max_iters=m, dump=True)
+        k = r.j
+        G = r.V[:, :k].T @ r.V[:, :k]
+        assert np.max(np.abs(np.tril(r.T[:k, :k], -1) - np.tril(G, -1))) <= 1e-15
+        assert np.all(np.triu(r.T[:k, :k]) == 0.0)
 
 
 # ----------------------------------------------- reductions per Arnoldi step
