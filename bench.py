@@ -401,7 +401,7 @@ def main():
     if args.precision_N:
         out["fp32_ir_precision_config"] = precision_config(args)
     if not args.no_baselines:
-        for scheme in ("mgs", "cgs2"):
+        for scheme in ("mgs", "cgs2", "cgs2_3r", "two_synch"):
             sv = GmresSolver(rp, ci, va, m, scheme)
             dt2, it2, r2, _ = time_solves(sv, b, x, rtol, args.max_iters, max(1, min(args.steps, 3)),
                                           1)

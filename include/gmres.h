@@ -17,6 +17,14 @@
  *                 i+2 reductions in iteration i.
  *   GMRES_CGS2    two reductions per step: lagged iterated classical
  *                 Gram-Schmidt (Section II, level-2 CGS2 with normalization lag).
+ *   GMRES_CGS2_3R three reductions per step: classical Gram-Schmidt with one
+ *                 re-orthogonalization pass on a normalized basis (Section II,
+ *                 the first listing, two iterations; the paper's GPU approach
+ *                 "CGS-2 GMRES").
+ *   GMRES_TWO_SYNCH  two reductions per step: iterated classical Gram-Schmidt
+ *                 in Ruhe's two-synchronization form, [V^T w, V^T v_i] in one
+ *                 reduction, coefficients (I - L - L^T) V^T w, then the norm
+ *                 (Section II; the paper's GPU approach "two-synch GMRES").
  *   GMRES_MGS_1R_IR32  the GMRES_MGS_1R step on a float32 basis. Every
  *                 restart computes r = b - A x and ||r|| in float64 from the
  *                 CSR arrays (the float64 master), checks the tolerance on
@@ -67,7 +75,9 @@ typedef enum {
   GMRES_MGS_1R = 1,
   GMRES_CGS2 = 2,
   GMRES_MGS_1R_IR32 = 3,
-  GMRES_MGS_1R_IR16 = 4
+  GMRES_MGS_1R_IR16 = 4,
+  GMRES_CGS2_3R = 5,
+  GMRES_TWO_SYNCH = 6
 } gmres_scheme;
 
 typedef enum {
@@ -144,10 +154,10 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
  *   lower part of V^T V: entry i of a cycle covers its basis vectors
  *   v_0..v_i (the leading (i+1) x (i+1) block of T; 0 for i = 0). Computed on
  *   the host after each cycle from the T (one-reduce MGS) or L (CGS2) the
- *   device built (T for GMRES_MGS_1R_IR32 and _IR16 too), by power iteration to a
- *   relative change of 1e-14; NaN for
- *   GMRES_MGS, which forms neither. It adds host work per cycle; pass NULL
- *   when timing.
+ *   device built (T for GMRES_MGS_1R_IR32 and _IR16 too, L for
+ *   GMRES_TWO_SYNCH), by power iteration to a relative change of 1e-14; NaN
+ *   for GMRES_MGS and GMRES_CGS2_3R, which form neither. It adds host work
+ *   per cycle; pass NULL when timing.
  * Blocks until the solve has finished on the stream. Returns GMRES_OK when the
  * solve ran to convergence or to max_iters (info->converged tells which),
  * GMRES_ERR_NONFINITE if a NaN or Inf appeared (x then holds the last finished
@@ -217,8 +227,9 @@ int gmres_spmv(gmres_ctx* ctx, const double* x, double* y);
  *   T (host, (m+2) x (m+2), column-major): for GMRES_MGS_1R (and _IR32, _IR16) the Malard-Paige
  *     T = (I + L^T)^{-1} built one column per step, whose leading blocks give
  *     Paige's loss-of-orthogonality measure S = I - T (Section II); for
- *     GMRES_CGS2 the strictly lower L with V^T V = I + L + L^T, one row per
- *     step; zeros for GMRES_MGS. Columns 0..j-1 are formed: the cycle's last
+ *     GMRES_CGS2 and GMRES_TWO_SYNCH the strictly lower L with
+ *     V^T V = I + L + L^T, one row per step; zeros for GMRES_MGS and
+ *     GMRES_CGS2_3R. Columns 0..j-1 are formed: the cycle's last
  *     step computes only the norm of column j (and of a cycle that ends on
  *     the tolerance check, column j is formed too);
  *   g (host, m+2): the rotated right-hand side of the least-squares problem

@@ -283,16 +283,18 @@ double spectral_norm(const double* S, int K, int ld, std::vector<double>& x) {
 
 // ||S||_2 with S = I - (I + L^T)^{-1} (Paige's S for the basis v_0..v_K-1),
 // for the leading K x K blocks, K = 1..j, of the cycle that just ended:
-// one-reduce MGS holds T = (I + L^T)^{-1} itself, CGS2 holds L (its rows are
-// the lagged projections l); plain MGS forms neither, so its entries are NaN.
+// one-reduce MGS holds T = (I + L^T)^{-1} itself, CGS2 and the
+// two-synchronization CGS hold L (its rows are the projections l of the newest
+// column); plain MGS and the three-reduction CGS form neither, so their
+// entries are NaN.
 void orth_history(gmres_ctx* c, int j, double* out) {
-  if (c->scheme == kSchemeMgs) {
+  if (c->scheme == kSchemeMgs || c->scheme == kSchemeCgs2r3) {
     for (int q = 0; q < j; ++q) out[q] = NAN;
     return;
   }
   const int ldt = c->m + 2;
   std::vector<double> S((size_t)j * j, 0.0);  // column-major, ld j
-  if (c->scheme != kSchemeCgs2) {
+  if (c->scheme != kSchemeCgs2 && c->scheme != kSchemeTwoSynch) {
     for (int col = 0; col < j; ++col)
       for (int i = 0; i < col; ++i) S[(size_t)col * j + i] = -c->h_T[(size_t)col * ldt + i];
   } else {
@@ -411,20 +413,43 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
   } else {
     TRY(spmv(c, x, b, col(0), nullptr, s));  // V[:,0] = b - A x
   }
-  if (c->scheme == kSchemeMgs) {
+  if (c->scheme == kSchemeMgs || c->scheme == kSchemeCgs2r3 || c->scheme == kSchemeTwoSynch) {
+    // normalized basis: the restart norm first, then per step the
+    // orthogonalization of w = A v_i and a separate norm reduction
     TRY(launch_axpy_dot(ws, rpt, col(0), nullptr, nullptr, col(0), kTailMgsBeta, 0, 0, m_eff, 0.0,
                         G, s));
     TRY(launch_scale(ws, col(0), s));
     for (int i = 0; i < m_eff; ++i) {
       double* w = col(i + 1);
-      TRY(spmv(c, col(i), nullptr, w, ws.st, s));
-      for (int q = 0; q <= i; ++q) {
-        const double* a = q > 0 ? col(q - 1) : nullptr;
-        const double* cf = q > 0 ? ws.H + (size_t)i * ws.ldh + (q - 1) : nullptr;
-        TRY(launch_axpy_dot(ws, rpt, w, a, cf, col(q), kTailMgsH, i, q, m_eff, 0.0, G, s));
+      if (c->scheme == kSchemeMgs) {
+        TRY(spmv(c, col(i), nullptr, w, ws.st, s));
+        for (int q = 0; q <= i; ++q) {
+          const double* a = q > 0 ? col(q - 1) : nullptr;
+          const double* cf = q > 0 ? ws.H + (size_t)i * ws.ldh + (q - 1) : nullptr;
+          TRY(launch_axpy_dot(ws, rpt, w, a, cf, col(q), kTailMgsH, i, q, m_eff, 0.0, G, s));
+        }
+        TRY(launch_axpy_dot(ws, rpt, w, col(i), ws.H + (size_t)i * ws.ldh + i, w, kTailMgsNorm, i, 0,
+                            m_eff, 0.0, G, s));
+      } else if (c->scheme == kSchemeCgs2r3) {
+        // two classical passes: coef = V^T w, w -= V coef; coef2 = V^T w,
+        // w -= V coef2, H[:,i] = coef + coef2; then ||w||
+        TRY(spmv(c, col(i), nullptr, w, ws.st, s));
+        TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, i + 1, i + 1, kWNone, m_eff, kTailCgsPass1, G,
+                         kBasisF64, s, nullptr, nullptr));
+        TRY(launch_maxpy(ws, rpt, i, 2, G, kBasisF64, s, nullptr, nullptr));
+        TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, i + 1, i + 1, kWNone, m_eff, kTailCgs2Second, G,
+                         kBasisF64, s, nullptr, nullptr));
+        TRY(launch_maxpy(ws, rpt, i, 1, G, kBasisF64, s, nullptr, nullptr));
+        TRY(launch_axpy_dot(ws, rpt, w, nullptr, nullptr, w, kTailMgsNorm, i, 0, m_eff, 0.0, G, s));
+      } else {
+        // one reduction for [V^T w, V[:,0:i]^T v_i], coef = (I - L - L^T) y,
+        // w = A v_i - V coef; then ||w||
+        TRY(spmv(c, col(i), nullptr, ws.w, ws.st, s));
+        TRY(launch_fused(c->A, c->sell, c->S, ws, rpt, i, i, kWLoad, m_eff, kTailTwoSynch, G,
+                         kBasisF64, s, nullptr, nullptr));
+        TRY(launch_maxpy(ws, rpt, i, 3, G, kBasisF64, s, nullptr, nullptr));
+        TRY(launch_axpy_dot(ws, rpt, w, nullptr, nullptr, w, kTailMgsNorm, i, 0, m_eff, 0.0, G, s));
       }
-      TRY(launch_axpy_dot(ws, rpt, w, col(i), ws.H + (size_t)i * ws.ldh + i, w, kTailMgsNorm, i, 0,
-                          m_eff, 0.0, G, s));
       TRY(launch_scale(ws, w, s));
     }
   } else {
@@ -483,7 +508,7 @@ int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
 extern "C" {
 
 size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme) {
-  if (scheme < GMRES_MGS || scheme > GMRES_MGS_1R_IR16) return 0;
+  if (scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH) return 0;
   Layout L;
   if (!make_layout(n, m, scheme, &L)) return 0;
   return L.total;
@@ -506,7 +531,7 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   if (!out) return GMRES_ERR_ARG;
   *out = nullptr;
   if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31) || m < 1 ||
-      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_MGS_1R_IR16)
+      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH)
     return GMRES_ERR_ARG;
   if (!is_device_ptr(row_ptr) || !is_device_ptr(workspace) ||
       (nnz > 0 && (!is_device_ptr(col_idx) || !is_device_ptr(vals))))

@@ -1122,6 +1122,66 @@ __device__ void tail_cgs2_second(const Ws& ws, const double* vals, int k) {
   }
 }
 
+// Re-orthogonalized CGS, first projection: vals[2q] = V_q . w for q <= k,
+// the coefficients of the first pass into coef.
+__device__ void tail_cgs_pass1(const Ws& ws, const double* vals, int k) {
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  if (tid == 0) {
+    ws.st->reductions += 1;
+    s_bad = 0;
+  }
+  __syncthreads();
+  for (int i = tid; i <= k; i += bs) {
+    const double s = vals[2 * i];
+    ws.coef[i] = s;
+    if (!isfinite(s)) s_bad = 1;
+  }
+  __syncthreads();
+  if (tid == 0 && s_bad) {
+    ws.st->status = kNonfinite;
+    ws.st->done = 1;
+  }
+}
+
+// Two-synchronization CGS (Ruhe's form of iterated classical Gram-Schmidt),
+// with u = v_i (normalized) and w = A v_i:
+//   vals[2q] = v_q . v_i (q < i): row i of the strictly lower L of V^T V,
+//   vals[2q+1] = v_q . w (q <= i): y;
+// then r = (I - L - L^T) y over the leading (i+1) x (i+1) block is both the
+// MAXPY coefficients and H[0:i+1, i]. L is kept row-major in TT and
+// column-major in T (as for CGS2), so both sums read contiguous entries.
+__device__ void tail_two_synch(const Ws& ws, const double* vals, int i) {
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int ldt = ws.ldt;
+  if (tid == 0) {
+    ws.st->reductions += 1;
+    s_bad = 0;
+  }
+  for (int q = tid; q < i; q += bs) {
+    const double l = vals[2 * q];
+    ws.TT[(size_t)i * ldt + q] = l;
+    ws.T[(size_t)q * ldt + i] = l;
+  }
+  __syncthreads();
+  for (int a = tid; a <= i; a += bs) {
+    double r = vals[2 * a + 1];
+    const double* Lrow = ws.TT + (size_t)a * ldt;  // L(a, q), q < a
+    for (int q = 0; q < a; ++q) r -= Lrow[q] * vals[2 * q + 1];
+    const double* Lcol = ws.T + (size_t)a * ldt;   // L(q, a), q > a
+    for (int q = a + 1; q <= i; ++q) r -= Lcol[q] * vals[2 * q + 1];
+    ws.coef[a] = r;
+    ws.H[(size_t)i * ws.ldh + a] = r;
+    if (!isfinite(r)) s_bad = 1;
+  }
+  __syncthreads();
+  if (tid == 0 && s_bad) {
+    ws.st->status = kNonfinite;
+    ws.st->done = 1;
+  }
+}
+
 // Fused Arnoldi step for the lagged schemes, K = index of the column being
 // normalized (u = V[:,K]). Where w comes from (WSRC):
 //   kWSpmv: w = A u for the tile, computed here (written to ws.w, kept in LDS);
@@ -1343,12 +1403,16 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   pf.snl = scr + 5 * M2;
   pf.k = K;
   pf.scheme = tail == kTailLagged1r ? kSchemeMgs1r : kSchemeCgs2;
-  pf.active = tail != kTailCgs2Second;
+  pf.active = tail == kTailLagged1r || tail == kTailLaggedCgs2;
   pf.staged = K * (K - 1) / 2 <= TR;
   pf.ntri = (pf.active && pf.staged && !norm_only) ? K * (K - 1) / 2 : 0;
   if (!grid_reduce(vals, cnt, ws, tile, G, red, pf)) return;
   if (tail == kTailCgs2Second)
     tail_cgs2_second(ws, vals, K - 1);
+  else if (tail == kTailCgsPass1)
+    tail_cgs_pass1(ws, vals, K - 1);
+  else if (tail == kTailTwoSynch)
+    tail_two_synch(ws, vals, K);
   else
     tail_lagged(ws, vals, scr, K, norm_only, m_eff, pf.scheme, pf);
 }
@@ -1357,7 +1421,9 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
 
 // mode 0 (lagged step k): V[:,k] = u / rho and V[:,k+1] = w / rho - V[:,0:k+1] coef,
 //   where column k enters already normalized;
-// mode 1 (CGS2 second pass): V[:,k+1] -= V[:,0:k+1] coef2.
+// mode 1 (CGS2 second pass): V[:,k+1] -= V[:,0:k+1] coef2;
+// mode 2 (re-orthogonalized CGS, first pass): V[:,k+1] -= V[:,0:k+1] coef;
+// mode 3 (two-synchronization CGS): V[:,k+1] = w - V[:,0:k+1] coef.
 // VT is the basis type; for float32 the coefficients and 1/rho are rounded
 // to float32 and the sums run in float32.
 template <int RPT, typename VT>
@@ -1370,7 +1436,7 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   const int tid = threadIdx.x;
   VT* __restrict__ V = basis_of<VT>(ws);
   const int64_t ldv = ws.ldv;
-  const double* __restrict__ cf = mode == 0 ? ws.coef : ws.coef2;
+  const double* __restrict__ cf = mode == 1 ? ws.coef2 : ws.coef;
   using CT = arith_t<VT>;  // arithmetic type of the basis
   const CT invr = (CT)ws.st->inv_rho;
   // Loads at clamped rows (unconditional, so they are all in flight at once);
@@ -1382,7 +1448,8 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
   uint32_t off[RPT];
   const int64_t rb = row0 < n ? row0 : n - 1;
   const int64_t nvalid = n - rb;
-  const MaxpyCol<VT> src0((mode == 0 ? wbuf_of<VT>(ws) : V + (size_t)(k + 1) * ldv) + rb, nvalid);
+  const MaxpyCol<VT> src0(((mode == 0 || mode == 3) ? wbuf_of<VT>(ws) : V + (size_t)(k + 1) * ldv) + rb,
+                          nvalid);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int64_t r = row0 + i * 256 + tid;

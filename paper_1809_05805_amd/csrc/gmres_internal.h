@@ -16,6 +16,8 @@ constexpr int kSchemeMgs1r = 1;
 constexpr int kSchemeCgs2 = 2;
 constexpr int kSchemeIr32 = 3;  // one-reduce MGS cycles on an FP32 basis, FP64 refinement
 constexpr int kSchemeIr16 = 4;  // the same on a bfloat16 basis (float32 arithmetic)
+constexpr int kSchemeCgs2r3 = 5;   // classical Gram-Schmidt, two passes: 3 reductions per step
+constexpr int kSchemeTwoSynch = 6; // two-synchronization classical Gram-Schmidt
 // Basis element types of the step kernels.
 enum BasisType { kBasisF64 = 0, kBasisF32 = 1, kBasisBf16 = 2 };
 
@@ -32,7 +34,9 @@ enum Tail {
   kTailMgsBeta = 6,     // level-1 MGS restart norm
   kTailMgsH = 7,        // level-1 MGS coefficient h_{q,i}
   kTailMgsNorm = 8,     // level-1 MGS h_{i+1,i}, Givens, flags
-  kTailIrBeta = 9       // FP32-basis cycle: ||r|| of the FP64 restart residual, check, scales
+  kTailIrBeta = 9,      // FP32-basis cycle: ||r|| of the FP64 restart residual, check, scales
+  kTailCgsPass1 = 10,   // re-orthogonalized CGS, first projection: coef = V^T w
+  kTailTwoSynch = 11    // two-synchronization CGS: new row of L, coef = (I - L - L^T) y
 };
 
 // Per-solve state in device memory; the host reads it once per cycle.

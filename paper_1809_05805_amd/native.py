@@ -18,8 +18,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgmres_hip.so")
 
 GMRES_MGS, GMRES_MGS_1R, GMRES_CGS2, GMRES_MGS_1R_IR32, GMRES_MGS_1R_IR16 = 0, 1, 2, 3, 4
+GMRES_CGS2_3R, GMRES_TWO_SYNCH = 5, 6
 SCHEMES = {"mgs": GMRES_MGS, "mgs1r": GMRES_MGS_1R, "cgs2": GMRES_CGS2,
-           "mgs1r_ir32": GMRES_MGS_1R_IR32, "mgs1r_ir16": GMRES_MGS_1R_IR16}
+           "mgs1r_ir32": GMRES_MGS_1R_IR32, "mgs1r_ir16": GMRES_MGS_1R_IR16,
+           "cgs2_3r": GMRES_CGS2_3R, "two_synch": GMRES_TWO_SYNCH}
 GMRES_OK, GMRES_ERR_ARG, GMRES_ERR_HIP, GMRES_ERR_NONFINITE, GMRES_ERR_WORKSPACE = 0, -1, -2, -3, -4
 GMRES_MAX_RESTART = 256
 

@@ -47,7 +47,7 @@ def test_workspace_sizing(lib):
     # the bfloat16 experiment: a 2-byte basis and SpMV output plus the float64 residual
     f16 = native.gmres_workspace_bytes(2_097_152, 50, native.GMRES_MGS_1R_IR16)
     assert 2_097_152 * 53 * 2 + 2_097_152 * 8 <= f16 < 0.6 * f32
-    assert native.gmres_workspace_bytes(100, 30, 5) == 0
+    assert native.gmres_workspace_bytes(100, 30, 7) == 0
     small = native.gmres_workspace_bytes(4096, 30, 1)
     # the basis alone: n x (m+2) doubles
     assert small >= 4096 * 32 * 8
@@ -69,7 +69,7 @@ def test_header_constants_match_binding():
     src = open(os.path.join(ROOT, "include", "gmres.h")).read()
     assert int(re.search(r"GMRES_MAX_RESTART (\d+)", src).group(1)) == native.GMRES_MAX_RESTART
     for name, val in (("GMRES_MGS", 0), ("GMRES_MGS_1R", 1), ("GMRES_CGS2", 2), ("GMRES_MGS_1R_IR32", 3),
-                      ("GMRES_MGS_1R_IR16", 4),
+                      ("GMRES_MGS_1R_IR16", 4), ("GMRES_CGS2_3R", 5), ("GMRES_TWO_SYNCH", 6),
                       ("GMRES_ERR_ARG", -1), ("GMRES_ERR_HIP", -2), ("GMRES_ERR_NONFINITE", -3),
                       ("GMRES_ERR_WORKSPACE", -4)):
         assert re.search(rf"{name} = {val}\b", src), name
