@@ -109,6 +109,21 @@ __device__ inline double wave_sum_last(double v) {
 #ifndef GMRES_PROJ_COLS
 #define GMRES_PROJ_COLS 1
 #endif
+//   GMRES_PROJ_REVERSE  1: the projection streams the basis columns last to
+//                       first, so it starts on the columns the previous MAXPY
+//                       read last and ends on those the next MAXPY reads
+//                       first (both still in the last-level cache); 0: first
+//                       to last. Each column's sums are separate, so the order
+//                       changes no result.
+#ifndef GMRES_PROJ_REVERSE
+#define GMRES_PROJ_REVERSE 1
+#endif
+//   GMRES_SELL_CPOL  cache policy bits of the sliced copy's index and value
+//                    loads (0: default; 2: non-temporal, so streaming A does
+//                    not evict basis columns from the last-level cache).
+#ifndef GMRES_SELL_CPOL
+#define GMRES_SELL_CPOL 2
+#endif
 //   GMRES_SPMV_PIPELINE  1: the fused kernel's SpMV prefetches the next pass (spmv_tile);
 //                        0: passes run one after another (spmv_pass).
 #ifndef GMRES_SPMV_PIPELINE
@@ -149,14 +164,16 @@ struct BufCol {
     r = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0,
                                           (int)(nb < 0x7ffffff8 ? nb : 0x7ffffff8), 0x00020000);
   }
-  __device__ T operator()(uint32_t boff) const {
+  template <int CPOL = 0>
+  __device__ T load(uint32_t boff) const {
     if constexpr (sizeof(T) == 8)
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)boff, 0, 0));
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)boff, 0, CPOL));
     else if constexpr (sizeof(T) == 4)
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, 0));
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, CPOL));
     else
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)boff, 0, 0));
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)boff, 0, CPOL));
   }
+  __device__ T operator()(uint32_t boff) const { return load<0>(boff); }
 };
 
 // The same interface over a plain global load (scalar base + 32-bit offset);
@@ -768,8 +785,8 @@ __device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l,
   for (int t = 0; t < U; ++t) {
     const int j = j0 + t < W ? j0 + t : W - 1;
     const uint32_t e = (uint32_t)(j * 64 + l);
-    c[t] = __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(e * 4u), 0, 0);
-    v[t] = vb(e * (uint32_t)sizeof(SVT));
+    c[t] = __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(e * 4u), 0, GMRES_SELL_CPOL);
+    v[t] = vb.template load<GMRES_SELL_CPOL>(e * (uint32_t)sizeof(SVT));
   }
 }
 
@@ -1285,10 +1302,12 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   // cache hit), which keeps the loads free of branches.
   constexpr int NVC = HAS_SPMV ? 2 * CB : CB;
   const int64_t nvalid = n - rb;  // rows rb .. n-1 of every column
+  // the column at position t of the stream
+  auto colat = [&](int t) { return GMRES_PROJ_REVERSE ? nproj - 1 - t : t; };
   auto load_chunk = [&](VT (&buf)[CB][RPT], int j) {
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      const ProjCol<VT> col(Vt + (size_t)(j + c) * ldv, nvalid);
+      const ProjCol<VT> col(Vt + (size_t)colat(j + c) * ldv, nvalid);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) buf[c][i] = col(rows[i]);
     }
@@ -1318,10 +1337,10 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
 #pragma unroll
         for (int t = 0; t < NVC; ++t) {
           if constexpr (HAS_SPMV) {
-            myred[2 * j + t] = acc[t];
+            myred[2 * colat(j + t / 2) + (t & 1)] = acc[t];
           } else {
-            myred[2 * (j + t)] = acc[t];
-            myred[2 * (j + t) + 1] = 0.0;
+            myred[2 * colat(j + t)] = acc[t];
+            myred[2 * colat(j + t) + 1] = 0.0;
           }
         }
       }
@@ -1331,10 +1350,10 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
       if ((lane & ((64 / NVC) - 1)) == 0) {
         const int vi = lane >> (6 - LOGNV);
         if constexpr (HAS_SPMV) {
-          myred[2 * j + vi] = tot;
+          myred[2 * colat(j + vi / 2) + (vi & 1)] = tot;
         } else {
-          myred[2 * (j + vi)] = tot;
-          myred[2 * (j + vi) + 1] = 0.0;
+          myred[2 * colat(j + vi)] = tot;
+          myred[2 * colat(j + vi) + 1] = 0.0;
         }
       }
     }
@@ -1358,7 +1377,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   }
   for (; j0 < nproj; ++j0) {
     VT vv[RPT];
-    const ProjCol<VT> col(Vt + (size_t)j0 * ldv, nvalid);
+    const ProjCol<VT> col(Vt + (size_t)colat(j0) * ldv, nvalid);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) vv[i] = col(rows[i]);
     CT pl = (CT)0, cl = (CT)0;
@@ -1370,8 +1389,8 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     const double p = wave_sum_last((double)pl);
     const double c = HAS_SPMV ? wave_sum_last((double)cl) : 0.0;
     if (lane == 63) {
-      myred[2 * j0] = p;
-      myred[2 * j0 + 1] = c;
+      myred[2 * colat(j0)] = p;
+      myred[2 * colat(j0) + 1] = c;
     }
   }
   {
