@@ -4,6 +4,12 @@
 // step, the device-coherent partial-sum accesses).
 #pragma once
 
+//   GMRES_BATCH_TAIL_ROWS  rows per wavefront pass in the small dense step's
+//                          T products (fewer rows hold fewer registers live).
+#ifndef GMRES_BATCH_TAIL_ROWS
+#define GMRES_BATCH_TAIL_ROWS 4
+#endif
+
 // ---------------------------------------------------- batched persistent solver
 //
 // A batch is a block-diagonal matrix: system i owns rows [r0, r0 + n) and its
@@ -461,7 +467,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
         pf.ntri = 0;
         pf.issue();
         pf.commit();
-        tail_lagged(ws, vals, scr, k, last, m_eff, kSchemeMgs1r, pf);
+        tail_lagged<1, GMRES_BATCH_TAIL_ROWS>(ws, vals, scr, k, last, m_eff, kSchemeMgs1r, pf);
         if (F32 && k == 0 && tid == 0) st->tol_cycle = tol_abs / beta_cycle;
         __syncthreads();
         if (tid == 0) {

@@ -524,33 +524,33 @@ __device__ inline bool grid_reduce(double* vals, int cnt, const Ws& ws, int slot
 // every lane has 8 independent loads in flight, and one halving butterfly
 // reduces the 8 sums. Loads use clamped indices (M must hold nrows rows of ld
 // entries); the values are masked.
-template <typename Lo, typename Hi>
+template <int NR = 8, typename Lo, typename Hi>
 __device__ void rows_dot(const double* M, int ld, const double* vec, int nrows, int qmax, Lo lo,
                          Hi hi, double* out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i0 = wv * 8; i0 < nrows; i0 += nw * 8) {
-    double acc[8];
+  for (int i0 = wv * NR; i0 < nrows; i0 += nw * NR) {
+    double acc[NR];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+    for (int t = 0; t < NR; ++t) acc[t] = 0.0;
     for (int q0 = 0; q0 < qmax; q0 += 64) {
       const int q = q0 + lane;
       const int qc = q < ld ? q : ld - 1;
-      double v[8];
+      double v[NR];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < NR; ++t) {
         const int i = i0 + t < nrows ? i0 + t : nrows - 1;
         v[t] = M[(size_t)i * ld + qc];
       }
       const double x = vec[q < qmax ? q : 0];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < NR; ++t) {
         const int i = i0 + t;
         acc[t] += (i < nrows && q >= lo(i) && q < hi(i)) ? v[t] * x : 0.0;
       }
     }
-    wave_multi_sum<8>(acc, lane);
-    if ((lane & 7) == 0) {
-      const int i = i0 + (lane >> 3);
+    wave_multi_sum<NR>(acc, lane);
+    if ((lane & (64 / NR - 1)) == 0) {
+      const int i = i0 + lane / (64 / NR);
       if (i < nrows) out[i] = acc[0];
     }
   }
@@ -969,7 +969,7 @@ struct TailPrefetch {
 // With norm_only (the end-of-cycle step) vals[0] = u.u is all there is: only
 // the last Hessenberg entry and its rotation are needed, not a new T column.
 // pf holds the prefetched inputs (H column, rotations, scalars, T or L).
-template <int NT>
+template <int NT, int NR = 8>
 __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool norm_only,
                             int m_eff, int scheme, const TailPrefetch<NT>& pf) {
   __shared__ double s_rho;
@@ -1048,7 +1048,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
       }
     } else {
       // row i of T (entries i..k-1) is contiguous in the row-major copy TT
-      rows_dot(ws.TT, ldt, ell, k, k, [](int i) { return i; }, [&](int) { return k; }, tcol);
+      rows_dot<NR>(ws.TT, ldt, ell, k, k, [](int i) { return i; }, [&](int) { return k; }, tcol);
     }
     __syncthreads();
     for (int i = tid; i < k; i += bs) {
@@ -1091,7 +1091,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
     }
   } else {
     // column i of T (rows 0..i-1) is contiguous in T; row i of L in TT
-    rows_dot(scheme == kSchemeMgs1r ? ws.T : ws.TT, ldt, rr, k, k, [](int) { return 0; },
+    rows_dot<NR>(scheme == kSchemeMgs1r ? ws.T : ws.TT, ldt, rr, k, k, [](int) { return 0; },
              [](int i) { return i; }, hbuf);
   }
   if (tid < 64) {
