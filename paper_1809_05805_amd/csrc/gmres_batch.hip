@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -239,6 +240,14 @@ int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, 
   B.bar = (unsigned*)(base + L.o_bar);
   B.queue = (unsigned*)(base + L.o_queue);
   B.out = (BatchOut*)(base + L.o_out);
+  // polls of a team barrier before a part gives up: 2^23 (about half a
+  // minute at least); GMRES_BATCH_SPIN_LIMIT lowers it so that tests can
+  // exercise the give-up path with every kernel still ending normally
+  B.spin_limit = 1u << 23;
+  if (const char* e = getenv("GMRES_BATCH_SPIN_LIMIT")) {
+    const long v = atol(e);
+    if (v >= 0 && v < (1l << 23)) B.spin_limit = (uint32_t)v;
+  }
   bt->nsys = nsys;
   bt->m = m;
   bt->scheme = scheme;

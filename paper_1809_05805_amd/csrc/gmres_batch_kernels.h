@@ -87,15 +87,17 @@ struct Team {
   unsigned target;   // barrier count this part waits for next
   int nparts, part, P, buf;
   bool failed;       // a wait ran out: the solve of this entry is abandoned
+  uint32_t spins;    // polls a team barrier may take before it gives up
   int64_t lo, hi;    // own rows (local indices)
 };
 
 // All parts of the team have arrived: every store made before it by any
 // part (completed, agent-scope where another part reads it) is visible.
-// The wait is bounded (short sleeps first, then long ones, at least about
-// half a minute in all): a team that cannot assemble ends its solve with a
-// failure instead of holding the GPU. Returns false (and sets failed, the
-// same in every thread) when the wait ran out or failed was already set.
+// The wait is bounded by `spins` polls (short sleeps for the first 4096, then
+// long ones; the default limit is at least about half a minute in all): a team
+// that cannot assemble ends its solve with a failure instead of holding the
+// GPU. Returns false (and sets failed, the same in every thread) when the wait
+// ran out or failed was already set.
 __device__ inline bool team_sync(Team& tm) {
   __shared__ int s_ok;
   if (tm.nparts == 1) {
@@ -111,14 +113,14 @@ __device__ inline bool team_sync(Team& tm) {
     int ok = 1;
     for (uint32_t spin = 0;; ++spin) {
       if (__hip_atomic_load(tm.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= tm.target) break;
-      if (spin < 4096) {
-        __builtin_amdgcn_s_sleep(1);
-      } else if (spin < (1u << 23)) {
-        __builtin_amdgcn_s_sleep(127);
-      } else {
+      if (spin >= tm.spins) {
         ok = 0;
         break;
       }
+      if (spin < 4096)
+        __builtin_amdgcn_s_sleep(1);
+      else
+        __builtin_amdgcn_s_sleep(127);
     }
     s_ok = ok;
   }
@@ -228,6 +230,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
   tm.P = P;
   tm.buf = 0;
   tm.failed = false;
+  tm.spins = B.spin_limit;
   {
     const int64_t per = (n + K.nparts - 1) / K.nparts;
     const int64_t chunk = (per + 63) / 64 * 64;

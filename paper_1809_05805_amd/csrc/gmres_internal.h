@@ -144,6 +144,7 @@ struct Batch {
   double* x;
   double rtol;
   int64_t max_iters;
+  uint32_t spin_limit;       // polls of a team barrier before the team gives up
 };
 
 // Doubles of one system's small workspace: H and R ((m+1) m each), T and TT

@@ -300,3 +300,41 @@ def test_full_batch(scheme):
             assert abs(int(info["iters"][i]) - o.iters) <= 1
         assert rel(xi, o.x) <= 10 * 1e4 * TOL
     del A
+
+
+def test_team_wait_limit():
+    """A team whose parts stop waiting gives up with GMRES_ERR_HIP for that
+    system, and every kernel still ends. The wait limit is forced to zero polls
+    from the host (GMRES_BATCH_SPIN_LIMIT, read at create), so a part that
+    arrives before its partners gives up at once; one-part systems are not
+    affected."""
+    import os
+
+    import torch
+
+    from paper_1809_05805_amd import native
+
+    bp = SMALL
+    log("batch team wait limit")
+    os.environ["GMRES_BATCH_SPIN_LIMIT"] = "0"
+    try:
+        s = solver(bp)
+    finally:
+        del os.environ["GMRES_BATCH_SPIN_LIMIT"]
+    s.set_config(256, 0, 1, 256)
+    bt = torch.from_numpy(bp.b).cuda()
+    x = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+    rc, info = s.solve(bt, x, TOL, 20000, check=False)
+    torch.cuda.synchronize()
+    assert rc == native.GMRES_ERR_HIP
+    sizes = np.diff(bp.row_off)
+    teams = sizes > 256
+    assert np.all(np.isin(info["status"][teams], (0, native.GMRES_ERR_HIP)))
+    assert np.any(info["status"][teams] == native.GMRES_ERR_HIP)
+    xs = x.cpu().numpy()
+    for i in np.nonzero(~teams)[0]:
+        assert info["status"][i] == 0 and info["converged"][i] == 1
+        assert true_rel(bp, i, xs) <= TOL * (1 + 1e-6)
+    # the default limit: the same context shape solves normally
+    rc, info = run(bp, config=(256, 0, 1, 256))[:2]
+    assert rc == 0 and np.all(info["converged"] == 1)
