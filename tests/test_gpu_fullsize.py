@@ -28,7 +28,7 @@ def cfg2():
     return P.make_config("cfg2")
 
 
-@pytest.mark.parametrize("scheme", ["mgs1r", "mgs", "cgs2"])
+@pytest.mark.parametrize("scheme", ["mgs1r", "mgs", "cgs2", "cgs2_3r", "two_synch"])
 def test_cfg2_fixed_budget_cycle(cfg2, scheme):
     p = cfg2
     log(f"cfg2 fixed-budget cycle {scheme} n={p.n} m={p.m}")
@@ -57,6 +57,25 @@ def test_cfg2_solve_to_tolerance(cfg2):
     h = r.hist
     inside = [i for i in range(1, len(h)) if i % p.m != 0]
     assert np.all(h[inside] <= h[np.array(inside) - 1] * (1 + 1e-12))
+
+
+@pytest.mark.parametrize("scheme", ["mgs1r_ir32", "mgs1r_ir16"])
+def test_cfg2_reduced_precision_basis_to_tolerance(cfg2, scheme):
+    """The float32- and bfloat16-basis refinement at full size: the float64
+    residual recomputed here meets 1e-10 and the solution is as close to x_true
+    as the float64 solve's (the error is set by the stopping point, not by the
+    basis)."""
+    p = cfg2
+    log(f"cfg2 {scheme} to 1e-10")
+    g = gpu_run(p, scheme)
+    r = g["res"]
+    assert r.status == 0 and r.converged
+    res_cpu = np.linalg.norm(p.b - p.scipy() @ g["x"]) / np.linalg.norm(p.b)
+    assert res_cpu <= p.rtol * (1 + 1e-6)
+    assert abs(res_cpu - r.rel_res_true) <= 1e-3 * res_cpu
+    err = rel(g["x"], p.x_true)
+    log(f"  iters {r.iters}, rel res {res_cpu:.2e}, error vs x_true {err:.2e}")
+    assert err <= 1e-6
 
 
 def test_cfg3_orthogonality_curve():
