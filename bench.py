@@ -184,6 +184,47 @@ def precision_config(args):
     return out
 
 
+def orth_study(args):
+    """Stability study: loss of orthogonality per Arnoldi step for every
+    Gram-Schmidt scheme on the row-scaled 27-point system (rows scaled
+    log-uniformly over eight decades, kappa ~ 1e8): one 100-column cycle from
+    x0 = 0 per scheme; ||I - V_k^T V_k||_2 of the GPU's own basis for the
+    leading k columns (Gram matrix formed on the GPU, norms on the host), and
+    Paige's ||S_k||_2 from the T or L the device built, where the scheme forms one."""
+    import numpy as np
+    import torch
+
+    from paper_1809_05805_amd import problems
+    from paper_1809_05805_amd.native import GmresSolver
+
+    m = 100
+    p = problems.make_config("cfg3", N=args.orth_study_N)
+    dev = torch.device("cuda:0")
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (p.row_ptr, p.col_idx, p.vals))
+    b = torch.from_numpy(p.b).to(dev)
+    out = {"workload": f"27-point stencil {args.orth_study_N}^3, off-diagonals N(0,1)/27, rows scaled "
+                       "by 10^(8 U(0,1)); one GMRES(100) cycle from x0 = 0", "n": p.n, "m": m}
+    marks = [10, 20, 40, 60, 80, 100]
+    for scheme in ("mgs", "mgs1r", "cgs2", "cgs2_3r", "two_synch"):
+        s = GmresSolver(rp, ci, va, m, scheme)
+        x = torch.zeros(p.n, dtype=torch.float64, device=dev)
+        r = s.solve(b, x, 0.0, m, orth=True)
+        _, _, _, j = s.last_cycle()
+        V = s.basis()[:, :j]
+        G = (V.t() @ V).cpu().numpy()
+        loss = [float(np.linalg.norm(np.eye(k) - G[:k, :k], 2)) for k in range(1, j + 1)]
+        rec = {"columns": j, "orth_loss_at": {str(k): loss[k - 1] for k in marks if k <= j},
+               "relative_residual_after_cycle": r.rel_res_true}
+        if r.orth is not None and np.all(np.isfinite(r.orth)):
+            rec["paige_s_at"] = {str(k): float(r.orth[k - 1]) for k in marks if k <= len(r.orth)}
+        out[scheme] = rec
+        log(f"orth study {scheme}: ||I - V^T V|| at k=10..100: "
+            + " ".join(f"{loss[k - 1]:.1e}" for k in marks if k <= j))
+        s.close()
+        del V, x
+    return out
+
+
 BATCH_WORKLOAD = ("512 independent 2D 5-point upwind convection-diffusion systems, grid side "
                   "U{32..256} (n 1,024-65,536), Peclet U(1,100), wind angle U(0,2pi), GMRES(30) to 1e-10")
 
@@ -311,6 +352,9 @@ def main():
                     help="first run one plain device copy of this many MiB (a reference kernel "
                          "for hardware byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solver section")
+    ap.add_argument("--orth-study-N", type=int, default=0,
+                    help="also run the loss-of-orthogonality study of every scheme on the row-scaled "
+                         "27-point N^3 system (100: its full size)")
     ap.add_argument("--no-batch-autotune", action="store_true",
                     help="batched solves with the default launch configuration")
     ap.add_argument("--batch-systems", type=int, default=512)
@@ -415,6 +459,8 @@ def main():
         out["speedup_vs_mgs"] = round(out["value"] / out["mgs_baseline"]["iters_per_s"], 3)
     if not args.no_batch:
         out["batch"] = batch_result(args)
+    if args.orth_study_N:
+        out["orth_study"] = orth_study(args)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, one restart cycle ...")
         out["cpu_baseline"] = cpu_baseline(p, m)
