@@ -338,3 +338,20 @@ def test_team_wait_limit():
     # the default limit: the same context shape solves normally
     rc, info = run(bp, config=(256, 0, 1, 256))[:2]
     assert rc == 0 and np.all(info["converged"] == 1)
+
+
+@pytest.mark.parametrize("bs", [256, 1024])
+def test_long_restart(bs):
+    """m = 100 (the per-wavefront sums and the small dense arrays at their
+    largest in these tests), one-part systems and teams, against the oracle
+    after 120 steps."""
+    bp = P.make_batch(nsys=6, seed=7, side_lo=12, side_hi=30, m=100, rtol=TOL)
+    log(f"batch long restart bs={bs}")
+    for part_rows in (0, 256):
+        rc, info, x, _ = run(bp, rtol=0.0, max_iters=120, config=(bs, 0, 1, part_rows), m=100)
+        assert rc == 0
+        for i in range(bp.nsys):
+            p = bp.system(i)
+            o = oracle_run(p, "mgs1r", m=100, rtol=0.0, max_iters=120, dump=False)
+            assert info["iters"][i] == o.iters == 120
+            assert rel(x[bp.row_off[i]: bp.row_off[i + 1]], o.x) <= TOL, (i, part_rows)
