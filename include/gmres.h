@@ -320,8 +320,10 @@ enum { GMRES_BATCH_ORDER_NATURAL = 0, GMRES_BATCH_ORDER_LARGEST_FIRST = 1 };
  * 2^28 rows, total below 2^31), restart m (1..GMRES_MAX_RESTART) and scheme
  * GMRES_MGS_1R or GMRES_MGS_1R_IR32; 0 if the arguments are invalid. Per
  * system: the basis (m+1 columns of n_i rounded up to 64, float64 or
- * float32), the Hessenberg, T and Givens arrays and a state record; for the
- * batch: the SpMV output, a float64 copy of x for the autotuner, and for
+ * float32), a barrier counter and a result record; per possible row part of
+ * a system (min(16, ceil(n_i / 256)) of them): the Hessenberg, T and Givens
+ * arrays, a state record and two rows of reduction partials; for the batch:
+ * the queue, the SpMV output, a float64 copy of x for the autotuner, and for
  * GMRES_MGS_1R_IR32 the float64 restart residual.
  */
 size_t gmres_batch_workspace_bytes(int32_t nsys, const int64_t* row_off, int32_t m, int32_t scheme);
