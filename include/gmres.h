@@ -1,9 +1,10 @@
 /*
- * gmres.h - restarted GMRES(m) on one AMD MI355X (gfx950) with three
+ * gmres.h - restarted GMRES(m) on one AMD MI355X (gfx950) with five
  * Gram-Schmidt schemes for the Arnoldi process, after Swirydowicz, Langou,
  * Ananthan, Yang, Thomas, "Low synchronization GMRES algorithms"
- * (arXiv:1809.05805), in FP64, and the one-reduce scheme also on an FP32
- * basis inside FP64 iterative refinement:
+ * (arXiv:1809.05805), in FP64; the one-reduce scheme also on a float32 or
+ * bfloat16 basis inside FP64 iterative refinement, and for many independent
+ * systems in one persistent launch (the gmres_batch_* calls below):
  *
  *   GMRES_MGS_1R  one global reduction per Arnoldi step: the level-2 MGS in
  *                 compact WY form with lagged normalization of R's diagonal
@@ -105,7 +106,7 @@ typedef struct {
 /*
  * Bytes of device workspace gmres_create needs for n rows, restart m and the
  * given scheme (0 if the arguments are invalid). The workspace holds the
- * basis V (n x (m+2), column-major, leading dimension n rounded up to 32),
+ * basis V (n x (m+2), column-major, leading dimension n rounded up to 64),
  * the Hessenberg and T matrices, Givens data and reduction scratch.
  */
 size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
