@@ -2,8 +2,11 @@
 //
 // Many independent systems, the diagonal blocks of one CSR matrix, are solved
 // by restarted one-reduce GMRES(m) (the lagged compact-WY MGS step of
-// Section III) in a single persistent launch: workgroups take systems from a
-// device-side queue and run each system's whole solve. Everything a solve
+// Section III) in a single persistent launch: workgroups take entries from a
+// device-side queue, each a whole system or one row part of a larger one
+// (a team), and run that entry's whole solve. The host side builds the queue
+// for a configuration (team sizes, order, grid), times configurations for the
+// autotuner and captures the launch into a HIP graph. Everything a solve
 // needs lives in the caller's workspace, laid out here once at create.
 #include "gmres.h"
 #include "gmres_internal.h"
