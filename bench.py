@@ -190,7 +190,9 @@ def orth_study(args):
     log-uniformly over eight decades, kappa ~ 1e8): one 100-column cycle from
     x0 = 0 per scheme; ||I - V_k^T V_k||_2 of the GPU's own basis for the
     leading k columns (Gram matrix formed on the GPU, norms on the host), and
-    Paige's ||S_k||_2 from the T or L the device built, where the scheme forms one."""
+    Paige's ||S_k||_2 from the T or L the device built, where the scheme forms
+    one. Each scheme's cycle is also timed (after a warm-up, without the
+    host-side S history)."""
     import numpy as np
     import torch
 
@@ -208,17 +210,26 @@ def orth_study(args):
     for scheme in ("mgs", "mgs1r", "cgs2", "cgs2_3r", "two_synch"):
         s = GmresSolver(rp, ci, va, m, scheme)
         x = torch.zeros(p.n, dtype=torch.float64, device=dev)
+        s.solve(b, x, 0.0, m)  # warm-up, then one timed cycle without the host-side S history
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(b, x, 0.0, m)
+        dt = time.perf_counter() - t0
+        x.zero_()
         r = s.solve(b, x, 0.0, m, orth=True)
         _, _, _, j = s.last_cycle()
         V = s.basis()[:, :j]
         G = (V.t() @ V).cpu().numpy()
         loss = [float(np.linalg.norm(np.eye(k) - G[:k, :k], 2)) for k in range(1, j + 1)]
         rec = {"columns": j, "orth_loss_at": {str(k): loss[k - 1] for k in marks if k <= j},
-               "relative_residual_after_cycle": r.rel_res_true}
+               "relative_residual_after_cycle": r.rel_res_true,
+               "iters_per_s": round(r.iters / dt, 1), "ms_per_cycle": round(dt * 1e3, 2),
+               "reductions": r.reductions}
         if r.orth is not None and np.all(np.isfinite(r.orth)):
             rec["paige_s_at"] = {str(k): float(r.orth[k - 1]) for k in marks if k <= len(r.orth)}
         out[scheme] = rec
-        log(f"orth study {scheme}: ||I - V^T V|| at k=10..100: "
+        log(f"orth study {scheme}: {r.iters / dt:.0f} iters/s, ||I - V^T V|| at k=10..100: "
             + " ".join(f"{loss[k - 1]:.1e}" for k in marks if k <= j))
         s.close()
         del V, x
