@@ -152,7 +152,7 @@ def precision_config(args):
     from paper_1809_05805_amd.native import GmresSolver
 
     t0 = time.perf_counter()
-    p = problems.make_config("cfg2", N=args.precision_N)
+    p = problems.make_config("convdiff3d", N=args.precision_N)
     log(f"precision config n={p.n} nnz={p.nnz} built in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     rp, ci, va = (torch.from_numpy(a).to(dev) for a in (p.row_ptr, p.col_idx, p.vals))
@@ -200,7 +200,7 @@ def orth_study(args):
     from paper_1809_05805_amd.native import GmresSolver
 
     m = 100
-    p = problems.make_config("cfg3", N=args.orth_study_N)
+    p = problems.make_config("stencil27", N=args.orth_study_N)
     dev = torch.device("cuda:0")
     rp, ci, va = (torch.from_numpy(a).to(dev) for a in (p.row_ptr, p.col_idx, p.vals))
     b = torch.from_numpy(p.b).to(dev)
@@ -384,7 +384,7 @@ def main():
     from paper_1809_05805_amd import problems
     from paper_1809_05805_amd.native import GmresSolver
 
-    p = problems.make_config("cfg2", N=args.N)
+    p = problems.make_config("convdiff3d", N=args.N)
     n, nnz, m, rtol = p.n, p.nnz, p.m, p.rtol
     log(f"workload n={n} nnz={nnz} m={m} rtol={rtol}")
     dev = torch.device("cuda:0")

@@ -201,9 +201,9 @@ def random_dense(n: int, seed: int = 0, shift: float = 4.0) -> Problem:
 
 # name -> (config id, description)
 CONFIGS = {
-    "cfg1": (1, "2D 5-point upwind convection-diffusion, 64^2, wind (1,1), Pe 10, m=30, rtol 1e-8"),
-    "cfg2": (2, "3D 7-point upwind convection-diffusion, 128^3, wind (1,0.5,0.25), Pe 50, m=50, rtol 1e-10"),
-    "cfg3": (3, "3D 27-point random stencil, 100^3, rows scaled log-uniform in [1,1e8], m=100, rtol 1e-10"),
+    "convdiff2d": (1, "2D 5-point upwind convection-diffusion, 64^2, wind (1,1), Pe 10, m=30, rtol 1e-8"),
+    "convdiff3d": (2, "3D 7-point upwind convection-diffusion, 128^3, wind (1,0.5,0.25), Pe 50, m=50, rtol 1e-10"),
+    "stencil27": (3, "3D 27-point random stencil, 100^3, rows scaled log-uniform in [1,1e8], m=100, rtol 1e-10"),
 }
 
 
@@ -212,12 +212,12 @@ def make_config(name: str, seed: int = 0, N: int | None = None) -> Problem:
     if name not in CONFIGS:
         raise KeyError(f"unknown config {name!r}; known: {sorted(CONFIGS)}")
     cid = CONFIGS[name][0]
-    if name == "cfg1":
+    if name == "convdiff2d":
         N = 64 if N is None else N
         A = convdiff(N, 2, (1.0, 1.0), 10.0)
         rp, ci, va = csr_from_scipy(A)
         m, rtol = 30, 1e-8
-    elif name == "cfg2":
+    elif name == "convdiff3d":
         N = 128 if N is None else N
         A = convdiff(N, 3, (1.0, 0.5, 0.25), 50.0)
         rp, ci, va = csr_from_scipy(A)

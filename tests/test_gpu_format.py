@@ -42,9 +42,9 @@ def test_format_choice():
     import scipy.sparse as sp
 
     cases = {
-        "cfg1": (P.make_config("cfg1"), "sell64"),                  # 5-point rows
-        "cfg2_24": (P.make_config("cfg2", N=24), "sell64"),         # 7-point rows
-        "cfg3_12": (P.make_config("cfg3", N=12), "sell64"),         # 27-point rows
+        "convdiff2d": (P.make_config("convdiff2d"), "sell64"),                  # 5-point rows
+        "convdiff3d_24": (P.make_config("convdiff3d", N=24), "sell64"),         # 7-point rows
+        "stencil27_12": (P.make_config("stencil27", N=12), "sell64"),         # 27-point rows
         "dense50": (P.random_dense(50, seed=3), "csr"),             # one slice, 14 padding rows
     }
     A = sp.csr_matrix(sp.random(3000, 3000, density=0.003, random_state=4) + sp.identity(3000))
@@ -65,7 +65,7 @@ def test_refresh_matrix(fmt):
     """Scale two rows' values in place: after refresh the solve is the one on the new matrix."""
     import torch
 
-    p = P.make_config("cfg1", N=40)
+    p = P.make_config("convdiff2d", N=40)
     s, (rp, ci, va) = solver(p, m=20, fmt=fmt)
     log(f"refresh {fmt}")
     b = torch.from_numpy(p.b).cuda()
@@ -90,7 +90,7 @@ def test_refresh_refuses_bad_structure():
     from paper_1809_05805_amd import native
     from paper_1809_05805_amd.native import GmresError
 
-    p = P.make_config("cfg1", N=40)
+    p = P.make_config("convdiff2d", N=40)
     s, (rp, ci, va) = solver(p, fmt="sell")
     log("refresh bad structure")
     bad = p.col_idx.copy()
@@ -123,7 +123,7 @@ def test_sell_small_and_one_row(scheme):
     g = gpu_run(p, scheme, fmt="sell")
     assert g["solver"].format()[0] == "sell64"
     assert g["res"].converged and abs(g["x"][0] - 2.0) <= 1e-15
-    p = P.make_config("cfg1", N=5)  # n = 25
+    p = P.make_config("convdiff2d", N=5)  # n = 25
     g = gpu_run(p, scheme, m=10, rtol=0.0, max_iters=10, fmt="sell")
     o = oracle_run(p, scheme, m=10, rtol=0.0, max_iters=10)
     assert g["res"].iters == o.iters
@@ -136,7 +136,7 @@ def test_storage_calls():
 
     from paper_1809_05805_amd import native
 
-    p = P.make_config("cfg1", N=33)  # n = 1089: 18 slices, the last one ragged
+    p = P.make_config("convdiff2d", N=33)  # n = 1089: 18 slices, the last one ragged
     rp, ci, va = (torch.from_numpy(a).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
     m = 10
     need = native.gmres_workspace_bytes(p.n, m, native.GMRES_MGS_1R)

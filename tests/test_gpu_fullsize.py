@@ -24,14 +24,14 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def cfg2():
-    return P.make_config("cfg2")
+def convdiff3d():
+    return P.make_config("convdiff3d")
 
 
 @pytest.mark.parametrize("scheme", ["mgs1r", "mgs", "cgs2", "cgs2_3r", "two_synch"])
-def test_cfg2_fixed_budget_cycle(cfg2, scheme):
-    p = cfg2
-    log(f"cfg2 fixed-budget cycle {scheme} n={p.n} m={p.m}")
+def test_convdiff3d_fixed_budget_cycle(convdiff3d, scheme):
+    p = convdiff3d
+    log(f"convdiff3d fixed-budget cycle {scheme} n={p.n} m={p.m}")
     g = gpu_run(p, scheme, rtol=0.0, max_iters=p.m)
     o = oracle_run(p, scheme, rtol=0.0, max_iters=p.m)
     r = g["res"]
@@ -42,9 +42,9 @@ def test_cfg2_fixed_budget_cycle(cfg2, scheme):
     assert rel(g["H"], o.H) <= 1e-9
 
 
-def test_cfg2_solve_to_tolerance(cfg2):
-    p = cfg2
-    log("cfg2 one-reduce to 1e-10")
+def test_convdiff3d_solve_to_tolerance(convdiff3d):
+    p = convdiff3d
+    log("convdiff3d one-reduce to 1e-10")
     g = gpu_run(p, "mgs1r")
     r = g["res"]
     assert r.converged and r.rel_res_true <= p.rtol
@@ -60,13 +60,13 @@ def test_cfg2_solve_to_tolerance(cfg2):
 
 
 @pytest.mark.parametrize("scheme", ["mgs1r_ir32", "mgs1r_ir16"])
-def test_cfg2_reduced_precision_basis_to_tolerance(cfg2, scheme):
+def test_convdiff3d_reduced_precision_basis_to_tolerance(convdiff3d, scheme):
     """The float32- and bfloat16-basis refinement at full size: the float64
     residual recomputed here meets 1e-10 and the solution is as close to x_true
     as the float64 solve's (the error is set by the stopping point, not by the
     basis)."""
-    p = cfg2
-    log(f"cfg2 {scheme} to 1e-10")
+    p = convdiff3d
+    log(f"convdiff3d {scheme} to 1e-10")
     g = gpu_run(p, scheme)
     r = g["res"]
     assert r.status == 0 and r.converged
@@ -78,7 +78,7 @@ def test_cfg2_reduced_precision_basis_to_tolerance(cfg2, scheme):
     assert err <= 1e-6
 
 
-def test_cfg3_orthogonality_curve():
+def test_stencil27_orthogonality_curve():
     """Paige's ||S_k||_2 per iteration on the row-scaled 27-point system (kappa ~ 1e8).
 
     The curve's magnitude is set by the rounding of the inner products: rows
@@ -89,8 +89,8 @@ def test_cfg3_orthogonality_curve():
     oracle, stay within the O(eps) kappa bound for MGS, grow monotonically
     (leading-block norms of one triangular matrix), and agree on x and H.
     """
-    p = P.make_config("cfg3", N=40)
-    log(f"cfg3 N=40 orthogonality n={p.n}")
+    p = P.make_config("stencil27", N=40)
+    log(f"stencil27 N=40 orthogonality n={p.n}")
     g = gpu_run(p, "mgs1r", m=100, rtol=0.0, max_iters=100)
     o = oracle_run(p, "mgs1r", m=100, rtol=0.0, max_iters=100)
     # the cycle's last step forms only a norm, so T has columns 0..j-1

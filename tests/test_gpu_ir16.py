@@ -38,9 +38,9 @@ def _torch_cuda():
 
 
 CASES = {
-    "cfg1": P.make_config("cfg1"),
-    "cfg1_ragged": P.make_config("cfg1", N=37),
-    "cfg2_24": P.make_config("cfg2", N=24),
+    "convdiff2d": P.make_config("convdiff2d"),
+    "convdiff2d_ragged": P.make_config("convdiff2d", N=37),
+    "convdiff3d_24": P.make_config("convdiff3d", N=24),
 }
 
 
@@ -49,7 +49,7 @@ def true_rel_res(p, x):
 
 
 @pytest.mark.parametrize("fmt", ["sell", "csr"])
-@pytest.mark.parametrize("case", ["cfg1", "cfg1_ragged", "cfg2_24"])
+@pytest.mark.parametrize("case", ["convdiff2d", "convdiff2d_ragged", "convdiff3d_24"])
 def test_ir16_to_tolerance(case, fmt):
     p = CASES[case]
     rtol = 1e-10
@@ -72,7 +72,7 @@ def test_ir16_to_tolerance(case, fmt):
     assert r.iters <= 3 * f64.iters + m
 
 
-@pytest.mark.parametrize("case", ["cfg1", "cfg2_24"])
+@pytest.mark.parametrize("case", ["convdiff2d", "convdiff3d_24"])
 def test_ir16_one_cycle_vs_fp64_oracle(case):
     p = CASES[case]
     m = min(p.m, 40)
@@ -89,7 +89,7 @@ def test_ir16_one_cycle_vs_fp64_oracle(case):
 
 
 def test_ir16_deterministic():
-    p = CASES["cfg2_24"]
+    p = CASES["convdiff3d_24"]
     a = gpu_run(p, "mgs1r_ir16", m=30, rtol=1e-10)
     b = gpu_run(p, "mgs1r_ir16", m=30, rtol=1e-10)
     assert a["res"].iters == b["res"].iters
@@ -102,7 +102,7 @@ def test_ir16_errors_and_edges():
     from paper_1809_05805_amd import native
     from paper_1809_05805_amd.native import GmresError
 
-    p = P.make_config("cfg1", N=16)
+    p = P.make_config("convdiff2d", N=16)
     b = p.b.copy()
     b[3] = np.nan
     g = gpu_run(p, "mgs1r_ir16", b=b)

@@ -31,10 +31,10 @@ EPS32 = float(np.finfo(np.float32).eps)
 
 def cases():
     return {
-        "cfg1": P.make_config("cfg1"),
-        "cfg1_ragged": P.make_config("cfg1", N=37),
-        "cfg2_24": P.make_config("cfg2", N=24),
-        "cfg3_12": P.make_config("cfg3", N=12),
+        "convdiff2d": P.make_config("convdiff2d"),
+        "convdiff2d_ragged": P.make_config("convdiff2d", N=37),
+        "convdiff3d_24": P.make_config("convdiff3d", N=24),
+        "stencil27_12": P.make_config("stencil27", N=12),
     }
 
 
@@ -57,7 +57,7 @@ def true_rel_res(p, x):
 
 
 @pytest.mark.parametrize("fmt", ["sell", "csr"])
-@pytest.mark.parametrize("case", ["cfg1", "cfg1_ragged", "cfg2_24"])
+@pytest.mark.parametrize("case", ["convdiff2d", "convdiff2d_ragged", "convdiff3d_24"])
 def test_ir32_to_tolerance(case, fmt):
     # (the row-scaled 27-point system, kappa ~ 3e9, is left out: restarted
     # GMRES(40) stagnates on it above 1e-10 in float64 as well)
@@ -81,7 +81,7 @@ def test_ir32_to_tolerance(case, fmt):
     assert r.iters <= int(np.ceil(1.34 * f64.iters)) + m
 
 
-@pytest.mark.parametrize("case", ["cfg1", "cfg2_24", "cfg3_12"])
+@pytest.mark.parametrize("case", ["convdiff2d", "convdiff3d_24", "stencil27_12"])
 def test_ir32_one_cycle_vs_fp64_oracle(case):
     p = CASES[case]
     m = min(p.m, 40)
@@ -107,7 +107,7 @@ def test_ir32_one_cycle_vs_fp64_oracle(case):
 
 
 def test_ir32_deterministic():
-    p = CASES["cfg2_24"]
+    p = CASES["convdiff3d_24"]
     a = gpu_run(p, "mgs1r_ir32", m=30, rtol=1e-10)
     b = gpu_run(p, "mgs1r_ir32", m=30, rtol=1e-10)
     assert a["res"].iters == b["res"].iters
@@ -117,7 +117,7 @@ def test_ir32_deterministic():
 
 def test_ir32_orthogonality_output():
     """hist_orth from the float32 cycle's T: float32-level loss, restarting at 0."""
-    p = CASES["cfg1"]
+    p = CASES["convdiff2d"]
     g = gpu_run(p, "mgs1r_ir32", m=20, rtol=1e-10, orth=True)
     r = g["res"]
     assert np.all(r.orth[0::20] == 0.0) and np.all(np.isfinite(r.orth))
@@ -131,7 +131,7 @@ def test_ir32_errors_and_edges():
     from paper_1809_05805_amd import native
     from paper_1809_05805_amd.native import GmresError
 
-    p = P.make_config("cfg1", N=16)
+    p = P.make_config("convdiff2d", N=16)
     b = p.b.copy()
     b[3] = np.inf
     g = gpu_run(p, "mgs1r_ir32", b=b)

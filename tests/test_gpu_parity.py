@@ -28,10 +28,10 @@ TOL = 1e-10
 
 def small_cases():
     return {
-        "cfg1": P.make_config("cfg1"),                 # 2D 5-point 64^2 (16 tiles)
-        "cfg1_ragged": P.make_config("cfg1", N=37),    # n = 1369: ragged last tile
-        "cfg2_24": P.make_config("cfg2", N=24),        # 3D 7-point, n = 13824
-        "cfg3_12": P.make_config("cfg3", N=12),        # 27-point, rows scaled to kappa ~ 1e8
+        "convdiff2d": P.make_config("convdiff2d"),                 # 2D 5-point 64^2 (16 tiles)
+        "convdiff2d_ragged": P.make_config("convdiff2d", N=37),    # n = 1369: ragged last tile
+        "convdiff3d_24": P.make_config("convdiff3d", N=24),        # 3D 7-point, n = 13824
+        "stencil27_12": P.make_config("stencil27", N=12),        # 27-point, rows scaled to kappa ~ 1e8
         "dense50": P.random_dense(50, seed=3),         # 50 nonzeros per row
     }
 
@@ -106,8 +106,8 @@ def test_fixed_budget_cycle_parity(scheme, case, fmt):
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_to_tolerance_parity(scheme):
     """Restarted solve to rtol: same iteration count, both truly converged."""
-    p = CASES["cfg1"]
-    log(f"to-tolerance {scheme} cfg1")
+    p = CASES["convdiff2d"]
+    log(f"to-tolerance {scheme} convdiff2d")
     g = gpu_run(p, scheme)
     o = oracle_run(p, scheme, dump=False)
     r = g["res"]
@@ -125,8 +125,8 @@ def test_to_tolerance_parity(scheme):
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_basis_properties(scheme):
     """The GPU's own basis satisfies the Arnoldi relation and the scheme's orthogonality bound."""
-    p = CASES["cfg3_12"]
-    log(f"basis {scheme} cfg3_12")
+    p = CASES["stencil27_12"]
+    log(f"basis {scheme} stencil27_12")
     g = gpu_run(p, scheme, m=60, rtol=0.0, max_iters=60, basis=True)
     j = g["j"]
     V = g["V"][:, :j]
@@ -148,7 +148,7 @@ def test_basis_properties(scheme):
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_deterministic(scheme):
     """The grid reductions sum in a fixed order: repeated solves are bitwise equal."""
-    p = CASES["cfg2_24"]
+    p = CASES["convdiff3d_24"]
     log(f"determinism {scheme}")
     a = gpu_run(p, scheme, m=30, rtol=0.0, max_iters=60)
     b = gpu_run(p, scheme, m=30, rtol=0.0, max_iters=60)
@@ -182,7 +182,7 @@ def test_edge_sizes(scheme):
     g = gpu_run(p, scheme)
     assert g["res"].converged and abs(g["x"][0] - 2.0) <= 1e-15
     # restart length 1
-    p = P.make_config("cfg1", N=8)
+    p = P.make_config("convdiff2d", N=8)
     g = gpu_run(p, scheme, m=1, rtol=1e-8, max_iters=3000)
     o = oracle_run(p, scheme, m=1, rtol=1e-8, max_iters=3000, dump=False)
     assert g["res"].converged and g["res"].iters == o.iters
@@ -193,7 +193,7 @@ def test_edge_sizes(scheme):
     g = gpu_run(p, scheme, b=np.zeros(p.n), x0=np.ones(p.n))
     assert g["res"].converged and g["res"].iters == 0 and np.all(g["x"] == 0.0)
     # converged on the first column
-    g = gpu_run(P.make_config("cfg1", N=16), scheme, rtol=0.9, max_iters=50)
+    g = gpu_run(P.make_config("convdiff2d", N=16), scheme, rtol=0.9, max_iters=50)
     assert g["res"].converged and g["res"].iters == 1
     # empty rows are allowed in the structure (a zero row makes A singular)
     A = sp.random(300, 300, density=0.02, random_state=1, format="csr") + sp.identity(300)
@@ -216,7 +216,7 @@ def test_error_paths(scheme):
     from paper_1809_05805_amd import native
     from paper_1809_05805_amd.native import GmresError, GmresSolver
 
-    p = P.make_config("cfg1", N=16)
+    p = P.make_config("convdiff2d", N=16)
     log(f"errors {scheme}")
     b = p.b.copy()
     b[7] = np.nan
@@ -268,7 +268,7 @@ def test_error_paths(scheme):
 def test_hist_orth(scheme):
     """||S||_2 per column from the library equals numpy's 2-norm of I - (I + L^T)^{-1} built
     from the library's own T (or L), and stays within the oracle's level."""
-    p = CASES["cfg3_12"]
+    p = CASES["stencil27_12"]
     m = 40
     log(f"hist_orth {scheme}")
     g = gpu_run(p, scheme, m=m, rtol=0.0, max_iters=m, orth=True)
@@ -295,7 +295,7 @@ def test_hist_orth(scheme):
 
 def test_hist_orth_restarts():
     """Across restarts each cycle starts again at 0 (its first basis vector)."""
-    p = CASES["cfg1"]
+    p = CASES["convdiff2d"]
     log("hist_orth restarts")
     g = gpu_run(p, "mgs1r", m=10, rtol=1e-8, orth=True)
     r = g["res"]

@@ -72,7 +72,7 @@ def test_p2_iterate_is_krylov_least_squares_minimizer(scheme, j):
 
 # ------------------------------------------------------- P3 Arnoldi relation
 @pytest.mark.parametrize("scheme", SCHEMES)
-@pytest.mark.parametrize("name,N", [("cfg1", 64), ("cfg1", 24), ("cfg3", 12), ("simonici", 0)])
+@pytest.mark.parametrize("name,N", [("convdiff2d", 64), ("convdiff2d", 24), ("stencil27", 12), ("simonici", 0)])
 def test_p3_arnoldi_relation(scheme, name, N):
     """A V_j = V_{j+1} H_j to rounding (Section III, QR view of Arnoldi)."""
     p = P.simonici() if name == "simonici" else P.make_config(name, N=N)
@@ -88,14 +88,14 @@ def test_p3_arnoldi_relation(scheme, name, N):
 @pytest.mark.parametrize("scheme,bound", [("mgs", 1e-10), ("mgs1r", 1e-10), ("cgs2", 1e-13),
                                           ("cgs2_3r", 1e-13), ("two_synch", 1e-13)])
 def test_p4_orthogonality_well_conditioned(scheme, bound):
-    p = P.make_config("cfg1")
+    p = P.make_config("convdiff2d")
     r = run(p, scheme, rtol=0.0, max_iters=p.m, dump=True)
     assert D.orth_loss(r.V[:, : r.j + 1]) <= bound
 
 
 def test_p4_orthogonality_ill_conditioned():
     """MGS loses orthogonality like eps*kappa, CGS2 keeps it at eps (Sections I-III)."""
-    p = P.make_config("cfg3", N=14)
+    p = P.make_config("stencil27", N=14)
     loss = {}
     for s in SCHEMES:
         r = run(p, s, m=100, rtol=0.0, max_iters=100, dump=True)
@@ -113,7 +113,7 @@ def test_p4_orthogonality_ill_conditioned():
 def test_p4_one_reduce_behaves_like_mgs(N):
     """The compact-WY lagged form is MGS (Ruhe's invariant r = (I+L)^{-1} Q^T a), so it
     keeps MGS's O(eps)kappa orthogonality and MGS's H, not classical Gram-Schmidt's."""
-    p = P.make_config("cfg3", N=N)
+    p = P.make_config("stencil27", N=N)
     ref = run(p, "mgs", m=100, rtol=0.0, max_iters=100, dump=True)
     r = run(p, "mgs1r", m=100, rtol=0.0, max_iters=100, dump=True)
     l_ref = D.orth_loss(ref.V[:, : ref.j])
@@ -125,7 +125,7 @@ def test_p4_one_reduce_behaves_like_mgs(N):
 # ------------------------------------------------------ P5 monotone residual
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_p5_residual_monotone(scheme):
-    p = P.make_config("cfg1", N=32)
+    p = P.make_config("convdiff2d", N=32)
     r = run(p, scheme, m=10, rtol=1e-10, max_iters=400)
     h = r.hist
     assert len(h) == r.iters
@@ -152,7 +152,7 @@ def test_p6_identity_converges_in_one_step(scheme):
 def test_p6_converges_at_first_column(scheme):
     """With a loose tolerance the check after the first column must stop the solve
     (the lagged schemes check one step late, but at the first opportunity)."""
-    p = P.make_config("cfg1", N=16)
+    p = P.make_config("convdiff2d", N=16)
     r = run(p, scheme, rtol=0.9, max_iters=50)
     assert r.hist[0] <= 0.9
     assert r.converged and r.iters == 1 and r.cycles == 1
@@ -195,7 +195,7 @@ def test_p6_cyclic_shift_exact(scheme):
 @pytest.mark.parametrize("scheme", ["mgs1r", "cgs2", "cgs2_3r", "two_synch"])
 def test_p7_same_hessenberg_as_mgs(scheme):
     """In exact arithmetic every scheme produces the same Arnoldi H (Sections II-III)."""
-    p = P.make_config("cfg1")
+    p = P.make_config("convdiff2d")
     ref = run(p, "mgs", rtol=0.0, max_iters=p.m, dump=True)
     r = run(p, scheme, rtol=0.0, max_iters=p.m, dump=True)
     assert np.linalg.norm(r.H - ref.H) / np.linalg.norm(ref.H) <= 1e-10
@@ -235,7 +235,7 @@ def test_p8_simonici_bands():
 # ------------------------------------------------------ P9 known solution
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_p9_known_solution(scheme):
-    p = P.make_config("cfg1", N=32)
+    p = P.make_config("convdiff2d", N=32)
     kappa = np.linalg.cond(p.scipy().toarray())
     r = run(p, scheme, rtol=1e-10, max_iters=5000)
     assert r.converged and r.rel_res_true <= 1e-10
@@ -246,7 +246,7 @@ def test_p9_known_solution(scheme):
 # ---------------------------------------------------------- P10 S = I - T
 def test_p10_malard_paige_t_matches_explicit_gram():
     """T built one column per step equals (I + L^T)^{-1} from explicit V^T V (Section II)."""
-    for p, m in ((P.make_config("cfg1"), 30), (P.make_config("cfg3", N=12), 60), (P.simonici(), 100)):
+    for p, m in ((P.make_config("convdiff2d"), 30), (P.make_config("stencil27", N=12), 60), (P.simonici(), 100)):
         r = run(p, "mgs1r", m=m, rtol=0.0, max_iters=m, dump=True)
         k = r.j + 1
         T_exp = D.t_from_basis(r.V[:, :k])
@@ -258,7 +258,7 @@ def test_p10_malard_paige_t_matches_explicit_gram():
 def test_p10_l_matches_explicit_gram(scheme):
     """The L the CGS schemes build one row per step is the strictly lower part of
     the explicit V^T V of their basis (Section II: V^T V = I + L + L^T)."""
-    for p, m in ((P.make_config("cfg1"), 30), (P.make_config("cfg3", N=12), 60)):
+    for p, m in ((P.make_config("convdiff2d"), 30), (P.make_config("stencil27", N=12), 60)):
         r = run(p, scheme, m=m, rtol=0.0, max_iters=m, dump=True)
         k = r.j
         G = r.V[:, :k].T @ r.V[:, :k]
@@ -269,7 +269,7 @@ def test_p10_l_matches_explicit_gram(scheme):
 # ----------------------------------------------- reductions per Arnoldi step
 def test_reductions_per_step():
     """One reduction per step (one-reduce), two (CGS2), i+2 in iteration i (MGS)."""
-    p = P.make_config("cfg1")
+    p = P.make_config("convdiff2d")
     m = p.m
     counts = {s: run(p, s, rtol=0.0, max_iters=m).reductions for s in SCHEMES}
     # ||b||, the cycle, and the closing residual check
@@ -290,7 +290,7 @@ def test_classical_baselines_keep_orthogonality():
     without the L^T term 4e-11, without the L term 8e-14 (measured with an
     independent NumPy transcription of the same step); the oracle's
     two-synchronization run stays at 2e-14 and the re-orthogonalized one at 5e-15."""
-    p = P.make_config("cfg3", N=16)
+    p = P.make_config("stencil27", N=16)
     r3 = run(p, "cgs2_3r", m=150, rtol=0.0, max_iters=150, dump=True)
     r2 = run(p, "two_synch", m=150, rtol=0.0, max_iters=150, dump=True)
     assert r3.j == r2.j == 150
@@ -300,7 +300,7 @@ def test_classical_baselines_keep_orthogonality():
 
 # --------------------------------------------------------------- error paths
 def test_error_paths():
-    p = P.make_config("cfg1", N=8)
+    p = P.make_config("convdiff2d", N=8)
     assert run(p, "mgs1r", m=0).status == -1
     assert run(p, "mgs1r", rtol=-1.0).status == -1
     assert run(p, "mgs1r", rtol=float("nan")).status == -1
@@ -321,7 +321,7 @@ def test_error_paths():
 
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_zero_rhs_and_zero_budget(scheme):
-    p = P.make_config("cfg1", N=8)
+    p = P.make_config("convdiff2d", N=8)
     r = run(p, scheme, b=np.zeros(p.n), x0=np.ones(p.n))
     assert r.status == 0 and r.converged and np.all(r.x == 0.0) and r.iters == 0
     r = run(p, scheme, max_iters=0)
@@ -331,6 +331,6 @@ def test_zero_rhs_and_zero_budget(scheme):
 @pytest.mark.parametrize("scheme", SCHEMES)
 def test_restart_one(scheme):
     """GMRES(1) still converges on a positive-real matrix."""
-    p = P.make_config("cfg1", N=8)
+    p = P.make_config("convdiff2d", N=8)
     r = run(p, scheme, m=1, rtol=1e-8, max_iters=5000)
     assert r.converged and r.rel_res_true <= 1e-8 and r.cycles == r.iters
