@@ -104,3 +104,31 @@ def test_stencil27_orthogonality_curve():
     assert sg[-1] <= 1e2 * eps * 1e8
     assert rel(g["x"], o.x) <= 1e-8
     assert rel(g["H"], o.H) <= 1e-9
+
+
+def test_convdiff3d_256_precision_workload():
+    """The precision workload at its full size: 3D 7-point 256^3 (n = 16.8M),
+    GMRES(40) to 1e-10 in float64 and with the float32 and bfloat16 bases.
+    Each residual is recomputed here in float64; the reduced-precision
+    solutions are held to 10 kappa_est rtol of the float64 one, kappa_est being
+    the float64 solution's error against x_true over rtol."""
+    p = P.make_config("convdiff3d", N=256)
+    rtol = 1e-10
+    A = p.scipy()
+    nb = np.linalg.norm(p.b)
+    xs = {}
+    for scheme in ("mgs1r", "mgs1r_ir32", "mgs1r_ir16"):
+        log(f"256^3 {scheme}")
+        g = gpu_run(p, scheme, m=40, rtol=rtol, max_iters=20000)
+        r = g["res"]
+        res = np.linalg.norm(p.b - A @ g["x"]) / nb
+        log(f"  iters {r.iters}, rel res {res:.2e}, error vs x_true {rel(g['x'], p.x_true):.2e}")
+        assert r.status == 0 and r.converged
+        assert res <= rtol * (1 + 1e-6)
+        xs[scheme] = g["x"]
+        g["solver"].close()
+    kappa = max(rel(xs["mgs1r"], p.x_true) / rtol, 1.0)
+    for scheme in ("mgs1r_ir32", "mgs1r_ir16"):
+        e = rel(xs[scheme], xs["mgs1r"])
+        log(f"  {scheme}: |x - x_fp64| / |x_fp64| {e:.2e} (bound {10 * kappa * rtol:.1e})")
+        assert e <= 10 * kappa * rtol
