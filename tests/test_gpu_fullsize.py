@@ -78,7 +78,8 @@ def test_convdiff3d_reduced_precision_basis_to_tolerance(convdiff3d, scheme):
     assert err <= 1e-6
 
 
-def test_stencil27_orthogonality_curve():
+@pytest.mark.parametrize("N", [40, 100])
+def test_stencil27_orthogonality_curve(N):
     """Paige's ||S_k||_2 per iteration on the row-scaled 27-point system (kappa ~ 1e8).
 
     The curve's magnitude is set by the rounding of the inner products: rows
@@ -89,8 +90,8 @@ def test_stencil27_orthogonality_curve():
     oracle, stay within the O(eps) kappa bound for MGS, grow monotonically
     (leading-block norms of one triangular matrix), and agree on x and H.
     """
-    p = P.make_config("stencil27", N=40)
-    log(f"stencil27 N=40 orthogonality n={p.n}")
+    p = P.make_config("stencil27", N=N)
+    log(f"stencil27 N={N} orthogonality n={p.n}")
     g = gpu_run(p, "mgs1r", m=100, rtol=0.0, max_iters=100)
     o = oracle_run(p, "mgs1r", m=100, rtol=0.0, max_iters=100)
     # the cycle's last step forms only a norm, so T has columns 0..j-1
