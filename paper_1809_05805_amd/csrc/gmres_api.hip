@@ -110,8 +110,9 @@ struct Layout {
 };
 
 // The FP64 schemes keep the basis V and the SpMV output w in float64; the
-// FP32-basis scheme keeps them in float32 plus a float64 restart residual.
-// Columns are 64 elements apart at least, so every column starts 256-byte aligned.
+// refinement schemes keep them in float32 or bfloat16 plus a float64 restart
+// residual. Columns are 64 elements apart at least, so every column starts
+// 128-byte aligned (256 bytes for float32 and float64).
 bool make_layout(int64_t n, int m, int scheme, Layout* L) {
   if (n < 1 || m < 1 || m > GMRES_MAX_RESTART) return false;
   L->ldv = (int64_t)round_up((size_t)n, 64);
@@ -394,16 +395,16 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
   const Ws& ws = c->ws;
   hipStream_t s = c->stream;
   const int rpt = c->L.rpt, G = c->L.G;
-  const bool f32 = ir_scheme(c->scheme);       // a reduced-precision basis
+  const bool ir = ir_scheme(c->scheme);  // a reduced-precision basis inside float64 refinement
   const int bt = basis_type(c->scheme);
   const double n8 = (double)basis_bytes(c->scheme) * (double)c->A.n;  // one basis column
   // bytes of the matrix in the format the step's SpMV reads
   const double csr = c->format == kFormatSell
-                         ? (f32 ? 8.0 : 12.0) * (double)c->sell_entries + 8.0 * (double)(c->sell.ns + 1)
+                         ? (ir ? 8.0 : 12.0) * (double)c->sell_entries + 8.0 * (double)(c->sell.ns + 1)
                          : 12.0 * (double)c->nnz + 4.0 * (double)(c->A.n + 1);
   auto col = [&](int q) { return ws.V + (size_t)q * (size_t)ws.ldv; };
   TRY(launch_cycle_begin(ws, s));
-  if (f32) {
+  if (ir) {
     // float64 restart residual and its norm (the restart check), then the
     // cycle's first basis vector r / ||r|| in float32
     TRY(spmv(c, x, b, ws.r64, nullptr, s));
@@ -462,7 +463,7 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
         const bool last = k == m_eff;
         int wsrc = last ? kWNone : (c->format == kFormatSell ? kWSell : kWSpmv);
         double bytes = last ? n8 : csr + n8 * (k + 1) + n8;
-        if (!last && c->split && !f32) {
+        if (!last && c->split && !ir) {
           TimedLaunch t(c, GMRES_KSTAT_SPMV, k, k, csr + 2 * n8);
           TRY(spmv(c, col(k), nullptr, ws.w, ws.st, s, t.e0, t.e1));
           wsrc = kWLoad;
@@ -664,9 +665,9 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
     return GMRES_ERR_ARG;
   char* base = (char*)storage;
   const int64_t ns = (int64_t)c->sell_sp.size() - 1;
-  const bool f32 = ir_scheme(c->scheme);  // float32 values for the reduced-precision bases
+  const bool fv = ir_scheme(c->scheme);  // float32 values for the reduced-precision bases
   const Sell S{(const int64_t*)base, (int*)(base + c->o_ci),
-               f32 ? nullptr : (double*)(base + c->o_va), f32 ? (float*)(base + c->o_va) : nullptr,
+               fv ? nullptr : (double*)(base + c->o_va), fv ? (float*)(base + c->o_va) : nullptr,
                ns, c->A.n};
   if (hipMemcpyAsync(base, c->sell_sp.data(), sizeof(int64_t) * (size_t)(ns + 1),
                      hipMemcpyHostToDevice, c->stream) != hipSuccess ||
