@@ -118,6 +118,22 @@ __device__ inline double wave_sum_last(double v) {
 #ifndef GMRES_PROJ_REVERSE
 #define GMRES_PROJ_REVERSE 1
 #endif
+//   GMRES_NT_STORES  bit 0: the fused step's SpMV output w, bit 1: the two
+//                    columns MAXPY writes, are stored non-temporally, so they
+//                    neither displace basis columns from the caches nor leave
+//                    dirty lines for the write-back at the end of the kernel
+//                    (bfloat16 columns are always stored plainly).
+#ifndef GMRES_NT_STORES
+#define GMRES_NT_STORES 3
+#endif
+template <int BIT, typename T>
+__device__ inline void st_stream(T* p, T v) {
+  if constexpr ((GMRES_NT_STORES & BIT) != 0 && sizeof(T) >= 4)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 //   GMRES_SELL_CPOL  cache policy bits of the sliced copy's index and value
 //                    loads (0: default; 2: non-temporal, so streaming A does
 //                    not evict basis columns from the last-level cache).
@@ -1280,10 +1296,10 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     u[i] = ok ? uv : (CT)0;
     if constexpr (WSRC == kWSpmv) {
       w[i] = ok ? (CT)wl[lr] : (CT)0;
-      if (ok) wout[r] = (VT)w[i];
+      if (ok) st_stream<1>(wout + r, (VT)w[i]);
     } else if constexpr (WSRC == kWSell) {
       w[i] = ok ? ws_out[i] : (CT)0;
-      if (ok) wout[r] = (VT)w[i];
+      if (ok) st_stream<1>(wout + r, (VT)w[i]);
     } else if constexpr (WSRC == kWLoad) {
       const CT wv_ = (CT)ProjCol<VT>(wout + rb, n - rb)(rows[i]);
       w[i] = ok ? wv_ : (CT)0;
@@ -1518,9 +1534,9 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
       CT x = (CT)vk[i];
       if (mode == 0) {
         x *= invr;
-        V[(size_t)k * ldv + r] = (VT)x;
+        st_stream<2>(V + (size_t)k * ldv + r, (VT)x);
       }
-      V[(size_t)(k + 1) * ldv + r] = (VT)(acc[i] - x * ck);
+      st_stream<2>(V + (size_t)(k + 1) * ldv + r, (VT)(acc[i] - x * ck));
     }
   }
 }
