@@ -87,6 +87,37 @@ def time_solves(solver, b, x, rtol, max_iters, steps, warmup, timing=False):
     return dt, iters, res, kt
 
 
+def measured_ceilings(dev, mib=2048, reps=5):
+    """Rates of torch's own device copy (read + write) and sum (read only) over
+    a buffer far larger than the caches: practical bandwidth ceilings of this
+    GPU, reported beside the 8 TB/s peak."""
+    import torch
+
+    nb = mib * 2**20 // 8
+    src = torch.ones(nb, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    src.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy = 2.0 * 8 * nb * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    e0.record()
+    for _ in range(reps):
+        src.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read = 8.0 * nb * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return {"copy_GBps": round(copy, 1), "read_GBps": round(read, 1), "buffer_MiB": mib,
+            "how": f"torch copy_ and sum of a {mib} MiB float64 buffer, {reps} times each, timed "
+                   "with events"}
+
+
 def cpu_baseline(p, m):
     import oracle
 
@@ -363,6 +394,8 @@ def main():
                     help="first run one plain device copy of this many MiB (a reference kernel "
                          "for hardware byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solver section")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the device copy and sum rates reported beside the peak")
     ap.add_argument("--orth-study-N", type=int, default=0,
                     help="also run the loss-of-orthogonality study of every scheme on the row-scaled "
                          "27-point N^3 system (100: its full size)")
@@ -448,6 +481,12 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
+    if not args.no_ceilings and not args.copy_calibration_mib:
+        # (a counter run keeps its one calibration copy the only large copy)
+        ceil = measured_ceilings(dev)
+        ceil["dominant_kernel_frac_of_read"] = round(d["GBps"] / ceil["read_GBps"], 4)
+        out["measured_ceilings"] = ceil
+        log(f"ceilings: copy {ceil['copy_GBps']:.0f} GB/s, read {ceil['read_GBps']:.0f} GB/s")
     x64 = x.clone()
     if not args.no_ir32:
         out["fp32_ir"] = ir32_result(args, p, rp, ci, va, b, x, x64, dt / args.steps, res.iters)

@@ -126,6 +126,11 @@ __device__ inline double wave_sum_last(double v) {
 #ifndef GMRES_NT_STORES
 #define GMRES_NT_STORES 3
 #endif
+//   GMRES_XUPDATE_REVERSE  1: the end-of-cycle x update takes the basis
+//                          columns last to first (see k_xupdate).
+#ifndef GMRES_XUPDATE_REVERSE
+#define GMRES_XUPDATE_REVERSE 1
+#endif
 template <int BIT, typename T>
 __device__ inline void st_stream(T* p, T v) {
   if constexpr ((GMRES_NT_STORES & BIT) != 0 && sizeof(T) >= 4)
@@ -1724,7 +1729,10 @@ __global__ __launch_bounds__(256) void k_backsolve(Ws ws, int lds_doubles) {
 // x += xscale V[:,0:j] y, with each pass's loads all in flight (loads at
 // clamped rows; only rows below n are stored). The sums run
 // in float64 whatever the basis type VT; xscale (1 for the FP64 schemes, the
-// restart residual norm for the FP32-basis scheme) is folded into y.
+// restart residual norm for the FP32-basis scheme) is folded into y. With
+// GMRES_XUPDATE_REVERSE the columns are taken last to first: the cycle's last
+// MAXPY read them first to last, so the last-level cache still holds the
+// highest ones.
 template <int RPT, typename VT>
 __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, int G) {
   constexpr int TR = 256 * RPT;
@@ -1753,14 +1761,15 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
   }
   // GMRES_MAXPY_COLS columns per pass, as in the MAXPY
   constexpr int MC = GMRES_MAXPY_COLS;
+  auto colx = [&](int t) { return GMRES_XUPDATE_REVERSE ? j - 1 - t : t; };
   int q = 0;
   for (; q + MC <= j; q += MC) {
     double c[MC];
     VT v[MC][RPT];
 #pragma unroll
     for (int t = 0; t < MC; ++t) {
-      c[t] = xs * y[q + t];
-      const MaxpyCol<VT> col(Vt + (size_t)(q + t) * ldv, n - rb);
+      c[t] = xs * y[colx(q + t)];
+      const MaxpyCol<VT> col(Vt + (size_t)colx(q + t) * ldv, n - rb);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) v[t][i] = col(off[i]);
     }
@@ -1773,10 +1782,10 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
     }
   }
   for (; q < j; ++q) {
-    const double c0 = xs * y[q];
+    const double c0 = xs * y[colx(q)];
     double v[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) v[i] = (double)MaxpyCol<VT>(Vt + (size_t)q * ldv, n - rb)(off[i]);
+    for (int i = 0; i < RPT; ++i) v[i] = (double)MaxpyCol<VT>(Vt + (size_t)colx(q) * ldv, n - rb)(off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] += v[i] * c0;
   }
