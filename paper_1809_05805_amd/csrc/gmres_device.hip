@@ -121,10 +121,10 @@ __device__ inline double wave_sum_last(double v) {
 //   GMRES_NT_STORES  bit 0: the fused step's SpMV output w, bit 1: the two
 //                    columns MAXPY writes, are stored non-temporally, so they
 //                    neither displace basis columns from the caches nor leave
-//                    dirty lines for the write-back at the end of the kernel
-//                    (bfloat16 columns are always stored plainly).
+//                    dirty lines for the write-back at the end of the kernel;
+//                    bits 2 and 3: the same for bfloat16 columns.
 #ifndef GMRES_NT_STORES
-#define GMRES_NT_STORES 3
+#define GMRES_NT_STORES 15
 #endif
 //   GMRES_XUPDATE_REVERSE  1: the end-of-cycle x update takes the basis
 //                          columns last to first (see k_xupdate).
@@ -133,8 +133,11 @@ __device__ inline double wave_sum_last(double v) {
 #endif
 template <int BIT, typename T>
 __device__ inline void st_stream(T* p, T v) {
-  if constexpr ((GMRES_NT_STORES & BIT) != 0 && sizeof(T) >= 4)
+  if constexpr (sizeof(T) >= 4 && (GMRES_NT_STORES & BIT) != 0)
     __builtin_nontemporal_store(v, p);
+  else if constexpr (sizeof(T) == 2 && (GMRES_NT_STORES & (BIT << 2)) != 0)
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v),
+                                reinterpret_cast<unsigned short*>(p));
   else
     *p = v;
 }
