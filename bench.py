@@ -247,6 +247,15 @@ def orth_study(args):
         t0 = time.perf_counter()
         s.solve(b, x, 0.0, m)
         dt = time.perf_counter() - t0
+        # per-kernel rates from a separate cycle with HIP events on each dispatch
+        x.zero_()
+        s.set_timing(True)
+        s.solve(b, x, 0.0, m)
+        kt = s.timing()
+        s.set_timing(False)
+        kernels = {name: {"launches": st["launches"], "avg_us": round(st["ms"] / st["launches"] * 1e3, 2),
+                          "GBps": round(st["bytes"] / (st["ms"] * 1e-3) / 1e9, 1)}
+                   for name, st in kt.items() if st["launches"]}
         x.zero_()
         r = s.solve(b, x, 0.0, m, orth=True)
         _, _, _, j = s.last_cycle()
@@ -256,12 +265,13 @@ def orth_study(args):
         rec = {"columns": j, "orth_loss_at": {str(k): loss[k - 1] for k in marks if k <= j},
                "relative_residual_after_cycle": r.rel_res_true,
                "iters_per_s": round(r.iters / dt, 1), "ms_per_cycle": round(dt * 1e3, 2),
-               "reductions": r.reductions}
+               "reductions": r.reductions, "kernels": kernels}
         if r.orth is not None and np.all(np.isfinite(r.orth)):
             rec["paige_s_at"] = {str(k): float(r.orth[k - 1]) for k in marks if k <= len(r.orth)}
         out[scheme] = rec
         log(f"orth study {scheme}: {r.iters / dt:.0f} iters/s, ||I - V^T V|| at k=10..100: "
-            + " ".join(f"{loss[k - 1]:.1e}" for k in marks if k <= j))
+            + " ".join(f"{loss[k - 1]:.1e}" for k in marks if k <= j) + " | "
+            + " ".join(f"{k}: {v['avg_us']:.1f} us {v['GBps']:.0f} GB/s" for k, v in kernels.items()))
         s.close()
         del V, x
     return out
