@@ -9,7 +9,10 @@
 
 namespace gmres {
 
-constexpr int kGroup = 32;  // tiles per first-level group of the grid reduction
+#ifndef GMRES_GROUP
+#define GMRES_GROUP 32
+#endif
+constexpr int kGroup = GMRES_GROUP;  // tiles per first-level group of the grid reduction
 
 constexpr int kSchemeMgs = 0;
 constexpr int kSchemeMgs1r = 1;
