@@ -36,3 +36,16 @@ def test_batch_bytes_by_hand():
     got4 = bench.batch_bytes({"iters": np.array([3]), "cycles": np.array([1])}, [n], [nnz], m, 4)
     steps4 = sum(A + 4 * n * (2 * (k + 1) + 4) for k in range(3))
     assert got4 == steps4 + 4 * n + 8.0 * n * 3 + 16.0 * n + A + 24.0 * n + A + 24.0 * n
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    for argv, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        e = dict(os.environ, **env)
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv, env=e,
+                           capture_output=True, text=True, timeout=60)
+        assert r.returncode == 2
+        assert "one GPU only" in r.stderr
+        assert r.stdout == ""
