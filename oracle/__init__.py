@@ -57,6 +57,11 @@ def _load():
         lib.oracle_gmres_solve.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, ctypes.c_int32,
                                            ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_int64,
                                            ctypes.POINTER(_Info), P, P, P, P, P, P, P]
+        lib.oracle_gmres_solve_depth.restype = ctypes.c_int
+        lib.oracle_gmres_solve_depth.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P,
+                                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                 P, P, ctypes.c_double, ctypes.c_int64,
+                                                 ctypes.POINTER(_Info), P, P, P, P, P, P, P]
         lib.oracle_spmv.restype = None
         lib.oracle_spmv.argtypes = [ctypes.c_int64, P, P, P, P, P]
         _lib = lib
@@ -88,8 +93,10 @@ class OracleResult:
 
 
 def solve(row_ptr, col_idx, vals, b, x0, m: int, scheme: str = "mgs1r", rtol: float = 1e-8,
-          max_iters: int | None = None, dump: bool = False) -> OracleResult:
-    """Restarted GMRES(m) on host arrays; see ``oracle_gmres.h`` for the contract."""
+          max_iters: int | None = None, dump: bool = False, depth: int = 1) -> OracleResult:
+    """Restarted GMRES(m) on host arrays; see ``oracle_gmres.h`` for the contract.
+    depth: the pipeline depth of the lagged schemes (rotations and the stopping
+    test applied depth columns at a time)."""
     lib = _load()
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
@@ -109,10 +116,11 @@ def solve(row_ptr, col_idx, vals, b, x0, m: int, scheme: str = "mgs1r", rtol: fl
         S2 = np.zeros((m, m + 1))
     j = ctypes.c_int32(0)
     info = _Info()
-    st = lib.oracle_gmres_solve(n, col_idx.shape[0], _ptr(row_ptr), _ptr(col_idx), _ptr(vals), m,
-                                SCHEMES[scheme], _ptr(b), _ptr(x), float(rtol), int(max_iters),
-                                ctypes.byref(info), _ptr(hist), _ptr(V), _ptr(H), _ptr(T), _ptr(g),
-                                _ptr(S2), ctypes.byref(j))
+    st = lib.oracle_gmres_solve_depth(n, col_idx.shape[0], _ptr(row_ptr), _ptr(col_idx),
+                                      _ptr(vals), m, SCHEMES[scheme], int(depth), _ptr(b), _ptr(x),
+                                      float(rtol), int(max_iters), ctypes.byref(info), _ptr(hist),
+                                      _ptr(V), _ptr(H), _ptr(T), _ptr(g), _ptr(S2),
+                                      ctypes.byref(j))
     res = OracleResult(st, x, info.iters, info.cycles, bool(info.converged), bool(info.breakdown),
                        info.rel_res_true, info.rel_res_est, info.reductions,
                        hist[: info.iters].copy(), j.value)

@@ -97,12 +97,13 @@ typedef struct {
   double* h;  /* m+2 */
   double* y;  /* m+2 */
   double* S2; /* (m+1) x m: CGS2 second-pass coefficients s, per column */
+  double* gres; /* m+2: gres[c+1] = |g_{c+1}| as rotation c left it */
 } ws_t;
 
 static void ws_free(ws_t* ws) {
   free(ws->V); free(ws->H); free(ws->R); free(ws->T); free(ws->L); free(ws->g);
   free(ws->cs); free(ws->sn); free(ws->w); free(ws->p); free(ws->c); free(ws->r);
-  free(ws->h); free(ws->y); free(ws->S2);
+  free(ws->h); free(ws->y); free(ws->S2); free(ws->gres);
 }
 
 static int ws_alloc(ws_t* ws, int64_t n, int m) {
@@ -126,7 +127,8 @@ static int ws_alloc(ws_t* ws, int64_t n, int m) {
   ws->h = (double*)calloc((size_t)(m + 2), sizeof(double));
   ws->y = (double*)calloc((size_t)(m + 2), sizeof(double));
   ws->S2 = (double*)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));
-  if (!ws->S2 || !ws->V || !ws->H || !ws->R || !ws->T || !ws->L || !ws->g || !ws->cs || !ws->sn || !ws->w ||
+  ws->gres = (double*)calloc((size_t)(m + 2), sizeof(double));
+  if (!ws->S2 || !ws->gres || !ws->V || !ws->H || !ws->R || !ws->T || !ws->L || !ws->g || !ws->cs || !ws->sn || !ws->w ||
       !ws->p || !ws->c || !ws->r || !ws->h || !ws->y) {
     ws_free(ws);
     return -1;
@@ -249,6 +251,7 @@ static int cycle_mgs(const csr_t* A, const double* b, double* x, int m_eff, doub
       if (!isfinite(HH(ws, q, i))) return ORACLE_ERR_NONFINITE;
     double gk = rotate_column(ws, i);
     if (!isfinite(gk)) return ORACLE_ERR_NONFINITE;
+    ws->gres[i + 1] = gk;
     if (hist) hist[it0 + i] = gk / bnorm;
     if (hn == 0.0) {
       out->breakdown = 1;
@@ -353,6 +356,7 @@ static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, doub
       if (!isfinite(HH(ws, q, i))) return ORACLE_ERR_NONFINITE;
     double gk = rotate_column(ws, i);
     if (!isfinite(gk)) return ORACLE_ERR_NONFINITE;
+    ws->gres[i + 1] = gk;
     if (hist) hist[it0 + i] = gk / bnorm;
     if (hn == 0.0) {
       out->breakdown = 1;
@@ -390,14 +394,28 @@ static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, doub
  *   keeps L at O(eps), both the (I - L) correction and the s term of h change
  *   H only at the rounding level, so no output distinguishes them from their
  *   absence (or from a sign error in the correction).
+ *
+ * Pipeline depth (the depth-L pipeline of Section III, shown there for L = 2):
+ * the Givens rotations, and with them the stopping test, only consume
+ * completed Hessenberg columns and feed nothing back into the Arnoldi
+ * recurrence, so they may trail it. With depth L the pending columns are
+ * rotated L at a time (and at the last step of a cycle, or at a breakdown):
+ * step k rotates columns rot_next .. k-1 once k - rot_next reaches L. The
+ * cycle then stops at the first column count j whose |g_j| meets the
+ * tolerance, exactly the j that depth 1 (rotation every step) stops at, but
+ * up to L - 1 steps later: those extra steps are computed and discarded. H,
+ * the rotations, g, y and x for the j columns are the same arithmetic in the
+ * same order as at depth 1, so the iterate is identical.
  */
 static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, double tol_abs,
-                        double bnorm, int scheme, ws_t* ws, double* hist, int64_t it0,
+                        double bnorm, int scheme, int depth, ws_t* ws, double* hist, int64_t it0,
                         int64_t* nred, cycle_out* out) {
   int64_t n = A->n;
   memset(out, 0, sizeof(*out));
   ws_reset_small(ws);
   residual_into_v0(A, b, x, ws);
+  int rot_next = 0;  /* first Hessenberg column not yet rotated */
+  int stop_j = -1;   /* first column count whose |g| met the tolerance */
   for (int k = 0;; ++k) {
     double* u = VC(ws, k);
     int flush = (k == m_eff);
@@ -415,7 +433,6 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
     if (!isfinite(alpha) || alpha < 0.0) return ORACLE_ERR_NONFINITE;
     double rho = sqrt(alpha);
 
-    double gk = 0.0;
     if (k == 0) {
       out->beta = rho;
       ws->g[0] = rho;
@@ -426,9 +443,22 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
       if (flush) return ORACLE_OK;
     } else {
       HH(ws, k, k - 1) = rho;
-      gk = rotate_column(ws, k - 1);
-      if (!isfinite(gk)) return ORACLE_ERR_NONFINITE;
-      if (hist) hist[it0 + k - 1] = gk / bnorm;
+      /* column k-1 is complete; rotate the pending columns when L of them
+         are waiting, at the cycle's last step, or at a breakdown */
+      if (k - rot_next >= depth || flush || rho == 0.0) {
+        for (int c = rot_next; c < k; ++c) {
+          double gc = rotate_column(ws, c);
+          if (!isfinite(gc)) return ORACLE_ERR_NONFINITE;
+          ws->gres[c + 1] = gc;
+          if (hist) hist[it0 + c] = gc / bnorm;
+          if (stop_j < 0 && gc <= tol_abs) stop_j = c + 1;
+        }
+        rot_next = k;
+      }
+      if (stop_j >= 0 && stop_j < k) {  /* met earlier: the steps since are discarded */
+        out->j = stop_j;
+        return ORACLE_OK;
+      }
       if (rho == 0.0) {
         out->breakdown = 1;
         out->j = k;
@@ -450,7 +480,7 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
       for (int q = 0; q < k; ++q) LL(ws, k, q) = ws->p[q];
     }
 
-    if (k >= 1 && gk <= tol_abs) {
+    if (stop_j == k) {
       out->j = k;
       return ORACLE_OK;
     }
@@ -522,6 +552,17 @@ int oracle_gmres_solve(int64_t n, int64_t nnz, const int32_t* row_ptr, const int
                        double rtol, int64_t max_iters, oracle_info* info, double* hist_res,
                        double* V_out, double* H_out, double* T_out, double* g_out,
                        double* S2_out, int32_t* j_out) {
+  return oracle_gmres_solve_depth(n, nnz, row_ptr, col_idx, vals, m, scheme, 1, b, x, rtol,
+                                  max_iters, info, hist_res, V_out, H_out, T_out, g_out, S2_out,
+                                  j_out);
+}
+
+int oracle_gmres_solve_depth(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                             const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
+                             int32_t depth, const double* b, double* x, double rtol,
+                             int64_t max_iters, oracle_info* info, double* hist_res,
+                             double* V_out, double* H_out, double* T_out, double* g_out,
+                             double* S2_out, int32_t* j_out) {
   oracle_info loc;
   memset(&loc, 0, sizeof(loc));
   if (info) memset(info, 0, sizeof(*info));
@@ -531,6 +572,7 @@ int oracle_gmres_solve(int64_t n, int64_t nnz, const int32_t* row_ptr, const int
       (scheme != ORACLE_MGS && scheme != ORACLE_MGS_1R && scheme != ORACLE_CGS2 &&
        scheme != ORACLE_CGS2_3R && scheme != ORACLE_TWOSYNCH))
     return ORACLE_ERR_ARG;
+  if (depth < 1 || (depth > 1 && scheme != ORACLE_MGS_1R && scheme != ORACLE_CGS2)) return ORACLE_ERR_ARG;
   if (row_ptr[0] != 0 || row_ptr[n] != nnz) return ORACLE_ERR_ARG;
   for (int64_t i = 0; i < n; ++i)
     if (row_ptr[i + 1] < row_ptr[i]) return ORACLE_ERR_ARG;
@@ -566,13 +608,13 @@ int oracle_gmres_solve(int64_t n, int64_t nnz, const int32_t* row_ptr, const int
       status = cycle_cgs(&A, b, x, m_eff, tol_abs, bnorm, scheme, &ws, hist_res, it,
                          &loc.reductions, &co);
     else
-      status = cycle_lagged(&A, b, x, m_eff, tol_abs, bnorm, scheme, &ws, hist_res, it,
+      status = cycle_lagged(&A, b, x, m_eff, tol_abs, bnorm, scheme, depth, &ws, hist_res, it,
                             &loc.reductions, &co);
     if (status != ORACLE_OK) break;
     if (co.j > 0) {
       update_solution(&ws, co.j, x);
       loc.cycles++;
-      loc.rel_res_est = fabs(ws.g[co.j]) / bnorm;
+      loc.rel_res_est = ws.gres[co.j] / bnorm;
       dump_cycle(&ws, scheme, co.j, V_out, H_out, T_out, g_out, S2_out, j_out);
     }
     it += co.j;

@@ -76,6 +76,22 @@ int oracle_gmres_solve(int64_t n, int64_t nnz, const int32_t* row_ptr, const int
                        double* V_out, double* H_out, double* T_out, double* g_out, double* S2_out,
                        int32_t* j_out);
 
+/*
+ * The same solve with the Givens rotations and the stopping test of the
+ * lagged schemes (ORACLE_MGS_1R, ORACLE_CGS2) applied depth columns at a time
+ * (the depth-L pipeline of Section III; depth 1 is oracle_gmres_solve). The
+ * iterate, iteration counts and dumps are those of depth 1; a cycle that
+ * stops early runs up to depth - 1 more Arnoldi steps first, which shows in
+ * info->reductions. depth < 1, or depth > 1 with another scheme, gives
+ * ORACLE_ERR_ARG.
+ */
+int oracle_gmres_solve_depth(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                             const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
+                             int32_t depth, const double* b, double* x, double rtol,
+                             int64_t max_iters, oracle_info* info, double* hist_res,
+                             double* V_out, double* H_out, double* T_out, double* g_out,
+                             double* S2_out, int32_t* j_out);
+
 /* y = A x, sequential sum over each row in CSR order. */
 void oracle_spmv(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
                  const double* x, double* y);

@@ -334,3 +334,74 @@ def test_restart_one(scheme):
     p = P.make_config("convdiff2d", N=8)
     r = run(p, scheme, m=1, rtol=1e-8, max_iters=5000)
     assert r.converged and r.rel_res_true <= 1e-8 and r.cycles == r.iters
+
+
+# ------------------------------------- depth-L pipeline of the rotations
+LAGGED = ["mgs1r", "cgs2"]
+
+
+@pytest.mark.parametrize("scheme", LAGGED)
+@pytest.mark.parametrize("depth", [2, 3, 4, 7])
+def test_pipeline_fixed_budget_is_depth_one(scheme, depth):
+    """The depth-L pipeline of Section III only moves the Givens rotations: they
+    consume finished Hessenberg columns and feed nothing back. Without an early
+    stop, every output equals depth 1's bit for bit, and each Arnoldi step still
+    takes exactly one reduction (two for CGS2)."""
+    p = P.make_config("convdiff2d", N=24)
+    m = 30
+    a = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, m, scheme, 0.0, m, dump=True)
+    b = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, m, scheme, 0.0, m, dump=True,
+                     depth=depth)
+    assert a.status == b.status == 0 and a.j == b.j == m
+    for f in ("x", "hist", "H", "T", "g", "V"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    assert a.reductions == b.reductions == 1 + (m + 1) * (1 if scheme == "mgs1r" else 2) - \
+        (0 if scheme == "mgs1r" else 1) + 1
+
+
+@pytest.mark.parametrize("scheme", LAGGED)
+@pytest.mark.parametrize("depth", [2, 3, 5, 8])
+@pytest.mark.parametrize("name,N,m,rtol", [("convdiff2d", 64, 30, 1e-8), ("convdiff2d", 37, 25, 1e-10),
+                                          ("convdiff2d", 37, 17, 1e-10), ("stencil27", 10, 22, 1e-6)])
+def test_pipeline_stops_at_the_same_column_late(scheme, depth, name, N, m, rtol):
+    """With early stops the pipelined cycle stops at the same column count as
+    depth 1, so x, the iteration and cycle counts and the residual history are
+    bitwise equal; it finds out when the pending columns are next rotated,
+    i.e. at the next multiple of L (or at the cycle's last step), and the steps
+    run meanwhile are the only extra reductions."""
+    p = P.make_config(name, N=N)
+    a = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, m, scheme, rtol, 5000, dump=True)
+    b = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, m, scheme, rtol, 5000, dump=True,
+                     depth=depth)
+    assert a.status == b.status == 0 and a.converged and b.converged
+    assert a.iters == b.iters and a.cycles == b.cycles and a.j == b.j
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.hist, b.hist)
+    assert a.rel_res_true == b.rel_res_true and a.rel_res_est == b.rel_res_est
+    j = a.j
+    assert np.array_equal(a.H[:, :j], b.H[:, :j]) and np.array_equal(a.g[:j], b.g[:j])
+    assert np.array_equal(a.T[: j + 1, : j + 1], b.T[: j + 1, : j + 1])
+    # the last cycle with columns stopped on the tolerance at column j (unless
+    # it ran to m); the pipelined one ran to the next multiple of L first
+    per_step = 1 if scheme == "mgs1r" else 2
+    late = 0 if j == m else min(-(-j // depth) * depth, m) - j
+    assert 0 <= late <= depth - 1
+    assert b.reductions - a.reductions == per_step * late
+
+
+@pytest.mark.parametrize("depth", [2, 5])
+@pytest.mark.parametrize("n", [8, 33])
+def test_pipeline_full_krylov_space_matches_lu(depth, n):
+    """P1 through the pipelined cycle: m >= n reaches the LU solution."""
+    p = P.random_dense(n, seed=n)
+    A = p.scipy().toarray()
+    x_lu = np.linalg.solve(A, p.b)
+    r = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, n, "mgs1r", 0.0, n, depth=depth)
+    assert r.status == 0 and r.iters <= n
+    assert np.linalg.norm(r.x - x_lu) / np.linalg.norm(x_lu) <= 1e2 * np.linalg.cond(A) * EPS
+
+
+def test_pipeline_refusals():
+    p = P.make_config("convdiff2d", N=8)
+    for scheme, depth in (("mgs1r", 0), ("mgs", 2), ("cgs2_3r", 2), ("two_synch", 3)):
+        r = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, 10, scheme, 1e-8, 100, depth=depth)
+        assert r.status == -1
