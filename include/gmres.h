@@ -415,6 +415,9 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
  * earlier one); gmres_batch_replay launches it on the context's stream
  * without waiting. The graph keeps the pointers it was captured with: refill
  * b and x in place between replays. Results go to the context's own array.
+ * gmres_batch_set_config and gmres_batch_autotune discard the graph (it holds
+ * the old grid, block size and queue length): gmres_batch_replay then returns
+ * GMRES_ERR_ARG until the next capture.
  */
 int gmres_batch_capture(gmres_batch* bt, const double* b, double* x, double rtol,
                         int64_t max_iters);

@@ -136,11 +136,21 @@ struct gmres_batch {
 
 namespace {
 
+// A captured graph holds the grid, block size and queue length it was
+// captured with: any change of configuration discards it.
+void drop_graph(gmres_batch* bt) {
+  if (bt->graph_exec) (void)hipGraphExecDestroy(bt->graph_exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  bt->graph_exec = nullptr;
+  bt->graph = nullptr;
+}
+
 // Team sizes, queue order and grid for a configuration; uploads the queue
-// (blocking). Parts of a system: ceil(n / part_rows), at most kTeamMax, one per
+// (blocking), and discards any captured graph. Parts of a system: ceil(n / part_rows), at most kTeamMax, one per
 // kMinPartRows rows, and no more than the grid or what the GPU holds at once,
 // so that every team can assemble.
 int apply_config(gmres_batch* bt, int bs, int grid, int order, int64_t part_rows) {
+  drop_graph(bt);
   const int per_cu = batch_resident_blocks(bs, bt->m, bt->scheme == GMRES_MGS_1R_IR32);
   if (per_cu < 1) return GMRES_ERR_HIP;
   const int64_t resident = (int64_t)per_cu * bt->num_cu;
@@ -186,13 +196,6 @@ int enqueue(gmres_batch* bt, const double* b, double* x, double rtol, int64_t ma
   if (launch_batch(B, bt->bs, bt->grid_eff, bt->scheme == GMRES_MGS_1R_IR32, bt->stream, e0, e1))
     return GMRES_ERR_HIP;
   return GMRES_OK;
-}
-
-void drop_graph(gmres_batch* bt) {
-  if (bt->graph_exec) (void)hipGraphExecDestroy(bt->graph_exec);
-  if (bt->graph) (void)hipGraphDestroy(bt->graph);
-  bt->graph_exec = nullptr;
-  bt->graph = nullptr;
 }
 
 }  // namespace

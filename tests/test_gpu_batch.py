@@ -185,6 +185,40 @@ def test_graph_replay():
         assert np.isfinite(y)
 
 
+def test_graph_dropped_on_config_change():
+    """A configuration change discards the captured graph (it holds the old grid,
+    block size and queue): replay is refused until the next capture, whose
+    replays then equal the eager solve under the new configuration bit for bit."""
+    import torch
+
+    from paper_1809_05805_amd import native
+
+    bp = SMALL
+    log("batch graph dropped on set_config")
+    stream = torch.cuda.Stream()
+    s = solver(bp, stream=stream)
+    bt = torch.from_numpy(bp.b).cuda()
+    x = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    s.capture(bt, x, TOL, 20000)
+    s.set_config(512, 0, 1, 256)  # another block size and teams of 256-row parts
+    assert native.gmres_batch_replay(s.ctx) == native.GMRES_ERR_ARG
+    x_e = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        rc, info_e = s.solve(bt, x_e, TOL, 20000)
+    torch.cuda.synchronize()
+    assert rc == 0 and np.all(info_e["converged"] == 1)
+    s.capture(bt, x, TOL, 20000)
+    for rep in range(2):
+        with torch.cuda.stream(stream):
+            x.zero_()
+            s.replay()
+        stream.synchronize()
+        info = s.read_info()
+        assert torch.equal(x, x_e), rep
+        assert np.array_equal(info["iters"], info_e["iters"])
+
+
 def test_autotune():
     import torch
 
