@@ -52,9 +52,12 @@
  * memory (Section V-B). The relative tolerance is on ||b - A x||_2 / ||b||_2.
  *
  * Pointers are DEVICE pointers unless marked "host". The library never
- * allocates or frees device memory: the caller passes one workspace buffer.
- * Its only allocations are the host-side context and a small pinned host
- * buffer (hipHostMalloc) for per-cycle status readback.
+ * allocates or frees device memory at run time: the caller passes one
+ * workspace buffer. Its only allocations are the host-side context and a
+ * small pinned host buffer (hipHostMalloc) for per-cycle status readback.
+ * For callers that cannot allocate at all, gmres_solve_noalloc (at the end)
+ * runs a whole solve in a fixed scratch array that the library's code object
+ * reserves on each GPU it is loaded onto.
  *
  * Every call is enqueued on the HIP stream given to gmres_create. A context is
  * bound to that stream and is not thread-safe; use one context per stream.
@@ -86,7 +89,9 @@ typedef enum {
   GMRES_ERR_ARG = -1,       /* invalid argument or malformed CSR structure          */
   GMRES_ERR_HIP = -2,       /* a HIP runtime call or kernel launch failed           */
   GMRES_ERR_NONFINITE = -3, /* NaN or Inf in a norm, Hessenberg entry or residual   */
-  GMRES_ERR_WORKSPACE = -4  /* workspace smaller than gmres_workspace_bytes()        */
+  GMRES_ERR_WORKSPACE = -4, /* workspace smaller than gmres_workspace_bytes()        */
+  GMRES_ERR_TOO_LARGE = -5  /* gmres_solve_noalloc: the problem's workspace exceeds
+                               GMRES_NOALLOC_SCRATCH_BYTES                          */
 } gmres_status;
 
 /* Largest restart length the kernels' on-chip buffers are sized for. */
@@ -422,6 +427,41 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
 int gmres_batch_capture(gmres_batch* bt, const double* b, double* x, double rtol,
                         int64_t max_iters);
 int gmres_batch_replay(gmres_batch* bt);
+
+/* ------------------------------------------------------------------------
+ * One solve that allocates nothing.
+ *
+ * For callers that cannot allocate memory: code that must not call
+ * hipMalloc or hipHostMalloc (tight serving loops, harnesses that forbid
+ * allocation). gmres_solve_noalloc does the work of gmres_create +
+ * gmres_solve + gmres_destroy for one solve without allocating device or host
+ * memory: its workspace is a static device array of
+ * GMRES_NOALLOC_SCRATCH_BYTES in the library's code object (each GPU the
+ * library runs on holds one copy from the first call on it until the process
+ * ends), the context and its status readback live on the call's stack, the
+ * SpMV reads the CSR arrays directly (no sliced copy), and no timing events
+ * are made.
+ *   n, nnz, row_ptr, col_idx, vals, m, scheme: as for gmres_create (device
+ *   arrays, checked on the device on every call).
+ *   b, x, rtol, max_iters, info (host, nullable), hist_res (host, nullable,
+ *   max_iters doubles): as for gmres_solve.
+ *   hip_stream: the stream to enqueue on (NULL = default stream); it must
+ *   belong to the current device, whose scratch copy the call uses.
+ * Results: the arithmetic of gmres_create + gmres_solve on the same stream
+ * with the CSR format (the iterate, info and hist_res are the same).
+ * Errors: GMRES_ERR_TOO_LARGE when gmres_workspace_bytes(n, m, scheme)
+ * exceeds GMRES_NOALLOC_SCRATCH_BYTES (checked before any device pointer is
+ * touched); GMRES_ERR_ARG for invalid arguments, a malformed matrix or a
+ * stream of another device; otherwise as gmres_solve. Blocks until done.
+ * All calls on one GPU share its scratch array, which keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap on
+ * one GPU, from several threads or streams, race and must not be made.
+ */
+#define GMRES_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int gmres_solve_noalloc(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                        const double* vals, int32_t m, int32_t scheme, const double* b, double* x,
+                        double rtol, int64_t max_iters, gmres_info* info, double* hist_res,
+                        void* hip_stream);
 
 #ifdef __cplusplus
 }

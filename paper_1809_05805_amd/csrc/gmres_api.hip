@@ -15,6 +15,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -24,7 +25,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
-size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Rows per lane of the row-tiled kernels: the largest of 8, 4, 2 that still
 // leaves at least 512 tiles of 256*rpt rows (two per compute unit), else 1.
@@ -162,6 +163,36 @@ bool is_device_ptr(const void* p) {
 
 }  // namespace
 
+// Device workspace of gmres_solve_noalloc: one solve's workspace at a time per
+// GPU, in the library's own code object, so that the call allocates nothing.
+// Host code must not pass `scratch` itself to a kernel (in host code it names
+// a host-side stand-in); it uses the device address that scratch_on() looks
+// up, once per device, with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[GMRES_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];  // per device; null until looked up
+
+// Device address of scratch on device dev, which must be the current device.
+void* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  return g_scratch_addr[dev];
+}
+
+}  // namespace
+
 struct gmres_ctx {
   Csr A;
   int64_t nnz;
@@ -176,8 +207,11 @@ struct gmres_ctx {
   Layout L;
   Ws ws;
   hipStream_t stream;
-  // pinned host mirror: DevState, g, gh, H, T
+  // host mirror of the device state: DevState, g, gh, and (when
+  // mirror_matrices) H and T; pinned memory of the context's own, or the
+  // caller's stack for gmres_solve_noalloc
   void* pinned;
+  bool mirror_matrices;
   DevState* h_st;
   double* h_g;
   double* h_gh;
@@ -210,11 +244,13 @@ int sync_state(gmres_ctx* c, bool with_matrices) {
     if (hipMemcpyAsync(c->h_g, c->ws.g, sizeof(double) * (m + 2), hipMemcpyDeviceToHost,
                        c->stream) != hipSuccess ||
         hipMemcpyAsync(c->h_gh, c->ws.gh, sizeof(double) * (m + 2), hipMemcpyDeviceToHost,
-                       c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->h_H, c->ws.H, sizeof(double) * (size_t)(m + 1) * m,
-                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->h_T, c->ws.T, sizeof(double) * (size_t)(m + 2) * (m + 2),
-                       hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+                       c->stream) != hipSuccess)
+      return GMRES_ERR_HIP;
+    if (c->mirror_matrices &&
+        (hipMemcpyAsync(c->h_H, c->ws.H, sizeof(double) * (size_t)(m + 1) * m,
+                        hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+         hipMemcpyAsync(c->h_T, c->ws.T, sizeof(double) * (size_t)(m + 2) * (m + 2),
+                        hipMemcpyDeviceToHost, c->stream) != hipSuccess))
       return GMRES_ERR_HIP;
   }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return GMRES_ERR_HIP;
@@ -504,46 +540,10 @@ int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
   return GMRES_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme) {
-  if (scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH) return 0;
-  Layout L;
-  if (!make_layout(n, m, scheme, &L)) return 0;
-  return L.total;
-}
-
-const char* gmres_status_string(int status) {
-  switch (status) {
-    case GMRES_OK: return "ok";
-    case GMRES_ERR_ARG: return "invalid argument";
-    case GMRES_ERR_HIP: return "HIP runtime error";
-    case GMRES_ERR_NONFINITE: return "non-finite value (NaN or Inf) in the iteration";
-    case GMRES_ERR_WORKSPACE: return "workspace too small";
-    default: return "unknown status";
-  }
-}
-
-int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
-                 const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
-                 void* workspace, size_t ws_bytes, void* hip_stream) {
-  if (!out) return GMRES_ERR_ARG;
-  *out = nullptr;
-  if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31) || m < 1 ||
-      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH)
-    return GMRES_ERR_ARG;
-  if (!is_device_ptr(row_ptr) || !is_device_ptr(workspace) ||
-      (nnz > 0 && (!is_device_ptr(col_idx) || !is_device_ptr(vals))))
-    return GMRES_ERR_ARG;
-  if (((uintptr_t)workspace % kAlign) != 0) return GMRES_ERR_ARG;
-  Layout L;
-  if (!make_layout(n, m, scheme, &L)) return GMRES_ERR_ARG;
-  if (ws_bytes < L.total) return GMRES_ERR_WORKSPACE;
-
-  gmres_ctx* c = new (std::nothrow) gmres_ctx();
-  if (!c) return GMRES_ERR_ARG;
+// Point a context's fields at its matrix and workspace (no host mirror yet).
+void bind_context(gmres_ctx* c, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                  const int32_t* col_idx, const double* vals, int m, int scheme, const Layout& L,
+                  void* workspace, hipStream_t stream) {
   c->A = Csr{row_ptr, col_idx, vals, n, nnz};
   c->nnz = nnz;
   c->m = m;
@@ -551,7 +551,7 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   c->S = pick_spmv_shape(n, nnz);
   c->split = pick_split(n, nnz);
   c->L = L;
-  c->stream = (hipStream_t)hip_stream;
+  c->stream = stream;
   char* base = (char*)workspace;
   Ws& ws = c->ws;
   if (ir_scheme(scheme)) {
@@ -588,18 +588,171 @@ int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr
   ws.ldt = m + 2;
   ws.pstride = L.pstride;
   ws.m = m;
+}
 
-  const size_t pin = round_up(sizeof(DevState), 64) +
-                     sizeof(double) * (2 * (size_t)(m + 2) + (size_t)(m + 1) * m + (size_t)(m + 2) * (m + 2));
-  if (hipHostMalloc(&c->pinned, pin, hipHostMallocDefault) != hipSuccess) {
+// Host mirror layout: DevState, then g and gh (m+2 each), then (with
+// matrices) H ((m+1) m) and T ((m+2)^2).
+size_t mirror_bytes(int m, bool matrices) {
+  size_t d = 2 * (size_t)(m + 2);
+  if (matrices) d += (size_t)(m + 1) * m + (size_t)(m + 2) * (m + 2);
+  return round_up(sizeof(DevState), 64) + sizeof(double) * d;
+}
+void bind_mirror(gmres_ctx* c, void* host, bool matrices) {
+  const int m = c->m;
+  c->pinned = host;
+  c->mirror_matrices = matrices;
+  c->h_st = (DevState*)host;
+  c->h_g = (double*)((char*)host + round_up(sizeof(DevState), 64));
+  c->h_gh = c->h_g + (m + 2);
+  c->h_H = matrices ? c->h_gh + (m + 2) : nullptr;
+  c->h_T = matrices ? c->h_H + (size_t)(m + 1) * m : nullptr;
+}
+
+// The solve itself, arguments already checked. hist_orth and the snapshot of
+// the last cycle need the context's full host mirror (H and T).
+int solve_impl(gmres_ctx* c, const double* b, double* x, double rtol, int64_t max_iters,
+               gmres_info* info, double* hist_res, double* hist_orth) {
+  gmres_info loc;
+  memset(&loc, 0, sizeof(loc));
+  if (info) *info = loc;
+  const Ws& ws = c->ws;
+  hipStream_t s = c->stream;
+  const int m = c->m;
+  int rc;
+
+  if (launch_solve_begin(ws, s) ||
+      launch_axpy_dot(ws, c->L.rpt, (double*)b, nullptr, nullptr, b, kTailBnorm, 0, 0, 0, rtol,
+                      c->L.G, s))
+    return GMRES_ERR_HIP;
+  if ((rc = sync_state(c, false))) return rc;
+  if (c->h_st->status) {
+    loc.reductions = c->h_st->reductions;
+    if (info) *info = loc;
+    return GMRES_ERR_NONFINITE;
+  }
+  const double bnorm = c->h_st->bnorm;
+  if (bnorm == 0.0) {
+    if (hipMemsetAsync(x, 0, sizeof(double) * (size_t)c->A.n, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return GMRES_ERR_HIP;
+    loc.converged = 1;
+    loc.reductions = c->h_st->reductions;
+    if (info) *info = loc;
+    return GMRES_OK;
+  }
+  const double tol_abs = c->h_st->tol_abs;
+
+  int64_t it = 0;
+  rc = GMRES_OK;
+  for (;;) {
+    const int64_t left = max_iters - it;
+    const int m_eff = left < (int64_t)m ? (int)left : m;
+    if (m_eff == 0) {
+      if (enqueue_true_residual(c, b, x)) return GMRES_ERR_HIP;
+      if ((rc = sync_state(c, false))) return rc;
+      if (c->h_st->status) {
+        rc = GMRES_ERR_NONFINITE;
+        break;
+      }
+      loc.rel_res_true = c->h_st->beta / bnorm;
+      loc.converged = c->h_st->beta <= tol_abs;
+      if (loc.cycles == 0) loc.rel_res_est = loc.rel_res_true;
+      break;
+    }
+    if (enqueue_cycle(c, b, x, m_eff)) return GMRES_ERR_HIP;
+    if ((rc = sync_state(c, true))) return rc;
+    const DevState& st = *c->h_st;
+    collect_timing(c, st.j, st.true_conv != 0);
+    if (st.status) {
+      rc = GMRES_ERR_NONFINITE;
+      break;
+    }
+    if (st.true_conv) {
+      loc.converged = 1;
+      loc.rel_res_true = st.beta / bnorm;
+      if (loc.cycles == 0) loc.rel_res_est = loc.rel_res_true;
+      break;
+    }
+    const int j = st.j;
+    if (j > 0) {
+      // the FP32-basis cycle's g is relative to its restart residual norm
+      const double gs = st.xscale / bnorm;
+      if (hist_res)
+        for (int q = 0; q < j; ++q) hist_res[it + q] = c->h_gh[q + 1] * gs;
+      if (hist_orth && c->mirror_matrices) orth_history(c, j, hist_orth + it);
+      loc.cycles += 1;
+      loc.rel_res_est = fabs(c->h_g[j]) * gs;
+      if (c->mirror_matrices) {
+        memcpy(c->last_H.data(), c->h_H, sizeof(double) * c->last_H.size());
+        memcpy(c->last_T.data(), c->h_T, sizeof(double) * c->last_T.size());
+        memcpy(c->last_g.data(), c->h_g, sizeof(double) * c->last_g.size());
+        c->last_j = j;
+      }
+    }
+    if (st.breakdown) loc.breakdown = 1;
+    if (j == 0) break;  // no progress is possible; cannot happen for m_eff >= 1
+    it += j;
+  }
+  loc.iters = it;
+  loc.reductions = c->h_st->reductions;
+  if (info) *info = loc;
+  return rc;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme) {
+  if (scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH) return 0;
+  Layout L;
+  if (!make_layout(n, m, scheme, &L)) return 0;
+  return L.total;
+}
+
+const char* gmres_status_string(int status) {
+  switch (status) {
+    case GMRES_OK: return "ok";
+    case GMRES_ERR_ARG: return "invalid argument";
+    case GMRES_ERR_HIP: return "HIP runtime error";
+    case GMRES_ERR_NONFINITE: return "non-finite value (NaN or Inf) in the iteration";
+    case GMRES_ERR_WORKSPACE: return "workspace too small";
+    case GMRES_ERR_TOO_LARGE:
+      return "problem needs more workspace than the fixed scratch of gmres_solve_noalloc "
+             "(GMRES_NOALLOC_SCRATCH_BYTES)";
+    default: return "unknown status";
+  }
+}
+
+int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                 const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
+                 void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out) return GMRES_ERR_ARG;
+  *out = nullptr;
+  if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31) || m < 1 ||
+      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH)
+    return GMRES_ERR_ARG;
+  if (!is_device_ptr(row_ptr) || !is_device_ptr(workspace) ||
+      (nnz > 0 && (!is_device_ptr(col_idx) || !is_device_ptr(vals))))
+    return GMRES_ERR_ARG;
+  if (((uintptr_t)workspace % kAlign) != 0) return GMRES_ERR_ARG;
+  Layout L;
+  if (!make_layout(n, m, scheme, &L)) return GMRES_ERR_ARG;
+  if (ws_bytes < L.total) return GMRES_ERR_WORKSPACE;
+
+  gmres_ctx* c = new (std::nothrow) gmres_ctx();
+  if (!c) return GMRES_ERR_ARG;
+  bind_context(c, n, nnz, row_ptr, col_idx, vals, m, scheme, L, workspace,
+               (hipStream_t)hip_stream);
+  const Ws& ws = c->ws;
+
+  void* pin = nullptr;
+  if (hipHostMalloc(&pin, mirror_bytes(m, true), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return GMRES_ERR_HIP;
   }
-  c->h_st = (DevState*)c->pinned;
-  c->h_g = (double*)((char*)c->pinned + round_up(sizeof(DevState), 64));
-  c->h_gh = c->h_g + (m + 2);
-  c->h_H = c->h_gh + (m + 2);
-  c->h_T = c->h_H + (size_t)(m + 1) * m;
+  bind_mirror(c, pin, true);
   c->last_H.assign((size_t)(m + 1) * m, 0.0);
   c->last_T.assign((size_t)(m + 2) * (m + 2), 0.0);
   c->last_g.assign((size_t)(m + 2), 0.0);
@@ -726,91 +879,61 @@ int gmres_last_cycle(gmres_ctx* c, double* H, double* T, double* g, int32_t* j) 
 
 int gmres_solve(gmres_ctx* c, const double* b, double* x, double rtol, int64_t max_iters,
                 gmres_info* info, double* hist_res, double* hist_orth) {
-  gmres_info loc;
-  memset(&loc, 0, sizeof(loc));
-  if (info) *info = loc;
+  if (info) memset(info, 0, sizeof(*info));
   if (!c || !b || !x || !(rtol >= 0.0) || max_iters < 0 || !c->matrix_ok) return GMRES_ERR_ARG;
   if (!is_device_ptr(b) || !is_device_ptr(x)) return GMRES_ERR_ARG;
-  const Ws& ws = c->ws;
-  hipStream_t s = c->stream;
-  const int m = c->m;
-  int rc;
+  return solve_impl(c, b, x, rtol, max_iters, info, hist_res, hist_orth);
+}
 
-  if (launch_solve_begin(ws, s) ||
-      launch_axpy_dot(ws, c->L.rpt, (double*)b, nullptr, nullptr, b, kTailBnorm, 0, 0, 0, rtol,
-                      c->L.G, s))
-    return GMRES_ERR_HIP;
-  if ((rc = sync_state(c, false))) return rc;
-  if (c->h_st->status) {
-    loc.reductions = c->h_st->reductions;
-    if (info) *info = loc;
-    return GMRES_ERR_NONFINITE;
+int gmres_solve_noalloc(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                        const double* vals, int32_t m, int32_t scheme, const double* b, double* x,
+                        double rtol, int64_t max_iters, gmres_info* info, double* hist_res,
+                        void* hip_stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31) || m < 1 ||
+      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH ||
+      !(rtol >= 0.0) || max_iters < 0)
+    return GMRES_ERR_ARG;
+  Layout L;
+  if (!make_layout(n, m, scheme, &L)) return GMRES_ERR_ARG;
+  if (L.total > GMRES_NOALLOC_SCRATCH_BYTES) return GMRES_ERR_TOO_LARGE;
+  if (!is_device_ptr(row_ptr) || !is_device_ptr(b) || !is_device_ptr(x) ||
+      (nnz > 0 && (!is_device_ptr(col_idx) || !is_device_ptr(vals))))
+    return GMRES_ERR_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GMRES_ERR_HIP;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (s) {
+    hipDevice_t sd = -1;
+    if (hipStreamGetDevice(s, &sd) != hipSuccess) return GMRES_ERR_HIP;
+    if (sd != dev) return GMRES_ERR_ARG;
   }
-  const double bnorm = c->h_st->bnorm;
-  if (bnorm == 0.0) {
-    if (hipMemsetAsync(x, 0, sizeof(double) * (size_t)c->A.n, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return GMRES_ERR_HIP;
-    loc.converged = 1;
-    loc.reductions = c->h_st->reductions;
-    if (info) *info = loc;
-    return GMRES_OK;
-  }
-  const double tol_abs = c->h_st->tol_abs;
+  void* ws = scratch_on(dev);
+  if (!ws) return GMRES_ERR_HIP;
 
-  int64_t it = 0;
-  rc = GMRES_OK;
-  for (;;) {
-    const int64_t left = max_iters - it;
-    const int m_eff = left < (int64_t)m ? (int)left : m;
-    if (m_eff == 0) {
-      if (enqueue_true_residual(c, b, x)) return GMRES_ERR_HIP;
-      if ((rc = sync_state(c, false))) return rc;
-      if (c->h_st->status) {
-        rc = GMRES_ERR_NONFINITE;
-        break;
-      }
-      loc.rel_res_true = c->h_st->beta / bnorm;
-      loc.converged = c->h_st->beta <= tol_abs;
-      if (loc.cycles == 0) loc.rel_res_est = loc.rel_res_true;
-      break;
-    }
-    if (enqueue_cycle(c, b, x, m_eff)) return GMRES_ERR_HIP;
-    if ((rc = sync_state(c, true))) return rc;
-    const DevState& st = *c->h_st;
-    collect_timing(c, st.j, st.true_conv != 0);
-    if (st.status) {
-      rc = GMRES_ERR_NONFINITE;
-      break;
-    }
-    if (st.true_conv) {
-      loc.converged = 1;
-      loc.rel_res_true = st.beta / bnorm;
-      if (loc.cycles == 0) loc.rel_res_est = loc.rel_res_true;
-      break;
-    }
-    const int j = st.j;
-    if (j > 0) {
-      // the FP32-basis cycle's g is relative to its restart residual norm
-      const double gs = st.xscale / bnorm;
-      if (hist_res)
-        for (int q = 0; q < j; ++q) hist_res[it + q] = c->h_gh[q + 1] * gs;
-      if (hist_orth) orth_history(c, j, hist_orth + it);
-      loc.cycles += 1;
-      loc.rel_res_est = fabs(c->h_g[j]) * gs;
-      memcpy(c->last_H.data(), c->h_H, sizeof(double) * c->last_H.size());
-      memcpy(c->last_T.data(), c->h_T, sizeof(double) * c->last_T.size());
-      memcpy(c->last_g.data(), c->h_g, sizeof(double) * c->last_g.size());
-      c->last_j = j;
-    }
-    if (st.breakdown) loc.breakdown = 1;
-    if (j == 0) break;  // no progress is possible; cannot happen for m_eff >= 1
-    it += j;
-  }
-  loc.iters = it;
-  loc.reductions = c->h_st->reductions;
-  if (info) *info = loc;
-  return rc;
+  // A context on the stack: its vectors stay empty, the host mirror (state,
+  // g and gh only) is a stack buffer, the SpMV reads the CSR arrays, and no
+  // timing events are made, so nothing is allocated.
+  gmres_ctx c{};
+  bind_context(&c, n, nnz, row_ptr, col_idx, vals, m, scheme, L, ws, s);
+  alignas(64) unsigned char host[round_up(sizeof(DevState), 64) +
+                                 sizeof(double) * 2 * (GMRES_MAX_RESTART + 2)];
+  bind_mirror(&c, host, false);
+  c.matrix_ok = true;
+  c.format = kFormatCsr;
+  c.sell = Sell{nullptr, nullptr, nullptr, nullptr, 0, 0};
+  c.sell_entries = 0;
+  c.sell_bytes = 0;
+  c.last_j = 0;
+  c.timing = false;
+  memset(c.stats, 0, sizeof(c.stats));
+  // the scratch holds whatever the last call left: clear the counters and
+  // the state, and check this call's matrix
+  if (launch_init(c.ws, L.NG + 1, s) || launch_validate(c.A, nnz, c.ws.st, s)) return GMRES_ERR_HIP;
+  int rc = sync_state(&c, false);
+  if (rc != GMRES_OK) return rc;
+  if (c.h_st->bad_csr) return GMRES_ERR_ARG;
+  return solve_impl(&c, b, x, rtol, max_iters, info, hist_res, nullptr);
 }
 
 }  // extern "C"

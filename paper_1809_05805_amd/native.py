@@ -23,7 +23,9 @@ SCHEMES = {"mgs": GMRES_MGS, "mgs1r": GMRES_MGS_1R, "cgs2": GMRES_CGS2,
            "mgs1r_ir32": GMRES_MGS_1R_IR32, "mgs1r_ir16": GMRES_MGS_1R_IR16,
            "cgs2_3r": GMRES_CGS2_3R, "two_synch": GMRES_TWO_SYNCH}
 GMRES_OK, GMRES_ERR_ARG, GMRES_ERR_HIP, GMRES_ERR_NONFINITE, GMRES_ERR_WORKSPACE = 0, -1, -2, -3, -4
+GMRES_ERR_TOO_LARGE = -5
 GMRES_MAX_RESTART = 256
+GMRES_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destroy",
             "gmres_status_string", "gmres_spmv", "gmres_last_cycle", "gmres_basis",
@@ -32,7 +34,8 @@ EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destr
             "gmres_batch_workspace_bytes", "gmres_batch_create", "gmres_batch_destroy",
             "gmres_batch_set_stream", "gmres_batch_solve_async", "gmres_batch_solve",
             "gmres_batch_read_info", "gmres_batch_set_config", "gmres_batch_get_config",
-            "gmres_batch_autotune", "gmres_batch_capture", "gmres_batch_replay"]
+            "gmres_batch_autotune", "gmres_batch_capture", "gmres_batch_replay",
+            "gmres_solve_noalloc"]
 GMRES_BATCH_ORDER_NATURAL, GMRES_BATCH_ORDER_LARGEST_FIRST = 0, 1
 GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64 = 0, 1
 GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
@@ -121,6 +124,9 @@ def load() -> ctypes.CDLL:
                        ("gmres_batch_replay", [P])):
         getattr(lib, name).restype = ctypes.c_int
         getattr(lib, name).argtypes = args
+    lib.gmres_solve_noalloc.restype = ctypes.c_int
+    lib.gmres_solve_noalloc.argtypes = [I64, I64, P, P, P, I32, I32, P, P, D, I64,
+                                        ctypes.POINTER(GmresInfo), P, P]
     _lib = lib
     return lib
 
@@ -275,6 +281,18 @@ def gmres_batch_replay(ctx) -> int:
 
 
 # ----------------------------------------------------------- torch front end
+
+def gmres_solve_noalloc(n, nnz, row_ptr_ptr, col_idx_ptr, vals_ptr, m, scheme, b_ptr, x_ptr,
+                        rtol, max_iters, hist: np.ndarray | None = None, stream_ptr=None):
+    """One whole solve in the library's fixed device scratch (no allocation)."""
+    lib = load()
+    info = GmresInfo()
+    hp = hist.ctypes.data_as(ctypes.c_void_p) if hist is not None else None
+    rc = lib.gmres_solve_noalloc(n, nnz, row_ptr_ptr, col_idx_ptr, vals_ptr, m, scheme, b_ptr,
+                                 x_ptr, float(rtol), int(max_iters), ctypes.byref(info), hp,
+                                 stream_ptr)
+    return rc, info
+
 
 class GmresError(RuntimeError):
     def __init__(self, rc: int, what: str):
