@@ -21,18 +21,33 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle_gmres.c")
 _LIB = os.path.join(_HERE, "liboracle_gmres.so")
+# Builds of the same source: "double" is the oracle; "long double" the
+# test-only reference whose long sums (SpMV rows and length-n dot products)
+# accumulate in long double (ORACLE_ACC); "openmp" a timing-only build whose
+# length-n loops run on all host cores (ORACLE_OMP), never used for parity.
+_BUILDS = {
+    "double": (_LIB, []),
+    "long double": (os.path.join(_HERE, "liboracle_gmres_ld.so"), ["-DORACLE_ACC=long double"]),
+    "openmp": (os.path.join(_HERE, "liboracle_gmres_omp.so"), ["-fopenmp", "-DORACLE_OMP"]),
+}
 
 SCHEMES = {"mgs": 0, "mgs1r": 1, "cgs2": 2, "cgs2_3r": 3, "two_synch": 4}
 STATUS = {0: "ok", -1: "invalid argument", -3: "non-finite value"}
 
 
+def _compile(out: str, extra: list[str]) -> None:
+    tmp = out + f".tmp{os.getpid()}"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+                    "-ffp-contract=off", *extra, "-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2: no FMA contraction, no vector ISA flags)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-                        "-ffp-contract=off", "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain -O2: no FMA contraction, no vector ISA
+    flags), its long-double-sum reference build and its OpenMP timing build."""
+    for path, extra in _BUILDS.values():
+        if force or not os.path.exists(path):
+            _compile(path, extra)
     return _LIB
 
 
@@ -43,15 +58,20 @@ class _Info(ctypes.Structure):
                 ("rel_res_est", ctypes.c_double), ("reductions", ctypes.c_int64)]
 
 
-_lib = None
+_libs: dict[str, ctypes.CDLL] = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def _load(acc: str = "double"):
+    """The oracle library: acc "double" (the oracle), "long double" (the
+    test-only reference build whose long sums carry 11 more bits) or "openmp"
+    (the timing build)."""
+    if acc not in _BUILDS:
+        raise ValueError(acc)
+    if acc not in _libs:
+        path = _BUILDS[acc][0]
+        if not os.path.exists(path):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.oracle_gmres_solve.restype = ctypes.c_int
         lib.oracle_gmres_solve.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, ctypes.c_int32,
@@ -64,8 +84,8 @@ def _load():
                                                  ctypes.POINTER(_Info), P, P, P, P, P, P, P]
         lib.oracle_spmv.restype = None
         lib.oracle_spmv.argtypes = [ctypes.c_int64, P, P, P, P, P]
-        _lib = lib
-    return _lib
+        _libs[acc] = lib
+    return _libs[acc]
 
 
 def _ptr(a):
@@ -93,11 +113,14 @@ class OracleResult:
 
 
 def solve(row_ptr, col_idx, vals, b, x0, m: int, scheme: str = "mgs1r", rtol: float = 1e-8,
-          max_iters: int | None = None, dump: bool = False, depth: int = 1) -> OracleResult:
+          max_iters: int | None = None, dump: bool = False, depth: int = 1,
+          acc: str = "double") -> OracleResult:
     """Restarted GMRES(m) on host arrays; see ``oracle_gmres.h`` for the contract.
     depth: the pipeline depth of the lagged schemes (rotations and the stopping
-    test applied depth columns at a time)."""
-    lib = _load()
+    test applied depth columns at a time). acc: "long double" runs the
+    test-only reference build (long sums in extended precision), "openmp" the
+    timing build (threads from OMP_NUM_THREADS)."""
+    lib = _load(acc)
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
     vals = np.ascontiguousarray(vals, dtype=np.float64)
@@ -133,8 +156,8 @@ def solve(row_ptr, col_idx, vals, b, x0, m: int, scheme: str = "mgs1r", rtol: fl
     return res
 
 
-def spmv(row_ptr, col_idx, vals, x) -> np.ndarray:
-    lib = _load()
+def spmv(row_ptr, col_idx, vals, x, acc: str = "double") -> np.ndarray:
+    lib = _load(acc)
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
     vals = np.ascontiguousarray(vals, dtype=np.float64)

@@ -30,12 +30,41 @@ typedef struct {
   const double* vals;
 } csr_t;
 
+/*
+ * Accumulator of the long sums: the SpMV row sums and the length-n dot
+ * products. FP64 in the oracle proper. A second, test-only build defines
+ * ORACLE_ACC as long double (x87 extended precision, 64-bit significand):
+ * every product is still the FP64 product, rounded once, but the sums carry
+ * 11 more bits, so that build's results differ from exact-sum arithmetic by
+ * about 2^-11 of what the FP64 oracle's sequential sums contribute. It is the
+ * reference against which the FP64 oracle's and the GPU's summation errors
+ * are compared; the algorithm and its order are the same.
+ */
+#ifndef ORACLE_ACC
+#define ORACLE_ACC double
+#endif
+
+/*
+ * A third, timing-only build (ORACLE_OMP, with -fopenmp) runs the length-n
+ * loops as OpenMP parallel loops: row-wise loops keep their arithmetic, and a
+ * dot product then sums per thread and adds the threads' sums. It times the
+ * oracle on all of a host's cores; parity always uses the sequential build.
+ */
+#ifdef ORACLE_OMP
+#define ORACLE_ROWS _Pragma("omp parallel for schedule(static)")
+#define ORACLE_SUM _Pragma("omp parallel for schedule(static) reduction(+ : s)")
+#else
+#define ORACLE_ROWS
+#define ORACLE_SUM
+#endif
+
 void oracle_spmv(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
                  const double* x, double* y) {
+  ORACLE_ROWS
   for (int64_t i = 0; i < n; ++i) {
-    double s = 0.0;
-    for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += vals[e] * x[col_idx[e]];
-    y[i] = s;
+    ORACLE_ACC s = 0.0;
+    for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) s += (ORACLE_ACC)(vals[e] * x[col_idx[e]]);
+    y[i] = (double)s;
   }
 }
 
@@ -44,9 +73,10 @@ static void spmv(const csr_t* A, const double* x, double* y) {
 }
 
 static double dot(int64_t n, const double* a, const double* b) {
-  double s = 0.0;
-  for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
-  return s;
+  ORACLE_ACC s = 0.0;
+  ORACLE_SUM
+  for (int64_t i = 0; i < n; ++i) s += (ORACLE_ACC)(a[i] * b[i]);
+  return (double)s;
 }
 
 /*
@@ -187,6 +217,7 @@ static void update_solution(ws_t* ws, int j, double* x) {
   for (int q = 0; q < j; ++q) {
     const double* v = VC(ws, q);
     double yq = ws->y[q];
+    ORACLE_ROWS
     for (int64_t i = 0; i < ws->n; ++i) x[i] += v[i] * yq;
   }
 }
@@ -202,6 +233,7 @@ typedef struct {
 static void residual_into_v0(const csr_t* A, const double* b, const double* x, ws_t* ws) {
   double* v0 = VC(ws, 0);
   spmv(A, x, ws->w);
+  ORACLE_ROWS
   for (int64_t i = 0; i < A->n; ++i) v0[i] = b[i] - ws->w[i];
 }
 
@@ -231,6 +263,7 @@ static int cycle_mgs(const csr_t* A, const double* b, double* x, int m_eff, doub
     return ORACLE_OK;
   }
   if (m_eff == 0) return ORACLE_OK;
+  ORACLE_ROWS
   for (int64_t i = 0; i < n; ++i) v0[i] = v0[i] / beta;
   for (int i = 0; i < m_eff; ++i) {
     double* w = VC(ws, i + 1);
@@ -239,6 +272,7 @@ static int cycle_mgs(const csr_t* A, const double* b, double* x, int m_eff, doub
       const double* vq = VC(ws, q);
       double hq = dot(n, w, vq);
       (*nred)++;
+      ORACLE_ROWS
       for (int64_t e = 0; e < n; ++e) w[e] = w[e] - hq * vq[e];
       HH(ws, q, i) = hq;
     }
@@ -258,6 +292,7 @@ static int cycle_mgs(const csr_t* A, const double* b, double* x, int m_eff, doub
       out->j = i + 1;
       return ORACLE_OK;
     }
+    ORACLE_ROWS
     for (int64_t e = 0; e < n; ++e) w[e] = w[e] / hn;
     if (gk <= tol_abs) {
       out->j = i + 1;
@@ -315,6 +350,7 @@ static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, doub
     return ORACLE_OK;
   }
   if (m_eff == 0) return ORACLE_OK;
+  ORACLE_ROWS
   for (int64_t i = 0; i < n; ++i) v0[i] = v0[i] / beta;
   for (int i = 0; i < m_eff; ++i) {
     double* w = VC(ws, i + 1);
@@ -326,6 +362,7 @@ static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, doub
         for (int q = 0; q <= i; ++q) {
           const double* vq = VC(ws, q);
           double sq = ws->p[q];
+          ORACLE_ROWS
           for (int64_t e = 0; e < n; ++e) w[e] = w[e] - vq[e] * sq;
           HH(ws, q, i) = HH(ws, q, i) + sq;
         }
@@ -343,6 +380,7 @@ static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, doub
       for (int q = 0; q <= i; ++q) {
         const double* vq = VC(ws, q);
         double rq = ws->r[q];
+        ORACLE_ROWS
         for (int64_t e = 0; e < n; ++e) w[e] = w[e] - vq[e] * rq;
         HH(ws, q, i) = rq;
       }
@@ -363,6 +401,7 @@ static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, doub
       out->j = i + 1;
       return ORACLE_OK;
     }
+    ORACLE_ROWS
     for (int64_t e = 0; e < n; ++e) w[e] = w[e] / hn;
     if (gk <= tol_abs) {
       out->j = i + 1;
@@ -467,6 +506,7 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
     }
 
     /* lagged normalization of column k and the new row of L */
+    ORACLE_ROWS
     for (int64_t i = 0; i < n; ++i) u[i] = u[i] / rho;
     for (int q = 0; q < k; ++q) ws->p[q] = ws->p[q] / rho;
     if (scheme == ORACLE_MGS_1R) {
@@ -499,10 +539,12 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
         for (int q = 0; q <= i; ++q) s += TT(ws, q, i) * ws->r[q];
         ws->h[i] = s;
       }
+      ORACLE_ROWS
       for (int64_t e = 0; e < n; ++e) vnext[e] = ws->w[e] / rho;
       for (int q = 0; q <= k; ++q) {
         const double* vq = VC(ws, q);
         double hq = ws->h[q];
+        ORACLE_ROWS
         for (int64_t e = 0; e < n; ++e) vnext[e] = vnext[e] - vq[e] * hq;
       }
       for (int q = 0; q <= k; ++q) HH(ws, q, k) = ws->h[q];
@@ -513,10 +555,12 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
         for (int q = 0; q < i; ++q) s -= LL(ws, i, q) * ws->r[q];
         ws->h[i] = s;
       }
+      ORACLE_ROWS
       for (int64_t e = 0; e < n; ++e) vnext[e] = ws->w[e] / rho;
       for (int q = 0; q <= k; ++q) {
         const double* vq = VC(ws, q);
         double hq = ws->h[q];
+        ORACLE_ROWS
         for (int64_t e = 0; e < n; ++e) vnext[e] = vnext[e] - vq[e] * hq;
       }
       /* second reduction: s = V[:,0:k+1]^T z, then z = z - V s */
@@ -525,6 +569,7 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
       for (int q = 0; q <= k; ++q) {
         const double* vq = VC(ws, q);
         double sq = ws->y[q];
+        ORACLE_ROWS
         for (int64_t e = 0; e < n; ++e) vnext[e] = vnext[e] - vq[e] * sq;
       }
       for (int q = 0; q <= k; ++q) HH(ws, q, k) = ws->h[q] + ws->y[q];
@@ -587,6 +632,7 @@ int oracle_gmres_solve_depth(int64_t n, int64_t nnz, const int32_t* row_ptr,
     return ORACLE_ERR_NONFINITE;
   }
   if (bnorm == 0.0) {
+    ORACLE_ROWS
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
     loc.converged = 1;
     if (info) *info = loc;

@@ -405,3 +405,48 @@ def test_pipeline_refusals():
     for scheme, depth in (("mgs1r", 0), ("mgs", 2), ("cgs2_3r", 2), ("two_synch", 3)):
         r = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, 10, scheme, 1e-8, 100, depth=depth)
         assert r.status == -1
+
+
+# ------------------------------------------- the oracle's other two builds
+def test_long_double_build_sums_in_extended_precision():
+    """The reference build's long sums carry a 64-bit significand: a row whose
+    exact sum is 1 but whose FP64 running sum rounds it away (1e16 + 1 - 1e16)
+    gives 1 there and 0 in the oracle."""
+    rp = np.array([0, 3], dtype=np.int32)
+    ci = np.zeros(3, dtype=np.int32)
+    va = np.array([1e16, 1.0, -1e16])
+    x = np.ones(1)
+    assert oracle.spmv(rp, ci, va, x)[0] == 0.0
+    assert oracle.spmv(rp, ci, va, x, acc="long double")[0] == 1.0
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_long_double_build_is_the_same_algorithm(scheme):
+    """Same iterates as the oracle up to rounding (and LU on a full Krylov space),
+    and at least as close to exact arithmetic: on the row-scaled 27-point system
+    (kappa ~ 1e8) its basis keeps orthogonality no worse than the oracle's."""
+    p = P.random_dense(24, seed=5)
+    A = p.scipy().toarray()
+    r = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, 24, scheme, 0.0, 24,
+                     acc="long double")
+    x_lu = np.linalg.solve(A, p.b)
+    assert np.linalg.norm(r.x - x_lu) <= 1e2 * np.linalg.cond(A) * EPS * np.linalg.norm(x_lu)
+    q = P.make_config("stencil27", N=10)
+    a = run(q, scheme, m=40, rtol=0.0, max_iters=40, dump=True)
+    b = oracle.solve(q.row_ptr, q.col_idx, q.vals, q.b, q.x0, 40, scheme, 0.0, 40, dump=True,
+                     acc="long double")
+    assert a.iters == b.iters == 40 and a.reductions == b.reductions
+    assert np.linalg.norm(a.x - b.x) <= 1e-8 * np.linalg.norm(b.x)
+    la, lb = D.orth_loss(a.V[:, :40]), D.orth_loss(b.V[:, :40])
+    assert lb <= 2 * la + 1e-15, (la, lb)
+
+
+def test_openmp_timing_build_matches():
+    """The OpenMP timing build runs the same algorithm: same iteration count and
+    iterate to rounding (its dot products sum per thread)."""
+    p = P.make_config("convdiff2d", N=24)
+    a = run(p, "mgs1r", m=20, rtol=1e-8, max_iters=400)
+    b = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, 20, "mgs1r", 1e-8, 400,
+                     acc="openmp")
+    assert b.converged and abs(a.iters - b.iters) <= 1
+    assert np.linalg.norm(a.x - b.x) <= 1e-8 * np.linalg.norm(a.x)
