@@ -93,6 +93,11 @@ struct Team {
 
 // All parts of the team have arrived: every store made before it by any
 // part (completed, agent-scope where another part reads it) is visible.
+// The counter is relaxed, not a release/acquire pair: visibility rests on each
+// part's stores being acknowledged (s_waitcnt vmcnt(0)) before it arrives and
+// on the agent-scope encoding, which keeps those accesses coherent across the
+// XCDs' otherwise non-coherent L2 caches. Repeated solves of a whole batch
+// with teams are tested to be bitwise equal.
 // The wait is bounded by `spins` polls (short sleeps for the first 4096, then
 // long ones; the default limit is at least about half a minute in all): a team
 // that cannot assemble ends its solve with a failure instead of holding the

@@ -336,6 +336,32 @@ def test_full_batch(scheme):
     del A
 
 
+def test_full_batch_repeat_bitwise():
+    """The team barrier and the per-system reductions sum in a fixed order: the
+    whole 512-system batch, solved twice on one context with teams of parts
+    (the configuration the autotuner picks), gives bitwise equal iterates and
+    iteration counts, and so does a second context."""
+    import torch
+
+    bp = P.make_batch()
+    log(f"full batch repeat: n={bp.n}")
+    outs = []
+    for _ in range(2):
+        s = solver(bp)
+        s.set_config(1024, 0, 1, 4096)
+        bt = torch.from_numpy(bp.b).cuda()
+        for _ in range(2):
+            xt = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+            rc, info = s.solve(bt, xt, TOL, 20000)
+            torch.cuda.synchronize()
+            assert rc == 0 and np.all(info["converged"] == 1)
+            outs.append((xt.cpu().numpy(), info["iters"].copy()))
+        s.close()
+    for x, it in outs[1:]:
+        assert np.array_equal(it, outs[0][1])
+        assert np.array_equal(x, outs[0][0])
+
+
 def test_team_wait_limit():
     """A team whose parts stop waiting gives up with GMRES_ERR_HIP for that
     system, and every kernel still ends. The wait limit is forced to zero polls

@@ -83,19 +83,26 @@ def test_fixed_budget_cycle_parity(scheme, case, fmt):
     p = CASES[case]
     m = min(p.m, 40)
     log(f"fixed-budget {scheme} {case} {fmt} n={p.n} m={m}")
-    g = gpu_run(p, scheme, m=m, rtol=0.0, max_iters=m, fmt=fmt)
+    g = gpu_run(p, scheme, m=m, rtol=0.0, max_iters=m, fmt=fmt, basis=True)
     o = oracle_run(p, scheme, m=m, rtol=0.0, max_iters=m)
     r = g["res"]
     assert r.status == 0 and o.status == 0
     assert r.iters == o.iters == m and g["j"] == o.j == m
     assert r.reductions == o.reductions
     assert rel(g["x"], o.x) <= TOL
+    assert np.max(np.abs(g["x"] - o.x)) <= TOL * np.max(np.abs(o.x))
     assert np.max(np.abs(r.hist - o.hist)) <= TOL
     eps = np.finfo(float).eps
-    r_c = np.concatenate([[1.0], o.hist[: m - 1]])
+    r_c = np.concatenate([[1.0], o.hist[:m]])
     for c in range(m):
         tol_c = TOL + 1e3 * eps / max(r_c[c], 1e-300)
         assert rel(g["H"][:, c], o.H[:, c]) <= tol_c, (c, r_c[c])
+    # the basis element by element; the cycle ends with the norm of column m,
+    # which then stays unnormalized (no kernel of the cycle runs after it)
+    for c in range(m):
+        tol_c = TOL + 1e3 * eps / max(r_c[c], 1e-300)
+        err = np.max(np.abs(g["V"][:, c] - o.V[:, c]))
+        assert err <= tol_c * np.max(np.abs(o.V[:, c])), (c, r_c[c])
     kc = int(np.argmax(r_c < 1e-4)) if np.any(r_c < 1e-4) else m
     assert abs(r.rel_res_true - o.rel_res_true) <= TOL * max(o.rel_res_true, 1e-3)
     if scheme == "mgs1r":
