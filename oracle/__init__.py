@@ -30,6 +30,13 @@ _BUILDS = {
     "long double": (os.path.join(_HERE, "liboracle_gmres_ld.so"), ["-DORACLE_ACC=long double"]),
     "openmp": (os.path.join(_HERE, "liboracle_gmres_omp.so"), ["-fopenmp", "-DORACLE_OMP"]),
 }
+# A checking build of the oracle itself (not one of its arithmetic variants):
+# AddressSanitizer and UndefinedBehaviorSanitizer, any report fatal. With
+# ORACLE_SANITIZE=1 in the environment it replaces the "double" build; the
+# process must then preload the sanitizer runtimes (tests/test_oracle_sanitize.py).
+_SANITIZED = (os.path.join(_HERE, "liboracle_gmres_san.so"),
+              ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=all"])
 
 SCHEMES = {"mgs": 0, "mgs1r": 1, "cgs2": 2, "cgs2_3r": 3, "two_synch": 4}
 STATUS = {0: "ok", -1: "invalid argument", -3: "non-finite value"}
@@ -51,6 +58,12 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized() -> str:
+    """Compile the checking build (AddressSanitizer + UBSan) of the oracle."""
+    _compile(*_SANITIZED)
+    return _SANITIZED[0]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("cycles", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("breakdown", ctypes.c_int32),
@@ -69,6 +82,8 @@ def _load(acc: str = "double"):
         raise ValueError(acc)
     if acc not in _libs:
         path = _BUILDS[acc][0]
+        if acc == "double" and os.environ.get("ORACLE_SANITIZE") == "1":
+            path = _SANITIZED[0]
         if not os.path.exists(path):
             build(force=False)
         lib = ctypes.CDLL(path)
