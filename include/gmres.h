@@ -117,6 +117,56 @@ typedef struct {
 size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
 
 /*
+ * Launch and format choices of a context, for gmres_workspace_bytes_ex and
+ * gmres_create_ex. Zero every field (gmres_options_init) and set only what
+ * should differ: a zero field always means the library's own choice, which
+ * is what gmres_workspace_bytes and gmres_create use. The arithmetic of a
+ * solve does not depend on these, except the pipeline depth (below) and the
+ * order of the per-row sums, which changes with the format (rounding only).
+ *   format: GMRES_OPT_FORMAT_AUTO (sliced copy of A for regular matrices,
+ *     see gmres_create), _CSR (always read the CSR arrays) or _SELL64 (plan
+ *     the sliced copy whatever its padding; rows wider than 4096 or n >= 2^28
+ *     still fall back to CSR).
+ *   rows_per_lane: 0, or 1, 2, 4 or 8 rows per lane of the row-tiled kernels
+ *     (tiles of 256 rows per lane-row). The default is the largest that leaves
+ *     at least 512 tiles. The workspace size depends on it: give the same
+ *     options to gmres_workspace_bytes_ex and gmres_create_ex.
+ *   csr_spmv_shape: 0, or the CSR SpMV shape as 100 * (lanes per row) +
+ *     (entries per lane): 108, 208, 408, 804, 808 or 6401. The default
+ *     follows the mean row length.
+ *   split_spmv: 0 computes w = A u inside the step kernel; 1 in a launch of
+ *     its own before it (the step kernel then reads w back).
+ *   pipeline_depth: 0 or 1 applies the Givens rotations and the stopping test
+ *     every step; L >= 2 (the lagged schemes GMRES_MGS_1R, GMRES_CGS2 and the
+ *     refinement forms only) every L steps, to the L columns finished since
+ *     (Section III, the depth-L pipeline; the paper's listing has L = 2). The
+ *     rotations feed nothing back into the Arnoldi recurrence: the iterate is
+ *     the same, and a cycle stops at the same column count, noticed up to
+ *     L - 1 steps later (the steps run in between cost reductions and are
+ *     discarded). On the GPU the rotations always run beside the next MAXPY,
+ *     off the step's critical path; the depth only batches them.
+ *   reserved: must be zero.
+ * A field out of range gives GMRES_ERR_ARG (0 bytes from
+ * gmres_workspace_bytes_ex).
+ */
+enum { GMRES_OPT_FORMAT_AUTO = 0, GMRES_OPT_FORMAT_CSR = 1, GMRES_OPT_FORMAT_SELL64 = 2 };
+typedef struct {
+  int32_t format;
+  int32_t rows_per_lane;
+  int32_t csr_spmv_shape;
+  int32_t split_spmv;
+  int32_t pipeline_depth;
+  int32_t reserved[3];
+} gmres_options;
+
+/* Zero every field: the library's own choices. */
+void gmres_options_init(gmres_options* opt /* host */);
+
+/* gmres_workspace_bytes for a context created with these options (NULL: defaults). */
+size_t gmres_workspace_bytes_ex(int64_t n, int32_t m, int32_t scheme,
+                                const gmres_options* opt /* host, nullable */);
+
+/*
  * Bind a CSR matrix and a workspace to a new context.
  *   n >= 1 rows (square A); nnz in [0, 2^31); row_ptr int32[n+1], col_idx
  *   int32[nnz] (any order within a row), vals float64[nnz]: caller-owned
@@ -143,6 +193,17 @@ size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
 int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
                  const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
                  void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * gmres_create with launch and format options (NULL: the defaults, the same
+ * as gmres_create). The workspace must be at least
+ * gmres_workspace_bytes_ex(n, m, scheme, opt). GMRES_ERR_ARG as for
+ * gmres_create, or for an invalid option.
+ */
+int gmres_create_ex(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                    const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
+                    void* workspace, size_t ws_bytes, void* hip_stream,
+                    const gmres_options* opt /* host, nullable */);
 
 /*
  * Solve A x = b by restarted GMRES(m) with the context's scheme.
@@ -353,6 +414,17 @@ int gmres_batch_destroy(gmres_batch* bt);
 
 /* Change the stream later work is enqueued on. */
 int gmres_batch_set_stream(gmres_batch* bt, void* hip_stream);
+
+/*
+ * Polls a part of a team makes at one team barrier before it gives up and
+ * its system ends with status GMRES_ERR_HIP (every kernel still ends
+ * normally). The default, GMRES_BATCH_WAIT_LIMIT, is about half a minute of
+ * waiting at least; smaller limits serve tests of that failure path. polls in
+ * [0, GMRES_BATCH_WAIT_LIMIT], else GMRES_ERR_ARG. Discards a captured graph
+ * (gmres_batch_replay then returns GMRES_ERR_ARG until the next capture).
+ */
+#define GMRES_BATCH_WAIT_LIMIT (1u << 23)
+int gmres_batch_set_wait_limit(gmres_batch* bt, uint32_t polls);
 
 /*
  * Enqueue one batched solve and return without waiting.

@@ -21,6 +21,8 @@
 
 using namespace gmres;
 
+static_assert(kMaxRestart == GMRES_MAX_RESTART, "kernel LDS sizes follow the public restart cap");
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -28,14 +30,10 @@ constexpr size_t kAlign = 256;
 constexpr size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Rows per lane of the row-tiled kernels: the largest of 8, 4, 2 that still
-// leaves at least 512 tiles of 256*rpt rows (two per compute unit), else 1.
-// GMRES_ROWS_PER_LANE (1, 2, 4 or 8) overrides the choice for tuning sweeps;
-// it must not change between gmres_workspace_bytes and gmres_create.
-int pick_rpt(int64_t n) {
-  if (const char* e = getenv("GMRES_ROWS_PER_LANE")) {
-    const int r = atoi(e);
-    if (r == 1 || r == 2 || r == 4 || r == 8) return r;
-  }
+// leaves at least 512 tiles of 256*rpt rows (two per compute unit), else 1;
+// or the caller's choice (gmres_options.rows_per_lane).
+int pick_rpt(int64_t n, int want) {
+  if (want == 1 || want == 2 || want == 4 || want == 8) return want;
   for (int r : {8, 4, 2})
     if ((n + 256 * r - 1) / (256 * r) >= 512) return r;
   return 1;
@@ -49,15 +47,15 @@ int pick_grid(int64_t n, int rpt) {
   return (int)tiles;
 }
 
-// SpMV shape (100 * lanes per row + entries per lane) from the mean row
+// CSR SpMV shape (100 * lanes per row + entries per lane) from the mean row
 // length: the fewest lanes per row whose entry slots cover it. One thread per
-// row for up to 8 entries; 8 lanes of 4 entries for 27-point rows.
-// GMRES_SPMV_SHAPE overrides the choice for tuning sweeps.
-int pick_spmv_shape(int64_t n, int64_t nnz) {
-  if (const char* e = getenv("GMRES_SPMV_SHAPE")) {
-    const int v = atoi(e);
-    if (v == 108 || v == 208 || v == 408 || v == 804 || v == 808 || v == 6401) return v;
-  }
+// row for up to 8 entries; 8 lanes of 4 entries for 27-point rows. Or the
+// caller's choice (gmres_options.csr_spmv_shape).
+bool valid_shape(int v) {
+  return v == 108 || v == 208 || v == 408 || v == 804 || v == 808 || v == 6401;
+}
+int pick_spmv_shape(int64_t n, int64_t nnz, int want) {
+  if (valid_shape(want)) return want;
   const int64_t avg = (nnz + n - 1) / n;
   if (avg <= 8) return 108;
   if (avg <= 16) return 208;
@@ -66,31 +64,33 @@ int pick_spmv_shape(int64_t n, int64_t nnz) {
   return 6401;
 }
 
-// Whether the lagged step computes w = A u in a launch of its own before the
-// projection kernel (which then reads w back) instead of inside it. Fusing
-// saves the write-then-read of w, but the tiles that finish their gathers
-// early start streaming the basis and slow down the gathers still in flight.
-// GMRES_SPLIT_SPMV (0 or 1) overrides the default for tuning sweeps.
-bool pick_split(int64_t, int64_t) {
-  if (const char* e = getenv("GMRES_SPLIT_SPMV")) return atoi(e) != 0;
-  return false;
-}
-
 // Sparse format of the SpMV. The sliced ELL copy (SELL-64, built at create)
 // makes every column-index and value load of a wavefront one contiguous
-// 512-byte block and needs no row pointers; it is used when padding every
-// slice to its longest row costs at most a quarter more entries, no slice is
-// wider than kSellMaxWidth and n < kSellMaxRows. GMRES_SPMV_FORMAT ("csr" or "sell") overrides
-// the choice for tuning sweeps and tests ("sell" still requires the width cap).
+// 512-byte block and needs no row pointers; by default it is used when
+// padding every slice to its longest row costs at most a quarter more
+// entries, no slice is wider than kSellMaxWidth and n < kSellMaxRows.
+// gmres_options.format forces CSR, or the copy whatever its padding (the
+// width and row limits still hold).
 constexpr int kSellMaxWidth = 4096;
 constexpr int64_t kSellMaxRows = (int64_t)1 << 28;  // gathers use 32-bit byte offsets
 enum { kFormatCsr = 0, kFormatSell = 1 };
-int format_override() {
-  if (const char* e = getenv("GMRES_SPMV_FORMAT")) {
-    if (!strcmp(e, "csr")) return kFormatCsr;
-    if (!strcmp(e, "sell")) return kFormatSell;
-  }
-  return -1;
+
+// The caller's options, checked; zero fields take the library's choices.
+bool check_options(const gmres_options* o, int scheme) {
+  if (!o) return true;
+  if (o->format < GMRES_OPT_FORMAT_AUTO || o->format > GMRES_OPT_FORMAT_SELL64) return false;
+  if (o->rows_per_lane != 0 && o->rows_per_lane != 1 && o->rows_per_lane != 2 &&
+      o->rows_per_lane != 4 && o->rows_per_lane != 8)
+    return false;
+  if (o->csr_spmv_shape != 0 && !valid_shape(o->csr_spmv_shape)) return false;
+  if (o->split_spmv != 0 && o->split_spmv != 1) return false;
+  if (o->pipeline_depth < 0 || o->pipeline_depth > GMRES_MAX_RESTART) return false;
+  const bool lagged = scheme == GMRES_MGS_1R || scheme == GMRES_CGS2 ||
+                      scheme == GMRES_MGS_1R_IR32 || scheme == GMRES_MGS_1R_IR16;
+  if (o->pipeline_depth > 1 && !lagged) return false;
+  for (int r : o->reserved)
+    if (r != 0) return false;
+  return true;
 }
 
 // The refinement schemes: one-reduce cycles on a reduced-precision basis
@@ -106,18 +106,18 @@ size_t basis_bytes(int scheme) {
 struct Layout {
   int64_t ldv;
   int rpt, G, NG, pstride;
-  size_t V, w, r64, H, R, T, TT, g, gh, cs, sn, coef, coef2, y, partials, gpartials, counters,
-      state, total;
+  size_t V, w, r64, H, R, T, TT, g, gh, cs, sn, coef, coef2, lvec, y, partials, gpartials,
+      counters, state, total;
 };
 
 // The FP64 schemes keep the basis V and the SpMV output w in float64; the
 // refinement schemes keep them in float32 or bfloat16 plus a float64 restart
 // residual. Columns are 64 elements apart at least, so every column starts
 // 128-byte aligned (256 bytes for float32 and float64).
-bool make_layout(int64_t n, int m, int scheme, Layout* L) {
+bool make_layout(int64_t n, int m, int scheme, Layout* L, int rpt_want = 0) {
   if (n < 1 || m < 1 || m > GMRES_MAX_RESTART) return false;
   L->ldv = (int64_t)round_up((size_t)n, 64);
-  L->rpt = pick_rpt(n);
+  L->rpt = pick_rpt(n, rpt_want);
   L->G = pick_grid(n, L->rpt);
   L->NG = (L->G + kGroup - 1) / kGroup;
   L->pstride = (int)round_up((size_t)(2 * (m + 2)), 32);
@@ -142,6 +142,7 @@ bool make_layout(int64_t n, int m, int scheme, Layout* L) {
   L->sn = take((size_t)(m + 2) * d);
   L->coef = take((size_t)(m + 2) * d);
   L->coef2 = take((size_t)(m + 2) * d);
+  L->lvec = take((size_t)(m + 2) * d);
   L->y = take((size_t)(m + 2) * d);
   L->partials = take((size_t)L->G * (size_t)L->pstride * d);
   L->gpartials = take((size_t)L->NG * (size_t)L->pstride * d);
@@ -198,6 +199,8 @@ struct gmres_ctx {
   int64_t nnz;
   int m, scheme, S;  // S: SpMV shape code
   bool split;        // separate SpMV launch in the lagged step
+  int depth;         // pipeline depth of the rotations (lagged schemes; 1 otherwise)
+  int format_want;   // gmres_options.format
   bool matrix_ok;    // false after a refresh found a bad structure: no more SpMVs
   int format;        // kFormatCsr or kFormatSell
   Sell sell;         // the sliced copy (format == kFormatSell), in caller memory
@@ -385,7 +388,9 @@ int plan_format(gmres_ctx* c) {
   c->sell_sp.clear();
   c->sell_entries = 0;
   c->sell_bytes = 0;
-  const int want = format_override();
+  const int want = c->format_want == GMRES_OPT_FORMAT_CSR      ? kFormatCsr
+                   : c->format_want == GMRES_OPT_FORMAT_SELL64 ? kFormatSell
+                                                               : -1;
   if (want == kFormatCsr || c->nnz == 0 || c->A.n >= kSellMaxRows) return GMRES_OK;
   const int64_t ns = (c->A.n + 63) / 64;
   // ns ints fit easily in the basis region (n (m+2) doubles, or floats)
@@ -512,7 +517,8 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
       if (k == m_eff) break;
       {
         TimedLaunch t(c, GMRES_KSTAT_MAXPY, k, k + 1, n8 * (k + 1) + 2 * n8);
-        TRY(launch_maxpy(ws, rpt, k, 0, G, bt, s, t.e0, t.e1));
+        TRY(launch_maxpy(ws, rpt, k, 0, G, bt, s, t.e0, t.e1,
+                         c->scheme == kSchemeCgs2 ? kSchemeCgs2 : kSchemeMgs1r, c->depth));
       }
       if (c->scheme == kSchemeCgs2) {
         {
@@ -543,13 +549,15 @@ int enqueue_true_residual(gmres_ctx* c, const double* b, const double* x) {
 // Point a context's fields at its matrix and workspace (no host mirror yet).
 void bind_context(gmres_ctx* c, int64_t n, int64_t nnz, const int32_t* row_ptr,
                   const int32_t* col_idx, const double* vals, int m, int scheme, const Layout& L,
-                  void* workspace, hipStream_t stream) {
+                  void* workspace, hipStream_t stream, const gmres_options* opt) {
   c->A = Csr{row_ptr, col_idx, vals, n, nnz};
   c->nnz = nnz;
   c->m = m;
   c->scheme = scheme;
-  c->S = pick_spmv_shape(n, nnz);
-  c->split = pick_split(n, nnz);
+  c->S = pick_spmv_shape(n, nnz, opt ? opt->csr_spmv_shape : 0);
+  c->split = opt && opt->split_spmv == 1;
+  c->depth = opt && opt->pipeline_depth > 1 ? opt->pipeline_depth : 1;
+  c->format_want = opt ? opt->format : GMRES_OPT_FORMAT_AUTO;
   c->L = L;
   c->stream = stream;
   char* base = (char*)workspace;
@@ -577,6 +585,7 @@ void bind_context(gmres_ctx* c, int64_t n, int64_t nnz, const int32_t* row_ptr,
   ws.sn = (double*)(base + L.sn);
   ws.coef = (double*)(base + L.coef);
   ws.coef2 = (double*)(base + L.coef2);
+  ws.lvec = (double*)(base + L.lvec);
   ws.y = (double*)(base + L.y);
   ws.partials = (double*)(base + L.partials);
   ws.gpartials = (double*)(base + L.gpartials);
@@ -681,7 +690,9 @@ int solve_impl(gmres_ctx* c, const double* b, double* x, double rtol, int64_t ma
         for (int q = 0; q < j; ++q) hist_res[it + q] = c->h_gh[q + 1] * gs;
       if (hist_orth && c->mirror_matrices) orth_history(c, j, hist_orth + it);
       loc.cycles += 1;
-      loc.rel_res_est = fabs(c->h_g[j]) * gs;
+      // |g_j| as it stood right after rotation j-1: with a pipeline depth above
+      // 1, later rotations of the same batch may have changed g[j] itself
+      loc.rel_res_est = c->h_gh[j] * gs;
       if (c->mirror_matrices) {
         memcpy(c->last_H.data(), c->h_H, sizeof(double) * c->last_H.size());
         memcpy(c->last_T.data(), c->h_T, sizeof(double) * c->last_T.size());
@@ -704,11 +715,19 @@ int solve_impl(gmres_ctx* c, const double* b, double* x, double rtol, int64_t ma
 
 extern "C" {
 
-size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme) {
-  if (scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH) return 0;
+size_t gmres_workspace_bytes_ex(int64_t n, int32_t m, int32_t scheme, const gmres_options* opt) {
+  if (scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH || !check_options(opt, scheme)) return 0;
   Layout L;
-  if (!make_layout(n, m, scheme, &L)) return 0;
+  if (!make_layout(n, m, scheme, &L, opt ? opt->rows_per_lane : 0)) return 0;
   return L.total;
+}
+
+size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme) {
+  return gmres_workspace_bytes_ex(n, m, scheme, nullptr);
+}
+
+void gmres_options_init(gmres_options* opt) {
+  if (opt) memset(opt, 0, sizeof(*opt));
 }
 
 const char* gmres_status_string(int status) {
@@ -728,23 +747,31 @@ const char* gmres_status_string(int status) {
 int gmres_create(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
                  const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
                  void* workspace, size_t ws_bytes, void* hip_stream) {
+  return gmres_create_ex(out, n, nnz, row_ptr, col_idx, vals, m, scheme, workspace, ws_bytes,
+                         hip_stream, nullptr);
+}
+
+int gmres_create_ex(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                    const int32_t* col_idx, const double* vals, int32_t m, int32_t scheme,
+                    void* workspace, size_t ws_bytes, void* hip_stream, const gmres_options* opt) {
   if (!out) return GMRES_ERR_ARG;
   *out = nullptr;
   if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31) || m < 1 ||
-      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH)
+      m > GMRES_MAX_RESTART || scheme < GMRES_MGS || scheme > GMRES_TWO_SYNCH ||
+      !check_options(opt, scheme))
     return GMRES_ERR_ARG;
   if (!is_device_ptr(row_ptr) || !is_device_ptr(workspace) ||
       (nnz > 0 && (!is_device_ptr(col_idx) || !is_device_ptr(vals))))
     return GMRES_ERR_ARG;
   if (((uintptr_t)workspace % kAlign) != 0) return GMRES_ERR_ARG;
   Layout L;
-  if (!make_layout(n, m, scheme, &L)) return GMRES_ERR_ARG;
+  if (!make_layout(n, m, scheme, &L, opt ? opt->rows_per_lane : 0)) return GMRES_ERR_ARG;
   if (ws_bytes < L.total) return GMRES_ERR_WORKSPACE;
 
   gmres_ctx* c = new (std::nothrow) gmres_ctx();
   if (!c) return GMRES_ERR_ARG;
   bind_context(c, n, nnz, row_ptr, col_idx, vals, m, scheme, L, workspace,
-               (hipStream_t)hip_stream);
+               (hipStream_t)hip_stream, opt);
   const Ws& ws = c->ws;
 
   void* pin = nullptr;
@@ -915,7 +942,7 @@ int gmres_solve_noalloc(int64_t n, int64_t nnz, const int32_t* row_ptr, const in
   // g and gh only) is a stack buffer, the SpMV reads the CSR arrays, and no
   // timing events are made, so nothing is allocated.
   gmres_ctx c{};
-  bind_context(&c, n, nnz, row_ptr, col_idx, vals, m, scheme, L, ws, s);
+  bind_context(&c, n, nnz, row_ptr, col_idx, vals, m, scheme, L, ws, s, nullptr);
   alignas(64) unsigned char host[round_up(sizeof(DevState), 64) +
                                  sizeof(double) * 2 * (GMRES_MAX_RESTART + 2)];
   bind_mirror(&c, host, false);

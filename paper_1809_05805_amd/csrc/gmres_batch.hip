@@ -246,14 +246,9 @@ int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, 
   B.bar = (unsigned*)(base + L.o_bar);
   B.queue = (unsigned*)(base + L.o_queue);
   B.out = (BatchOut*)(base + L.o_out);
-  // polls of a team barrier before a part gives up: 2^23 (about half a
-  // minute at least); GMRES_BATCH_SPIN_LIMIT lowers it so that tests can
-  // exercise the give-up path with every kernel still ending normally
-  B.spin_limit = 1u << 23;
-  if (const char* e = getenv("GMRES_BATCH_SPIN_LIMIT")) {
-    const long v = atol(e);
-    if (v >= 0 && v < (1l << 23)) B.spin_limit = (uint32_t)v;
-  }
+  // polls of a team barrier before a part gives up: GMRES_BATCH_WAIT_LIMIT
+  // (about half a minute at least); gmres_batch_set_wait_limit lowers it
+  B.spin_limit = GMRES_BATCH_WAIT_LIMIT;
   bt->nsys = nsys;
   bt->m = m;
   bt->scheme = scheme;
@@ -308,6 +303,13 @@ int gmres_batch_destroy(gmres_batch* bt) {
 int gmres_batch_set_stream(gmres_batch* bt, void* hip_stream) {
   if (!bt) return GMRES_ERR_ARG;
   bt->stream = (hipStream_t)hip_stream;
+  return GMRES_OK;
+}
+
+int gmres_batch_set_wait_limit(gmres_batch* bt, uint32_t polls) {
+  if (!bt || polls > GMRES_BATCH_WAIT_LIMIT) return GMRES_ERR_ARG;
+  bt->B.spin_limit = polls;
+  drop_graph(bt);  // a captured graph holds the old limit
   return GMRES_OK;
 }
 

@@ -465,9 +465,6 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
         TailPrefetch<1> pf;
         pf.ws = &ws;
         pf.tri = nullptr;
-        pf.hc = scr + 3 * (m + 2);
-        pf.csl = scr + 4 * (m + 2);
-        pf.snl = scr + 5 * (m + 2);
         pf.k = k;
         pf.scheme = kSchemeMgs1r;
         pf.active = true;
@@ -475,7 +472,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
         pf.ntri = 0;
         pf.issue();
         pf.commit();
-        tail_lagged<1, GMRES_BATCH_TAIL_ROWS>(ws, vals, scr, k, last, m_eff, kSchemeMgs1r, pf);
+        tail_lagged<1, GMRES_BATCH_TAIL_ROWS, false>(ws, vals, scr, k, last, m_eff, kSchemeMgs1r, pf);
         if (F32 && k == 0 && tid == 0) st->tol_cycle = tol_abs / beta_cycle;
         __syncthreads();
         if (tid == 0) {

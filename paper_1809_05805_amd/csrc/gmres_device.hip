@@ -9,9 +9,13 @@
 //              the tall-skinny projection [V[:,0:k+1]^T u, V[:,0:k+1]^T w], one
 //              device-wide reduction (two-level ticket reduction in a fixed
 //              order, so results are bitwise reproducible) and, in the last
-//              workgroup to finish, the small dense step: lagged norm, new T
-//              column, h = T^T r, Givens rotation, convergence flag;
-//   k_maxpy  - V[:,k] = u / rho and V[:,k+1] = w / rho - V[:,0:k+1] h.
+//              workgroup to finish, the part of the small dense step that the
+//              MAXPY needs: lagged norm and h = (I + L)^{-1} r;
+//   k_maxpy  - V[:,k] = u / rho and V[:,k+1] = w / rho - V[:,0:k+1] h, with
+//              one extra workgroup for the rest of the small dense step: the
+//              new column of T, and the Givens rotations and stopping test
+//              for the finished Hessenberg columns, every step or every L
+//              steps (Section III, the depth-L pipeline).
 // The level-1 MGS and two-reduce CGS2 baselines reuse the same building
 // blocks. Everything is memory-bound BLAS-2 work: no matrix cores.
 #include "gmres_internal.h"
@@ -628,12 +632,12 @@ __device__ double givens_column(const Ws& ws, int col) {
   return res;
 }
 
-// The same rotation step with the column, cosines and sines already staged in
-// LDS by the whole workgroup (hc[0..col+1], csl[0..col-1], snl[0..col-1]) and
-// gk = g[col] read beforehand, so the serial loop does not wait on global
-// memory. Writes R, cs, sn, g, gh.
-__device__ double givens_column_lds(const Ws& ws, int col, const double* hc, const double* csl,
-                                    const double* snl, double gk) {
+// The same rotation step with column col staged in LDS (hc[0..col+1]) with
+// the earlier rotations (csl, snl[0..col-1]), so the serial loop does not wait
+// on global memory. g holds g[col] on entry and g[col+1] on exit. Writes R,
+// cs, sn, g, gh, and the new rotation into csl[col], snl[col] as well.
+__device__ double rotate_staged(const Ws& ws, int col, const double* hc, double* csl, double* snl,
+                                double& g) {
   double* Rc = ws.R + (size_t)col * ws.ldh;
   double a = hc[0];
 #pragma unroll 4
@@ -650,12 +654,115 @@ __device__ double givens_column_lds(const Ws& ws, int col, const double* hc, con
   Rc[col + 1] = 0.0;
   ws.cs[col] = c;
   ws.sn[col] = s;
-  const double gn = -s * gk;
-  ws.g[col] = c * gk;
+  csl[col] = c;
+  snl[col] = s;
+  const double gn = -s * g;
+  ws.g[col] = c * g;
   ws.g[col + 1] = gn;
+  g = gn;
   const double res = fabs(gn);
   ws.gh[col + 1] = res;
   return res;
+}
+
+// The Givens least-squares update for the completed Hessenberg columns
+// first..k-1, in order. The rotations and the stopping test consume finished
+// columns and feed nothing back into the Arnoldi recurrence, so they may
+// trail the steps by several columns (Section III, the depth-L pipeline).
+// Each column is staged in LDS with the rotations so far; one thread applies
+// the earlier rotations, forms the new one and updates g. Returns, in every
+// thread, the first column count c + 1 whose |g| meets the cycle's tolerance
+// (-1 if none), or -2 once a value is not finite (no column after it is
+// rotated). Whole workgroup; lds holds 3 (m + 2) doubles.
+__device__ int rotate_columns(const Ws& ws, int first, int k, double* lds) {
+  __shared__ int s_res;
+  __shared__ double s_g, s_tol;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int M2 = ws.m + 2;
+  double* hc = lds;
+  double* csl = lds + M2;
+  double* snl = lds + 2 * M2;
+  for (int i = tid; i < first; i += bs) {
+    csl[i] = ws.cs[i];
+    snl[i] = ws.sn[i];
+  }
+  if (tid == 0) {
+    s_res = -1;
+    s_g = ws.g[first];
+    s_tol = ws.st->tol_cycle;
+  }
+  for (int c = first; c < k; ++c) {
+    for (int i = tid; i <= c + 1; i += bs) hc[i] = ws.H[(size_t)c * ws.ldh + i];
+    __syncthreads();
+    if (tid == 0) {
+      double g = s_g;
+      const double res = rotate_staged(ws, c, hc, csl, snl, g);
+      s_g = g;
+      ws.st->gk = res;
+      if (!isfinite(res))
+        s_res = -2;
+      else if (s_res == -1 && res <= s_tol)
+        s_res = c + 1;
+    }
+    __syncthreads();
+    if (s_res == -2) break;
+  }
+  __syncthreads();
+  return s_res;
+}
+
+// The new column k of the Malard-Paige T (one-reduce MGS: T[0:k,k] =
+// -T[0:k,0:k] l, T[k,k] = 1, so that T = (I + L^T)^{-1}; Section II) or row k
+// of L (CGS2), from l = V[:,0:k]^T v_k in LDS. T is read from its row-major
+// copy TT, whose row i holds T[i, i..k-1] contiguously. Both copies of the new
+// column (or row) are written. Whole workgroup; tcol holds k doubles of LDS.
+template <int NR>
+__device__ void extend_t(const Ws& ws, int k, int scheme, const double* ell, double* tcol) {
+  const int tid = threadIdx.x, bs = blockDim.x, ldt = ws.ldt;
+  if (scheme == kSchemeMgs1r) {
+    rows_dot<NR>(ws.TT, ldt, ell, k, k, [](int i) { return i; }, [&](int) { return k; }, tcol);
+    __syncthreads();
+    for (int i = tid; i < k; i += bs) {
+      const double t = -tcol[i];
+      ws.T[(size_t)k * ldt + i] = t;
+      ws.TT[(size_t)i * ldt + k] = t;
+    }
+    if (tid == 0) {
+      ws.T[(size_t)k * ldt + k] = 1.0;
+      ws.TT[(size_t)k * ldt + k] = 1.0;
+    }
+  } else {
+    for (int q = tid; q < k; q += bs) {
+      ws.TT[(size_t)k * ldt + q] = ell[q];
+      ws.T[(size_t)q * ldt + k] = ell[q];
+    }
+  }
+}
+
+// out[i] = sum over q < i of tri[i (i-1)/2 + q] vec[q], for i < nrows: dot
+// products of the rows of a packed strictly lower triangle (in LDS) with a
+// vector in LDS. Four lanes share a row; each keeps two sums over every
+// fourth entry, so the loads of a lane are independent, and the four lanes'
+// sums are added by two lane exchanges.
+__device__ void tri_dots(const double* tri, const double* vec, int nrows, double* out) {
+  const int tid = threadIdx.x, sl = tid & 3;
+  for (int i0 = 0; i0 < nrows; i0 += blockDim.x / 4) {
+    const int i = i0 + (tid >> 2);
+    double a0 = 0.0, a1 = 0.0;
+    if (i < nrows) {
+      const double* row = tri + i * (i - 1) / 2;
+      int q = sl;
+      for (; q + 4 < i; q += 8) {
+        a0 += row[q] * vec[q];
+        a1 += row[q + 4] * vec[q + 4];
+      }
+      if (q < i) a0 += row[q] * vec[q];
+    }
+    double a = a0 + a1;
+    a += __shfl_xor(a, 1, 64);
+    a += __shfl_xor(a, 2, 64);
+    if (sl == 0 && i < nrows) out[i] = a;
+  }
 }
 
 // ----------------------------------------------------------- small kernels
@@ -671,6 +778,7 @@ __global__ void k_init(Ws ws, int ncounters) {
     st->status = 0;
     st->bad_csr = 0;
     st->reductions = 0;
+    st->rot_next = 0;
     st->bnorm = st->tol_abs = st->beta = st->rho = st->inv_rho = st->gk = 0.0;
     st->tol_cycle = 0.0;
     st->xscale = 1.0;
@@ -704,6 +812,7 @@ __global__ void k_cycle_begin(Ws ws) {
     st->j = 0;
     st->true_conv = 0;
     st->breakdown = 0;
+    st->rot_next = 0;
     st->xscale = 1.0;
   }
 }
@@ -925,39 +1034,26 @@ __host__ __device__ inline size_t fused_lds_doubles(int rpt, int m) {
 
 // Inputs of the small dense step of lagged step k, loaded by the workgroup
 // that ends up holding the reduction's totals at the same time as the final
-// level's partials, so that their latency overlaps: column k-1 of H and the
-// earlier rotations into LDS, g[k-1] and two state scalars into thread 0's
-// registers, and, when it fits in the SpMV tile buffer, the strictly
+// level's partials, so that their latency overlaps: two state scalars into
+// thread 0's registers and, when it fits in the SpMV tile buffer, the strictly
 // triangular part of T (one-reduce MGS: tri[i (i-1)/2 + q] = T(q, i), q < i,
 // column i) or of L (CGS2: the same index holds L(i, q), row i).
 template <int NT>
 struct TailPrefetch {
   const Ws* ws;
   double* tri;
-  double* hc;
-  double* csl;
-  double* snl;
   int k, scheme;
   int ntri;     // entries of tri to load (0: T or L is read from HBM instead)
   bool active;  // false: this launch's tail needs none of it
   bool staged;  // tri holds the whole strictly triangular block
   double tv[NT];
-  double h0, c0, s0;
-  double gprev, tol;
+  double tol;
   int64_t red;
 
   __device__ void issue() {
     if (!active) return;
     const int tid = threadIdx.x;
-    if (k >= 1) {
-      const int i = tid < k ? tid : k - 1;
-      h0 = ws->H[(size_t)(k - 1) * ws->ldh + i];
-      const int j = tid < k - 1 ? tid : 0;
-      c0 = ws->cs[j];
-      s0 = ws->sn[j];
-    }
     if (tid == 0) {
-      gprev = ws->g[k >= 1 ? k - 1 : 0];
       tol = ws->st->tol_cycle;
       red = ws->st->reductions;
     }
@@ -978,13 +1074,6 @@ struct TailPrefetch {
   __device__ void commit() {
     if (!active) return;
     const int tid = threadIdx.x;
-    if (k >= 1) {
-      if (tid < k) hc[tid] = h0;
-      if (tid < k - 1) {
-        csl[tid] = c0;
-        snl[tid] = s0;
-      }
-    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int f = tid + 256 * t;
@@ -995,20 +1084,33 @@ struct TailPrefetch {
 };
 
 // The small dense step of a lagged scheme (one-reduce MGS or CGS2, first
-// reduction), run by the last workgroup with the totals in vals:
+// reduction), run by the workgroup that holds the totals in vals:
 //   vals[2q] = V_q . u, vals[2q+1] = V_q . w (q < k), vals[2k] = u.u, vals[2k+1] = u.w.
-// With norm_only (the end-of-cycle step) vals[0] = u.u is all there is: only
-// the last Hessenberg entry and its rotation are needed, not a new T column.
-// pf holds the prefetched inputs (H column, rotations, scalars, T or L).
-template <int NT, int NR = 8>
+// It forms the lagged norm rho = ||u|| (Section II, the normalization lag),
+// which completes Hessenberg column k-1, and the MAXPY coefficients of step k:
+// with l = V[:,0:k]^T v_k = p / rho and r = V[:,0:k+1]^T A v_k = [c / rho;
+// gamma / rho^2],
+//   one-reduce MGS: h = (I + L)^{-1} r. h[0:k] = T[0:k,0:k]^T r[0:k] with the
+//     T of the earlier steps (T = (I + L^T)^{-1}), and h_k = r_k - l . h[0:k],
+//     the last step of forward substitution with I + L, whose new row is
+//     [l^T, 1]. So h does not wait for the new column of T;
+//   CGS2: the first-pass coefficients corrected to first order, (I - L) r.
+// With DEFER (the single-system path) the new column of T (or row of L), the
+// Givens rotations and the stopping test are left to the extra workgroup of
+// the step's MAXPY launch (side_step), off the critical path; the tail
+// rotates only where the cycle ends here: at its norm-only last step
+// (norm_only) or on a breakdown, rho == 0. Without DEFER (the batched solver,
+// whose workgroup runs the whole step) it extends T and rotates column k-1
+// itself, as every step of depth 1.
+template <int NT, int NR, bool DEFER>
 __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool norm_only,
                             int m_eff, int scheme, const TailPrefetch<NT>& pf) {
-  __shared__ double s_rho;
-  __shared__ int s_go;  // 0: nothing more; 1: extend T (or L) only; 2: also the MAXPY coefficients
+  __shared__ double s_rho, s_last;
+  __shared__ int s_go;  // 0: nothing more; 1: rotate the pending columns, the cycle ends; 2: go on
+  __shared__ int s_first, s_bad;
   const int tid = threadIdx.x, bs = blockDim.x;
   DevState* st = ws.st;
   const int M2 = ws.m + 2;
-  double* hc = pf.hc;  // column k-1 of H, then rho
   if (tid == 0) {
     st->reductions = pf.red + 1;
     const double alpha = vals[norm_only ? 0 : 2 * k];
@@ -1031,23 +1133,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
         }
       } else {
         ws.H[(size_t)(k - 1) * ws.ldh + k] = rho;
-        hc[k] = rho;
-        const double gk = givens_column_lds(ws, k - 1, hc, pf.csl, pf.snl, pf.gprev);
-        st->gk = gk;
-        if (!isfinite(gk)) {
-          st->status = kNonfinite;
-          st->done = 1;
-          go = 0;
-        } else if (rho == 0.0) {
-          st->breakdown = 1;
-          st->done = 1;
-          st->j = k;
-          go = 0;
-        } else if (gk <= pf.tol || k == m_eff) {
-          st->done = 1;
-          st->j = k;
-          go = norm_only ? 0 : 1;
-        }
+        if (!DEFER || norm_only || rho == 0.0) go = 1;
       }
       if (go) {
         st->rho = rho;
@@ -1056,86 +1142,84 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
     }
     s_rho = rho;
     s_go = go;
+    s_first = DEFER ? st->rot_next : k - 1;
   }
   __syncthreads();
-  const int go = s_go;
+  int go = s_go;
   if (go == 0) return;
   const double rho = s_rho;
+  double* rot = scr + 3 * M2;  // 3 (m + 2) doubles for rotate_columns
+  if (go == 1) {
+    const int stop = rotate_columns(ws, s_first, k, rot);
+    if (tid == 0) {
+      st->rot_next = k;
+      int g2 = 2;
+      if (stop == -2) {
+        st->status = kNonfinite;
+        st->done = 1;
+        g2 = 0;
+      } else if (stop >= 0 && stop < k) {
+        st->done = 1;
+        st->j = stop;
+        g2 = 0;
+      } else if (rho == 0.0) {
+        st->breakdown = 1;
+        st->done = 1;
+        st->j = k;
+        g2 = 0;
+      } else if (stop == k || norm_only) {
+        // met at the newest column (the lag: one step after it was formed),
+        // or the cycle's last step: T still gets its column k
+        st->done = 1;
+        st->j = k;
+        g2 = norm_only ? 0 : 1;
+      }
+      s_go = g2;
+    }
+    __syncthreads();
+    go = s_go;
+    if (go == 0) return;
+  }
   const int ldt = ws.ldt;
   const double* tri = pf.tri;
   double* ell = scr;                 // l = V[:,0:k]^T v_k, the new row of L
   double* rr = scr + M2;             // r = V[:,0:k+1]^T A v_k
-  double* tcol = scr + 2 * M2;
-  for (int q = tid; q < k; q += bs) ell[q] = vals[2 * q] / rho;
-  __syncthreads();
-  if (scheme == kSchemeMgs1r) {
-    // Malard-Paige: T[0:k,k] = -T[0:k,0:k] l, T[k,k] = 1, so T = (I + L^T)^{-1}.
-    if (pf.staged) {
-      // row i of T from the packed columns in LDS (T(i,i) = 1)
-      for (int i = tid; i < k; i += bs) {
-        double a = ell[i];
-        for (int q = i + 1; q < k; ++q) a += tri[q * (q - 1) / 2 + i] * ell[q];
-        tcol[i] = a;
-      }
-    } else {
-      // row i of T (entries i..k-1) is contiguous in the row-major copy TT
-      rows_dot<NR>(ws.TT, ldt, ell, k, k, [](int i) { return i; }, [&](int) { return k; }, tcol);
-    }
+  double* hb = scr + 2 * M2;         // h[0:k]
+  for (int q = tid; q < k; q += bs) {
+    const double l = vals[2 * q] / rho;
+    ell[q] = l;
+    if (DEFER) ws.lvec[q] = l;
+  }
+  if (!DEFER) {
     __syncthreads();
-    for (int i = tid; i < k; i += bs) {
-      const double t = -tcol[i];
-      tcol[i] = t;
-      ws.T[(size_t)k * ldt + i] = t;
-      ws.TT[(size_t)i * ldt + k] = t;
-    }
-    if (tid == 0) {
-      tcol[k] = 1.0;
-      ws.T[(size_t)k * ldt + k] = 1.0;
-      ws.TT[(size_t)k * ldt + k] = 1.0;
-    }
-  } else {
-    // row k of L, kept row-major in TT for the (I - L) r product and
-    // column-major in T for the diagnostics
-    for (int q = tid; q < k; q += bs) {
-      ws.TT[(size_t)k * ldt + q] = ell[q];
-      ws.T[(size_t)q * ldt + k] = ell[q];
-    }
+    extend_t<NR>(ws, k, scheme, ell, rot);
   }
   if (go == 1) return;
   for (int q = tid; q < k; q += bs) rr[q] = vals[2 * q + 1] / rho;
-  if (tid == 0) rr[k] = (vals[2 * k + 1] / rho) / rho;
-  __syncthreads();
-  __shared__ int s_bad;
-  __shared__ double s_last;
-  if (tid == 0) s_bad = 0;
-  double* hbuf = scr + 3 * M2;  // the Givens staging area is free again
-  // One-reduce MGS: h = T^T r = (I + L)^{-1} V^T A v_k, the MGS coefficients:
-  // h_i for i < k uses column i of T (rows 0..i-1) plus T[i,i] r_i = r_i; h_k
-  // uses the new column, already in LDS. CGS2: the first-pass coefficients
-  // corrected to first order, (I - L) r, with row i of L (row k is the new one).
-  if (pf.staged) {
-    for (int i = tid; i < k; i += bs) {
-      const double* row = tri + i * (i - 1) / 2;
-      double a = 0.0;
-      for (int q = 0; q < i; ++q) a += row[q] * rr[q];
-      hbuf[i] = a;
-    }
-  } else {
-    // column i of T (rows 0..i-1) is contiguous in T; row i of L in TT
-    rows_dot<NR>(scheme == kSchemeMgs1r ? ws.T : ws.TT, ldt, rr, k, k, [](int) { return 0; },
-             [](int i) { return i; }, hbuf);
+  if (tid == 0) {
+    rr[k] = (vals[2 * k + 1] / rho) / rho;
+    s_bad = 0;
   }
+  __syncthreads();
+  // hb[i] = sum over q < i of T(q, i) r_q (column i of T) or L(i, q) r_q (row i of L)
+  if (pf.staged)
+    tri_dots(tri, rr, k, hb);
+  else
+    rows_dot<NR>(scheme == kSchemeMgs1r ? ws.T : ws.TT, ldt, rr, k, k, [](int) { return 0; },
+                 [](int i) { return i; }, hb);
+  __syncthreads();
+  for (int i = tid; i < k; i += bs) hb[i] = scheme == kSchemeMgs1r ? rr[i] + hb[i] : rr[i] - hb[i];
+  __syncthreads();
   if (tid < 64) {
-    const double* last = scheme == kSchemeMgs1r ? tcol : ell;
+    const double* y = scheme == kSchemeMgs1r ? hb : rr;
     double a = 0.0;
-    for (int q = tid; q < k; q += 64) a += last[q] * rr[q];
+    for (int q = tid; q < k; q += 64) a += ell[q] * y[q];
     a = wave_sum(a);
     if (tid == 0) s_last = a;
   }
   __syncthreads();
   for (int i = tid; i <= k; i += bs) {
-    const double dot = i < k ? hbuf[i] : s_last;
-    const double h = scheme == kSchemeMgs1r ? dot + rr[i] : rr[i] - dot;
+    const double h = i < k ? hb[i] : rr[k] - s_last;
     ws.coef[i] = h;
     if (scheme == kSchemeMgs1r) ws.H[(size_t)k * ws.ldh + i] = h;
     if (!isfinite(h)) s_bad = 1;
@@ -1144,6 +1228,46 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
   if (tid == 0 && s_bad) {
     st->status = kNonfinite;
     st->done = 1;
+  }
+}
+
+// The extra workgroup of a lagged step's MAXPY launch (step k), which the
+// tail left this work to: the new column of T (or row of L) from
+// l = lvec[0:k], then, once `depth` completed Hessenberg columns are pending
+// (depth 1: every step), their Givens rotations and the stopping test
+// (Section III: the rotations consume finished columns only, so they overlap
+// the next step's streaming). A met tolerance ends the cycle at the first
+// column count that met it; the steps that ran since then are discarded.
+template <int NR>
+__device__ void side_step(const Ws& ws, int k, int depth, int scheme) {
+  __shared__ double lds[5 * (kMaxRestart + 2)];
+  __shared__ int s_go, s_first;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  DevState* st = ws.st;
+  const int M2 = ws.m + 2;
+  double* ell = lds + 3 * M2;
+  double* tcol = lds + 4 * M2;
+  if (tid == 0) {
+    s_go = st->done == 0;
+    s_first = st->rot_next;
+  }
+  for (int q = tid; q < k; q += bs) ell[q] = ws.lvec[q];
+  __syncthreads();
+  if (!s_go) return;
+  extend_t<NR>(ws, k, scheme, ell, tcol);
+  const int first = s_first;
+  if (k >= 1 && k - first >= depth) {
+    const int stop = rotate_columns(ws, first, k, lds);
+    if (tid == 0) {
+      st->rot_next = k;
+      if (stop == -2) {
+        st->status = kNonfinite;
+        st->done = 1;
+      } else if (stop >= 0) {
+        st->j = stop;
+        st->done = 1;
+      }
+    }
   }
 }
 
@@ -1444,13 +1568,9 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   __syncthreads();
   // The tile buffer wl is free now; the tail's inputs are staged there.
   const bool norm_only = nproj < K;
-  const int M2 = ws.m + 2;
   TailPrefetch<RPT> pf;
   pf.ws = &ws;
   pf.tri = wl;
-  pf.hc = scr + 3 * M2;
-  pf.csl = scr + 4 * M2;
-  pf.snl = scr + 5 * M2;
   pf.k = K;
   pf.scheme = tail == kTailLagged1r ? kSchemeMgs1r : kSchemeCgs2;
   pf.active = tail == kTailLagged1r || tail == kTailLaggedCgs2;
@@ -1464,7 +1584,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   else if (tail == kTailTwoSynch)
     tail_two_synch(ws, vals, K);
   else
-    tail_lagged(ws, vals, scr, K, norm_only, m_eff, pf.scheme, pf);
+    tail_lagged<RPT, 8, true>(ws, vals, scr, K, norm_only, m_eff, pf.scheme, pf);
 }
 
 // ------------------------------------------------------------------ MAXPY
@@ -1476,9 +1596,16 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
 // mode 3 (two-synchronization CGS): V[:,k+1] = w - V[:,0:k+1] coef.
 // VT is the basis type; for float32 the coefficients and 1/rho are rounded
 // to float32 and the sums run in float32.
+// side != 0 (mode 0 only: kSchemeMgs1r or kSchemeCgs2): the launch has one
+// workgroup more than the G tiles, which runs side_step for the step's
+// scheme with pipeline depth `depth` instead of a tile.
 template <int RPT, typename VT>
-__global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G) {
+__global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G, int side, int depth) {
   constexpr int TR = 256 * RPT;
+  if (side && blockIdx.x == G) {
+    side_step<4>(ws, k, depth, side);
+    return;
+  }
   if (ws.st->done) return;
   const int tile = tile_of_block(G);
   const int64_t row0 = (int64_t)tile * TR;
@@ -1966,24 +2093,26 @@ int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt,
 }
 
 template <typename VT>
-static void maxpy_v(const Ws& ws, int rpt, int k, int mode, int G, hipStream_t s, hipEvent_t e0,
-                    hipEvent_t e1) {
+static void maxpy_v(const Ws& ws, int rpt, int k, int mode, int G, int side, int depth,
+                    hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid((unsigned)(G + (side ? 1 : 0)));
   switch (rpt) {
-    case 1: hipExtLaunchKernelGGL((k_maxpy<1, VT>), dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
-    case 2: hipExtLaunchKernelGGL((k_maxpy<2, VT>), dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
-    case 4: hipExtLaunchKernelGGL((k_maxpy<4, VT>), dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
-    default: hipExtLaunchKernelGGL((k_maxpy<8, VT>), dim3(G), dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G); break;
+    case 1: hipExtLaunchKernelGGL((k_maxpy<1, VT>), grid, dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G, side, depth); break;
+    case 2: hipExtLaunchKernelGGL((k_maxpy<2, VT>), grid, dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G, side, depth); break;
+    case 4: hipExtLaunchKernelGGL((k_maxpy<4, VT>), grid, dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G, side, depth); break;
+    default: hipExtLaunchKernelGGL((k_maxpy<8, VT>), grid, dim3(256), 0u, s, e0, e1, 0u, ws, k, mode, G, side, depth); break;
   }
 }
 
 int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, int bt, hipStream_t s,
-                 hipEvent_t e0, hipEvent_t e1) {
+                 hipEvent_t e0, hipEvent_t e1, int side, int depth) {
+  if (side && (mode != 0 || (side != kSchemeMgs1r && side != kSchemeCgs2) || depth < 1)) return -2;
   if (bt == kBasisF32)
-    maxpy_v<float>(ws, rpt, k, mode, G, s, e0, e1);
+    maxpy_v<float>(ws, rpt, k, mode, G, side, depth, s, e0, e1);
   else if (bt == kBasisBf16)
-    maxpy_v<__bf16>(ws, rpt, k, mode, G, s, e0, e1);
+    maxpy_v<__bf16>(ws, rpt, k, mode, G, side, depth, s, e0, e1);
   else
-    maxpy_v<double>(ws, rpt, k, mode, G, s, e0, e1);
+    maxpy_v<double>(ws, rpt, k, mode, G, side, depth, s, e0, e1);
   GMRES_CHECK_LAUNCH();
   return 0;
 }

@@ -13,6 +13,7 @@ namespace gmres {
 #define GMRES_GROUP 32
 #endif
 constexpr int kGroup = GMRES_GROUP;  // tiles per first-level group of the grid reduction
+constexpr int kMaxRestart = 256;     // GMRES_MAX_RESTART of the public header
 
 constexpr int kSchemeMgs = 0;
 constexpr int kSchemeMgs1r = 1;
@@ -51,6 +52,8 @@ struct DevState {
   int32_t status;     // 0 or kNonfinite
   int32_t bad_csr;    // set by the structure check
   int64_t reductions; // device-wide reductions completed
+  int32_t rot_next;   // first Hessenberg column of the cycle not yet rotated
+  int32_t pad_;
   double bnorm, tol_abs, beta, rho, inv_rho, gk;
   double tol_cycle;   // what |g_k| is compared with inside a cycle (tol_abs, or tol_abs / beta for IR)
   double xscale;      // x += xscale V y at the end of a cycle (1, or beta for IR)
@@ -94,6 +97,7 @@ struct Ws {
   double* sn;        // m+1 rotation sines
   double* coef;      // m+2 MAXPY coefficients of the current step
   double* coef2;     // m+2 second-pass coefficients (CGS2)
+  double* lvec;      // m+2: l = V[:,0:k]^T v_k of the current lagged step (for the new T column)
   double* y;         // m+2 least-squares solution
   double* partials;  // G x pstride tile sums
   double* gpartials; // ceil(G / kGroup) x pstride group sums
@@ -198,8 +202,11 @@ int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b,
 int launch_fused(const Csr& A, const Sell& SA, int shape, const Ws& ws, int rpt, int K, int nproj,
                  int wsrc, int m_eff, int tail, int G, int bt, hipStream_t s,
                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// side: 0, or (mode 0 of a lagged step) kSchemeMgs1r / kSchemeCgs2, which adds
+// one workgroup for the new T column (L row), the Givens rotations and the
+// stopping test, the rotations applied once `depth` columns are pending.
 int launch_maxpy(const Ws& ws, int rpt, int k, int mode, int G, int bt, hipStream_t s,
-                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, int side = 0, int depth = 1);
 int launch_axpy_dot(const Ws& ws, int rpt, double* w, const double* a, const double* coef,
                     const double* v, int tail, int i_col, int q_row, int m_eff, double aux, int G,
                     hipStream_t s);

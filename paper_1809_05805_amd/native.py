@@ -35,10 +35,35 @@ EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destr
             "gmres_batch_set_stream", "gmres_batch_solve_async", "gmres_batch_solve",
             "gmres_batch_read_info", "gmres_batch_set_config", "gmres_batch_get_config",
             "gmres_batch_autotune", "gmres_batch_capture", "gmres_batch_replay",
-            "gmres_solve_noalloc"]
+            "gmres_solve_noalloc", "gmres_options_init", "gmres_workspace_bytes_ex",
+            "gmres_create_ex", "gmres_batch_set_wait_limit"]
 GMRES_BATCH_ORDER_NATURAL, GMRES_BATCH_ORDER_LARGEST_FIRST = 0, 1
 GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64 = 0, 1
 GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
+GMRES_OPT_FORMAT_AUTO, GMRES_OPT_FORMAT_CSR, GMRES_OPT_FORMAT_SELL64 = 0, 1, 2
+OPT_FORMATS = {None: GMRES_OPT_FORMAT_AUTO, "auto": GMRES_OPT_FORMAT_AUTO,
+               "csr": GMRES_OPT_FORMAT_CSR, "sell": GMRES_OPT_FORMAT_SELL64,
+               "sell64": GMRES_OPT_FORMAT_SELL64}
+GMRES_BATCH_WAIT_LIMIT = 1 << 23
+
+
+class GmresOptions(ctypes.Structure):
+    """gmres_options: zero fields take the library's choices."""
+    _fields_ = [("format", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32),
+                ("csr_spmv_shape", ctypes.c_int32), ("split_spmv", ctypes.c_int32),
+                ("pipeline_depth", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+def make_options(format=None, rows_per_lane: int = 0, csr_spmv_shape: int = 0,
+                 split_spmv: bool = False, pipeline_depth: int = 0) -> GmresOptions:
+    """A gmres_options from keyword values (format: None/"auto", "csr" or "sell")."""
+    o = GmresOptions()
+    o.format = OPT_FORMATS[format] if format in OPT_FORMATS else int(format)
+    o.rows_per_lane = int(rows_per_lane)
+    o.csr_spmv_shape = int(csr_spmv_shape)
+    o.split_spmv = 1 if split_spmv else 0
+    o.pipeline_depth = int(pipeline_depth)
+    return o
 
 
 class GmresInfo(ctypes.Structure):
@@ -124,6 +149,15 @@ def load() -> ctypes.CDLL:
                        ("gmres_batch_replay", [P])):
         getattr(lib, name).restype = ctypes.c_int
         getattr(lib, name).argtypes = args
+    lib.gmres_options_init.restype = None
+    lib.gmres_options_init.argtypes = [ctypes.POINTER(GmresOptions)]
+    lib.gmres_workspace_bytes_ex.restype = SZ
+    lib.gmres_workspace_bytes_ex.argtypes = [I64, I32, I32, ctypes.POINTER(GmresOptions)]
+    lib.gmres_create_ex.restype = ctypes.c_int
+    lib.gmres_create_ex.argtypes = [ctypes.POINTER(P), I64, I64, P, P, P, I32, I32, P, SZ, P,
+                                    ctypes.POINTER(GmresOptions)]
+    lib.gmres_batch_set_wait_limit.restype = ctypes.c_int
+    lib.gmres_batch_set_wait_limit.argtypes = [P, ctypes.c_uint32]
     lib.gmres_solve_noalloc.restype = ctypes.c_int
     lib.gmres_solve_noalloc.argtypes = [I64, I64, P, P, P, I32, I32, P, P, D, I64,
                                         ctypes.POINTER(GmresInfo), P, P]
@@ -135,6 +169,29 @@ def load() -> ctypes.CDLL:
 
 def gmres_workspace_bytes(n: int, m: int, scheme: int) -> int:
     return int(load().gmres_workspace_bytes(n, m, scheme))
+
+
+def gmres_workspace_bytes_ex(n: int, m: int, scheme: int, opt: GmresOptions | None) -> int:
+    return int(load().gmres_workspace_bytes_ex(n, m, scheme, None if opt is None else ctypes.byref(opt)))
+
+
+def gmres_options_init() -> GmresOptions:
+    o = GmresOptions()
+    load().gmres_options_init(ctypes.byref(o))
+    return o
+
+
+def gmres_create_ex(n, nnz, row_ptr_ptr, col_idx_ptr, vals_ptr, m, scheme, ws_ptr, ws_bytes,
+                    stream_ptr, opt: GmresOptions | None) -> tuple[int, int | None]:
+    ctx = ctypes.c_void_p()
+    rc = load().gmres_create_ex(ctypes.byref(ctx), n, nnz, row_ptr_ptr, col_idx_ptr, vals_ptr, m,
+                                scheme, ws_ptr, ws_bytes, stream_ptr,
+                                None if opt is None else ctypes.byref(opt))
+    return rc, (ctx.value if rc == GMRES_OK else None)
+
+
+def gmres_batch_set_wait_limit(ctx, polls: int) -> int:
+    return load().gmres_batch_set_wait_limit(ctx, polls)
 
 
 def gmres_status_string(status: int) -> str:
@@ -315,9 +372,14 @@ class SolveResult:
 
 
 class GmresSolver:
-    """A context bound to CSR tensors on a GPU and a workspace it allocates with torch."""
+    """A context bound to CSR tensors on a GPU and a workspace it allocates with torch.
 
-    def __init__(self, row_ptr, col_idx, vals, m: int, scheme: str = "mgs1r", stream=None):
+    Keyword options go to gmres_create_ex (see make_options): format (None,
+    "csr" or "sell"), rows_per_lane, csr_spmv_shape, split_spmv, pipeline_depth.
+    """
+
+    def __init__(self, row_ptr, col_idx, vals, m: int, scheme: str = "mgs1r", stream=None,
+                 **options):
         import torch
 
         if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32 or vals.dtype != torch.float64:
@@ -332,18 +394,19 @@ class GmresSolver:
         self.device = row_ptr.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._keep = (row_ptr, col_idx, vals)
-        nbytes = gmres_workspace_bytes(self.n, self.m, self.scheme)
+        self.options = make_options(**options) if options else None
+        nbytes = gmres_workspace_bytes_ex(self.n, self.m, self.scheme, self.options)
         if nbytes == 0:
-            raise GmresError(GMRES_ERR_ARG, "gmres_workspace_bytes")
+            raise GmresError(GMRES_ERR_ARG, "gmres_workspace_bytes_ex")
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.ws.data_ptr()) % 256
         self.ws_ptr = self.ws.data_ptr() + off
         self.ws_bytes = nbytes
-        rc, ctx = gmres_create(self.n, self.nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
-                               vals.data_ptr() if self.nnz else None, self.m, self.scheme,
-                               self.ws_ptr, nbytes, self.stream.cuda_stream)
+        rc, ctx = gmres_create_ex(self.n, self.nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                  vals.data_ptr() if self.nnz else None, self.m, self.scheme,
+                                  self.ws_ptr, nbytes, self.stream.cuda_stream, self.options)
         if rc != GMRES_OK:
-            raise GmresError(rc, "gmres_create")
+            raise GmresError(rc, "gmres_create_ex")
         self.ctx = ctx
         # the sliced copy of A, when the library plans one, lives in a tensor of ours
         rc, mbytes = gmres_matrix_storage_bytes(ctx)
@@ -519,6 +582,12 @@ class BatchSolver:
         rc = gmres_batch_set_config(self.ctx, block_size, grid, order, part_rows)
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_batch_set_config")
+
+    def set_wait_limit(self, polls: int):
+        """Polls a part makes at a team barrier before its system gives up."""
+        rc = gmres_batch_set_wait_limit(self.ctx, polls)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_set_wait_limit")
 
     def config(self):
         rc, bs, grid, order, pr, mp = gmres_batch_get_config(self.ctx)

@@ -2,8 +2,6 @@
 
 from __future__ import annotations
 
-import contextlib
-import os
 import sys
 
 import numpy as np
@@ -24,26 +22,11 @@ def dev(p):
             torch.from_numpy(p.vals).cuda())
 
 
-@contextlib.contextmanager
-def spmv_format(fmt):
-    """Force the library's SpMV format ("csr" or "sell") for contexts created inside."""
-    old = os.environ.get("GMRES_SPMV_FORMAT")
-    if fmt is not None:
-        os.environ["GMRES_SPMV_FORMAT"] = fmt
-    try:
-        yield
-    finally:
-        if fmt is not None:
-            if old is None:
-                del os.environ["GMRES_SPMV_FORMAT"]
-            else:
-                os.environ["GMRES_SPMV_FORMAT"] = old
-
-
 def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis=False, fmt=None,
-            orth=False):
+            orth=False, **options):
     """One solve through the C ABI; returns a dict with x, info, hist and the last cycle.
-    fmt: None (the library's choice), "csr" or "sell"."""
+    fmt: None (the library's choice), "csr" or "sell"; further keyword options
+    (rows_per_lane, pipeline_depth, ...) go to gmres_create_ex."""
     import torch
 
     from paper_1809_05805_amd.native import GmresSolver
@@ -52,8 +35,9 @@ def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis
     rtol = p.rtol if rtol is None else rtol
     max_iters = min(10 * p.n, 10**6) if max_iters is None else max_iters
     rp, ci, va = dev(p)
-    with spmv_format(fmt):
-        s = GmresSolver(rp, ci, va, m, scheme)
+    if fmt is not None:
+        options["format"] = fmt
+    s = GmresSolver(rp, ci, va, m, scheme, **options)
     bt = torch.from_numpy(np.ascontiguousarray(p.b if b is None else b)).cuda()
     xt = torch.from_numpy(np.array(p.x0 if x0 is None else x0, dtype=np.float64)).cuda()
     r = s.solve(bt, xt, rtol, max_iters, hist=True, orth=orth)
@@ -77,4 +61,4 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-__all__ = ["log", "dev", "gpu_run", "oracle_run", "rel", "spmv_format", "D"]
+__all__ = ["log", "dev", "gpu_run", "oracle_run", "rel", "D"]

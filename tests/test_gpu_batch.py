@@ -364,23 +364,19 @@ def test_full_batch_repeat_bitwise():
 
 def test_team_wait_limit():
     """A team whose parts stop waiting gives up with GMRES_ERR_HIP for that
-    system, and every kernel still ends. The wait limit is forced to zero polls
-    from the host (GMRES_BATCH_SPIN_LIMIT, read at create), so a part that
-    arrives before its partners gives up at once; one-part systems are not
-    affected."""
-    import os
-
+    system, and every kernel still ends. The wait limit is set to zero polls
+    through the C ABI (gmres_batch_set_wait_limit), so a part that arrives
+    before its partners gives up at once; one-part systems are not affected."""
     import torch
 
     from paper_1809_05805_amd import native
 
     bp = SMALL
     log("batch team wait limit")
-    os.environ["GMRES_BATCH_SPIN_LIMIT"] = "0"
-    try:
-        s = solver(bp)
-    finally:
-        del os.environ["GMRES_BATCH_SPIN_LIMIT"]
+    s = solver(bp)
+    s.set_wait_limit(0)
+    with pytest.raises(native.GmresError):
+        s.set_wait_limit(native.GMRES_BATCH_WAIT_LIMIT + 1)
     s.set_config(256, 0, 1, 256)
     bt = torch.from_numpy(bp.b).cuda()
     x = torch.zeros(bp.n, dtype=torch.float64, device="cuda")

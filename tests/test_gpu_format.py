@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from paper_1809_05805_amd import problems as P
-from tests.gpu_util import gpu_run, log, oracle_run, rel, spmv_format
+from tests.gpu_util import gpu_run, log, oracle_run, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -33,8 +33,7 @@ def solver(p, m=10, scheme="mgs1r", fmt=None):
     from paper_1809_05805_amd.native import GmresSolver
 
     rp, ci, va = (torch.from_numpy(np.array(a)).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
-    with spmv_format(fmt):
-        s = GmresSolver(rp, ci, va, m, scheme)
+    s = GmresSolver(rp, ci, va, m, scheme, **({"format": fmt} if fmt else {}))
     return s, (rp, ci, va)
 
 

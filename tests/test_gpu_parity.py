@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 from paper_1809_05805_amd import problems as P
-from tests.gpu_util import D, gpu_run, log, oracle_run, rel, spmv_format
+from tests.gpu_util import D, gpu_run, log, oracle_run, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -60,8 +60,7 @@ def test_spmv_matches_oracle(case, fmt):
     p = CASES[case]
     log(f"spmv {case} {fmt} n={p.n}")
     rp, ci, va = (torch.from_numpy(a).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
-    with spmv_format(fmt):
-        s = GmresSolver(rp, ci, va, 4, "mgs1r")
+    s = GmresSolver(rp, ci, va, 4, "mgs1r", format=fmt)
     assert s.format()[0] == {"csr": "csr", "sell": "sell64"}[fmt]
     x = P.rng(77, 0).standard_normal(p.n)
     y = torch.empty(p.n, dtype=torch.float64, device="cuda")

@@ -110,3 +110,49 @@ def test_batch_info_layout():
     src = open(os.path.join(ROOT, "include", "gmres.h")).read()
     for name, val in (("GMRES_BATCH_ORDER_NATURAL", 0), ("GMRES_BATCH_ORDER_LARGEST_FIRST", 1)):
         assert re.search(rf"{name} = {val}\b", src), name
+
+
+def test_options_sizing_and_refusals(lib):
+    """gmres_options: zeros are the defaults, rows_per_lane changes the tiling
+    (and so the reduction scratch in the workspace), out-of-range fields and a
+    pipeline depth on a non-lagged scheme are refused."""
+    n, m = 2_097_152, 50
+    base = native.gmres_workspace_bytes(n, m, native.GMRES_MGS_1R)
+    assert native.gmres_workspace_bytes_ex(n, m, native.GMRES_MGS_1R, None) == base
+    assert native.gmres_workspace_bytes_ex(n, m, native.GMRES_MGS_1R, native.gmres_options_init()) == base
+    assert ctypes.sizeof(native.GmresOptions) == 32
+    o = native.gmres_options_init()
+    assert all(getattr(o, f) == 0 for f in ("format", "rows_per_lane", "csr_spmv_shape",
+                                              "split_spmv", "pipeline_depth"))
+    # one row per lane: 8x the tiles of the default 8 rows per lane at 128^3
+    one = native.gmres_workspace_bytes_ex(n, m, native.GMRES_MGS_1R, native.make_options(rows_per_lane=1))
+    assert one > base
+    ok = [dict(format="csr"), dict(format="sell"), dict(rows_per_lane=2), dict(csr_spmv_shape=804),
+          dict(split_spmv=True), dict(pipeline_depth=2), dict(pipeline_depth=1)]
+    for kw in ok:
+        assert native.gmres_workspace_bytes_ex(4096, 30, native.GMRES_MGS_1R, native.make_options(**kw)) > 0, kw
+    bad = [dict(format=3), dict(rows_per_lane=3), dict(rows_per_lane=16), dict(csr_spmv_shape=107),
+           dict(pipeline_depth=-1), dict(pipeline_depth=native.GMRES_MAX_RESTART + 1)]
+    for kw in bad:
+        assert native.gmres_workspace_bytes_ex(4096, 30, native.GMRES_MGS_1R, native.make_options(**kw)) == 0, kw
+    o = native.make_options(split_spmv=True)
+    o.split_spmv = 2
+    assert native.gmres_workspace_bytes_ex(4096, 30, native.GMRES_MGS_1R, o) == 0
+    o = native.gmres_options_init()
+    o.reserved[1] = 1
+    assert native.gmres_workspace_bytes_ex(4096, 30, native.GMRES_MGS_1R, o) == 0
+    # a pipeline depth only for the lagged schemes
+    for scheme in (native.GMRES_MGS_1R, native.GMRES_CGS2, native.GMRES_MGS_1R_IR32, native.GMRES_MGS_1R_IR16):
+        assert native.gmres_workspace_bytes_ex(4096, 30, scheme, native.make_options(pipeline_depth=3)) > 0
+    for scheme in (native.GMRES_MGS, native.GMRES_CGS2_3R, native.GMRES_TWO_SYNCH):
+        assert native.gmres_workspace_bytes_ex(4096, 30, scheme, native.make_options(pipeline_depth=2)) == 0
+        assert native.gmres_workspace_bytes_ex(4096, 30, scheme, native.make_options(pipeline_depth=1)) > 0
+
+
+def test_no_environment_knobs_in_the_library():
+    """Every launch and format choice goes through the C ABI (gmres_options,
+    gmres_batch_set_wait_limit): the library reads no environment variables."""
+    csrc = os.path.join(ROOT, "paper_1809_05805_amd", "csrc")
+    for name in os.listdir(csrc):
+        src = open(os.path.join(csrc, name)).read()
+        assert "getenv" not in src, name
