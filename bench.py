@@ -12,7 +12,20 @@ and seeded and sit in HBM before timing starts.
 Prints one JSON line. value = Arnoldi iterations per second of the one-reduce
 solve. The roofline object covers the dominant kernel (by summed time), timed
 with HIP events attached to its dispatches on the library's stream during the
-last solve of the timed region.
+last solve of the timed region; its bytes are the method's algorithmic bytes
+per launch (the CSR arrays, the SpMV's u and w, the projection's basis
+columns). Beside the headline the same JSON line reports, on this GPU:
+- the same solve with the rotations batched two steps at a time (depth 2);
+- the plain MGS, CGS2, re-orthogonalized CGS and two-synchronization CGS
+  solves of the same system;
+- the float32- and bfloat16-basis refinement on this system and on the 3D
+  7-point 256^3 precision workload (GMRES(40) to 1e-10);
+- the loss-of-orthogonality study on the row-scaled 27-point 100^3 system
+  (every scheme, ||I - V^T V|| and Paige's ||S|| per iteration);
+- the latency-bound 2D 64^2 system (microseconds per step);
+- the batched solver on 512 uneven 2D systems;
+- achievable read and copy rates from the project's own probe kernels;
+- the CPU oracle on the host's cores (OpenMP timing build) and on one.
 """
 
 from __future__ import annotations
@@ -60,10 +73,12 @@ def counted_traffic(kernel: str):
     return int(v.group(1))
 
 
-def time_solves(solver, b, x, rtol, max_iters, steps, warmup, timing=False):
-    """Time `steps` solves. With timing, the last timed solve carries HIP events
-    attached to each step-kernel dispatch (they add a few microseconds per
-    launch to that solve only; the kernels' own durations are unaffected)."""
+def time_solves(solver, b, x, rtol, max_iters, steps, warmup, timing=False, timed_runs=3):
+    """Time `steps` solves after `warmup` untimed ones, with no per-launch
+    events. With timing, `timed_runs` further solves carry HIP events attached
+    to each step-kernel dispatch (they add a few microseconds per launch, and
+    now and then a solve's step kernels read several microseconds long); the
+    per-kernel figures of the solve with the median event total are returned."""
     import torch
 
     res = None
@@ -74,60 +89,108 @@ def time_solves(solver, b, x, rtol, max_iters, steps, warmup, timing=False):
     t0 = time.perf_counter()
     iters = 0
     for i in range(steps):
-        if timing and i == steps - 1:
-            solver.set_timing(True)
         x.zero_()
         res = solver.solve(b, x, rtol, max_iters)
         iters += res.iters
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kt = solver.timing() if timing else None
+    kt = None
     if timing:
-        solver.set_timing(False)
+        runs = []
+        for _ in range(timed_runs):
+            solver.set_timing(True)
+            x.zero_()
+            solver.solve(b, x, rtol, max_iters)
+            runs.append(solver.timing())
+            solver.set_timing(False)
+        runs.sort(key=lambda t: sum(v["ms"] for v in t.values()))
+        kt = runs[len(runs) // 2]
     return dt, iters, res, kt
 
 
+PROBE_KINDS = {"read": 0, "read_nt": 1, "copy": 2, "copy_nt": 3}
+
+
 def measured_ceilings(dev, mib=2048, reps=5):
-    """Rates of torch's own device copy (read + write) and sum (read only) over
-    a buffer far larger than the caches: practical bandwidth ceilings of this
-    GPU, reported beside the 8 TB/s peak."""
+    """Achievable HBM rates of this GPU from the project's own probe kernels
+    (libgmres_probe.so): streaming 16-byte reads of a `mib` MiB buffer, and
+    copies of half of it into a second buffer, each buffer at least 4x the
+    256 MB last-level cache; the best over launch sizes and plain or
+    non-temporal loads (stores), reported beside the 8 TB/s peak."""
+    import ctypes
+
     import torch
 
-    nb = mib * 2**20 // 8
-    src = torch.ones(nb, dtype=torch.float64, device=dev)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    src.sum()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy = 2.0 * 8 * nb * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    e0.record()
-    for _ in range(reps):
-        src.sum()
-    e1.record()
-    torch.cuda.synchronize()
-    read = 8.0 * nb * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    from paper_1809_05805_amd import build_native
+
+    lib = ctypes.CDLL(build_native.PROBE_LIB)
+    f = lib.gmres_probe_bandwidth
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]
+    nbytes = mib * 2**20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty(nbytes // 16, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    table = {}
+    for name, kind in PROBE_KINDS.items():
+        # reads move the buffer; copies read half of it and write as much
+        size = nbytes if kind < 2 else nbytes // 2
+        moved = nbytes
+        for blocks in (1024, 2048, 4096, 8192):
+            ms = ctypes.c_float()
+            rc = f(kind, src.data_ptr(), dst.data_ptr(), size, blocks, reps, stream, ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"gmres_probe_bandwidth({name}, {blocks}) failed: {rc}")
+            table[f"{name}_{blocks}"] = round(moved * reps / (ms.value * 1e-3) / 1e9, 1)
     del src, dst
-    return {"copy_GBps": round(copy, 1), "read_GBps": round(read, 1), "buffer_MiB": mib,
-            "how": f"torch copy_ and sum of a {mib} MiB float64 buffer, {reps} times each, timed "
-                   "with events"}
+    read = max(v for k, v in table.items() if k.startswith("read"))
+    copy = max(v for k, v in table.items() if k.startswith("copy"))
+    return {"read_GBps": read, "copy_GBps": copy, "buffer_MiB": mib, "probes": table,
+            "how": f"own HIP probe kernels (gmres_probe.hip): reads of a {mib} MiB float64 buffer and "
+                   f"copies of {mib // 2} MiB into a second buffer, 16-byte vectors, 256-thread "
+                   "workgroups, best of 1024-8192 workgroups and of plain or non-temporal "
+                   f"loads/stores, {reps} timed launches each after one untimed"}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(p, m):
+    """The oracle on the host cores: its OpenMP timing build (the same
+    arithmetic per row; length-n loops on all threads the process may use,
+    OMP_NUM_THREADS or else the affinity set) for restart cycles of the same
+    system until about 4 s have passed, then one cycle on a single thread."""
     import oracle
 
+    threads = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    oracle.omp_threads(threads)
+    oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, m, "mgs1r", 0.0, 2, acc="openmp")
+    its, dt = 0, 0.0
+    while dt < 4.0 and its < 20 * m:
+        t0 = time.perf_counter()
+        r = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, m, "mgs1r", 0.0, m, acc="openmp")
+        dt += time.perf_counter() - t0
+        its += r.iters
+    oracle.omp_threads(1)
     t0 = time.perf_counter()
-    r = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, m, "mgs1r", 0.0, m)
-    dt = time.perf_counter() - t0
-    return {"value": r.iters / dt, "unit": "Arnoldi iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"one {m}-column restart cycle (one-reduce scheme, no early exit) of the same "
-                      f"system from x0=0; {r.iters} iterations in {dt:.2f} s, single-threaded "
-                      "sequential FP64 C"}
+    r1 = oracle.solve(p.row_ptr, p.col_idx, p.vals, p.b, p.x0, m, "mgs1r", 0.0, m, acc="openmp")
+    dt1 = time.perf_counter() - t0
+    oracle.omp_threads(threads)
+    return {"value": its / dt, "unit": "Arnoldi iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"{its // m} {m}-column restart cycles (one-reduce scheme, no early exit) of the "
+                      f"same system from x0=0 on {threads} threads: {its} iterations in {dt:.2f} s; "
+                      "the oracle's OpenMP timing build (its sequential build is the parity reference)",
+            "one_thread_iters_per_s": r1.iters / dt1,
+            "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                     "affinity_cpus": len(os.sched_getaffinity(0)), "threads_used": threads}}
 
 
 def kernel_table(kt, ms_per_solve):
@@ -195,7 +258,8 @@ def precision_config(args):
     A = p.scipy()
     for scheme in ("mgs1r", "mgs1r_ir32", "mgs1r_ir16"):
         s = GmresSolver(rp, ci, va, 40, scheme)
-        dt, iters, res, kt = time_solves(s, b, x, 1e-10, args.max_iters, 1, 1, timing=True)
+        dt, iters, res, kt = time_solves(s, b, x, 1e-10, args.max_iters, 1, 1, timing=True,
+                                         timed_runs=1)
         sols[scheme] = x.cpu().numpy()
         rel_res = float(np.linalg.norm(p.b - A @ sols[scheme]) / np.linalg.norm(p.b))
         out[scheme] = {"iters_per_s": round(iters / dt, 2), "ms_per_solve": round(dt * 1e3, 3),
@@ -268,12 +332,79 @@ def orth_study(args):
                "reductions": r.reductions, "kernels": kernels}
         if r.orth is not None and np.all(np.isfinite(r.orth)):
             rec["paige_s_at"] = {str(k): float(r.orth[k - 1]) for k in marks if k <= len(r.orth)}
+            rec["paige_s_per_iteration"] = [float(v) for v in r.orth]
+        rec["orth_loss_per_iteration"] = loss
         out[scheme] = rec
         log(f"orth study {scheme}: {r.iters / dt:.0f} iters/s, ||I - V^T V|| at k=10..100: "
             + " ".join(f"{loss[k - 1]:.1e}" for k in marks if k <= j) + " | "
             + " ".join(f"{k}: {v['avg_us']:.1f} us {v['GBps']:.0f} GB/s" for k, v in kernels.items()))
         s.close()
         del V, x
+    # the one-reduce cycle with the rotations batched two steps at a time
+    s = GmresSolver(rp, ci, va, m, "mgs1r", pipeline_depth=2)
+    x = torch.zeros(p.n, dtype=torch.float64, device=dev)
+    s.solve(b, x, 0.0, m)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = s.solve(b, x, 0.0, m)
+    dt = time.perf_counter() - t0
+    out["mgs1r_pipeline_depth_2"] = {"iters_per_s": round(r.iters / dt, 1),
+                                     "ms_per_cycle": round(dt * 1e3, 2), "reductions": r.reductions}
+    s.close()
+    return out
+
+
+def small_config(args):
+    """The 2D 5-point 64^2 system (n = 4,096, GMRES(30), rtol 1e-8): it sits in
+    the caches, so every step is latency-bound. Per scheme: one-cycle solves
+    with a fixed budget of 30 and of 10 columns (no early exit), timed over
+    many repetitions; the difference over the 20 extra columns gives the
+    marginal microseconds per step (columns 10..29, around k = m/2), the
+    30-column solve divided by 30 the whole-cycle rate. Then the solve to
+    1e-8."""
+    import numpy as np
+    import torch
+
+    from paper_1809_05805_amd import problems
+    from paper_1809_05805_amd.native import GmresSolver
+
+    p = problems.make_config("convdiff2d")
+    dev = torch.device("cuda:0")
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (p.row_ptr, p.col_idx, p.vals))
+    b = torch.from_numpy(p.b).to(dev)
+    x = torch.zeros(p.n, dtype=torch.float64, device=dev)
+    out = {"workload": "2D 5-point upwind convection-diffusion 64^2 (wind (1,1), Peclet 10), GMRES(30)",
+           "n": p.n, "nnz": p.nnz, "m": p.m, "rtol": p.rtol}
+    reps = 60
+
+    def cycle_time(s, cols):
+        x.zero_()
+        s.solve(b, x, 0.0, cols)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x.zero_()
+            s.solve(b, x, 0.0, cols)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    for scheme in ("mgs1r", "mgs", "cgs2"):
+        s = GmresSolver(rp, ci, va, p.m, scheme)
+        t30, t10 = cycle_time(s, p.m), cycle_time(s, 10)
+        dt, iters, res, _ = time_solves(s, b, x, p.rtol, args.max_iters, 20, 2)
+        err = float(np.linalg.norm(x.cpu().numpy() - p.x_true) / np.linalg.norm(p.x_true))
+        out[scheme] = {"us_per_step_marginal": round((t30 - t10) / (p.m - 10) * 1e6, 2),
+                       "us_per_step_whole_cycle": round(t30 / p.m * 1e6, 2),
+                       "solve_ms": round(dt / 20 * 1e3, 3), "iters_per_solve": iters // 20,
+                       "converged": bool(res.converged), "rel_res_true": res.rel_res_true,
+                       "err_vs_x_true": err, "reductions_per_solve": res.reductions}
+        log(f"64^2 {scheme}: {out[scheme]['us_per_step_marginal']:.1f} us/step marginal, "
+            f"solve {out[scheme]['solve_ms']:.2f} ms ({iters // 20} iters)")
+        s.close()
+    for base in ("mgs", "cgs2"):
+        out[f"one_reduce_speedup_per_step_vs_{base}"] = round(
+            out[base]["us_per_step_marginal"] / out["mgs1r"]["us_per_step_marginal"], 3)
     return out
 
 
@@ -397,18 +528,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baselines", action="store_true", help="skip the MGS and CGS2 solves")
     ap.add_argument("--no-ir32", action="store_true", help="skip the FP32-basis solve")
-    ap.add_argument("--precision-N", type=int, default=0,
-                    help="also run the FP32-basis vs float64 comparison on an N^3 system (256: the "
-                         "precision workload)")
+    ap.add_argument("--precision-N", type=int, default=256,
+                    help="the float64 vs float32- and bfloat16-basis comparison on an N^3 system "
+                         "(default 256: the precision workload; 0 skips it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a reference kernel "
                          "for hardware byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solver section")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the device copy and sum rates reported beside the peak")
-    ap.add_argument("--orth-study-N", type=int, default=0,
-                    help="also run the loss-of-orthogonality study of every scheme on the row-scaled "
-                         "27-point N^3 system (100: its full size)")
+    ap.add_argument("--orth-study-N", type=int, default=100,
+                    help="the loss-of-orthogonality study of every scheme on the row-scaled 27-point "
+                         "N^3 system (default 100: its full size; 0 skips it)")
+    ap.add_argument("--no-small", action="store_true", help="skip the latency-bound 64^2 system")
     ap.add_argument("--no-batch-autotune", action="store_true",
                     help="batched solves with the default launch configuration")
     ap.add_argument("--batch-systems", type=int, default=512)
@@ -466,7 +598,11 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(d["GBps"] / HBM_PEAK_GBPS, 4),
                 "traffic": counted_traffic(KERNEL_NAMES[dom]),
-                "kernel": KERNEL_LABELS[dom]}
+                "kernel": KERNEL_LABELS[dom],
+                "bytes_per_launch": round(d["avg_bytes"]), "avg_us": round(d["avg_us"], 2),
+                "bytes_model": "per step k with its SpMV: 12 nnz + 4 (n+1) (the CSR arrays) + 16 n (u "
+                               "read, w written) + 8 n (k+1) (V[:,0:k+1] read); the cycle's norm-only "
+                               "step: 8 n (u read)"}
     arnoldi_bytes = sum(kt[k]["bytes"] for k in kt)
     out = {
         "metric": "Arnoldi iters/s + achieved HBM GB/s, one-reduce vs plain GMRES at 1e-10 residual",
@@ -495,9 +631,20 @@ def main():
         # (a counter run keeps its one calibration copy the only large copy)
         ceil = measured_ceilings(dev)
         ceil["dominant_kernel_frac_of_read"] = round(d["GBps"] / ceil["read_GBps"], 4)
+        if "maxpy" in kernels:
+            ceil["maxpy_frac_of_copy"] = round(kernels["maxpy"]["GBps"] / ceil["copy_GBps"], 4)
         out["measured_ceilings"] = ceil
         log(f"ceilings: copy {ceil['copy_GBps']:.0f} GB/s, read {ceil['read_GBps']:.0f} GB/s")
     x64 = x.clone()
+    # the same solve with the rotations and stopping test batched two steps at a time
+    sd = GmresSolver(rp, ci, va, m, "mgs1r", pipeline_depth=2)
+    kd = max(1, min(args.steps, 5))
+    dtd, itd, rd, _ = time_solves(sd, b, x, rtol, args.max_iters, kd, 1)
+    out["pipeline_depth_2"] = {"iters_per_s": round(itd / dtd, 2), "ms_per_solve": round(dtd / kd * 1e3, 3),
+                               "iters_per_solve": itd // kd, "reductions_per_solve": rd.reductions,
+                               "converged": bool(rd.converged)}
+    log(f"mgs1r depth 2: {itd / kd:.0f} iters/solve, {dtd / kd * 1e3:.2f} ms/solve, {rd.reductions} reductions")
+    sd.close()
     if not args.no_ir32:
         out["fp32_ir"] = ir32_result(args, p, rp, ci, va, b, x, x64, dt / args.steps, res.iters)
         out["bf16_ir"] = ir32_result(args, p, rp, ci, va, b, x, x64, dt / args.steps, res.iters,
@@ -517,13 +664,17 @@ def main():
             log(f"{scheme}: {it2 / k2:.0f} iters/solve, {dt2 / k2 * 1e3:.2f} ms/solve")
             sv.close()
         out["speedup_vs_mgs"] = round(out["value"] / out["mgs_baseline"]["iters_per_s"], 3)
+    if not args.no_small:
+        out["small_64x64"] = small_config(args)
     if not args.no_batch:
         out["batch"] = batch_result(args)
     if args.orth_study_N:
         out["orth_study"] = orth_study(args)
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle, one restart cycle ...")
+        log("cpu baseline: the oracle's OpenMP timing build on the host cores ...")
         out["cpu_baseline"] = cpu_baseline(p, m)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.1f} iters/s on "
+            f"{out['cpu_baseline']['cores']} threads, {out['cpu_baseline']['one_thread_iters_per_s']:.1f} on one")
     print(json.dumps(out), flush=True)
 
 

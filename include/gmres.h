@@ -321,13 +321,15 @@ int gmres_basis(gmres_ctx* ctx, double** V, int64_t* ldv);
  * step, with the SpMV fused in unless it runs as a launch of its own), of the
  * separate SpMV kernel and of the MAXPY kernel carries start/stop HIP events
  * attached to its dispatch (hipExtLaunchKernel), so they time the kernel
- * alone; launches that the cycle's done flag skipped are not counted. bytes is
- * the algorithmic HBM traffic of the counted launches, with A the matrix bytes
- * of the format in use (CSR: 12 nnz + 4 (n+1); SELL64: 12 per stored entry,
- * 8 for the float32 values of the refinement schemes, plus 8 per slice
- * offset, ceil(n/64) + 1 of them). The figures below are for a float64
- * basis; for the float32 (bfloat16) basis every 8 n is 4 n (2 n):
- *   step k, SpMV fused:     A + 8 n (k+1) + 8 n     (A, V[:,0:k+1], w written)
+ * alone; launches that the cycle's done flag skipped, and the MAXPY of a step
+ * whose extra workgroup ended the cycle, are not counted. bytes is the
+ * algorithmic HBM traffic of the counted launches by the method's byte
+ * model, whatever the format in use: A = 12 nnz + 4 (n+1), the CSR arrays
+ * (8 nnz + 4 (n+1) for the refinement schemes, whose SpMV reads float32
+ * values). The figures below are for a float64 basis; for the float32
+ * (bfloat16) basis every 8 n is 4 n (2 n):
+ *   step k, SpMV fused:     A + 16 n + 8 n (k+1)    (A, u read and w written by
+ *                                                     the SpMV, V[:,0:k+1] read)
  *   step k, SpMV separate:  8 n (k+1) + 8 n         (V[:,0:k+1], w read)
  *   separate SpMV:          A + 16 n                (A, u, w written)
  *   last step of a cycle (norm of column k only):  8 n

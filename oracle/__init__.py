@@ -171,6 +171,16 @@ def solve(row_ptr, col_idx, vals, b, x0, m: int, scheme: str = "mgs1r", rtol: fl
     return res
 
 
+def omp_threads(n: int = 0) -> int:
+    """Threads the OpenMP timing build uses from now on (n >= 1), or the count
+    in effect (n = 0)."""
+    lib = _load("openmp")
+    f = lib.oracle_omp_threads
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int]
+    return int(f(int(n)))
+
+
 def spmv(row_ptr, col_idx, vals, x, acc: str = "double") -> np.ndarray:
     lib = _load(acc)
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)

@@ -51,8 +51,15 @@ typedef struct {
  * oracle on all of a host's cores; parity always uses the sequential build.
  */
 #ifdef ORACLE_OMP
+#include <omp.h>
 #define ORACLE_ROWS _Pragma("omp parallel for schedule(static)")
 #define ORACLE_SUM _Pragma("omp parallel for schedule(static) reduction(+ : s)")
+/* Threads of the timing build's loops from now on (n >= 1), or just the
+   count in effect (n < 1); returns the count in effect. */
+int oracle_omp_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
 #else
 #define ORACLE_ROWS
 #define ORACLE_SUM

@@ -11,6 +11,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgmres_hip.so")
 SOURCES = ["gmres_device.hip", "gmres_api.hip", "gmres_batch.hip"]
+# the bandwidth probes the benchmark measures ceilings with (not the solver)
+PROBE_LIB = os.path.join(HERE, "libgmres_probe.so")
+PROBE_SOURCES = ["gmres_probe.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
@@ -21,15 +24,21 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def _hipcc(sources, out, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + f".tmp{os.getpid()}"
+    tmp = out + f".tmp{os.getpid()}"
     cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+           *[os.path.join(CSRC, s) for s in sources], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the solver library and the bandwidth-probe library."""
+    _hipcc(SOURCES, LIB, verbose)
+    _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
     return LIB
 
 

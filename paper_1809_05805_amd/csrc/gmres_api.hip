@@ -439,10 +439,10 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
   const bool ir = ir_scheme(c->scheme);  // a reduced-precision basis inside float64 refinement
   const int bt = basis_type(c->scheme);
   const double n8 = (double)basis_bytes(c->scheme) * (double)c->A.n;  // one basis column
-  // bytes of the matrix in the format the step's SpMV reads
-  const double csr = c->format == kFormatSell
-                         ? (ir ? 8.0 : 12.0) * (double)c->sell_entries + 8.0 * (double)(c->sell.ns + 1)
-                         : 12.0 * (double)c->nnz + 4.0 * (double)(c->A.n + 1);
+  // Algorithmic bytes of the timed launches (the method's model, whatever the
+  // format in use): the CSR arrays with int32 indices and float64 values
+  // (float32 values for the refinement schemes), one basis column n8.
+  const double csr = (ir ? 8.0 : 12.0) * (double)c->nnz + 4.0 * (double)(c->A.n + 1);
   auto col = [&](int q) { return ws.V + (size_t)q * (size_t)ws.ldv; };
   TRY(launch_cycle_begin(ws, s));
   if (ir) {
@@ -503,7 +503,8 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
         // The last step of a cycle only finishes the lagged norm of column m_eff.
         const bool last = k == m_eff;
         int wsrc = last ? kWNone : (c->format == kFormatSell ? kWSell : kWSpmv);
-        double bytes = last ? n8 : csr + n8 * (k + 1) + n8;
+        // A; u read and w written by the SpMV; V[:,0:k+1] (u included) read by the projection
+        double bytes = last ? n8 : csr + 2 * n8 + n8 * (k + 1);
         if (!last && c->split && !ir) {
           TimedLaunch t(c, GMRES_KSTAT_SPMV, k, k, csr + 2 * n8);
           TRY(spmv(c, col(k), nullptr, ws.w, ws.st, s, t.e0, t.e1));

@@ -156,3 +156,26 @@ def test_no_environment_knobs_in_the_library():
     for name in os.listdir(csrc):
         src = open(os.path.join(csrc, name)).read()
         assert "getenv" not in src, name
+
+
+def test_probe_library_exports_its_header():
+    from paper_1809_05805_amd import build_native
+
+    if not os.path.exists(build_native.PROBE_LIB):
+        build_native.build()
+    src = open(os.path.join(ROOT, "include", "gmres_probe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(gmres_[a-z_]+)\s*\(", src)))
+    assert names == ["gmres_probe_bandwidth"]
+    lib = ctypes.CDLL(build_native.PROBE_LIB)
+    for name in names:
+        assert isinstance(getattr(lib, name), ctypes._CFuncPtr), name
+    # argument checks run on the host before any device call
+    ms = ctypes.c_float()
+    f = lib.gmres_probe_bandwidth
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]
+    assert f(9, 16, 16, 1024, 1, 1, None, ctypes.byref(ms)) == -1
+    assert f(0, 16, 16, 1000, 1, 1, None, ctypes.byref(ms)) == -1
+    assert f(0, None, 16, 1024, 1, 1, None, ctypes.byref(ms)) == -1

@@ -441,6 +441,14 @@ def test_long_double_build_is_the_same_algorithm(scheme):
     assert lb <= 2 * la + 1e-15, (la, lb)
 
 
+def test_openmp_thread_setter():
+    n0 = oracle.omp_threads()
+    assert n0 >= 1
+    assert oracle.omp_threads(1) == 1
+    assert oracle.omp_threads(2) == 2
+    oracle.omp_threads(n0)
+
+
 def test_openmp_timing_build_matches():
     """The OpenMP timing build runs the same algorithm: same iteration count and
     iterate to rounding (its dot products sum per thread)."""
