@@ -102,6 +102,15 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1809_05805_amd.build_native "
                            "(or __graft_entry__.build()); there is no fallback path")
+    # This binding hands torch's device pointers to the library, so torch's
+    # HIP runtime is loaded first and the library binds to that same one:
+    # torch ships its own libamdhip64, and a library loaded before it would
+    # bring in the system's copy, a second runtime that knows nothing of
+    # torch's allocations (every pointer check then fails).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     lib.gmres_workspace_bytes.restype = SZ
