@@ -124,9 +124,12 @@ size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
  * solve does not depend on these, except the pipeline depth (below) and the
  * order of the per-row sums, which changes with the format (rounding only).
  *   format: GMRES_OPT_FORMAT_AUTO (sliced copy of A for regular matrices,
- *     see gmres_create), _CSR (always read the CSR arrays) or _SELL64 (plan
- *     the sliced copy whatever its padding; rows wider than 4096 or n >= 2^28
- *     still fall back to CSR).
+ *     with 16-bit column deltas where they fit; see gmres_create), _CSR
+ *     (always read the CSR arrays), _SELL64 (the sliced copy with int32
+ *     column indices, whatever its padding) or _SELL64_D16 (the sliced copy
+ *     whatever its padding, with 16-bit deltas where every slice column fits
+ *     them, else int32 indices). Rows wider than 4096 or n >= 2^28 always
+ *     fall back to CSR.
  *   rows_per_lane: 0, or 1, 2, 4 or 8 rows per lane of the row-tiled kernels
  *     (tiles of 256 rows per lane-row). The default is the largest that leaves
  *     at least 512 tiles. The workspace size depends on it: give the same
@@ -149,7 +152,12 @@ size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
  * A field out of range gives GMRES_ERR_ARG (0 bytes from
  * gmres_workspace_bytes_ex).
  */
-enum { GMRES_OPT_FORMAT_AUTO = 0, GMRES_OPT_FORMAT_CSR = 1, GMRES_OPT_FORMAT_SELL64 = 2 };
+enum {
+  GMRES_OPT_FORMAT_AUTO = 0,
+  GMRES_OPT_FORMAT_CSR = 1,
+  GMRES_OPT_FORMAT_SELL64 = 2,
+  GMRES_OPT_FORMAT_SELL64_D16 = 3
+};
 typedef struct {
   int32_t format;
   int32_t rows_per_lane;
@@ -182,7 +190,9 @@ size_t gmres_workspace_bytes_ex(int64_t n, int32_t m, int32_t scheme,
  * at most a quarter to nnz (stencil and other regular matrices) and n < 2^28,
  * gmres_create plans a sliced-ELL copy of A (SELL-64: per slice, entry j of
  * each row stored column by column, so a wavefront's index and value loads
- * are contiguous and no row pointers are read). The library allocates no
+ * are contiguous and no row pointers are read). Its column indices take 2
+ * bytes per entry instead of 4 when every slice column's col - row values
+ * span at most 65535 (see gmres_matrix_storage_bytes). The library allocates no
  * device memory: gmres_matrix_storage_bytes gives the size of the copy and
  * gmres_set_matrix_storage builds it in a caller-owned buffer; from then on
  * every SpMV reads the copy, not the caller's arrays (after changing vals in
@@ -243,9 +253,13 @@ int gmres_destroy(gmres_ctx* ctx);
 /*
  * Device bytes the context's sliced-ELL copy of A needs (0 when no copy is
  * planned and the SpMV reads the CSR arrays): ceil(n/64) + 1 int64 slice
- * offsets, then int32 column indices and float64 values for every stored
- * entry (64 per slice and slice column; padding entries hold value 0), each
- * part 256-byte aligned.
+ * offsets, then the column indices and the float64 values (float32 for the
+ * refinement schemes) of every stored entry (64 per slice and slice column;
+ * padding entries hold value 0), each part 256-byte aligned. The column
+ * indices are int32, or, when every slice column's col - row values span at
+ * most 65535 (stencil and other banded matrices), one int32 base per slice
+ * column followed by a 16-bit delta per entry: the column of entry j of row r
+ * is r + base + delta.
  */
 int gmres_matrix_storage_bytes(gmres_ctx* ctx, size_t* bytes /* host */);
 
@@ -269,10 +283,11 @@ int gmres_set_matrix_storage(gmres_ctx* ctx, void* storage, size_t bytes);
  */
 int gmres_refresh_matrix(gmres_ctx* ctx);
 
-enum { GMRES_FORMAT_CSR = 0, GMRES_FORMAT_SELL64 = 1 };
+enum { GMRES_FORMAT_CSR = 0, GMRES_FORMAT_SELL64 = 1, GMRES_FORMAT_SELL64_D16 = 2 };
 /*
  * The SpMV format in use (GMRES_FORMAT_*) and the matrix entries it reads:
- * nnz for CSR, nnz plus padding for SELL64. The arithmetic is the same
+ * nnz for CSR, nnz plus padding for the sliced copies (SELL64: int32 column
+ * indices; SELL64_D16: 16-bit column deltas). The arithmetic is the same
  * either way: each row's products are summed in storage order (padding adds
  * exact zeros).
  */

@@ -68,9 +68,13 @@ int pick_spmv_shape(int64_t n, int64_t nnz, int want) {
 // makes every column-index and value load of a wavefront one contiguous
 // 512-byte block and needs no row pointers; by default it is used when
 // padding every slice to its longest row costs at most a quarter more
-// entries, no slice is wider than kSellMaxWidth and n < kSellMaxRows.
-// gmres_options.format forces CSR, or the copy whatever its padding (the
-// width and row limits still hold).
+// entries, no slice is wider than kSellMaxWidth and n < kSellMaxRows. Its
+// column indices are 16-bit deltas from a per-slice-column base (2 bytes per
+// entry instead of 4) when every slice column's col - row values span at
+// most kSellDeltaSpan, as for stencil and other banded matrices.
+// gmres_options.format forces CSR, the copy with int32 indices, or the copy
+// with deltas where they fit, whatever the padding (the width and row limits
+// still hold).
 constexpr int kSellMaxWidth = 4096;
 constexpr int64_t kSellMaxRows = (int64_t)1 << 28;  // gathers use 32-bit byte offsets
 enum { kFormatCsr = 0, kFormatSell = 1 };
@@ -78,7 +82,7 @@ enum { kFormatCsr = 0, kFormatSell = 1 };
 // The caller's options, checked; zero fields take the library's choices.
 bool check_options(const gmres_options* o, int scheme) {
   if (!o) return true;
-  if (o->format < GMRES_OPT_FORMAT_AUTO || o->format > GMRES_OPT_FORMAT_SELL64) return false;
+  if (o->format < GMRES_OPT_FORMAT_AUTO || o->format > GMRES_OPT_FORMAT_SELL64_D16) return false;
   if (o->rows_per_lane != 0 && o->rows_per_lane != 1 && o->rows_per_lane != 2 &&
       o->rows_per_lane != 4 && o->rows_per_lane != 8)
     return false;
@@ -206,7 +210,9 @@ struct gmres_ctx {
   Sell sell;         // the sliced copy (format == kFormatSell), in caller memory
   std::vector<int64_t> sell_sp;  // planned slice offsets (empty: no copy planned)
   int64_t sell_entries;          // planned stored entries
-  size_t sell_bytes, o_ci, o_va; // planned storage size and its layout
+  bool sell_d16;                 // the planned copy holds 16-bit column deltas
+  size_t sell_bytes, o_ci, o_va; // planned storage size and its layout (o_ci: indices or deltas)
+  size_t o_cb;                   // per-slice-column bases (16-bit deltas only)
   Layout L;
   Ws ws;
   hipStream_t stream;
@@ -384,22 +390,23 @@ void collect_timing(gmres_ctx* c, int j, bool stopped_at_restart) {
 // no copy is planned, the SpMV reads the CSR arrays.
 int plan_format(gmres_ctx* c) {
   c->format = kFormatCsr;
-  c->sell = Sell{nullptr, nullptr, nullptr, nullptr, 0, 0};
+  c->sell = Sell{};
   c->sell_sp.clear();
   c->sell_entries = 0;
+  c->sell_d16 = false;
   c->sell_bytes = 0;
-  const int want = c->format_want == GMRES_OPT_FORMAT_CSR      ? kFormatCsr
-                   : c->format_want == GMRES_OPT_FORMAT_SELL64 ? kFormatSell
-                                                               : -1;
-  if (want == kFormatCsr || c->nnz == 0 || c->A.n >= kSellMaxRows) return GMRES_OK;
+  const int want = c->format_want;
+  if (want == GMRES_OPT_FORMAT_CSR || c->nnz == 0 || c->A.n >= kSellMaxRows) return GMRES_OK;
   const int64_t ns = (c->A.n + 63) / 64;
-  // ns ints fit easily in the basis region (n (m+2) doubles, or floats)
+  // ns + 1 ints fit easily in the basis region (n (m+2) doubles, or floats)
   int* dw = ir_scheme(c->scheme) ? reinterpret_cast<int*>(c->ws.Vf)
                                  : reinterpret_cast<int*>(c->ws.V);
-  std::vector<int> wh((size_t)ns);
-  if (launch_sell_width(c->A, ns, dw, c->stream) ||
-      hipMemcpyAsync(wh.data(), dw, sizeof(int) * (size_t)ns, hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
+  std::vector<int> wh((size_t)ns + 1);
+  const bool deltas = want != GMRES_OPT_FORMAT_SELL64;
+  if (hipMemsetAsync(dw + ns, 0, sizeof(int), c->stream) != hipSuccess ||
+      launch_sell_width(c->A, ns, dw, deltas ? dw + ns : nullptr, kSellMaxWidth, c->stream) ||
+      hipMemcpyAsync(wh.data(), dw, sizeof(int) * (size_t)(ns + 1), hipMemcpyDeviceToHost,
+                     c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return GMRES_ERR_HIP;
   std::vector<int64_t> sp((size_t)ns + 1);
@@ -411,12 +418,21 @@ int plan_format(gmres_ctx* c) {
   }
   const int64_t total = sp[ns];
   const bool cheap = total * 4 <= c->nnz * 5;
-  if (wmax > kSellMaxWidth || (want != kFormatSell && !cheap)) return GMRES_OK;
+  if (wmax > kSellMaxWidth || (want == GMRES_OPT_FORMAT_AUTO && !cheap)) return GMRES_OK;
   c->sell_sp.swap(sp);
   c->sell_entries = total;
-  c->o_ci = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
-  c->o_va = round_up(c->o_ci + sizeof(int) * (size_t)total, kAlign);
+  c->sell_d16 = deltas && wh[ns] <= kSellDeltaSpan;
   const size_t vsize = ir_scheme(c->scheme) ? sizeof(float) : sizeof(double);
+  const size_t off_sp = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
+  if (c->sell_d16) {
+    c->o_cb = off_sp;
+    c->o_ci = round_up(c->o_cb + sizeof(int) * (size_t)(total / 64), kAlign);
+    c->o_va = round_up(c->o_ci + sizeof(uint16_t) * (size_t)total, kAlign);
+  } else {
+    c->o_cb = 0;
+    c->o_ci = off_sp;
+    c->o_va = round_up(c->o_ci + sizeof(int) * (size_t)total, kAlign);
+  }
   c->sell_bytes = c->o_va + vsize * (size_t)total;
   return GMRES_OK;
 }
@@ -502,7 +518,9 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
       {
         // The last step of a cycle only finishes the lagged norm of column m_eff.
         const bool last = k == m_eff;
-        int wsrc = last ? kWNone : (c->format == kFormatSell ? kWSell : kWSpmv);
+        int wsrc = last ? kWNone
+                        : c->format == kFormatSell ? (c->sell.cd ? kWSellD16 : kWSell)
+                                                   : kWSpmv;
         // A; u read and w written by the SpMV; V[:,0:k+1] (u included) read by the projection
         double bytes = last ? n8 : csr + 2 * n8 + n8 * (k + 1);
         if (!last && c->split && !ir) {
@@ -838,7 +856,7 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
   if (!c) return GMRES_ERR_ARG;
   if (!storage) {
     c->format = kFormatCsr;
-    c->sell = Sell{nullptr, nullptr, nullptr, nullptr, 0, 0};
+    c->sell = Sell{};
     return GMRES_OK;
   }
   if (c->sell_bytes == 0 || bytes < c->sell_bytes || ((uintptr_t)storage % kAlign) != 0 ||
@@ -847,9 +865,15 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
   char* base = (char*)storage;
   const int64_t ns = (int64_t)c->sell_sp.size() - 1;
   const bool fv = ir_scheme(c->scheme);  // float32 values for the reduced-precision bases
-  const Sell S{(const int64_t*)base, (int*)(base + c->o_ci),
-               fv ? nullptr : (double*)(base + c->o_va), fv ? (float*)(base + c->o_va) : nullptr,
-               ns, c->A.n};
+  Sell S{};
+  S.sp = (const int64_t*)base;
+  S.ci = c->sell_d16 ? nullptr : (int*)(base + c->o_ci);
+  S.cd = c->sell_d16 ? (uint16_t*)(base + c->o_ci) : nullptr;
+  S.cbase = c->sell_d16 ? (int*)(base + c->o_cb) : nullptr;
+  S.va = fv ? nullptr : (double*)(base + c->o_va);
+  S.vaf = fv ? (float*)(base + c->o_va) : nullptr;
+  S.ns = ns;
+  S.n = c->A.n;
   if (hipMemcpyAsync(base, c->sell_sp.data(), sizeof(int64_t) * (size_t)(ns + 1),
                      hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemsetAsync(&c->ws.st->bad_csr, 0, sizeof(int32_t), c->stream) != hipSuccess ||
@@ -865,7 +889,9 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
 
 int gmres_get_format(gmres_ctx* c, int32_t* format, int64_t* stored_entries) {
   if (!c || !format || !stored_entries) return GMRES_ERR_ARG;
-  *format = c->format == kFormatSell ? GMRES_FORMAT_SELL64 : GMRES_FORMAT_CSR;
+  *format = c->format != kFormatSell ? GMRES_FORMAT_CSR
+            : c->sell.cd              ? GMRES_FORMAT_SELL64_D16
+                                      : GMRES_FORMAT_SELL64;
   *stored_entries = c->format == kFormatSell ? c->sell_entries : c->nnz;
   return GMRES_OK;
 }
@@ -949,8 +975,9 @@ int gmres_solve_noalloc(int64_t n, int64_t nnz, const int32_t* row_ptr, const in
   bind_mirror(&c, host, false);
   c.matrix_ok = true;
   c.format = kFormatCsr;
-  c.sell = Sell{nullptr, nullptr, nullptr, nullptr, 0, 0};
+  c.sell = Sell{};
   c.sell_entries = 0;
+  c.sell_d16 = false;
   c.sell_bytes = 0;
   c.last_j = 0;
   c.timing = false;

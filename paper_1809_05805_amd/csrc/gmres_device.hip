@@ -23,6 +23,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <limits.h>
 #include <math.h>
 
 #include <type_traits>
@@ -863,13 +864,78 @@ __global__ __launch_bounds__(256) void k_spmv(Csr A, const double* __restrict__ 
 // ------------------------------------------------ sliced ELL copy of A
 
 // Width of each slice, max(1, longest row): wavefront per slice, lane per row.
-__global__ __launch_bounds__(256) void k_sell_width(Csr A, int64_t ns, int* __restrict__ width) {
+// With spread, also the largest spread of col - row over the entries of one
+// slice column (entry j of every row of the slice), for slices at most
+// max_width wide (a wider slice records INT_MAX: no copy is made then).
+__global__ __launch_bounds__(256) void k_sell_width(Csr A, int64_t ns, int* __restrict__ width,
+                                                     int* __restrict__ spread, int max_width) {
   const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (s >= ns) return;  // uniform over the wavefront
-  const int64_t r = s * 64 + (threadIdx.x & 63);
-  int len = r < A.n ? A.rp[r + 1] - A.rp[r] : 0;
-  for (int mask = 32; mask >= 1; mask >>= 1) len = max(len, __shfl_xor(len, mask, 64));
-  if ((threadIdx.x & 63) == 0) width[s] = len < 1 ? 1 : len;
+  const int l = threadIdx.x & 63;
+  const int64_t r = s * 64 + l;
+  const int e0 = r < A.n ? A.rp[r] : 0;
+  const int len = r < A.n ? A.rp[r + 1] - e0 : 0;
+  int W = len;
+  for (int mask = 32; mask >= 1; mask >>= 1) W = max(W, __shfl_xor(W, mask, 64));
+  if (l == 0) width[s] = W < 1 ? 1 : W;
+  if (!spread) return;
+  if (W > max_width) {
+    if (l == 0) atomicMax(spread, INT_MAX);
+    return;
+  }
+  int widest = 0;
+  for (int j = 0; j < W; ++j) {
+    const bool real = j < len;
+    const int d = real ? A.ci[e0 + j] - (int)r : 0;
+    int mn = real ? d : INT_MAX, mx = real ? d : INT_MIN;
+    for (int mask = 32; mask >= 1; mask >>= 1) {
+      mn = min(mn, __shfl_xor(mn, mask, 64));
+      mx = max(mx, __shfl_xor(mx, mask, 64));
+    }
+    if (mn != INT_MAX) widest = max(widest, mx - mn);
+  }
+  if (l == 0 && widest > 0) atomicMax(spread, widest);
+}
+
+// Copy of A into slices with 16-bit column deltas (sp already set), values in
+// SVT: wavefront per slice, lane per row. Slice column j's base (the smallest
+// col - row of its entries, 0 if it has none) goes to cbase, each entry's
+// col - row - base to cd. A row that leaves [0, nnz) or does not fit its
+// slice, or a slice column whose spread exceeds kSellDeltaSpan (a changed
+// structure), sets st->bad_csr.
+template <typename SVT>
+__global__ __launch_bounds__(256) void k_sell_fill_d16(Csr A, Sell S, SVT* __restrict__ va,
+                                                        DevState* st) {
+  const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= S.ns) return;  // uniform over the wavefront
+  const int l = threadIdx.x & 63;
+  const int64_t r = s * 64 + l;
+  const int64_t b = S.sp[s];
+  const int W = (int)((S.sp[s + 1] - b) >> 6);
+  const int64_t e0 = r < A.n ? A.rp[r] : 0;
+  const int64_t e1 = r < A.n ? A.rp[r + 1] : 0;
+  int len = (int)(e1 - e0);
+  int bad = 0;
+  if (e0 < 0 || e1 < e0 || e1 > A.nnz || len > W) {
+    bad = 1;
+    len = 0;
+  }
+  for (int j = 0; j < W; ++j) {
+    const bool real = j < len;
+    const int d = real ? A.ci[e0 + j] - (int)r : 0;
+    int mn = real ? d : INT_MAX, mx = real ? d : INT_MIN;
+    for (int mask = 32; mask >= 1; mask >>= 1) {
+      mn = min(mn, __shfl_xor(mn, mask, 64));
+      mx = max(mx, __shfl_xor(mx, mask, 64));
+    }
+    const int base = mn == INT_MAX ? 0 : mn;
+    if (mn != INT_MAX && mx - mn > kSellDeltaSpan) bad = 1;
+    const int64_t e = b + (int64_t)j * 64 + l;
+    if (l == 0) S.cbase[(b >> 6) + j] = base;
+    S.cd[e] = real ? (uint16_t)(d - base) : (uint16_t)0;
+    va[e] = real ? (SVT)A.va[e0 + j] : (SVT)0;
+  }
+  if (bad) atomicOr(&st->bad_csr, 1);
 }
 
 // Copy of A into the slices (sp already set), thread per row, with values in
@@ -911,22 +977,41 @@ __device__ inline const SVT* sell_vals(const Sell& S) {
     return S.vaf;
 }
 
-// Entries j0 .. j0+U-1 of lane l's row in the slice at entry offset b, width
-// W (>= 1): indices past W are clamped to W-1 (their products are masked by
-// the caller). Buffer loads over the slice's own entries (the descriptors are
-// scalar; a lane supplies a 32-bit byte offset).
-template <int U, typename SVT>
-__device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l, int (&c)[U],
-                                 SVT (&v)[U]) {
-  const __amdgpu_buffer_rsrc_t rc =
-      __builtin_amdgcn_make_buffer_rsrc(S.ci + b, (short)0, W * 64 * 4, 0x00020000);
+// Entries j0 .. j0+U-1 of lane l's row (row r) in the slice at entry offset
+// b, width W (>= 1): indices past W are clamped to W-1 (their products are
+// masked by the caller). Buffer loads over the slice's own entries (the
+// descriptors are scalar; a lane supplies a 32-bit byte offset). D16: the
+// column is r + the slice column's base + the 16-bit delta, as unsigned and
+// at most n - 1 (a padding entry's value is 0 whatever column it names).
+template <int U, typename SVT, bool D16>
+__device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l, int r,
+                                 int (&c)[U], SVT (&v)[U]) {
   const BufCol<SVT> vb(sell_vals<SVT>(S) + b, (int64_t)W * 64);
+  if constexpr (D16) {
+    const __amdgpu_buffer_rsrc_t rd =
+        __builtin_amdgcn_make_buffer_rsrc(S.cd + b, (short)0, W * 64 * 2, 0x00020000);
+    const int* cb = S.cbase + (b >> 6);
+    const uint32_t last = (uint32_t)(S.n - 1);
 #pragma unroll
-  for (int t = 0; t < U; ++t) {
-    const int j = j0 + t < W ? j0 + t : W - 1;
-    const uint32_t e = (uint32_t)(j * 64 + l);
-    c[t] = __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(e * 4u), 0, GMRES_SELL_CPOL);
-    v[t] = vb.template load<GMRES_SELL_CPOL>(e * (uint32_t)sizeof(SVT));
+    for (int t = 0; t < U; ++t) {
+      const int j = j0 + t < W ? j0 + t : W - 1;
+      const uint32_t e = (uint32_t)(j * 64 + l);
+      const uint32_t dl =
+          (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(rd, (int)(e * 2u), 0, GMRES_SELL_CPOL);
+      const uint32_t col = (uint32_t)(r + cb[j]) + dl;
+      c[t] = (int)(col < last ? col : last);
+      v[t] = vb.template load<GMRES_SELL_CPOL>(e * (uint32_t)sizeof(SVT));
+    }
+  } else {
+    const __amdgpu_buffer_rsrc_t rc =
+        __builtin_amdgcn_make_buffer_rsrc(S.ci + b, (short)0, W * 64 * 4, 0x00020000);
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const int j = j0 + t < W ? j0 + t : W - 1;
+      const uint32_t e = (uint32_t)(j * 64 + l);
+      c[t] = __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(e * 4u), 0, GMRES_SELL_CPOL);
+      v[t] = vb.template load<GMRES_SELL_CPOL>(e * (uint32_t)sizeof(SVT));
+    }
   }
 }
 
@@ -938,28 +1023,37 @@ __device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l,
 // value loads of the next chunk (of this slice or the next) are issued before
 // the gathers of the current one are consumed, so one memory latency per
 // chunk is hidden.
-template <int NS, int U, typename XT>
+template <int NS, int U, typename XT, bool D16>
 __device__ inline void sell_slices(const Sell& S, const XT* __restrict__ x, int64_t s0,
                                    int64_t sstride, int l, arith_t<XT> (&out)[NS]) {
   using T = arith_t<XT>;
   using SVT = sval_t<XT>;
+  // s0 is the same in every lane of the wavefront (the callers derive it from
+  // the wavefront index); saying so keeps the slice offsets, widths and buffer
+  // descriptors in scalar registers (the compiler cannot tell by itself, and
+  // would wrap every buffer load in a loop over the distinct descriptors)
+  s0 = __builtin_amdgcn_readfirstlane((int)s0);
   auto clampslice = [&](int64_t s) { return s < S.ns ? s : S.ns - 1; };
   // gathers from x[0, n) by 32-bit byte offset (the sliced format is used only
   // for n < 2^28)
   const BufCol<XT> xb(x, S.n);
-  int64_t b = S.sp[clampslice(s0)];
-  int W = (int)((S.sp[clampslice(s0) + 1] - b) >> 6);
+  int64_t sc = clampslice(s0);
+  int64_t b = S.sp[sc];
+  int W = (int)((S.sp[sc + 1] - b) >> 6);
+  int r = (int)(sc * 64 + l);  // the lane's row in that slice
   int c[U];
   SVT v[U];
-  sell_load<U, SVT>(S, b, W, 0, l, c, v);
+  sell_load<U, SVT, D16>(S, b, W, 0, l, r, c, v);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     int64_t bn = b;
     int Wn = W;
+    int rn = r;
     if (i + 1 < NS) {
       const int64_t sn = clampslice(s0 + (i + 1) * sstride);
       bn = S.sp[sn];
       Wn = (int)((S.sp[sn + 1] - bn) >> 6);
+      rn = (int)(sn * 64 + l);
     }
     T acc = (T)0;
     for (int j0 = 0; j0 < W; j0 += U) {
@@ -970,21 +1064,22 @@ __device__ inline void sell_slices(const Sell& S, const XT* __restrict__ x, int6
         vv[t] = (T)v[t];
       }
       if (j0 + U < W)
-        sell_load<U, SVT>(S, b, W, j0 + U, l, c, v);
+        sell_load<U, SVT, D16>(S, b, W, j0 + U, l, r, c, v);
       else if (i + 1 < NS)
-        sell_load<U, SVT>(S, bn, Wn, 0, l, c, v);
+        sell_load<U, SVT, D16>(S, bn, Wn, 0, l, rn, c, v);
 #pragma unroll
       for (int t = 0; t < U; ++t) acc += (j0 + t < W) ? vv[t] * xv[t] : (T)0;
     }
     out[i] = acc;
     b = bn;
     W = Wn;
+    r = rn;
   }
 }
 
 // y = A x (b == nullptr) or y = b - A x from the sliced copy: each wavefront
 // takes NS consecutive slices. Skipped when a state is given and its cycle is done.
-template <int NS>
+template <int NS, bool D16>
 __global__ __launch_bounds__(256) void k_spmv_sell(Sell S, int64_t n, const double* __restrict__ x,
                                                     const double* __restrict__ b,
                                                     double* __restrict__ y, const DevState* st) {
@@ -992,7 +1087,7 @@ __global__ __launch_bounds__(256) void k_spmv_sell(Sell S, int64_t n, const doub
   const int l = threadIdx.x & 63;
   const int64_t s0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * NS;
   double out[NS];
-  sell_slices<NS, 8, double>(S, x, s0, 1, l, out);
+  sell_slices<NS, 8, double, D16>(S, x, s0, 1, l, out);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int64_t r = (s0 + i) * 64 + l;
@@ -1391,13 +1486,14 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   const VT* __restrict__ u_g = V + (size_t)K * ldv;
   using CT = arith_t<VT>;  // arithmetic type of the basis
   constexpr bool HAS_SPMV = WSRC != kWNone;
-  // kWSell: the lane's rows are row 64 s + lane of slices s = row0/64 + wv RPT + i
+  // kWSell, kWSellD16: the lane's rows are row 64 s + lane of slices s = row0/64 + wv RPT + i
   CT ws_out[RPT];
-  if constexpr (WSRC == kWSell) {
+  if constexpr (WSRC == kWSell || WSRC == kWSellD16) {
+    constexpr bool D16 = WSRC == kWSellD16;
     if constexpr (GMRES_FUSED_ROWMAP == 1)
-      sell_slices<RPT, 8, VT>(SA, u_g, (row0 >> 6) + wv, 4, lane, ws_out);
+      sell_slices<RPT, 8, VT, D16>(SA, u_g, (row0 >> 6) + wv, 4, lane, ws_out);
     else
-      sell_slices<RPT, 8, VT>(SA, u_g, (row0 >> 6) + wv * RPT, 1, lane, ws_out);
+      sell_slices<RPT, 8, VT, D16>(SA, u_g, (row0 >> 6) + wv * RPT, 1, lane, ws_out);
   }
 
   if constexpr (WSRC == kWSpmv) {
@@ -1436,7 +1532,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     if constexpr (WSRC == kWSpmv) {
       w[i] = ok ? (CT)wl[lr] : (CT)0;
       if (ok) st_stream<1>(wout + r, (VT)w[i]);
-    } else if constexpr (WSRC == kWSell) {
+    } else if constexpr (WSRC == kWSell || WSRC == kWSellD16) {
       w[i] = ok ? ws_out[i] : (CT)0;
       if (ok) st_stream<1>(wout + r, (VT)w[i]);
     } else if constexpr (WSRC == kWLoad) {
@@ -1997,19 +2093,27 @@ int launch_spmv(const Csr& A, int shape, const double* x, const double* b, doubl
   return 0;
 }
 
-int launch_sell_width(const Csr& A, int64_t ns, int* width, hipStream_t s) {
+int launch_sell_width(const Csr& A, int64_t ns, int* width, int* spread, int max_width,
+                      hipStream_t s) {
   const int64_t blocks = (ns + 3) / 4;
-  hipLaunchKernelGGL(k_sell_width, dim3((unsigned)blocks), dim3(256), 0, s, A, ns, width);
+  hipLaunchKernelGGL(k_sell_width, dim3((unsigned)blocks), dim3(256), 0, s, A, ns, width, spread,
+                     max_width);
   GMRES_CHECK_LAUNCH();
   return 0;
 }
 
 int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s) {
-  const int64_t blocks = (S.ns * 64 + 255) / 256;
-  if (S.vaf)
+  const int64_t blocks = (S.ns * 64 + 255) / 256;  // a wavefront per slice, or a thread per row
+  if (S.cd) {
+    if (S.vaf)
+      hipLaunchKernelGGL(k_sell_fill_d16<float>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.vaf, st);
+    else
+      hipLaunchKernelGGL(k_sell_fill_d16<double>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.va, st);
+  } else if (S.vaf) {
     hipLaunchKernelGGL(k_sell_fill<float>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.vaf, st);
-  else
+  } else {
     hipLaunchKernelGGL(k_sell_fill<double>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.va, st);
+  }
   GMRES_CHECK_LAUNCH();
   return 0;
 }
@@ -2030,8 +2134,12 @@ int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b,
                      const DevState* st, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   constexpr int NS = 2;
   const int64_t blocks = (S.ns + 4 * NS - 1) / (4 * NS);
-  hipExtLaunchKernelGGL(k_spmv_sell<NS>, dim3((unsigned)blocks), dim3(256), 0u, s, e0, e1, 0u, S,
-                        n, x, b, y, st);
+  if (S.cd)
+    hipExtLaunchKernelGGL((k_spmv_sell<NS, true>), dim3((unsigned)blocks), dim3(256), 0u, s, e0, e1,
+                          0u, S, n, x, b, y, st);
+  else
+    hipExtLaunchKernelGGL((k_spmv_sell<NS, false>), dim3((unsigned)blocks), dim3(256), 0u, s, e0, e1,
+                          0u, S, n, x, b, y, st);
   GMRES_CHECK_LAUNCH();
   return 0;
 }
@@ -2055,6 +2163,7 @@ static int fused_r(const Csr& A, const Sell& SA, int shape, int wsrc, const Ws& 
     case kWNone: fused_t<RPT, 1, 1, kWNone, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
     case kWLoad: fused_t<RPT, 1, 1, kWLoad, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
     case kWSell: fused_t<RPT, 1, 1, kWSell, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
+    case kWSellD16: fused_t<RPT, 1, 1, kWSellD16, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
     case kWSpmv: break;
     default: return -2;
   }

@@ -69,16 +69,23 @@ struct Csr {
 
 // Sliced ELL copy of A owned by the library (SELL-64): slice s holds rows
 // 64 s .. 64 s + 63; entry j of row 64 s + l is at sp[s] + 64 j + l, for
-// j < W_s = (sp[s+1] - sp[s]) / 64 (at least 1). Padding entries hold value 0
-// and the row's own index (0 for rows past n).
+// j < W_s = (sp[s+1] - sp[s]) / 64 (at least 1). Padding entries hold value 0.
+// Column indices are either int32 (ci; padding holds the row's own index, 0
+// for rows past n) or, when every slice column's col - row values span less
+// than 2^16, 16-bit deltas (cd): the column of entry j of row r in slice s is
+// min(r + cbase[sp[s] / 64 + j] + cd[...], n - 1) taken as unsigned, so a
+// padding entry (delta 0) can never leave [0, n).
 struct Sell {
   const int64_t* sp;  // ns + 1 slice offsets (entries)
-  int* ci;
+  int* ci;            // int32 column indices, or null with 16-bit deltas
   double* va;         // float64 values (the FP64 schemes) ...
   float* vaf;         // ... or float32 values (the FP32-basis scheme)
   int64_t ns;         // slices, ceil(n / 64)
   int64_t n;          // rows (below 2^28: gathers take 32-bit byte offsets)
+  uint16_t* cd;       // 16-bit column deltas (null with int32 indices)
+  int* cbase;         // per slice column: the smallest col - row of its entries
 };
+constexpr int kSellDeltaSpan = 65535;  // largest col - row spread a slice column may have for cd
 
 // Views into the caller's workspace.
 struct Ws {
@@ -189,11 +196,16 @@ enum WSource {
   kWNone = 0,  // w = 0: only the sums over u
   kWSpmv = 1,  // w = A u computed in the kernel from the CSR arrays
   kWLoad = 2,  // w read from ws.w, written by a separate SpMV launch
-  kWSell = 3   // w = A u computed in the kernel from the sliced ELL copy
+  kWSell = 3,  // w = A u computed in the kernel from the sliced ELL copy (int32 indices)
+  kWSellD16 = 4  // the same from the sliced copy with 16-bit column deltas
 };
 // Sliced ELL construction: slice widths, then (with sp filled in) the copy;
 // rows longer than their slice's width set st->bad_csr.
-int launch_sell_width(const Csr& A, int64_t ns, int* width, hipStream_t s);
+// width[s] = max(1, longest row of slice s); *spread (device, nullable, set
+// to 0 beforehand) = the largest col - row spread over the slice columns of
+// slices at most max_width wide (INT_MAX when a slice is wider).
+int launch_sell_width(const Csr& A, int64_t ns, int* width, int* spread, int max_width,
+                      hipStream_t s);
 int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s);
 int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b, double* y,
                      const DevState* st, hipStream_t s, hipEvent_t e0 = nullptr,

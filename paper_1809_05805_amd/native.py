@@ -38,12 +38,16 @@ EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destr
             "gmres_solve_noalloc", "gmres_options_init", "gmres_workspace_bytes_ex",
             "gmres_create_ex", "gmres_batch_set_wait_limit"]
 GMRES_BATCH_ORDER_NATURAL, GMRES_BATCH_ORDER_LARGEST_FIRST = 0, 1
-GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64 = 0, 1
+GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64, GMRES_FORMAT_SELL64_D16 = 0, 1, 2
 GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
 GMRES_OPT_FORMAT_AUTO, GMRES_OPT_FORMAT_CSR, GMRES_OPT_FORMAT_SELL64 = 0, 1, 2
+GMRES_OPT_FORMAT_SELL64_D16 = 3
 OPT_FORMATS = {None: GMRES_OPT_FORMAT_AUTO, "auto": GMRES_OPT_FORMAT_AUTO,
                "csr": GMRES_OPT_FORMAT_CSR, "sell": GMRES_OPT_FORMAT_SELL64,
-               "sell64": GMRES_OPT_FORMAT_SELL64}
+               "sell64": GMRES_OPT_FORMAT_SELL64, "sell_d16": GMRES_OPT_FORMAT_SELL64_D16,
+               "sell64_d16": GMRES_OPT_FORMAT_SELL64_D16}
+FORMAT_NAMES = {GMRES_FORMAT_CSR: "csr", GMRES_FORMAT_SELL64: "sell64",
+                GMRES_FORMAT_SELL64_D16: "sell64_d16"}
 GMRES_BATCH_WAIT_LIMIT = 1 << 23
 
 
@@ -469,11 +473,11 @@ class GmresSolver:
             raise GmresError(rc, "gmres_refresh_matrix")
 
     def format(self):
-        """("csr" | "sell64", stored entries) of the context's SpMV."""
+        """("csr" | "sell64" | "sell64_d16", stored entries) of the context's SpMV."""
         rc, fmt, stored = gmres_get_format(self.ctx)
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_get_format")
-        return ("sell64" if fmt == GMRES_FORMAT_SELL64 else "csr"), stored
+        return FORMAT_NAMES[fmt], stored
 
     def last_cycle(self):
         rc, H, T, g, j = gmres_last_cycle(self.ctx, self.m)

@@ -22,7 +22,7 @@ from tests.gpu_util import D, gpu_run, log, oracle_run, rel
 pytestmark = pytest.mark.gpu
 
 SCHEMES = ["mgs", "mgs1r", "cgs2", "cgs2_3r", "two_synch"]
-FORMATS = ["csr", "sell"]
+FORMATS = ["csr", "sell", "sell_d16"]
 TOL = 1e-10
 
 
@@ -61,7 +61,7 @@ def test_spmv_matches_oracle(case, fmt):
     log(f"spmv {case} {fmt} n={p.n}")
     rp, ci, va = (torch.from_numpy(a).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
     s = GmresSolver(rp, ci, va, 4, "mgs1r", format=fmt)
-    assert s.format()[0] == {"csr": "csr", "sell": "sell64"}[fmt]
+    assert s.format()[0] == {"csr": "csr", "sell": "sell64", "sell_d16": "sell64_d16"}[fmt]
     x = P.rng(77, 0).standard_normal(p.n)
     y = torch.empty(p.n, dtype=torch.float64, device="cuda")
     s.spmv(torch.from_numpy(x).cuda(), y)

@@ -127,11 +127,12 @@ def test_options_sizing_and_refusals(lib):
     # one row per lane: 8x the tiles of the default 8 rows per lane at 128^3
     one = native.gmres_workspace_bytes_ex(n, m, native.GMRES_MGS_1R, native.make_options(rows_per_lane=1))
     assert one > base
-    ok = [dict(format="csr"), dict(format="sell"), dict(rows_per_lane=2), dict(csr_spmv_shape=804),
+    ok = [dict(format="csr"), dict(format="sell"), dict(format="sell_d16"), dict(rows_per_lane=2),
+          dict(csr_spmv_shape=804),
           dict(split_spmv=True), dict(pipeline_depth=2), dict(pipeline_depth=1)]
     for kw in ok:
         assert native.gmres_workspace_bytes_ex(4096, 30, native.GMRES_MGS_1R, native.make_options(**kw)) > 0, kw
-    bad = [dict(format=3), dict(rows_per_lane=3), dict(rows_per_lane=16), dict(csr_spmv_shape=107),
+    bad = [dict(format=4), dict(format=-1), dict(rows_per_lane=3), dict(rows_per_lane=16), dict(csr_spmv_shape=107),
            dict(pipeline_depth=-1), dict(pipeline_depth=native.GMRES_MAX_RESTART + 1)]
     for kw in bad:
         assert native.gmres_workspace_bytes_ex(4096, 30, native.GMRES_MGS_1R, native.make_options(**kw)) == 0, kw
