@@ -410,6 +410,10 @@ def small_config(args):
 
 BATCH_WORKLOAD = ("512 independent 2D 5-point upwind convection-diffusion systems, grid side "
                   "U{32..256} (n 1,024-65,536), Peclet U(1,100), wind angle U(0,2pi), GMRES(30) to 1e-10")
+BATCH3D_WORKLOAD = ("64 independent 3D 7-point upwind convection-diffusion systems, grid side "
+                    "U{32..64} (n 32,768-262,144), Peclet U(1,50), wind (cos t, sin t, 1/2) with "
+                    "t U(0,2pi), GMRES(50) to 1e-10: about 3.1 GB of float64 basis in use at once, "
+                    "12x the 256 MB last-level cache")
 
 
 def batch_bytes(info, sizes, nnz_sys, m, vb):
@@ -433,10 +437,12 @@ def batch_bytes(info, sizes, nnz_sys, m, vb):
     return total
 
 
-def batch_result(args):
+def batch_result(args, dim=2):
     """The batched form: one persistent launch per solve of the whole batch,
     float64 and float32 basis, each with the autotuned launch configuration,
-    against single-system float64 solves of a stratified sample run one by one."""
+    against single-system float64 solves of a stratified sample run one by one.
+    dim 2: the 512-system batch; dim 3: the 64-system 3D batch whose bases far
+    exceed the last-level cache."""
     import numpy as np
     import scipy.sparse as sp
     import torch
@@ -445,8 +451,9 @@ def batch_result(args):
     from paper_1809_05805_amd.native import BatchSolver, GmresSolver
 
     t0 = time.perf_counter()
-    bp = problems.make_batch(nsys=args.batch_systems)
-    log(f"batch: {bp.nsys} systems, n={bp.n} nnz={bp.nnz}, built in {time.perf_counter() - t0:.1f} s")
+    bp = problems.make_batch(nsys=args.batch_systems) if dim == 2 else problems.make_batch3d()
+    tag = "batch" if dim == 2 else "batch3d"
+    log(f"{tag}: {bp.nsys} systems, n={bp.n} nnz={bp.nnz}, built in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     rp, ci, va = (torch.from_numpy(a).to(dev) for a in (bp.row_ptr, bp.col_idx, bp.vals))
     b = torch.from_numpy(bp.b).to(dev)
@@ -454,8 +461,12 @@ def batch_result(args):
     sizes = np.diff(bp.row_off)
     nnz_sys = bp.row_ptr[bp.row_off[1:]].astype(np.int64) - bp.row_ptr[bp.row_off[:-1]]
     bnorm = np.sqrt(np.add.reduceat(bp.b ** 2, bp.row_off[:-1]))
-    out = {"workload": BATCH_WORKLOAD if args.batch_systems == 512 else f"{bp.nsys} systems",
-           "systems": bp.nsys, "rows": bp.n, "nnz": bp.nnz, "m": bp.m, "rtol": bp.rtol}
+    if dim == 3:
+        workload = BATCH3D_WORKLOAD
+    else:
+        workload = BATCH_WORKLOAD if args.batch_systems == 512 else f"{bp.nsys} systems"
+    out = {"workload": workload, "systems": bp.nsys, "rows": bp.n, "nnz": bp.nnz, "m": bp.m,
+           "rtol": bp.rtol}
     for scheme, key, vb in (("mgs1r", "fp64", 8), ("mgs1r_ir32", "fp32_basis", 4)):
         s = BatchSolver(bp.row_off, rp, ci, va, bp.m, scheme)
         x = torch.zeros(bp.n, dtype=torch.float64, device=dev)
@@ -486,13 +497,13 @@ def batch_result(args):
                     "autotune_trials": [{"block_size": t[0], "grid": t[1],
                                          "order": "largest_first" if t[2] else "natural",
                                          "part_rows": t[4], "ms": round(t[3], 2)} for t in trials]}
-        log(f"batch {scheme}: {iters} iters in {dt * 1e3:.1f} ms ({iters / dt:.0f} it/s), cfg {cfg}, "
+        log(f"{tag} {scheme}: {iters} iters in {dt * 1e3:.1f} ms ({iters / dt:.0f} it/s), cfg {cfg}, "
             f"worst rel res {res.max():.2e}")
         s.close()
         del x
     # single-system float64 solves, one after another, on systems spread over the sizes
     order = np.argsort(sizes, kind="stable")
-    sample = order[np.linspace(0, bp.nsys - 1, min(16, bp.nsys)).astype(int)]
+    sample = order[np.linspace(0, bp.nsys - 1, min(16 if dim == 2 else 8, bp.nsys)).astype(int)]
     it_s, t_s = 0, 0.0
     for i in sample:
         p = bp.system(int(i))
@@ -514,7 +525,7 @@ def batch_result(args):
                                         "each solved alone by the single-system float64 path"}
     out["fp64_speedup_vs_sequential"] = round(out["fp64"]["iters_per_s"] / seq, 2)
     out["fp32_basis_speedup_vs_sequential"] = round(out["fp32_basis"]["iters_per_s"] / seq, 2)
-    log(f"batch: sequential sample {seq:.0f} it/s")
+    log(f"{tag}: sequential sample {seq:.0f} it/s")
     return out
 
 
@@ -535,6 +546,8 @@ def main():
                     help="first run one plain device copy of this many MiB (a reference kernel "
                          "for hardware byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solver section")
+    ap.add_argument("--no-batch3d", action="store_true",
+                    help="skip the 3D batch whose bases exceed the last-level cache")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the device copy and sum rates reported beside the peak")
     ap.add_argument("--orth-study-N", type=int, default=100,
@@ -668,6 +681,8 @@ def main():
         out["small_64x64"] = small_config(args)
     if not args.no_batch:
         out["batch"] = batch_result(args)
+    if not args.no_batch3d:
+        out["batch_3d"] = batch_result(args, dim=3)
     if args.orth_study_N:
         out["orth_study"] = orth_study(args)
     if not args.no_cpu_baseline:

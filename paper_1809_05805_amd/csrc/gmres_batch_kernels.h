@@ -80,6 +80,18 @@ __device__ inline void coh_st(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Entry i of a per-system array, addressed as a uniform base plus a 32-bit
+// byte offset (a system has fewer than 2^28 rows, so the offset fits): one
+// address register per lane instead of two.
+template <typename T>
+__device__ inline T& at(T* base, uint32_t i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ inline const T& at(const T* base, uint32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * (uint32_t)sizeof(T));
+}
+
 // One workgroup's view of its queue entry.
 struct Team {
   unsigned* bar;     // the system's barrier counter
@@ -148,15 +160,27 @@ __device__ inline void team_reduce(Team& tm, const double* loc, double* vals, in
     return;
   }
   double* mine = tm.rows + ((size_t)tm.part * 2 + tm.buf) * tm.P;
-  for (int c = tid; c < cnt; c += bs) atomic_st(mine + c, loc[c]);
+  for (int c = tid; c < cnt; c += bs) atomic_st(&at(mine, (uint32_t)c), loc[c]);
   if (!team_sync(tm)) {
     for (int c = tid; c < cnt; c += bs) vals[c] = 0.0;
     __syncthreads();
     return;
   }
+  // every part's row, added in part order; the loads of 8 parts are issued
+  // together (one at a time, each would wait for its reply before the next)
   for (int c = tid; c < cnt; c += bs) {
     double a = 0.0;
-    for (int q = 0; q < tm.nparts; ++q) a += atomic_ld(tm.rows + ((size_t)q * 2 + tm.buf) * tm.P + c);
+    for (int q0 = 0; q0 < tm.nparts; q0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int q = q0 + t < tm.nparts ? q0 + t : tm.nparts - 1;
+        v[t] = atomic_ld(&at(tm.rows + ((size_t)q * 2 + tm.buf) * tm.P, (uint32_t)c));
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (q0 + t < tm.nparts) a += v[t];
+    }
     vals[c] = a;
   }
   tm.buf ^= 1;
@@ -182,21 +206,23 @@ __device__ inline double team_sum(Team& tm, double v, double* loc) {
   return t;
 }
 
-// Row r (local) of A x for one system, x indexed locally. With COH, entries
-// outside [lo, hi) (another part's rows) are gathered with coherent loads.
+// Row r (local) of A x for one system: rp is the system's first row pointer,
+// r0 its first global row, x indexed locally. With COH, entries outside
+// [lo, hi) (another part's rows) are gathered with coherent loads.
 template <typename XT>
-__device__ inline double batch_row(const Csr& A, int64_t r0, int64_t r, const XT* __restrict__ x,
-                                   bool COH, int64_t lo, int64_t hi) {
+__device__ inline double batch_row(const int* __restrict__ rp, const int* __restrict__ ci,
+                                   const double* __restrict__ va, int r0, uint32_t r,
+                                   const XT* __restrict__ x, bool COH, uint32_t lo, uint32_t hi) {
   double a = 0.0;
-  const int e1 = A.rp[r0 + r + 1];
-  for (int e = A.rp[r0 + r]; e < e1; ++e) {
-    const int64_t c = A.ci[e] - r0;
+  const int e1 = at(rp, r + 1);
+  for (int e = at(rp, r); e < e1; ++e) {
+    const uint32_t c = (uint32_t)(ci[e] - r0);
     XT v;
     if (COH && (c < lo || c >= hi))
-      v = coh_ld(x + c);
+      v = coh_ld(&at(x, c));
     else
-      v = x[c];
-    a += A.va[e] * (double)v;
+      v = at(x, c);
+    a += va[e] * (double)v;
   }
   return a;
 }
@@ -215,8 +241,8 @@ template <int BS, typename VT>
 __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, double* vals,
                            double* scr) {
   constexpr int NW = BS / 64;
-  // rows per thread per row block (fewer for 1024 threads, whose 128
-  // registers per lane the deeper unrolling would overflow)
+  // rows per thread per row block (fewer for 1024 threads, which have 128
+  // registers per lane)
   constexpr int RB = BS >= 1024 ? 4 : 8;
   constexpr bool F32 = sizeof(VT) == 4;
   __shared__ int s_flag[4];
@@ -242,7 +268,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
     tm.lo = chunk * K.part < n ? chunk * K.part : n;
     tm.hi = tm.lo + chunk < n ? tm.lo + chunk : n;
   }
-  const int64_t lo = tm.lo, hi = tm.hi;
+  const uint32_t lo = (uint32_t)tm.lo, hi = (uint32_t)tm.hi;
   // coherent gathers across part boundaries and coherent stores of what
   // other parts gather: only in a real team
   const bool coh = K.nparts > 1;
@@ -282,13 +308,17 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
   const int64_t ldv = ws.ldv;
   const double* __restrict__ b = B.b + r0;
   double* __restrict__ x = B.x + r0;
-  const int64_t nrow = hi - lo;
-  const int64_t nblk = (nrow + (int64_t)BS * RB - 1) / ((int64_t)BS * RB);
+  const int nblk = (int)((hi - lo + BS * RB - 1) / (BS * RB));
+  const int* __restrict__ rp_s = B.A.rp + r0;
+  // row r of this system's A times x (x indexed locally)
+  auto row = [&](uint32_t r, const auto* __restrict__ xx) {
+    return batch_row(rp_s, B.A.ci, B.A.va, (int)r0, r, xx, coh, lo, hi);
+  };
   double* loc = vals + P;  // team_sum's LDS (NW + 2 doubles after vals)
 
   // ||b|| and the tolerance
   double sb = 0.0;
-  for (int64_t r = lo + tid; r < hi; r += BS) sb += b[r] * b[r];
+  for (uint32_t r = lo + tid; r < hi; r += BS) sb += at(b, r) * at(b, r);
   const double bnorm = sqrt(team_sum<BS>(tm, sb, loc));
   if (tid == 0) {
     st->done = st->j = st->true_conv = st->breakdown = st->status = 0;
@@ -308,7 +338,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
   } else if (!isfinite(bnorm)) {
     out.status = kNonfinite;
   } else if (bnorm == 0.0) {
-    for (int64_t r = lo + tid; r < hi; r += BS) x[r] = 0.0;
+    for (uint32_t r = lo + tid; r < hi; r += BS) at(x, r) = 0.0;
     out.converged = 1;
   } else {
     const double tol_abs = B.rtol * bnorm;
@@ -321,8 +351,8 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
       if (m_eff == 0) {
         // the iteration budget is spent: the true residual of the final x
         double sr = 0.0;
-        for (int64_t r = lo + tid; r < hi; r += BS) {
-          const double d = b[r] - batch_row(B.A, r0, r, x, coh, lo, hi);
+        for (uint32_t r = lo + tid; r < hi; r += BS) {
+          const double d = at(b, r) - row(r, x);
           sr += d * d;
         }
         const double rn = sqrt(team_sum<BS>(tm, sr, loc));
@@ -335,7 +365,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
       // cycle start: clear the small dense matrices and the flags
       {
         const size_t tot = 2 * (size_t)(m + 1) * m + 2 * (size_t)(m + 2) * (m + 2) + 2 * (size_t)(m + 2);
-        for (size_t e = tid; e < tot; e += BS) ws.H[e] = 0.0;  // H, R, T, TT, g, gh are contiguous
+        for (uint32_t e = tid; e < tot; e += BS) at(ws.H, e) = 0.0;  // H, R, T, TT, g, gh are contiguous
         if (tid == 0) {
           st->done = st->j = st->true_conv = st->breakdown = 0;
           st->xscale = 1.0;
@@ -347,9 +377,9 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
       double beta_cycle = 0.0;
       if constexpr (F32) {
         double sr = 0.0;
-        for (int64_t r = lo + tid; r < hi; r += BS) {
-          const double d = b[r] - batch_row(B.A, r0, r, x, coh, lo, hi);
-          ws.r64[r] = d;
+        for (uint32_t r = lo + tid; r < hi; r += BS) {
+          const double d = at(b, r) - row(r, x);
+          at(ws.r64, r) = d;
           sr += d * d;
         }
         const double beta = sqrt(team_sum<BS>(tm, sr, loc));
@@ -364,7 +394,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
           break;
         }
         const double inv = 1.0 / beta;
-        for (int64_t r = lo + tid; r < hi; r += BS) put(cst, V + r, (VT)(ws.r64[r] * inv));
+        for (uint32_t r = lo + tid; r < hi; r += BS) put(cst, &at(V, r), (VT)(at(ws.r64, r) * inv));
         // the float64 check above is the restart test: the normalized float32
         // start vector is not tested again (tol_cycle 0 for step 0)
         if (tid == 0) {
@@ -374,8 +404,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
         }
         beta_cycle = beta;
       } else {
-        for (int64_t r = lo + tid; r < hi; r += BS)
-          put(cst, V + r, (VT)(b[r] - batch_row(B.A, r0, r, x, coh, lo, hi)));
+        for (uint32_t r = lo + tid; r < hi; r += BS) put(cst, &at(V, r), (VT)(at(b, r) - row(r, x)));
       }
       for (int k = 0; k <= m_eff; ++k) {
         // column k is complete on every part before the SpMV gathers it
@@ -385,21 +414,21 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
         const int cnt = 2 * (nproj + 1);
         for (int c = lane; c < cnt; c += 64) red[wv * P + c] = 0.0;
         const VT* __restrict__ u_g = V + (size_t)k * ldv;
-        for (int64_t blk = 0; blk < nblk; ++blk) {
+        for (int blk = 0; blk < nblk; ++blk) {
           // this thread's rows of the block: clamped loads, masked values
           VT u[RB], w[RB];
           uint32_t off[RB];
 #pragma unroll
           for (int t = 0; t < RB; ++t) {
-            const int64_t r = lo + blk * BS * RB + (int64_t)t * BS + tid;
+            const uint32_t r = lo + (uint32_t)(blk * BS * RB + t * BS + tid);
             const bool ok = r < hi;
-            const int64_t rc = ok ? r : hi - 1;
-            off[t] = (uint32_t)rc * (uint32_t)sizeof(VT);
-            u[t] = ok ? u_g[rc] : (VT)0;
+            const uint32_t rc = ok ? r : hi - 1;
+            off[t] = rc * (uint32_t)sizeof(VT);
+            u[t] = ok ? at(u_g, rc) : (VT)0;
             if (!last) {
-              const double a = ok ? batch_row(B.A, r0, rc, u_g, coh, lo, hi) : 0.0;
+              const double a = ok ? row(rc, u_g) : 0.0;
               w[t] = (VT)a;
-              if (ok) wv_[r] = w[t];
+              if (ok) at(wv_, r) = w[t];
             } else {
               w[t] = (VT)0;
             }
@@ -480,21 +509,23 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
           s_flag[1] = st->j;
         }
         double* cl = scr;  // the MAXPY coefficients (the tail's LDS scratch is free again)
-        for (int q = tid; q <= k; q += BS) cl[q] = ws.coef[q];
+        for (int q = tid; q <= k; q += BS) cl[q] = at(ws.coef, (uint32_t)q);
         __syncthreads();
         if (s_flag[0]) break;
         // MAXPY: V[:,k] = u / rho, V[:,k+1] = w / rho - V[:,0:k+1] h
         const VT invr = (VT)st->inv_rho;
-        for (int64_t blk = 0; blk < nblk; ++blk) {
+        VT* __restrict__ vk_g = V + (size_t)k * ldv;
+        VT* __restrict__ vn_g = vk_g + ldv;
+        for (int blk = 0; blk < nblk; ++blk) {
           VT acc[RB], vk[RB];
           uint32_t off[RB];
 #pragma unroll
           for (int t = 0; t < RB; ++t) {
-            const int64_t r = lo + blk * BS * RB + (int64_t)t * BS + tid;
-            const int64_t rc = r < hi ? r : hi - 1;
-            off[t] = (uint32_t)rc * (uint32_t)sizeof(VT);
-            acc[t] = wv_[rc] * invr;
-            vk[t] = V[(size_t)k * ldv + rc] * invr;
+            const uint32_t r = lo + (uint32_t)(blk * BS * RB + t * BS + tid);
+            const uint32_t rc = r < hi ? r : hi - 1;
+            off[t] = rc * (uint32_t)sizeof(VT);
+            acc[t] = at(wv_, rc) * invr;
+            vk[t] = at(vk_g, rc) * invr;
           }
           auto load_col = [&](VT (&buf)[RB], int j) {
             const GlbCol<VT> col(V + (size_t)j * ldv, n);
@@ -522,10 +553,10 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
           const VT ck = (VT)cl[k];
 #pragma unroll
           for (int t = 0; t < RB; ++t) {
-            const int64_t r = lo + blk * BS * RB + (int64_t)t * BS + tid;
+            const uint32_t r = lo + (uint32_t)(blk * BS * RB + t * BS + tid);
             if (r < hi) {
-              V[(size_t)k * ldv + r] = vk[t];
-              put(cst, V + (size_t)(k + 1) * ldv + r, acc[t] - vk[t] * ck);
+              at(vk_g, r) = vk[t];
+              put(cst, &at(vn_g, r), acc[t] - vk[t] * ck);
             }
           }
         }
@@ -563,10 +594,10 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
         }
       }
       __syncthreads();
-      for (int64_t r = lo + tid; r < hi; r += BS) {
-        double a = x[r];
-        for (int q = 0; q < j; ++q) a += (double)V[(size_t)q * ldv + r] * yl[q];
-        put(cst, x + r, a);
+      for (uint32_t r = lo + tid; r < hi; r += BS) {
+        double a = at(x, r);
+        for (int q = 0; q < j; ++q) a += (double)at(V + (size_t)q * ldv, r) * yl[q];
+        put(cst, &at(x, r), a);
       }
       __syncthreads();
       it += j;

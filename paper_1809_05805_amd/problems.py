@@ -280,6 +280,35 @@ class BatchProblem:
                              "angle": float(self.angle[i])})
 
 
+def _batch_of(name: str, cid: int, seed: int, dim: int, sides, peclet, angle, m: int,
+              rtol: float) -> BatchProblem:
+    """The block-diagonal batch of upwind convection-diffusion systems with the
+    given grid sides, Peclet numbers and wind angles (in 3D the wind is
+    (cos t, sin t, 1/2)); x_true ~ U(-1, 1) over the batch from stream 0."""
+    sizes = sides.astype(np.int64) ** dim
+    row_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(row_off[-1])
+    rps, cis, vas = [], [], []
+    nnz = 0
+    for i in range(len(sides)):
+        wind = (np.cos(angle[i]), np.sin(angle[i])) + ((0.5,) if dim == 3 else ())
+        A = convdiff(int(sides[i]), dim, wind, float(peclet[i]))
+        rp, ci, va = csr_from_scipy(A)
+        rps.append(rp[:-1].astype(np.int64) + nnz)
+        cis.append(ci.astype(np.int64) + row_off[i])
+        vas.append(va)
+        nnz += int(rp[-1])
+    if nnz >= 2**31 or n >= 2**31:
+        raise ValueError("batch too large for int32 CSR indices")
+    row_ptr = np.concatenate(rps + [np.array([nnz])]).astype(np.int32)
+    col_idx = np.concatenate(cis).astype(np.int32)
+    vals = np.concatenate(vas)
+    x_true = rng(cid, 0, seed).uniform(-1.0, 1.0, n)
+    b = sp.csr_matrix((vals, col_idx, row_ptr), shape=(n, n)) @ x_true
+    return BatchProblem(name, row_off, row_ptr, col_idx, vals, np.ascontiguousarray(b),
+                        np.zeros(n), x_true, m, rtol, sides, peclet, angle)
+
+
 def make_batch(nsys: int = 512, seed: int = 0, side_lo: int = 32, side_hi: int = 256,
                m: int = 30, rtol: float = 1e-10) -> BatchProblem:
     """Batch of 2D 5-point upwind convection-diffusion systems (config id 5).
@@ -295,24 +324,24 @@ def make_batch(nsys: int = 512, seed: int = 0, side_lo: int = 32, side_hi: int =
     sides = g.integers(side_lo, side_hi + 1, size=nsys)
     peclet = g.uniform(1.0, 100.0, size=nsys)
     angle = g.uniform(0.0, 2.0 * np.pi, size=nsys)
-    sizes = sides.astype(np.int64) ** 2
-    row_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    n = int(row_off[-1])
-    rps, cis, vas = [], [], []
-    nnz = 0
-    for i in range(nsys):
-        A = convdiff(int(sides[i]), 2, (np.cos(angle[i]), np.sin(angle[i])), float(peclet[i]))
-        rp, ci, va = csr_from_scipy(A)
-        rps.append(rp[:-1].astype(np.int64) + nnz)
-        cis.append(ci.astype(np.int64) + row_off[i])
-        vas.append(va)
-        nnz += int(rp[-1])
-    if nnz >= 2**31 or n >= 2**31:
-        raise ValueError("batch too large for int32 CSR indices")
-    row_ptr = np.concatenate(rps + [np.array([nnz])]).astype(np.int32)
-    col_idx = np.concatenate(cis).astype(np.int32)
-    vals = np.concatenate(vas)
-    x_true = rng(cid, 0, seed).uniform(-1.0, 1.0, n)
-    b = sp.csr_matrix((vals, col_idx, row_ptr), shape=(n, n)) @ x_true
-    return BatchProblem(f"batch{nsys}", row_off, row_ptr, col_idx, vals, np.ascontiguousarray(b),
-                        np.zeros(n), x_true, m, rtol, sides, peclet, angle)
+    return _batch_of(f"batch{nsys}", cid, seed, 2, sides, peclet, angle, m, rtol)
+
+
+def make_batch3d(nsys: int = 64, seed: int = 0, side_lo: int = 32, side_hi: int = 64,
+                 m: int = 50, rtol: float = 1e-10) -> BatchProblem:
+    """Batch of 3D 7-point upwind convection-diffusion systems (id 6), sized so
+    that the bases in use at once far exceed the GPU's 256 MB last-level cache
+    (64 systems of 32^3..64^3 rows at m = 50: about 3 GB of basis).
+
+    Per system: grid side N ~ U{side_lo..side_hi} (n = N^3), Peclet ~ U(1, 50)
+    and wind (cos t, sin t, 1/2) with t ~ U(0, 2 pi), all from stream 3;
+    x_true ~ U(-1, 1) over the whole batch from stream 0; b = A x_true, x0 = 0.
+    """
+    if nsys < 1 or side_lo < 1 or side_hi < side_lo:
+        raise ValueError("need nsys >= 1 and 1 <= side_lo <= side_hi")
+    cid = 6
+    g = rng(cid, 3, seed)
+    sides = g.integers(side_lo, side_hi + 1, size=nsys)
+    peclet = g.uniform(1.0, 50.0, size=nsys)
+    angle = g.uniform(0.0, 2.0 * np.pi, size=nsys)
+    return _batch_of(f"batch3d_{nsys}", cid, seed, 3, sides, peclet, angle, m, rtol)

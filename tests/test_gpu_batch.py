@@ -411,3 +411,43 @@ def test_long_restart(bs):
             o = oracle_run(p, "mgs1r", m=100, rtol=0.0, max_iters=120, dump=False)
             assert info["iters"][i] == o.iters == 120
             assert rel(x[bp.row_off[i]: bp.row_off[i + 1]], o.x) <= TOL, (i, part_rows)
+
+
+@pytest.mark.parametrize("bs,part_rows", [(256, 0), (1024, 0), (256, 1024), (1024, 512)])
+def test_batch3d_fixed_budget_parity(bs, part_rows):
+    """3D 7-point systems (sides 8..24, m = 50): every system against the
+    oracle's solve of that system alone after 70 steps, with and without teams."""
+    bp = P.make_batch3d(nsys=6, seed=3, side_lo=8, side_hi=24, m=50)
+    log(f"3D batch fixed budget bs={bs} part_rows={part_rows} n={bp.n}")
+    rc, info, x, s = run(bp, rtol=0.0, max_iters=70, config=(bs, 0, 1, part_rows))
+    assert rc == 0
+    for i in range(bp.nsys):
+        p = bp.system(i)
+        o = oracle_run(p, "mgs1r", m=50, rtol=0.0, max_iters=70, dump=False)
+        assert info["iters"][i] == o.iters == 70 and info["cycles"][i] == o.cycles, i
+        assert rel(x[bp.row_off[i]: bp.row_off[i + 1]], o.x) <= TOL, (i, p.n)
+
+
+@pytest.mark.parametrize("scheme", ["mgs1r", "mgs1r_ir32"])
+def test_full_batch3d(scheme):
+    """The 64-system 3D batch (sides 32..64, m = 50, about 3 GB of float64
+    basis): every system truly converged to 1e-10 (residuals recomputed here),
+    the two smallest against the oracle."""
+    bp = P.make_batch3d()
+    log(f"full 3D batch {scheme}: n={bp.n} nnz={bp.nnz}")
+    rc, info, x, _ = run(bp, scheme, config=(1024, 0, 1, 4096))
+    assert rc == 0
+    assert np.all(info["status"] == 0) and np.all(info["converged"] == 1)
+    worst = 0.0
+    for i in range(bp.nsys):
+        r = true_rel(bp, i, x)
+        worst = max(worst, r)
+        assert r <= TOL * (1 + 1e-6), (i, r)
+    log(f"  iters total {int(info['iters'].sum())}, max {int(info['iters'].max())}, "
+        f"worst true rel res {worst:.2e}")
+    for i in np.argsort(np.diff(bp.row_off), kind="stable")[:2]:
+        p = bp.system(int(i))
+        o = oracle_run(p, "mgs1r", m=50, rtol=TOL, dump=False)
+        if scheme == "mgs1r":
+            assert abs(int(info["iters"][i]) - o.iters) <= 1
+        assert rel(x[bp.row_off[i]: bp.row_off[i + 1]], o.x) <= 10 * 1e4 * TOL
