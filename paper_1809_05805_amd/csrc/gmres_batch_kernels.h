@@ -4,12 +4,6 @@
 // step, the device-coherent partial-sum accesses).
 #pragma once
 
-//   GMRES_BATCH_TAIL_ROWS  rows per wavefront pass in the small dense step's
-//                          T products (fewer rows hold fewer registers live).
-#ifndef GMRES_BATCH_TAIL_ROWS
-#define GMRES_BATCH_TAIL_ROWS 4
-#endif
-
 // ---------------------------------------------------- batched persistent solver
 //
 // A batch is a block-diagonal matrix: system i owns rows [r0, r0 + n) and its
@@ -235,11 +229,170 @@ __device__ inline void put(bool coh, T* p, T v) {
     *p = v;
 }
 
+// Restarts up to this m keep T in LDS with the rest of a cycle's small dense
+// state; longer ones keep T in the system's global small workspace (T alone
+// would outgrow the LDS).
+constexpr int kBatchLdsTriMaxM = 128;
+
+// LDS doubles of a cycle's small dense state for restart m: the rotations
+// (cs, sn), the newest Hessenberg column and two scalars, and with T in LDS
+// its strictly upper triangle.
+constexpr size_t batch_state_lds_doubles(int m) {
+  return 3 * (size_t)(m + 2) + 2 + (m <= kBatchLdsTriMaxM ? (size_t)m * (m + 1) / 2 : 0);
+}
+
+// A cycle's small dense state (in LDS; T in LDS or global memory).
+struct BatchSml {
+  double* cs;   // m + 2: the Givens rotations of the cycle so far
+  double* sn;   // m + 2
+  double* h;    // m + 2: the newest Hessenberg column h[0..k] (the MAXPY
+                // coefficients), with rho below it once known
+  double* sc;   // [0] the running residual entry g_k, [1] 1 / rho
+  double* tri;  // T above its unit diagonal: T(q, i) at i (i - 1) / 2 + q, q < i
+};
+
+// The small dense step of lagged step k of the batched solver, with the
+// cycle's state in LDS (T too, for m <= kBatchLdsTriMaxM), so that it makes no
+// global round trip but T's for longer restarts:
+//   thread 0: the lagged norm rho = ||u|| (Section II, the normalization lag),
+//     which completes Hessenberg column k-1; that column's Givens rotation,
+//     the update of g and the stopping test |g_k| <= tol (one step late,
+//     Section III);
+//   all: l = V[:,0:k]^T v_k = p / rho, r = [c / rho; gamma / rho^2], the new
+//     column of T (T(q, k) = -(l_q + sum over q < j < k of T(q, j) l_j), so
+//     that T = (I + L^T)^{-1}), and h = (I + L)^{-1} r: h[0:k] = r[0:k] +
+//     (the earlier T)^T r[0:k] and h_k = r_k - l . h[0:k].
+// Only R and g (read by the back substitution) and the state record go to
+// memory besides. vals holds the step's totals: vals[2q] = V_q . u,
+// vals[2q+1] = V_q . w (q < k), vals[2k] = u.u, vals[2k+1] = u.w; scr holds
+// 3 (m + 2) doubles of scratch. Returns true, the same in every thread, when
+// the cycle ends here.
+__device__ bool batch_tail(const Ws& ws, const double* vals, double* scr, int k, bool norm_only,
+                               double tol, const BatchSml& L) {
+  __shared__ int s_go, s_bad;
+  __shared__ double s_rho;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  DevState* st = ws.st;
+  if (tid == 0) {
+    st->reductions += 1;
+    const double alpha = vals[norm_only ? 0 : 2 * k];
+    int go = 1;
+    double rho = 0.0;
+    if (!(alpha >= 0.0) || !isfinite(alpha)) {
+      st->status = kNonfinite;
+      st->done = 1;
+      go = 0;
+    } else {
+      rho = sqrt(alpha);
+      if (k == 0) {
+        st->beta = rho;
+        ws.g[0] = rho;
+        L.sc[0] = rho;
+        if (rho <= tol) {
+          st->true_conv = 1;
+          st->done = 1;
+          st->j = 0;
+          go = 0;
+        }
+      } else {
+        // column k-1 = [h[0..k-1], rho]: the earlier rotations, then its own
+        double* Rc = ws.R + (size_t)(k - 1) * ws.ldh;
+        double a = L.h[0];
+        for (int i = 0; i < k - 1; ++i) {
+          const double b = L.h[i + 1], c = L.cs[i], s = L.sn[i];
+          Rc[i] = c * a + s * b;
+          a = -s * a + c * b;
+        }
+        double c, s;
+        rot_make(a, rho, &c, &s);
+        Rc[k - 1] = c * a + s * rho;
+        Rc[k] = 0.0;
+        L.cs[k - 1] = c;
+        L.sn[k - 1] = s;
+        const double g = L.sc[0];
+        const double gn = -s * g;
+        ws.g[k - 1] = c * g;
+        ws.g[k] = gn;
+        L.sc[0] = gn;
+        const double res = fabs(gn);
+        if (!isfinite(res)) {
+          st->status = kNonfinite;
+          st->done = 1;
+          go = 0;
+        } else if (rho == 0.0) {
+          st->breakdown = 1;
+          st->done = 1;
+          st->j = k;
+          go = 0;
+        } else if (res <= tol || norm_only) {
+          st->done = 1;
+          st->j = k;
+          go = 0;
+        }
+      }
+      if (go) {
+        st->rho = rho;
+        L.sc[1] = 1.0 / rho;
+      }
+    }
+    s_rho = rho;
+    s_go = go;
+    s_bad = 0;
+  }
+  __syncthreads();
+  if (!s_go) return true;
+  const double rho = s_rho;
+  const int M2 = ws.m + 2;
+  double* ell = scr;
+  double* rr = scr + M2;
+  double* hb = scr + 2 * M2;
+  for (int q = tid; q < k; q += bs) {
+    ell[q] = vals[2 * q] / rho;
+    rr[q] = vals[2 * q + 1] / rho;
+  }
+  if (tid == 0) rr[k] = (vals[2 * k + 1] / rho) / rho;
+  __syncthreads();
+  // column k of T (T's earlier columns only are read), and hb = T^T r over them
+  double* tk = L.tri + (size_t)k * (k - 1) / 2;
+  for (int q = tid; q < k; q += bs) {
+    double a = ell[q];
+    for (int j = q + 1; j < k; ++j) a += L.tri[(size_t)j * (j - 1) / 2 + q] * ell[j];
+    tk[q] = -a;
+  }
+  tri_dots(L.tri, rr, k, hb);
+  __syncthreads();
+  for (int i = tid; i < k; i += bs) {
+    const double h = rr[i] + hb[i];
+    L.h[i] = h;
+    if (!isfinite(h)) s_bad = 1;
+  }
+  if (tid < 64) {
+    double a = 0.0;
+    for (int q = tid; q < k; q += 64) a += ell[q] * (rr[q] + hb[q]);
+    a = wave_sum(a);
+    if (tid == 0) {
+      const double hk = rr[k] - a;
+      L.h[k] = hk;
+      if (!isfinite(hk)) s_bad = 1;
+    }
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) {
+      st->status = kNonfinite;
+      st->done = 1;
+    }
+    return true;
+  }
+  return false;
+}
+
 // The solve of one queue entry (a system, or one part of a team) by one
 // workgroup of BS threads. Team and ticket values are uniform.
-template <int BS, typename VT>
+// LT: T is kept in LDS (m <= kBatchLdsTriMaxM), else in global memory.
+template <int BS, typename VT, bool LT>
 __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, double* vals,
-                           double* scr) {
+                           double* scr, double* sml) {
   constexpr int NW = BS / 64;
   // rows per thread per row block (fewer for 1024 threads, which have 128
   // registers per lane)
@@ -303,6 +456,12 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
     ws.m = m;
   }
   DevState* st = ws.st;
+  BatchSml L;
+  L.cs = sml;
+  L.sn = L.cs + (m + 2);
+  L.h = L.sn + (m + 2);
+  L.sc = L.h + (m + 2);
+  L.tri = LT ? L.sc + 2 : ws.T;
   VT* __restrict__ V = basis_of<VT>(ws);
   VT* __restrict__ wv_ = wbuf_of<VT>(ws);
   const int64_t ldv = ws.ldv;
@@ -491,29 +650,13 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
         if (tm.failed) break;
         // the small dense step (H column, T column, Givens, flags, MAXPY
         // coefficients), run by every part on the same totals
-        TailPrefetch<1> pf;
-        pf.ws = &ws;
-        pf.tri = nullptr;
-        pf.k = k;
-        pf.scheme = kSchemeMgs1r;
-        pf.active = true;
-        pf.staged = false;
-        pf.ntri = 0;
-        pf.issue();
-        pf.commit();
-        tail_lagged<1, GMRES_BATCH_TAIL_ROWS, false>(ws, vals, scr, k, last, m_eff, kSchemeMgs1r, pf);
-        if (F32 && k == 0 && tid == 0) st->tol_cycle = tol_abs / beta_cycle;
-        __syncthreads();
-        if (tid == 0) {
-          s_flag[0] = st->done;
-          s_flag[1] = st->j;
-        }
-        double* cl = scr;  // the MAXPY coefficients (the tail's LDS scratch is free again)
-        for (int q = tid; q <= k; q += BS) cl[q] = at(ws.coef, (uint32_t)q);
-        __syncthreads();
-        if (s_flag[0]) break;
+        // the small dense step (Givens, T column, flags, the MAXPY
+        // coefficients h[0..k] into L.h), run by every part on the same totals
+        const double tol_k = F32 ? (k == 0 ? 0.0 : tol_abs / beta_cycle) : tol_abs;
+        if (batch_tail(ws, vals, scr, k, last, tol_k, L)) break;
+        const double* cl = L.h;
+        const VT invr = (VT)L.sc[1];
         // MAXPY: V[:,k] = u / rho, V[:,k+1] = w / rho - V[:,0:k+1] h
-        const VT invr = (VT)st->inv_rho;
         VT* __restrict__ vk_g = V + (size_t)k * ldv;
         VT* __restrict__ vn_g = vk_g + ldv;
         for (int blk = 0; blk < nblk; ++blk) {
@@ -614,7 +757,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
   __syncthreads();
 }
 
-template <int BS, typename VT>
+template <int BS, typename VT, bool LT>
 __global__ __launch_bounds__(BS) void k_batch(Batch B) {
   extern __shared__ double lds[];
   __shared__ int s_pos;
@@ -623,6 +766,7 @@ __global__ __launch_bounds__(BS) void k_batch(Batch B) {
   double* red = lds;              // NW x P per-wavefront sums
   double* vals = red + NW * P;    // P totals, then team_sum's NW + 2
   double* scr = vals + P + NW + 2; // 6 (m + 2) for the small dense step
+  double* sml = scr + 6 * (B.m + 2);  // batch_state_lds_doubles(m)
   for (;;) {
     if (threadIdx.x == 0) s_pos = (int)atomicAdd(B.queue, 1u);
     __syncthreads();
@@ -634,13 +778,15 @@ __global__ __launch_bounds__(BS) void k_batch(Batch B) {
     K.part = __builtin_amdgcn_readfirstlane(K.part);
     K.nparts = __builtin_amdgcn_readfirstlane(K.nparts);
     K.base = __builtin_amdgcn_readfirstlane(K.base);
-    batch_part<BS, VT>(B, K, red, vals, scr);
+    batch_part<BS, VT, LT>(B, K, red, vals, scr, sml);
   }
 }
 
 size_t batch_lds_bytes(int bs, int m) {
   const size_t P = 2 * (size_t)(m + 2);
-  return ((size_t)(bs / 64) * P + P + (size_t)(bs / 64) + 2 + 6 * (size_t)(m + 2)) * sizeof(double);
+  return ((size_t)(bs / 64) * P + P + (size_t)(bs / 64) + 2 + 6 * (size_t)(m + 2) +
+          batch_state_lds_doubles(m)) *
+         sizeof(double);
 }
 
 int launch_batch_validate(const Csr& A, const BatchSys* sys, int nsys, DevState* st, hipStream_t s) {
@@ -658,13 +804,25 @@ int launch_batch_reset(const Batch& B, hipStream_t s) {
   return 0;
 }
 
-template <int BS, typename VT>
+template <int BS, typename VT, bool LT>
 void batch_launch_one(const Batch& B, int grid, uint32_t lds, hipStream_t s, hipEvent_t e0,
                       hipEvent_t e1) {
   if (e0 || e1)
-    hipExtLaunchKernelGGL((k_batch<BS, VT>), dim3(grid), dim3(BS), lds, s, e0, e1, 0u, B);
+    hipExtLaunchKernelGGL((k_batch<BS, VT, LT>), dim3(grid), dim3(BS), lds, s, e0, e1, 0u, B);
   else
-    hipLaunchKernelGGL((k_batch<BS, VT>), dim3(grid), dim3(BS), lds, s, B);
+    hipLaunchKernelGGL((k_batch<BS, VT, LT>), dim3(grid), dim3(BS), lds, s, B);
+}
+
+template <int BS>
+void batch_launch_bs(const Batch& B, bool f32, int grid, uint32_t lds, hipStream_t s,
+                     hipEvent_t e0, hipEvent_t e1) {
+  const bool lt = B.m <= kBatchLdsTriMaxM;
+  if (f32)
+    lt ? batch_launch_one<BS, float, true>(B, grid, lds, s, e0, e1)
+       : batch_launch_one<BS, float, false>(B, grid, lds, s, e0, e1);
+  else
+    lt ? batch_launch_one<BS, double, true>(B, grid, lds, s, e0, e1)
+       : batch_launch_one<BS, double, false>(B, grid, lds, s, e0, e1);
 }
 
 int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipEvent_t e0,
@@ -673,16 +831,13 @@ int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipE
   const uint32_t lds = (uint32_t)batch_lds_bytes(bs, B.m);
   switch (bs) {
     case 256:
-      f32 ? batch_launch_one<256, float>(B, grid, lds, s, e0, e1)
-          : batch_launch_one<256, double>(B, grid, lds, s, e0, e1);
+      batch_launch_bs<256>(B, f32, grid, lds, s, e0, e1);
       break;
     case 512:
-      f32 ? batch_launch_one<512, float>(B, grid, lds, s, e0, e1)
-          : batch_launch_one<512, double>(B, grid, lds, s, e0, e1);
+      batch_launch_bs<512>(B, f32, grid, lds, s, e0, e1);
       break;
     case 1024:
-      f32 ? batch_launch_one<1024, float>(B, grid, lds, s, e0, e1)
-          : batch_launch_one<1024, double>(B, grid, lds, s, e0, e1);
+      batch_launch_bs<1024>(B, f32, grid, lds, s, e0, e1);
       break;
     default:
       return -1;
@@ -691,22 +846,29 @@ int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipE
   return 0;
 }
 
+template <int BS>
+hipError_t batch_occupancy(int* nb, int m, bool f32, size_t lds) {
+  const bool lt = m <= kBatchLdsTriMaxM;
+  if (f32)
+    return lt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, float, true>, BS, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, float, false>, BS, lds);
+  return lt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, double, true>, BS, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, double, false>, BS, lds);
+}
+
 int batch_resident_blocks(int bs, int m, bool f32) {
   const size_t lds = batch_lds_bytes(bs, m);
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (bs) {
     case 256:
-      e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<256, float>, 256, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<256, double>, 256, lds);
+      e = batch_occupancy<256>(&nb, m, f32, lds);
       break;
     case 512:
-      e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<512, float>, 512, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<512, double>, 512, lds);
+      e = batch_occupancy<512>(&nb, m, f32, lds);
       break;
     case 1024:
-      e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<1024, float>, 1024, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<1024, double>, 1024, lds);
+      e = batch_occupancy<1024>(&nb, m, f32, lds);
       break;
     default:
       break;

@@ -1190,14 +1190,12 @@ struct TailPrefetch {
 //     the last step of forward substitution with I + L, whose new row is
 //     [l^T, 1]. So h does not wait for the new column of T;
 //   CGS2: the first-pass coefficients corrected to first order, (I - L) r.
-// With DEFER (the single-system path) the new column of T (or row of L), the
-// Givens rotations and the stopping test are left to the extra workgroup of
-// the step's MAXPY launch (side_step), off the critical path; the tail
-// rotates only where the cycle ends here: at its norm-only last step
-// (norm_only) or on a breakdown, rho == 0. Without DEFER (the batched solver,
-// whose workgroup runs the whole step) it extends T and rotates column k-1
-// itself, as every step of depth 1.
-template <int NT, int NR, bool DEFER>
+// The new column of T (or row of L), the Givens rotations and the stopping
+// test are left to the extra workgroup of the step's MAXPY launch
+// (side_step), off the critical path; the tail rotates only where the cycle
+// ends here: at its norm-only last step (norm_only) or on a breakdown,
+// rho == 0.
+template <int NT, int NR>
 __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool norm_only,
                             int m_eff, int scheme, const TailPrefetch<NT>& pf) {
   __shared__ double s_rho, s_last;
@@ -1228,7 +1226,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
         }
       } else {
         ws.H[(size_t)(k - 1) * ws.ldh + k] = rho;
-        if (!DEFER || norm_only || rho == 0.0) go = 1;
+        if (norm_only || rho == 0.0) go = 1;
       }
       if (go) {
         st->rho = rho;
@@ -1237,7 +1235,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
     }
     s_rho = rho;
     s_go = go;
-    s_first = DEFER ? st->rot_next : k - 1;
+    s_first = st->rot_next;
   }
   __syncthreads();
   int go = s_go;
@@ -1283,11 +1281,7 @@ __device__ void tail_lagged(const Ws& ws, double* vals, double* scr, int k, bool
   for (int q = tid; q < k; q += bs) {
     const double l = vals[2 * q] / rho;
     ell[q] = l;
-    if (DEFER) ws.lvec[q] = l;
-  }
-  if (!DEFER) {
-    __syncthreads();
-    extend_t<NR>(ws, k, scheme, ell, rot);
+    ws.lvec[q] = l;
   }
   if (go == 1) return;
   for (int q = tid; q < k; q += bs) rr[q] = vals[2 * q + 1] / rho;
@@ -1680,7 +1674,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   else if (tail == kTailTwoSynch)
     tail_two_synch(ws, vals, K);
   else
-    tail_lagged<RPT, 8, true>(ws, vals, scr, K, norm_only, m_eff, pf.scheme, pf);
+    tail_lagged<RPT, 8>(ws, vals, scr, K, norm_only, m_eff, pf.scheme, pf);
 }
 
 // ------------------------------------------------------------------ MAXPY

@@ -396,20 +396,22 @@ def test_team_wait_limit():
     assert rc == 0 and np.all(info["converged"] == 1)
 
 
+@pytest.mark.parametrize("m,side_lo,steps", [(100, 12, 120), (150, 17, 170)])
 @pytest.mark.parametrize("bs", [256, 1024])
-def test_long_restart(bs):
-    """m = 100 (the per-wavefront sums and the small dense arrays at their
-    largest in these tests), one-part systems and teams, against the oracle
-    after 120 steps."""
-    bp = P.make_batch(nsys=6, seed=7, side_lo=12, side_hi=30, m=100, rtol=TOL)
-    log(f"batch long restart bs={bs}")
+def test_long_restart(bs, m, side_lo, steps):
+    """Long restarts, one-part systems and teams, against the oracle after a
+    cycle and part of the next: m = 100 keeps T in LDS, m = 150 in global
+    memory (beyond 128); the per-wavefront sums and the small dense arrays
+    are at their largest in these tests."""
+    bp = P.make_batch(nsys=6, seed=7, side_lo=side_lo, side_hi=30, m=m, rtol=TOL)
+    log(f"batch long restart bs={bs} m={m}")
     for part_rows in (0, 256):
-        rc, info, x, _ = run(bp, rtol=0.0, max_iters=120, config=(bs, 0, 1, part_rows), m=100)
+        rc, info, x, _ = run(bp, rtol=0.0, max_iters=steps, config=(bs, 0, 1, part_rows), m=m)
         assert rc == 0
         for i in range(bp.nsys):
             p = bp.system(i)
-            o = oracle_run(p, "mgs1r", m=100, rtol=0.0, max_iters=120, dump=False)
-            assert info["iters"][i] == o.iters == 120
+            o = oracle_run(p, "mgs1r", m=m, rtol=0.0, max_iters=steps, dump=False)
+            assert info["iters"][i] == o.iters == steps
             assert rel(x[bp.row_off[i]: bp.row_off[i + 1]], o.x) <= TOL, (i, part_rows)
 
 
