@@ -230,11 +230,13 @@ int gmres_create_ex(gmres_ctx** out, int64_t n, int64_t nnz, const int32_t* row_
  *   column, ||S||_2 with Paige's S = (I + L^T)^{-1} L^T = I - T, L the strictly
  *   lower part of V^T V: entry i of a cycle covers its basis vectors
  *   v_0..v_i (the leading (i+1) x (i+1) block of T; 0 for i = 0). Computed on
- *   the host after each cycle from the T (one-reduce MGS) or L (CGS2) the
- *   device built (T for GMRES_MGS_1R_IR32 and _IR16 too, L for
- *   GMRES_TWO_SYNCH), by power iteration to a relative change of 1e-14; NaN
- *   for GMRES_MGS and GMRES_CGS2_3R, which form neither. It adds host work
- *   per cycle; pass NULL when timing.
+ *   the host from the T (one-reduce MGS) or L (CGS2) the device built (T for
+ *   GMRES_MGS_1R_IR32 and _IR16 too, L for GMRES_TWO_SYNCH), by power
+ *   iteration to a relative change of 1e-14, while the device runs the next
+ *   cycle (the last cycle's after the device has finished); NaN for
+ *   GMRES_MGS and GMRES_CGS2_3R, which form neither. Its host work lengthens
+ *   the solve only where the power iterations outlast a cycle; pass NULL when
+ *   timing.
  * Blocks until the solve has finished on the stream. Returns GMRES_OK when the
  * solve ran to convergence or to max_iters (info->converged tells which),
  * GMRES_ERR_NONFINITE if a NaN or Inf appeared (x then holds the last finished

@@ -333,7 +333,7 @@ double spectral_norm(const double* S, int K, int ld, std::vector<double>& x) {
 // two-synchronization CGS hold L (its rows are the projections l of the newest
 // column); plain MGS and the three-reduction CGS form neither, so their
 // entries are NaN.
-void orth_history(gmres_ctx* c, int j, double* out) {
+void orth_history(const gmres_ctx* c, int j, const double* Tm, double* out) {
   if (c->scheme == kSchemeMgs || c->scheme == kSchemeCgs2r3) {
     for (int q = 0; q < j; ++q) out[q] = NAN;
     return;
@@ -342,7 +342,7 @@ void orth_history(gmres_ctx* c, int j, double* out) {
   std::vector<double> S((size_t)j * j, 0.0);  // column-major, ld j
   if (c->scheme != kSchemeCgs2 && c->scheme != kSchemeTwoSynch) {
     for (int col = 0; col < j; ++col)
-      for (int i = 0; i < col; ++i) S[(size_t)col * j + i] = -c->h_T[(size_t)col * ldt + i];
+      for (int i = 0; i < col; ++i) S[(size_t)col * j + i] = -Tm[(size_t)col * ldt + i];
   } else {
     // U = (I + L^T)^{-1}, unit upper triangular: column col solves
     // (I + L^T) u = e_col by back substitution; L(t, i) sits at h_T[i * ldt + t]
@@ -351,7 +351,7 @@ void orth_history(gmres_ctx* c, int j, double* out) {
       u[col] = 1.0;
       for (int i = col - 1; i >= 0; --i) {
         double a = 0.0;
-        for (int t = i + 1; t <= col; ++t) a += c->h_T[(size_t)i * ldt + t] * u[t];
+        for (int t = i + 1; t <= col; ++t) a += Tm[(size_t)i * ldt + t] * u[t];
         u[i] = -a;
       }
       for (int i = 0; i < col; ++i) S[(size_t)col * j + i] = -u[i];
@@ -672,10 +672,19 @@ int solve_impl(gmres_ctx* c, const double* b, double* x, double rtol, int64_t ma
 
   int64_t it = 0;
   rc = GMRES_OK;
+  // The orthogonality history of a finished cycle is computed on the host
+  // from its T (kept in last_T) while the device runs the next cycle.
+  int orth_j = 0;
+  int64_t orth_at = 0;
+  auto flush_orth = [&]() {
+    if (orth_j > 0) orth_history(c, orth_j, c->last_T.data(), hist_orth + orth_at);
+    orth_j = 0;
+  };
   for (;;) {
     const int64_t left = max_iters - it;
     const int m_eff = left < (int64_t)m ? (int)left : m;
     if (m_eff == 0) {
+      flush_orth();
       if (enqueue_true_residual(c, b, x)) return GMRES_ERR_HIP;
       if ((rc = sync_state(c, false))) return rc;
       if (c->h_st->status) {
@@ -688,6 +697,7 @@ int solve_impl(gmres_ctx* c, const double* b, double* x, double rtol, int64_t ma
       break;
     }
     if (enqueue_cycle(c, b, x, m_eff)) return GMRES_ERR_HIP;
+    flush_orth();
     if ((rc = sync_state(c, true))) return rc;
     const DevState& st = *c->h_st;
     collect_timing(c, st.j, st.true_conv != 0);
@@ -707,7 +717,6 @@ int solve_impl(gmres_ctx* c, const double* b, double* x, double rtol, int64_t ma
       const double gs = st.xscale / bnorm;
       if (hist_res)
         for (int q = 0; q < j; ++q) hist_res[it + q] = c->h_gh[q + 1] * gs;
-      if (hist_orth && c->mirror_matrices) orth_history(c, j, hist_orth + it);
       loc.cycles += 1;
       // |g_j| as it stood right after rotation j-1: with a pipeline depth above
       // 1, later rotations of the same batch may have changed g[j] itself
@@ -717,12 +726,17 @@ int solve_impl(gmres_ctx* c, const double* b, double* x, double rtol, int64_t ma
         memcpy(c->last_T.data(), c->h_T, sizeof(double) * c->last_T.size());
         memcpy(c->last_g.data(), c->h_g, sizeof(double) * c->last_g.size());
         c->last_j = j;
+        if (hist_orth) {
+          orth_j = j;
+          orth_at = it;
+        }
       }
     }
     if (st.breakdown) loc.breakdown = 1;
     if (j == 0) break;  // no progress is possible; cannot happen for m_eff >= 1
     it += j;
   }
+  flush_orth();
   loc.iters = it;
   loc.reductions = c->h_st->reductions;
   if (info) *info = loc;
