@@ -107,6 +107,20 @@ size_t basis_bytes(int scheme) {
   return scheme == kSchemeIr32 ? sizeof(float) : scheme == kSchemeIr16 ? 2 : sizeof(double);
 }
 
+// The block the host reads back after a cycle, one copy: the device state,
+// then g and gh ((m+2) each), then H ((m+1) m) and T ((m+2)^2), each part
+// 64-byte aligned. The host mirror has the same layout.
+struct Readback {
+  size_t g, gh, H, T, total;
+};
+constexpr Readback readback_layout(int m) {
+  const size_t v = round_up((size_t)(m + 2) * sizeof(double), 64);
+  const size_t g = round_up(sizeof(DevState), 64);
+  const size_t H = g + 2 * v;
+  const size_t T = H + round_up((size_t)(m + 1) * (size_t)m * sizeof(double), 64);
+  return Readback{g, g + v, H, T, T + round_up((size_t)(m + 2) * (size_t)(m + 2) * sizeof(double), 64)};
+}
+
 struct Layout {
   int64_t ldv;
   int rpt, G, NG, pstride;
@@ -136,12 +150,14 @@ bool make_layout(int64_t n, int m, int scheme, Layout* L, int rpt_want = 0) {
   L->V = take((size_t)L->ldv * (size_t)(m + 2) * vb);
   L->w = take((size_t)L->ldv * vb);
   L->r64 = ir_scheme(scheme) ? take((size_t)L->ldv * d) : 0;
-  L->H = take((size_t)(m + 1) * (size_t)m * d);
+  const Readback rb = readback_layout(m);
+  L->state = take(rb.total);
+  L->g = L->state + rb.g;
+  L->gh = L->state + rb.gh;
+  L->H = L->state + rb.H;
+  L->T = L->state + rb.T;
   L->R = take((size_t)(m + 1) * (size_t)m * d);
-  L->T = take((size_t)(m + 2) * (size_t)(m + 2) * d);
   L->TT = take((size_t)(m + 2) * (size_t)(m + 2) * d);
-  L->g = take((size_t)(m + 2) * d);
-  L->gh = take((size_t)(m + 2) * d);
   L->cs = take((size_t)(m + 2) * d);
   L->sn = take((size_t)(m + 2) * d);
   L->coef = take((size_t)(m + 2) * d);
@@ -151,7 +167,6 @@ bool make_layout(int64_t n, int m, int scheme, Layout* L, int rpt_want = 0) {
   L->partials = take((size_t)L->G * (size_t)L->pstride * d);
   L->gpartials = take((size_t)L->NG * (size_t)L->pstride * d);
   L->counters = take((size_t)(L->NG + 1) * sizeof(unsigned));
-  L->state = take(sizeof(DevState));
   L->total = off;
   return true;
 }
@@ -245,24 +260,14 @@ struct gmres_ctx {
 namespace {
 
 int sync_state(gmres_ctx* c, bool with_matrices) {
-  const int m = c->m;
-  if (hipMemcpyAsync(c->h_st, c->ws.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream) !=
-      hipSuccess)
+  // one copy of the readback block: the state, with g and gh after a cycle,
+  // and H and T too when the context mirrors them
+  const Readback rb = readback_layout(c->m);
+  const size_t bytes =
+      with_matrices ? (c->mirror_matrices ? rb.total : rb.H) : sizeof(DevState);
+  if (hipMemcpyAsync(c->h_st, c->ws.st, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
     return GMRES_ERR_HIP;
-  if (with_matrices) {
-    if (hipMemcpyAsync(c->h_g, c->ws.g, sizeof(double) * (m + 2), hipMemcpyDeviceToHost,
-                       c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->h_gh, c->ws.gh, sizeof(double) * (m + 2), hipMemcpyDeviceToHost,
-                       c->stream) != hipSuccess)
-      return GMRES_ERR_HIP;
-    if (c->mirror_matrices &&
-        (hipMemcpyAsync(c->h_H, c->ws.H, sizeof(double) * (size_t)(m + 1) * m,
-                        hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-         hipMemcpyAsync(c->h_T, c->ws.T, sizeof(double) * (size_t)(m + 2) * (m + 2),
-                        hipMemcpyDeviceToHost, c->stream) != hipSuccess))
-      return GMRES_ERR_HIP;
-  }
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return GMRES_ERR_HIP;
   return GMRES_OK;
 }
 
@@ -618,22 +623,22 @@ void bind_context(gmres_ctx* c, int64_t n, int64_t nnz, const int32_t* row_ptr,
   ws.m = m;
 }
 
-// Host mirror layout: DevState, then g and gh (m+2 each), then (with
-// matrices) H ((m+1) m) and T ((m+2)^2).
+// Host mirror: the readback block's layout (readback_layout), with or
+// without H and T.
 size_t mirror_bytes(int m, bool matrices) {
-  size_t d = 2 * (size_t)(m + 2);
-  if (matrices) d += (size_t)(m + 1) * m + (size_t)(m + 2) * (m + 2);
-  return round_up(sizeof(DevState), 64) + sizeof(double) * d;
+  const Readback rb = readback_layout(m);
+  return matrices ? rb.total : rb.H;
 }
 void bind_mirror(gmres_ctx* c, void* host, bool matrices) {
-  const int m = c->m;
+  const Readback rb = readback_layout(c->m);
+  char* h = (char*)host;
   c->pinned = host;
   c->mirror_matrices = matrices;
-  c->h_st = (DevState*)host;
-  c->h_g = (double*)((char*)host + round_up(sizeof(DevState), 64));
-  c->h_gh = c->h_g + (m + 2);
-  c->h_H = matrices ? c->h_gh + (m + 2) : nullptr;
-  c->h_T = matrices ? c->h_H + (size_t)(m + 1) * m : nullptr;
+  c->h_st = (DevState*)h;
+  c->h_g = (double*)(h + rb.g);
+  c->h_gh = (double*)(h + rb.gh);
+  c->h_H = matrices ? (double*)(h + rb.H) : nullptr;
+  c->h_T = matrices ? (double*)(h + rb.T) : nullptr;
 }
 
 // The solve itself, arguments already checked. hist_orth and the snapshot of
@@ -984,8 +989,7 @@ int gmres_solve_noalloc(int64_t n, int64_t nnz, const int32_t* row_ptr, const in
   // timing events are made, so nothing is allocated.
   gmres_ctx c{};
   bind_context(&c, n, nnz, row_ptr, col_idx, vals, m, scheme, L, ws, s, nullptr);
-  alignas(64) unsigned char host[round_up(sizeof(DevState), 64) +
-                                 sizeof(double) * 2 * (GMRES_MAX_RESTART + 2)];
+  alignas(64) unsigned char host[readback_layout(GMRES_MAX_RESTART).H];
   bind_mirror(&c, host, false);
   c.matrix_ok = true;
   c.format = kFormatCsr;
