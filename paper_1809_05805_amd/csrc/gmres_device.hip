@@ -216,6 +216,22 @@ struct GlbCol {
   }
 };
 
+// The same with non-temporal loads (streamed, not kept in the caches).
+template <typename T>
+struct GlbColNT {
+  const T* b;
+  __device__ GlbColNT(const T* base, int64_t) : b(base) {}
+  __device__ T operator()(uint32_t boff) const {
+    const char* p = reinterpret_cast<const char*>(b) + boff;
+    if constexpr (sizeof(T) == 8)
+      return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(p)));
+    else if constexpr (sizeof(T) == 4)
+      return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p)));
+    else
+      return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p)));
+  }
+};
+
 //   GMRES_PROJ_BUFFER / GMRES_MAXPY_BUFFER  1: the projection's (MAXPY's and
 //   x update's) column loads are buffer loads; 0: global loads.
 #ifndef GMRES_PROJ_BUFFER
@@ -1549,10 +1565,11 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   const int64_t nvalid = n - rb;  // rows rb .. n-1 of every column
   // the column at position t of the stream
   auto colat = [&](int t) { return GMRES_PROJ_REVERSE ? nproj - 1 - t : t; };
-  auto load_chunk = [&](VT (&buf)[CB][RPT], int j) {
+  auto load_chunk = [&](auto nt, VT (&buf)[CB][RPT], int j) {
+    using Col = std::conditional_t<decltype(nt)::value, GlbColNT<VT>, ProjCol<VT>>;
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      const ProjCol<VT> col(Vt + (size_t)colat(j + c) * ldv, nvalid);
+      const Col col(Vt + (size_t)colat(j + c) * ldv, nvalid);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) buf[c][i] = col(rows[i]);
     }
@@ -1603,23 +1620,35 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
       }
     }
   };
-  int j0 = 0;
-  if (nproj >= CB) {
-    VT ba[CB][RPT], bb[CB][RPT];
-    load_chunk(ba, 0);
-    for (;;) {
-      // ba holds chunk j0
-      load_chunk(bb, j0 + 2 * CB <= nproj ? j0 + CB : j0);
-      reduce_chunk(ba, j0);
-      j0 += CB;
-      if (j0 + CB > nproj) break;
-      // bb holds chunk j0
-      load_chunk(ba, j0 + 2 * CB <= nproj ? j0 + CB : j0);
-      reduce_chunk(bb, j0);
-      j0 += CB;
-      if (j0 + CB > nproj) break;
+  // stream positions [t0, t1) (non-temporal loads if nt); returns the first
+  // position not done (the rest of a partial chunk)
+  auto stream = [&](auto nt, int t0, int t1) {
+    int j0 = t0;
+    if (t1 - t0 >= CB) {
+      VT ba[CB][RPT], bb[CB][RPT];
+      load_chunk(nt, ba, j0);
+      for (;;) {
+        // ba holds chunk j0
+        load_chunk(nt, bb, j0 + 2 * CB <= t1 ? j0 + CB : j0);
+        reduce_chunk(ba, j0);
+        j0 += CB;
+        if (j0 + CB > t1) break;
+        // bb holds chunk j0
+        load_chunk(nt, ba, j0 + 2 * CB <= t1 ? j0 + CB : j0);
+        reduce_chunk(bb, j0);
+        j0 += CB;
+        if (j0 + CB > t1) break;
+      }
     }
-  }
+    return j0;
+  };
+  // The columns stream last to first. Columns keep.. go non-temporal: the
+  // next MAXPY reads them last, after they would have left the last-level
+  // cache anyway. Columns 0..keep-1, which it reads first, load through the
+  // caches so that they are still there. (The choice changes no result.)
+  const int split = GMRES_PROJ_REVERSE && nproj > ws.keep ? nproj - ws.keep : 0;
+  int j0 = stream(std::true_type{}, 0, split);
+  j0 = stream(std::false_type{}, j0, nproj);
   for (; j0 < nproj; ++j0) {
     VT vv[RPT];
     const ProjCol<VT> col(Vt + (size_t)colat(j0) * ldv, nvalid);

@@ -113,6 +113,8 @@ struct Ws {
   int64_t n;
   int64_t ldv;
   int ldh, ldt, pstride, m;
+  int keep;          // the projection loads columns 0..keep-1 through the caches, the others
+                     // non-temporal (those the next MAXPY reads first stay in the last-level cache)
 };
 
 // One system of a batch: rows [r0, r0 + n) of the block-diagonal matrix and
