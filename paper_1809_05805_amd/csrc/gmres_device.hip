@@ -1755,6 +1755,11 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G, in
   // GMRES_MAXPY_COLS columns per pass (their loads are in flight together).
   constexpr int MC = GMRES_MAXPY_COLS;
   const VT* __restrict__ Vt = V + rb;
+  // Columns below ntend are loaded non-temporal (buffer loads; a global
+  // non-temporal load in one arm of the branch would be merged with the
+  // other's plain load). The last keep columns, which the next step's
+  // projection reads first, load through the caches.
+  const int ntend = k - ws.keep;
   int q = 0;
   for (; q + MC <= k; q += MC) {
     CT c[MC];
@@ -1762,9 +1767,16 @@ __global__ __launch_bounds__(256) void k_maxpy(Ws ws, int k, int mode, int G, in
 #pragma unroll
     for (int t = 0; t < MC; ++t) {
       c[t] = (CT)cf[q + t];
-      const MaxpyCol<VT> col(Vt + (size_t)(q + t) * ldv, nvalid);
+      const VT* cp = Vt + (size_t)(q + t) * ldv;
+      if (q + t < ntend) {
+        const BufCol<VT> col(cp, nvalid);
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) v[t][i] = col(off[i]);
+        for (int i = 0; i < RPT; ++i) v[t][i] = col.template load<2>(off[i]);
+      } else {
+        const MaxpyCol<VT> col(cp, nvalid);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) v[t][i] = col(off[i]);
+      }
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
