@@ -108,7 +108,8 @@ def time_solves(solver, b, x, rtol, max_iters, steps, warmup, timing=False, time
     return dt, iters, res, kt
 
 
-PROBE_KINDS = {"read": 0, "read_nt": 1, "copy": 2, "copy_nt": 3}
+PROBE_KINDS = {"read": 0, "read_nt": 1, "copy": 2, "copy_nt": 3, "read_tiled": 4, "read_tiled_nt": 5,
+               "copy_tiled": 6, "copy_tiled_nt": 7}
 
 
 def measured_ceilings(dev, mib=2048, reps=5):
@@ -135,9 +136,9 @@ def measured_ceilings(dev, mib=2048, reps=5):
     table = {}
     for name, kind in PROBE_KINDS.items():
         # reads move the buffer; copies read half of it and write as much
-        size = nbytes if kind < 2 else nbytes // 2
+        size = nbytes if kind in (0, 1, 4, 5) else nbytes // 2
         moved = nbytes
-        for blocks in (1024, 2048, 4096, 8192):
+        for blocks in (1024, 4096, 8192):
             ms = ctypes.c_float()
             rc = f(kind, src.data_ptr(), dst.data_ptr(), size, blocks, reps, stream, ctypes.byref(ms))
             if rc != 0:
@@ -149,8 +150,9 @@ def measured_ceilings(dev, mib=2048, reps=5):
     return {"read_GBps": read, "copy_GBps": copy, "buffer_MiB": mib, "probes": table,
             "how": f"own HIP probe kernels (gmres_probe.hip): reads of a {mib} MiB float64 buffer and "
                    f"copies of {mib // 2} MiB into a second buffer, 16-byte vectors, 256-thread "
-                   "workgroups, best of 1024-8192 workgroups and of plain or non-temporal "
-                   f"loads/stores, {reps} timed launches each after one untimed"}
+                   "workgroups, grid-stride or tiled (each workgroup streaming one contiguous chunk), "
+                   "best of 1024-8192 workgroups and of plain or non-temporal loads/stores, "
+                   f"{reps} timed launches each after one untimed"}
 
 
 def cpu_model() -> str:

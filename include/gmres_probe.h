@@ -16,10 +16,15 @@ extern "C" {
 #endif
 
 enum {
-  GMRES_PROBE_READ = 0,     /* read nbytes of src; one double per workgroup to dst           */
-  GMRES_PROBE_READ_NT = 1,  /* the same with non-temporal loads                               */
-  GMRES_PROBE_COPY = 2,     /* copy nbytes from src to dst                                     */
-  GMRES_PROBE_COPY_NT = 3   /* the same with non-temporal stores                               */
+  GMRES_PROBE_READ = 0,           /* read nbytes of src, grid-stride; one double per workgroup to dst */
+  GMRES_PROBE_READ_NT = 1,        /* the same with non-temporal loads                                 */
+  GMRES_PROBE_COPY = 2,           /* copy nbytes from src to dst, grid-stride                         */
+  GMRES_PROBE_COPY_NT = 3,        /* the same with non-temporal stores                                */
+  GMRES_PROBE_READ_TILED = 4,     /* read, each workgroup streaming one contiguous chunk; 4 doubles
+                                     per workgroup to dst                                              */
+  GMRES_PROBE_READ_TILED_NT = 5,  /* the same with non-temporal loads                                 */
+  GMRES_PROBE_COPY_TILED = 6,     /* copy, each workgroup streaming one contiguous chunk              */
+  GMRES_PROBE_COPY_TILED_NT = 7   /* the same with non-temporal loads and stores                      */
 };
 
 /*
@@ -27,7 +32,8 @@ enum {
  * workgroups of 256 threads, timed with HIP events on hip_stream (NULL: the
  * default stream); *ms (host) receives the elapsed time of the reps launches.
  * src, dst: device pointers, 16-byte aligned; nbytes a positive multiple of
- * 16. dst must hold nbytes for the copies and `blocks` doubles for the reads;
+ * 16. dst must hold nbytes for the copies, `blocks` doubles for the grid-stride
+ * reads and 4 `blocks` doubles for the tiled reads;
  * the buffers must not overlap. Blocks until done. Returns 0, -1 for invalid
  * arguments, -2 for a HIP error.
  */

@@ -1,7 +1,9 @@
 // Bandwidth probes of this GPU (measurement only; not part of the solver):
 // the achievable HBM rates of streaming reads and of copies, the two access
 // patterns of the solver's step kernels, measured over buffers far larger
-// than the last-level cache. C ABI in include/gmres_probe.h.
+// than the last-level cache, in two orders: grid-stride (the whole grid
+// sweeps the buffer together) and tiled (each workgroup streams a contiguous
+// chunk of its own, 6-13% faster here). C ABI in include/gmres_probe.h.
 #include "gmres_probe.h"
 
 #include <hip/hip_runtime.h>
@@ -71,11 +73,75 @@ __global__ __launch_bounds__(256) void k_copy(const d2* __restrict__ a, d2* __re
   for (; i < n2; i += stride) b[i] = a[i];
 }
 
+// The same two patterns, tiled: workgroup b streams elements
+// [b per, min(n2, (b + 1) per)) in order, U 16-byte vectors per thread in
+// flight; the reads sum their values and write one double per wavefront
+// (out needs 4 doubles per workgroup).
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void k_read_tiled(const d2* __restrict__ a, int64_t n2,
+                                                     double* __restrict__ out) {
+  const int64_t per = (n2 + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = b0 + per < n2 ? b0 + per : n2;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t i = b0 + threadIdx.x;
+  for (; i + (U - 1) * 256 < b1; i += U * 256) {
+    d2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if constexpr (NT)
+        v[u] = __builtin_nontemporal_load(a + i + u * 256);
+      else
+        v[u] = a[i + u * 256];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s0 += v[u].x;
+      s1 += v[u].y;
+    }
+  }
+  for (; i < b1; i += 256) {
+    const d2 v = a[i];
+    s0 += v.x;
+    s1 += v.y;
+  }
+  double s = s0 + s1;
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) out[(int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)] = s;
+}
+
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void k_copy_tiled(const d2* __restrict__ a, d2* __restrict__ b,
+                                                     int64_t n2) {
+  const int64_t per = (n2 + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = b0 + per < n2 ? b0 + per : n2;
+  int64_t i = b0 + threadIdx.x;
+  for (; i + (U - 1) * 256 < b1; i += U * 256) {
+    d2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if constexpr (NT)
+        v[u] = __builtin_nontemporal_load(a + i + u * 256);
+      else
+        v[u] = a[i + u * 256];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if constexpr (NT)
+        __builtin_nontemporal_store(v[u], b + i + u * 256);
+      else
+        b[i + u * 256] = v[u];
+    }
+  }
+  for (; i < b1; i += 256) b[i] = a[i];
+}
+
 }  // namespace
 
 extern "C" int gmres_probe_bandwidth(int32_t kind, const double* src, double* dst, int64_t nbytes,
                                      int32_t blocks, int32_t reps, void* hip_stream, float* ms) {
-  if (kind < GMRES_PROBE_READ || kind > GMRES_PROBE_COPY_NT || !src || !dst || !ms ||
+  if (kind < GMRES_PROBE_READ || kind > GMRES_PROBE_COPY_TILED_NT || !src || !dst || !ms ||
       nbytes < 16 || (nbytes % 16) != 0 || blocks < 1 || reps < 1)
     return -1;
   if (((uintptr_t)src % 16) != 0 || ((uintptr_t)dst % 16) != 0) return -1;
@@ -101,8 +167,20 @@ extern "C" int gmres_probe_bandwidth(int32_t kind, const double* src, double* ds
       case GMRES_PROBE_COPY:
         hipLaunchKernelGGL((k_copy<4, false>), dim3(blocks), dim3(256), 0, s, a, (d2*)dst, n2);
         break;
-      default:
+      case GMRES_PROBE_COPY_NT:
         hipLaunchKernelGGL((k_copy<4, true>), dim3(blocks), dim3(256), 0, s, a, (d2*)dst, n2);
+        break;
+      case GMRES_PROBE_READ_TILED:
+        hipLaunchKernelGGL((k_read_tiled<4, false>), dim3(blocks), dim3(256), 0, s, a, n2, dst);
+        break;
+      case GMRES_PROBE_READ_TILED_NT:
+        hipLaunchKernelGGL((k_read_tiled<4, true>), dim3(blocks), dim3(256), 0, s, a, n2, dst);
+        break;
+      case GMRES_PROBE_COPY_TILED:
+        hipLaunchKernelGGL((k_copy_tiled<4, false>), dim3(blocks), dim3(256), 0, s, a, (d2*)dst, n2);
+        break;
+      default:
+        hipLaunchKernelGGL((k_copy_tiled<4, true>), dim3(blocks), dim3(256), 0, s, a, (d2*)dst, n2);
         break;
     }
     if (hipGetLastError() != hipSuccess) rc = -2;
