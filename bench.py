@@ -513,7 +513,8 @@ def batch_result(args, dim=2):
                     "config": cfg,
                     "autotune_trials": [{"block_size": t[0], "grid": t[1],
                                          "order": "largest_first" if t[2] else "natural",
-                                         "part_rows": t[4], "ms": round(t[3], 2)} for t in trials]}
+                                         "part_rows": t[4], "streamed": bool(t[5]),
+                                         "ms": round(t[3], 2)} for t in trials]}
         log(f"{tag} {scheme}: {iters} iters in {dt * 1e3:.1f} ms ({iters / dt:.0f} it/s), cfg {cfg}, "
             f"worst rel res {res.max():.2e}")
         s.close()

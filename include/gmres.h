@@ -485,10 +485,26 @@ int gmres_batch_set_config(gmres_batch* bt, int32_t block_size, int32_t grid, in
 int gmres_batch_get_config(gmres_batch* bt, int32_t* block_size, int32_t* grid, int32_t* order,
                            int64_t* part_rows, int32_t* max_parts);
 
+/*
+ * How the batched kernel loads basis columns: GMRES_BATCH_LOADS_CACHED through
+ * the caches (the MAXPY then re-reads a part's columns from the last-level
+ * cache), GMRES_BATCH_LOADS_STREAMED non-temporal (faster when the bases in
+ * use at once far exceed that cache), or GMRES_BATCH_LOADS_AUTO (the default):
+ * streamed when the running workgroups' share of the bases, queue entries
+ * times m+1 columns, exceeds 384 MiB. The results are the same either way.
+ * set_loads re-applies the configuration (Blocks; discards a captured graph).
+ * get_loads reports the mode and whether the current configuration streams
+ * (host pointers, nullable).
+ */
+enum { GMRES_BATCH_LOADS_AUTO = 0, GMRES_BATCH_LOADS_CACHED = 1, GMRES_BATCH_LOADS_STREAMED = 2 };
+int gmres_batch_set_loads(gmres_batch* bt, int32_t mode);
+int gmres_batch_get_loads(gmres_batch* bt, int32_t* mode, int32_t* streamed);
+
 typedef struct {
   int32_t block_size, grid, order;
   float ms; /* event-timed duration of the solve */
   int64_t part_rows;
+  int32_t streamed; /* basis columns loaded non-temporal in this trial */
 } gmres_batch_trial;
 
 /*
@@ -496,7 +512,9 @@ typedef struct {
  * after one warm-up solve: block sizes 256, 512 and 1024 with parts of
  * 16384, 8192 or 4096 rows or no split (largest first, as many workgroups as
  * the GPU holds), then for the fastest a grid of one workgroup per compute
- * unit and the natural order. Keeps the fastest and leaves x as it was on
+ * unit and the natural order, and (under GMRES_BATCH_LOADS_AUTO) the best so
+ * far with the other load form, which becomes the mode if it wins. Keeps the
+ * fastest and leaves x as it was on
  * entry (it is restored from the workspace's copy before every trial).
  * trials (host, nullable, max_trials entries) and ntrials (host, nullable)
  * report what was timed. Blocks.

@@ -55,6 +55,10 @@ bool is_device_ptr(const void* p) {
 constexpr int kTeamMax = 16;
 constexpr int64_t kDefaultPartRows = 8192;
 constexpr int64_t kMinPartRows = 256;
+// Bases in use at once beyond this size (1.5 times the MI355X's 256 MB
+// last-level cache) are streamed with non-temporal loads under
+// GMRES_BATCH_LOADS_AUTO: their re-reads would miss the cache anyway.
+constexpr double kStreamBytes = 384.0 * 1048576.0;
 
 int team_cap(int64_t n) {
   const int64_t c = (n + kMinPartRows - 1) / kMinPartRows;
@@ -122,6 +126,8 @@ struct gmres_batch {
   int64_t n;
   int bs, grid, order;  // grid 0: as many workgroups as the GPU holds
   int64_t part_rows;    // rows per part of a team (0: one workgroup per system)
+  int loads;            // GMRES_BATCH_LOADS_*
+  bool nt;              // basis columns loaded non-temporal in the current configuration
   int grid_eff;         // the grid of the current queue
   int num_cu;
   BatchTicket* tickets_d;
@@ -151,7 +157,10 @@ void drop_graph(gmres_batch* bt) {
 // so that every team can assemble.
 int apply_config(gmres_batch* bt, int bs, int grid, int order, int64_t part_rows) {
   drop_graph(bt);
-  const int per_cu = batch_resident_blocks(bs, bt->m, bt->scheme == GMRES_MGS_1R_IR32);
+  // the fewer of the two load forms' resident workgroups, whichever runs
+  const bool f32 = bt->scheme == GMRES_MGS_1R_IR32;
+  const int per_cu = std::min(batch_resident_blocks(bs, bt->m, f32, false),
+                              batch_resident_blocks(bs, bt->m, f32, true));
   if (per_cu < 1) return GMRES_ERR_HIP;
   const int64_t resident = (int64_t)per_cu * bt->num_cu;
   const int64_t cap = std::min<int64_t>(resident, grid > 0 ? grid : resident);
@@ -181,6 +190,16 @@ int apply_config(gmres_batch* bt, int bs, int grid, int order, int64_t part_rows
   bt->order = order;
   bt->part_rows = part_rows;
   bt->grid_eff = grid > 0 ? grid : (int)std::max<int64_t>(1, std::min<int64_t>(resident, bt->B.ntickets));
+  if (bt->loads == GMRES_BATCH_LOADS_AUTO) {
+    // basis in use at once: a queue entry's rows per running workgroup
+    const double vb = f32 ? 4.0 : 8.0;
+    const double per_entry = (double)bt->n / (double)std::max(1, bt->B.ntickets);
+    const double live = std::min((double)bt->n, per_entry * (double)std::min(bt->grid_eff, bt->B.ntickets)) *
+                        (double)(bt->m + 1) * vb;
+    bt->nt = live > kStreamBytes;
+  } else {
+    bt->nt = bt->loads == GMRES_BATCH_LOADS_STREAMED;
+  }
   return GMRES_OK;
 }
 
@@ -193,7 +212,8 @@ int enqueue(gmres_batch* bt, const double* b, double* x, double rtol, int64_t ma
   B.max_iters = max_iters;
   B.out = info ? reinterpret_cast<BatchOut*>(info) : bt->out_ws;
   if (launch_batch_reset(B, bt->stream)) return GMRES_ERR_HIP;
-  if (launch_batch(B, bt->bs, bt->grid_eff, bt->scheme == GMRES_MGS_1R_IR32, bt->stream, e0, e1))
+  if (launch_batch(B, bt->bs, bt->grid_eff, bt->scheme == GMRES_MGS_1R_IR32, bt->nt, bt->stream, e0,
+                   e1))
     return GMRES_ERR_HIP;
   return GMRES_OK;
 }
@@ -356,6 +376,19 @@ int gmres_batch_set_config(gmres_batch* bt, int32_t block_size, int32_t grid, in
   return apply_config(bt, block_size, grid, order, part_rows);
 }
 
+int gmres_batch_set_loads(gmres_batch* bt, int32_t mode) {
+  if (!bt || mode < GMRES_BATCH_LOADS_AUTO || mode > GMRES_BATCH_LOADS_STREAMED) return GMRES_ERR_ARG;
+  bt->loads = mode;
+  return apply_config(bt, bt->bs, bt->grid, bt->order, bt->part_rows);
+}
+
+int gmres_batch_get_loads(gmres_batch* bt, int32_t* mode, int32_t* streamed) {
+  if (!bt) return GMRES_ERR_ARG;
+  if (mode) *mode = bt->loads;
+  if (streamed) *streamed = bt->nt ? 1 : 0;
+  return GMRES_OK;
+}
+
 int gmres_batch_get_config(gmres_batch* bt, int32_t* block_size, int32_t* grid, int32_t* order,
                            int64_t* part_rows, int32_t* max_parts) {
   if (!bt) return GMRES_ERR_ARG;
@@ -383,6 +416,7 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
   struct Cand {
     int bs, grid, order;
     int64_t part_rows;
+    int loads;
   };
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return GMRES_ERR_HIP;
@@ -390,7 +424,7 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
     (void)hipEventDestroy(e0);
     return GMRES_ERR_HIP;
   }
-  const Cand saved{bt->bs, bt->grid, bt->order, bt->part_rows};
+  const Cand saved{bt->bs, bt->grid, bt->order, bt->part_rows, bt->loads};
   int rc = hipMemcpyAsync(bt->xsave, x, xb, hipMemcpyDeviceToDevice, s) == hipSuccess
                ? GMRES_OK
                : GMRES_ERR_HIP;
@@ -399,6 +433,7 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
   Cand pick = saved;
   // One solve under configuration c from the saved x; its event-timed duration.
   auto trial = [&](const Cand& c, bool record) -> int {
+    bt->loads = c.loads;
     int r = apply_config(bt, c.bs, c.grid, c.order, c.part_rows);
     if (r) return r;
     if (hipMemcpyAsync(x, bt->xsave, xb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -412,7 +447,7 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
       return GMRES_ERR_HIP;
     if (!record) return GMRES_OK;
     if (nt < max_trials)
-      trials[nt] = gmres_batch_trial{c.bs, bt->grid_eff, c.order, ms, c.part_rows};
+      trials[nt] = gmres_batch_trial{c.bs, bt->grid_eff, c.order, ms, c.part_rows, bt->nt ? 1 : 0};
     ++nt;
     if (best < 0.0f || ms < best) {
       best = ms;
@@ -422,15 +457,26 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
   };
   // first the workgroup size and the team split (largest systems first, as
   // many workgroups as the GPU holds), then the grid and the order for the best
-  const Cand first{256, 0, GMRES_BATCH_ORDER_LARGEST_FIRST, kDefaultPartRows};
+  const int lm = saved.loads;
+  const Cand first{256, 0, GMRES_BATCH_ORDER_LARGEST_FIRST, kDefaultPartRows, lm};
   if (rc == GMRES_OK) rc = trial(first, false);  // warm-up
   for (int bs : {256, 512, 1024})
     for (int64_t pr : {(int64_t)0, (int64_t)16384, (int64_t)8192, (int64_t)4096})
-      if (rc == GMRES_OK) rc = trial(Cand{bs, 0, GMRES_BATCH_ORDER_LARGEST_FIRST, pr}, true);
+      if (rc == GMRES_OK) rc = trial(Cand{bs, 0, GMRES_BATCH_ORDER_LARGEST_FIRST, pr, lm}, true);
   if (rc == GMRES_OK) {
     const Cand top = pick;
-    rc = trial(Cand{top.bs, std::min(bt->num_cu, bt->B.ntickets), top.order, top.part_rows}, true);
-    if (rc == GMRES_OK) rc = trial(Cand{top.bs, 0, GMRES_BATCH_ORDER_NATURAL, top.part_rows}, true);
+    rc = trial(Cand{top.bs, std::min(bt->num_cu, bt->B.ntickets), top.order, top.part_rows, lm},
+               true);
+    if (rc == GMRES_OK)
+      rc = trial(Cand{top.bs, 0, GMRES_BATCH_ORDER_NATURAL, top.part_rows, lm}, true);
+  }
+  if (rc == GMRES_OK && lm == GMRES_BATCH_LOADS_AUTO) {
+    // the best so far with the other load form
+    const Cand top = pick;
+    bt->loads = top.loads;
+    rc = apply_config(bt, top.bs, top.grid, top.order, top.part_rows);
+    const int other = bt->nt ? GMRES_BATCH_LOADS_CACHED : GMRES_BATCH_LOADS_STREAMED;
+    if (rc == GMRES_OK) rc = trial(Cand{top.bs, top.grid, top.order, top.part_rows, other}, true);
   }
   if (rc == GMRES_OK &&
       (hipMemcpyAsync(x, bt->xsave, xb, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -439,6 +485,7 @@ int gmres_batch_autotune(gmres_batch* bt, const double* b, double* x, double rto
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   const Cand keep = rc == GMRES_OK ? pick : saved;
+  bt->loads = keep.loads;
   const int rc2 = apply_config(bt, keep.bs, keep.grid, keep.order, keep.part_rows);
   if (rc != GMRES_OK) return rc;
   if (rc2 != GMRES_OK) return rc2;

@@ -390,7 +390,8 @@ __device__ bool batch_tail(const Ws& ws, const double* vals, double* scr, int k,
 // The solve of one queue entry (a system, or one part of a team) by one
 // workgroup of BS threads. Team and ticket values are uniform.
 // LT: T is kept in LDS (m <= kBatchLdsTriMaxM), else in global memory.
-template <int BS, typename VT, bool LT>
+// NT: the projection and MAXPY load basis columns non-temporal (streamed).
+template <int BS, typename VT, bool LT, bool NT>
 __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, double* vals,
                            double* scr, double* sml) {
   constexpr int NW = BS / 64;
@@ -398,6 +399,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
   // registers per lane)
   constexpr int RB = BS >= 1024 ? 4 : 8;
   constexpr bool F32 = sizeof(VT) == 4;
+  using BasisCol = std::conditional_t<NT, GlbColNT<VT>, GlbCol<VT>>;
   __shared__ int s_flag[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m = B.m;
@@ -594,7 +596,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
           }
           // projection over columns 0..nproj-1, the next column's loads in flight
           auto load_col = [&](VT (&buf)[RB], int j) {
-            const GlbCol<VT> col(V + (size_t)j * ldv, n);
+            const BasisCol col(V + (size_t)j * ldv, n);
 #pragma unroll
             for (int t = 0; t < RB; ++t) buf[t] = col(off[t]);
           };
@@ -671,7 +673,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
             vk[t] = at(vk_g, rc) * invr;
           }
           auto load_col = [&](VT (&buf)[RB], int j) {
-            const GlbCol<VT> col(V + (size_t)j * ldv, n);
+            const BasisCol col(V + (size_t)j * ldv, n);
 #pragma unroll
             for (int t = 0; t < RB; ++t) buf[t] = col(off[t]);
           };
@@ -757,7 +759,7 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
   __syncthreads();
 }
 
-template <int BS, typename VT, bool LT>
+template <int BS, typename VT, bool LT, bool NT>
 __global__ __launch_bounds__(BS) void k_batch(Batch B) {
   extern __shared__ double lds[];
   __shared__ int s_pos;
@@ -778,7 +780,7 @@ __global__ __launch_bounds__(BS) void k_batch(Batch B) {
     K.part = __builtin_amdgcn_readfirstlane(K.part);
     K.nparts = __builtin_amdgcn_readfirstlane(K.nparts);
     K.base = __builtin_amdgcn_readfirstlane(K.base);
-    batch_part<BS, VT, LT>(B, K, red, vals, scr, sml);
+    batch_part<BS, VT, LT, NT>(B, K, red, vals, scr, sml);
   }
 }
 
@@ -804,40 +806,47 @@ int launch_batch_reset(const Batch& B, hipStream_t s) {
   return 0;
 }
 
-template <int BS, typename VT, bool LT>
+template <int BS, typename VT, bool LT, bool NT>
 void batch_launch_one(const Batch& B, int grid, uint32_t lds, hipStream_t s, hipEvent_t e0,
                       hipEvent_t e1) {
   if (e0 || e1)
-    hipExtLaunchKernelGGL((k_batch<BS, VT, LT>), dim3(grid), dim3(BS), lds, s, e0, e1, 0u, B);
+    hipExtLaunchKernelGGL((k_batch<BS, VT, LT, NT>), dim3(grid), dim3(BS), lds, s, e0, e1, 0u, B);
   else
-    hipLaunchKernelGGL((k_batch<BS, VT, LT>), dim3(grid), dim3(BS), lds, s, B);
+    hipLaunchKernelGGL((k_batch<BS, VT, LT, NT>), dim3(grid), dim3(BS), lds, s, B);
+}
+
+template <int BS, typename VT, bool LT>
+void batch_launch_nt(const Batch& B, bool nt, int grid, uint32_t lds, hipStream_t s, hipEvent_t e0,
+                     hipEvent_t e1) {
+  nt ? batch_launch_one<BS, VT, LT, true>(B, grid, lds, s, e0, e1)
+     : batch_launch_one<BS, VT, LT, false>(B, grid, lds, s, e0, e1);
 }
 
 template <int BS>
-void batch_launch_bs(const Batch& B, bool f32, int grid, uint32_t lds, hipStream_t s,
+void batch_launch_bs(const Batch& B, bool f32, bool nt, int grid, uint32_t lds, hipStream_t s,
                      hipEvent_t e0, hipEvent_t e1) {
   const bool lt = B.m <= kBatchLdsTriMaxM;
   if (f32)
-    lt ? batch_launch_one<BS, float, true>(B, grid, lds, s, e0, e1)
-       : batch_launch_one<BS, float, false>(B, grid, lds, s, e0, e1);
+    lt ? batch_launch_nt<BS, float, true>(B, nt, grid, lds, s, e0, e1)
+       : batch_launch_nt<BS, float, false>(B, nt, grid, lds, s, e0, e1);
   else
-    lt ? batch_launch_one<BS, double, true>(B, grid, lds, s, e0, e1)
-       : batch_launch_one<BS, double, false>(B, grid, lds, s, e0, e1);
+    lt ? batch_launch_nt<BS, double, true>(B, nt, grid, lds, s, e0, e1)
+       : batch_launch_nt<BS, double, false>(B, nt, grid, lds, s, e0, e1);
 }
 
-int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipEvent_t e0,
+int launch_batch(const Batch& B, int bs, int grid, bool f32, bool nt, hipStream_t s, hipEvent_t e0,
                  hipEvent_t e1) {
   if (grid < 1) return -1;
   const uint32_t lds = (uint32_t)batch_lds_bytes(bs, B.m);
   switch (bs) {
     case 256:
-      batch_launch_bs<256>(B, f32, grid, lds, s, e0, e1);
+      batch_launch_bs<256>(B, f32, nt, grid, lds, s, e0, e1);
       break;
     case 512:
-      batch_launch_bs<512>(B, f32, grid, lds, s, e0, e1);
+      batch_launch_bs<512>(B, f32, nt, grid, lds, s, e0, e1);
       break;
     case 1024:
-      batch_launch_bs<1024>(B, f32, grid, lds, s, e0, e1);
+      batch_launch_bs<1024>(B, f32, nt, grid, lds, s, e0, e1);
       break;
     default:
       return -1;
@@ -846,29 +855,35 @@ int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipE
   return 0;
 }
 
-template <int BS>
-hipError_t batch_occupancy(int* nb, int m, bool f32, size_t lds) {
-  const bool lt = m <= kBatchLdsTriMaxM;
-  if (f32)
-    return lt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, float, true>, BS, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, float, false>, BS, lds);
-  return lt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, double, true>, BS, lds)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, double, false>, BS, lds);
+template <int BS, typename VT, bool LT>
+hipError_t batch_occupancy_nt(int* nb, bool nt, size_t lds) {
+  return nt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, VT, LT, true>, BS, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_batch<BS, VT, LT, false>, BS, lds);
 }
 
-int batch_resident_blocks(int bs, int m, bool f32) {
+template <int BS>
+hipError_t batch_occupancy(int* nb, int m, bool f32, bool nt, size_t lds) {
+  const bool lt = m <= kBatchLdsTriMaxM;
+  if (f32)
+    return lt ? batch_occupancy_nt<BS, float, true>(nb, nt, lds)
+              : batch_occupancy_nt<BS, float, false>(nb, nt, lds);
+  return lt ? batch_occupancy_nt<BS, double, true>(nb, nt, lds)
+            : batch_occupancy_nt<BS, double, false>(nb, nt, lds);
+}
+
+int batch_resident_blocks(int bs, int m, bool f32, bool nt) {
   const size_t lds = batch_lds_bytes(bs, m);
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (bs) {
     case 256:
-      e = batch_occupancy<256>(&nb, m, f32, lds);
+      e = batch_occupancy<256>(&nb, m, f32, nt, lds);
       break;
     case 512:
-      e = batch_occupancy<512>(&nb, m, f32, lds);
+      e = batch_occupancy<512>(&nb, m, f32, nt, lds);
       break;
     case 1024:
-      e = batch_occupancy<1024>(&nb, m, f32, lds);
+      e = batch_occupancy<1024>(&nb, m, f32, nt, lds);
       break;
     default:
       break;

@@ -2027,7 +2027,9 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
     off[i] = e * (uint32_t)sizeof(VT);
     acc[i] = MaxpyCol<double>(x + rb, n - rb)(e * 8u);
   }
-  // GMRES_MAXPY_COLS columns per pass, as in the MAXPY
+  // GMRES_MAXPY_COLS columns per pass, as in the MAXPY. The cycle's basis
+  // is not read again, so its columns are loaded non-temporal (the first
+  // ones, which the last MAXPY read last, still hit in the caches).
   constexpr int MC = GMRES_MAXPY_COLS;
   auto colx = [&](int t) { return GMRES_XUPDATE_REVERSE ? j - 1 - t : t; };
   int q = 0;
@@ -2037,7 +2039,7 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
 #pragma unroll
     for (int t = 0; t < MC; ++t) {
       c[t] = xs * y[colx(q + t)];
-      const MaxpyCol<VT> col(Vt + (size_t)colx(q + t) * ldv, n - rb);
+      const GlbColNT<VT> col(Vt + (size_t)colx(q + t) * ldv, n - rb);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) v[t][i] = col(off[i]);
     }
@@ -2053,7 +2055,7 @@ __global__ __launch_bounds__(256) void k_xupdate(Ws ws, double* __restrict__ x, 
     const double c0 = xs * y[colx(q)];
     double v[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) v[i] = (double)MaxpyCol<VT>(Vt + (size_t)colx(q) * ldv, n - rb)(off[i]);
+    for (int i = 0; i < RPT; ++i) v[i] = (double)GlbColNT<VT>(Vt + (size_t)colx(q) * ldv, n - rb)(off[i]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] += v[i] * c0;
   }

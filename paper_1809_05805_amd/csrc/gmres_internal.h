@@ -176,13 +176,14 @@ int launch_batch_validate(const Csr& A, const BatchSys* sys, int nsys, DevState*
 // result (a kernel, so a captured graph holds no memset node).
 int launch_batch_reset(const Batch& B, hipStream_t s);
 // The persistent solve: grid workgroups of bs threads (256, 512 or 1024)
-// take queue entries until the queue is empty. f32: float32 basis. A system
-// split into several parts needs all of them running at once: the caller
-// keeps every nparts within what the GPU holds concurrently.
-int launch_batch(const Batch& B, int bs, int grid, bool f32, hipStream_t s, hipEvent_t e0 = nullptr,
-                 hipEvent_t e1 = nullptr);
-// Workgroups of k_batch that one compute unit holds at once (0 on error).
-int batch_resident_blocks(int bs, int m, bool f32);
+// take queue entries until the queue is empty. f32: float32 basis; nt: the
+// basis columns are loaded non-temporal. A system split into several parts
+// needs all of them running at once: the caller keeps every nparts within
+// what the GPU holds concurrently.
+int launch_batch(const Batch& B, int bs, int grid, bool f32, bool nt, hipStream_t s,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// Workgroups of that k_batch form that one compute unit holds at once (0 on error).
+int batch_resident_blocks(int bs, int m, bool f32, bool nt);
 size_t batch_lds_bytes(int bs, int m);
 
 int launch_init(const Ws& ws, int ncounters, hipStream_t s);

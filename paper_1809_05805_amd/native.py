@@ -36,8 +36,11 @@ EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destr
             "gmres_batch_read_info", "gmres_batch_set_config", "gmres_batch_get_config",
             "gmres_batch_autotune", "gmres_batch_capture", "gmres_batch_replay",
             "gmres_solve_noalloc", "gmres_options_init", "gmres_workspace_bytes_ex",
-            "gmres_create_ex", "gmres_batch_set_wait_limit"]
+            "gmres_create_ex", "gmres_batch_set_wait_limit", "gmres_batch_set_loads",
+            "gmres_batch_get_loads"]
 GMRES_BATCH_ORDER_NATURAL, GMRES_BATCH_ORDER_LARGEST_FIRST = 0, 1
+GMRES_BATCH_LOADS_AUTO, GMRES_BATCH_LOADS_CACHED, GMRES_BATCH_LOADS_STREAMED = 0, 1, 2
+BATCH_LOADS = {"auto": 0, "cached": 1, "streamed": 2}
 GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64, GMRES_FORMAT_SELL64_D16 = 0, 1, 2
 GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
 GMRES_OPT_FORMAT_AUTO, GMRES_OPT_FORMAT_CSR, GMRES_OPT_FORMAT_SELL64 = 0, 1, 2
@@ -92,7 +95,8 @@ class GmresBatchInfo(ctypes.Structure):
 
 class GmresBatchTrial(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("ms", ctypes.c_float), ("part_rows", ctypes.c_int64)]
+                ("order", ctypes.c_int32), ("ms", ctypes.c_float), ("part_rows", ctypes.c_int64),
+                ("streamed", ctypes.c_int32)]
 
 
 _lib = None
@@ -159,6 +163,8 @@ def load() -> ctypes.CDLL:
                                                    ctypes.POINTER(I32)]),
                        ("gmres_batch_autotune", [P, P, P, D, I64, P, I32, ctypes.POINTER(I32)]),
                        ("gmres_batch_capture", [P, P, P, D, I64]),
+                       ("gmres_batch_set_loads", [P, I32]),
+                       ("gmres_batch_get_loads", [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
                        ("gmres_batch_replay", [P])):
         getattr(lib, name).restype = ctypes.c_int
         getattr(lib, name).argtypes = args
@@ -339,7 +345,18 @@ def gmres_batch_autotune(ctx, b_ptr, x_ptr, rtol, max_iters, max_trials: int = 3
     nt = ctypes.c_int32()
     rc = load().gmres_batch_autotune(ctx, b_ptr, x_ptr, float(rtol), int(max_iters), trials,
                                      max_trials, ctypes.byref(nt))
-    return rc, [(t.block_size, t.grid, t.order, t.ms, t.part_rows) for t in trials[: nt.value]]
+    return rc, [(t.block_size, t.grid, t.order, t.ms, t.part_rows, t.streamed)
+                for t in trials[: nt.value]]
+
+
+def gmres_batch_set_loads(ctx, mode: int) -> int:
+    return load().gmres_batch_set_loads(ctx, mode)
+
+
+def gmres_batch_get_loads(ctx):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    rc = load().gmres_batch_get_loads(ctx, ctypes.byref(a), ctypes.byref(b))
+    return rc, a.value, b.value
 
 
 def gmres_batch_capture(ctx, b_ptr, x_ptr, rtol, max_iters) -> int:
@@ -602,11 +619,22 @@ class BatchSolver:
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_batch_set_wait_limit")
 
+    def set_loads(self, mode: str):
+        """How basis columns are loaded: "auto", "cached" or "streamed"."""
+        rc = gmres_batch_set_loads(self.ctx, BATCH_LOADS[mode])
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_set_loads")
+
     def config(self):
         rc, bs, grid, order, pr, mp = gmres_batch_get_config(self.ctx)
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_batch_get_config")
-        return {"block_size": bs, "grid": grid, "order": order, "part_rows": pr, "max_parts": mp}
+        rc, mode, streamed = gmres_batch_get_loads(self.ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_get_loads")
+        names = {v: k for k, v in BATCH_LOADS.items()}
+        return {"block_size": bs, "grid": grid, "order": order, "part_rows": pr, "max_parts": mp,
+                "loads": names[mode], "streamed": bool(streamed)}
 
     def autotune(self, b, x, rtol: float, max_iters: int):
         self._check(b, x)

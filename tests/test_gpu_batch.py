@@ -232,10 +232,45 @@ def test_autotune():
     best = min(trials, key=lambda t: t[3])
     cfg = s.config()
     assert (cfg["block_size"], cfg["grid"], cfg["order"], cfg["part_rows"]) == (*best[:3], best[4])
+    assert cfg["streamed"] == bool(best[5])
+    assert len({t[5] for t in trials}) == 2  # both load forms were timed
     assert torch.count_nonzero(x).item() == 0  # x restored
     rc, info = s.solve(bt, x, TOL, 20000)
     assert rc == 0 and np.all(info["converged"] == 1)
-    log("  trials: " + ", ".join(f"{t[0]}/{t[1]}/{t[2]}/{t[4]}:{t[3]:.2f}ms" for t in trials))
+    log("  trials: " + ", ".join(f"{t[0]}/{t[1]}/{t[2]}/{t[4]}/{t[5]}:{t[3]:.2f}ms" for t in trials))
+
+
+@pytest.mark.parametrize("config", [(256, 0, 1, 256), (1024, 0, 1, 0), (1024, 0, 1, 512)])
+def test_load_forms_bitwise(config):
+    """Streamed (non-temporal) and cached loads of the basis give bitwise the
+    same iterates and iteration counts, with and without teams."""
+    import torch
+
+    bp = SMALL
+    log(f"batch load forms {config}")
+    outs = []
+    for mode in ("cached", "streamed"):
+        s = solver(bp)
+        s.set_config(*config)
+        s.set_loads(mode)
+        cfg = s.config()
+        assert cfg["loads"] == mode and cfg["streamed"] == (mode == "streamed")
+        bt = torch.from_numpy(bp.b).cuda()
+        x = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+        rc, info = s.solve(bt, x, TOL, 20000)
+        torch.cuda.synchronize()
+        assert rc == 0 and np.all(info["converged"] == 1)
+        outs.append((x.cpu().numpy(), info["iters"].copy()))
+        s.close()
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][0], outs[1][0])
+    from paper_1809_05805_amd import native
+    s = solver(bp)
+    with pytest.raises(native.GmresError):
+        native_rc = native.gmres_batch_set_loads(s.ctx, 3)
+        if native_rc != 0:
+            raise native.GmresError(native_rc, "gmres_batch_set_loads")
+    s.close()
 
 
 def test_edges():
@@ -315,7 +350,8 @@ def test_full_batch(scheme):
     converged (residuals recomputed here), the three smallest against the oracle."""
     bp = P.make_batch()
     log(f"full batch {scheme}: n={bp.n} nnz={bp.nnz}")
-    rc, info, x, _ = run(bp, scheme)
+    rc, info, x, s = run(bp, scheme)
+    assert s.config()["loads"] == "auto"
     assert rc == 0
     assert np.all(info["status"] == 0) and np.all(info["converged"] == 1)
     A = None
@@ -334,6 +370,20 @@ def test_full_batch(scheme):
             assert abs(int(info["iters"][i]) - o.iters) <= 1
         assert rel(xi, o.x) <= 10 * 1e4 * TOL
     del A
+
+
+def test_load_form_auto_choice():
+    """Under the default mode the kernel streams the basis exactly when the
+    bases in use at once exceed 384 MiB: the 512-system 2D batch at 1024
+    threads and parts of 4096 rows keeps about 240 MB in use (cached); the 3D
+    batch keeps about 900 MB (streamed)."""
+    for bp, want in ((P.make_batch(), False), (P.make_batch3d(), True)):
+        s = solver(bp)
+        s.set_config(1024, 0, 1, 4096)
+        cfg = s.config()
+        log(f"{bp.name}: grid {cfg['grid']} streamed {cfg['streamed']}")
+        assert cfg["loads"] == "auto" and cfg["streamed"] == want
+        s.close()
 
 
 def test_full_batch_repeat_bitwise():
@@ -437,7 +487,8 @@ def test_full_batch3d(scheme):
     the two smallest against the oracle."""
     bp = P.make_batch3d()
     log(f"full 3D batch {scheme}: n={bp.n} nnz={bp.nnz}")
-    rc, info, x, _ = run(bp, scheme, config=(1024, 0, 1, 4096))
+    rc, info, x, s = run(bp, scheme, config=(1024, 0, 1, 4096))
+    assert s.config()["streamed"]  # its bases in use at once exceed the last-level cache
     assert rc == 0
     assert np.all(info["status"] == 0) and np.all(info["converged"] == 1)
     worst = 0.0
