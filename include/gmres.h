@@ -122,14 +122,17 @@ size_t gmres_workspace_bytes(int64_t n, int32_t m, int32_t scheme);
  * should differ: a zero field always means the library's own choice, which
  * is what gmres_workspace_bytes and gmres_create use. The arithmetic of a
  * solve does not depend on these, except the pipeline depth (below) and the
- * order of the per-row sums, which changes with the format (rounding only).
+ * rounding of the per-row sums, which differs between the CSR path and the
+ * sliced copy (whose three forms agree bit for bit).
  *   format: GMRES_OPT_FORMAT_AUTO (sliced copy of A for regular matrices,
- *     with 16-bit column deltas where they fit; see gmres_create), _CSR
- *     (always read the CSR arrays), _SELL64 (the sliced copy with int32
- *     column indices, whatever its padding) or _SELL64_D16 (the sliced copy
- *     whatever its padding, with 16-bit deltas where every slice column fits
- *     them, else int32 indices). Rows wider than 4096 or n >= 2^28 always
- *     fall back to CSR.
+ *     stored by diagonals or with 16-bit column deltas where they fit; see
+ *     gmres_create), _CSR (always read the CSR arrays), _SELL64 (the sliced
+ *     copy with int32 column indices, whatever its padding), _SELL64_D16 (the
+ *     sliced copy whatever its padding, with 16-bit deltas where every slice
+ *     column fits them, else int32 indices) or _SELL64_DIAG (the sliced copy
+ *     by diagonals whatever its padding where every row's columns are
+ *     strictly increasing, else as _SELL64_D16). Slices wider than 4096 or
+ *     n >= 2^28 always fall back to CSR.
  *   rows_per_lane: 0, or 1, 2, 4 or 8 rows per lane of the row-tiled kernels
  *     (tiles of 256 rows per lane-row). The default is the largest that leaves
  *     at least 512 tiles. The workspace size depends on it: give the same
@@ -156,7 +159,8 @@ enum {
   GMRES_OPT_FORMAT_AUTO = 0,
   GMRES_OPT_FORMAT_CSR = 1,
   GMRES_OPT_FORMAT_SELL64 = 2,
-  GMRES_OPT_FORMAT_SELL64_D16 = 3
+  GMRES_OPT_FORMAT_SELL64_D16 = 3,
+  GMRES_OPT_FORMAT_SELL64_DIAG = 4
 };
 typedef struct {
   int32_t format;
@@ -186,13 +190,17 @@ size_t gmres_workspace_bytes_ex(int64_t n, int32_t m, int32_t scheme,
  * The CSR structure is checked on the device (row_ptr[0] == 0, row_ptr[n] ==
  * nnz, non-decreasing row_ptr, 0 <= col_idx < n); a malformed matrix gives
  * GMRES_ERR_ARG and no context. On success *out holds the context.
- * Sparse format: when padding every slice of 64 rows to its longest row adds
- * at most a quarter to nnz (stencil and other regular matrices) and n < 2^28,
- * gmres_create plans a sliced-ELL copy of A (SELL-64: per slice, entry j of
- * each row stored column by column, so a wavefront's index and value loads
- * are contiguous and no row pointers are read). Its column indices take 2
- * bytes per entry instead of 4 when every slice column's col - row values
- * span at most 65535 (see gmres_matrix_storage_bytes). The library allocates no
+ * Sparse format: for n < 2^28, gmres_create plans a sliced-ELL copy of A
+ * (SELL-64: per slice of 64 rows, slice column j of every row stored
+ * together, so a wavefront's index and value loads are contiguous and no row
+ * pointers are read) in one of three forms (see gmres_matrix_storage_bytes):
+ *   - by diagonals, when every row's columns are strictly increasing and a
+ *     slice column per distinct col - row value among each slice's rows adds
+ *     at most a quarter to nnz (stencils): no per-entry column index;
+ *   - otherwise, when padding every slice to its longest row adds at most a
+ *     quarter to nnz (other regular matrices), by rows, with 2-byte column
+ *     deltas when every slice column's col - row values span at most 65535,
+ *     else int32 column indices. The library allocates no
  * device memory: gmres_matrix_storage_bytes gives the size of the copy and
  * gmres_set_matrix_storage builds it in a caller-owned buffer; from then on
  * every SpMV reads the copy, not the caller's arrays (after changing vals in
@@ -258,10 +266,14 @@ int gmres_destroy(gmres_ctx* ctx);
  * offsets, then the column indices and the float64 values (float32 for the
  * refinement schemes) of every stored entry (64 per slice and slice column;
  * padding entries hold value 0), each part 256-byte aligned. The column
- * indices are int32, or, when every slice column's col - row values span at
- * most 65535 (stencil and other banded matrices), one int32 base per slice
- * column followed by a 16-bit delta per entry: the column of entry j of row r
- * is r + base + delta.
+ * indices are
+ *   - by diagonals: one int32 diagonal d per slice column and nothing per
+ *     entry: slice column j of row r holds A[r, r + d_j] (0 where A has no
+ *     such entry, or r + d_j is outside [0, n)); a slice's diagonals
+ *     increase with j, so each row's entries keep their order;
+ *   - with deltas: one int32 base per slice column followed by a 16-bit delta
+ *     per entry: the column of entry j of row r is r + base + delta;
+ *   - else an int32 column index per entry.
  */
 int gmres_matrix_storage_bytes(gmres_ctx* ctx, size_t* bytes /* host */);
 
@@ -285,13 +297,21 @@ int gmres_set_matrix_storage(gmres_ctx* ctx, void* storage, size_t bytes);
  */
 int gmres_refresh_matrix(gmres_ctx* ctx);
 
-enum { GMRES_FORMAT_CSR = 0, GMRES_FORMAT_SELL64 = 1, GMRES_FORMAT_SELL64_D16 = 2 };
+enum {
+  GMRES_FORMAT_CSR = 0,
+  GMRES_FORMAT_SELL64 = 1,
+  GMRES_FORMAT_SELL64_D16 = 2,
+  GMRES_FORMAT_SELL64_DIAG = 3
+};
 /*
  * The SpMV format in use (GMRES_FORMAT_*) and the matrix entries it reads:
  * nnz for CSR, nnz plus padding for the sliced copies (SELL64: int32 column
- * indices; SELL64_D16: 16-bit column deltas). The arithmetic is the same
- * either way: each row's products are summed in storage order (padding adds
- * exact zeros).
+ * indices; SELL64_D16: 16-bit column deltas; SELL64_DIAG: by diagonals). The
+ * sliced forms give the same bits: each row's products are accumulated in
+ * storage order by fused multiply-adds, padding adding exact zeros (for
+ * finite x). The CSR path sums the same products with other roundings (a
+ * separate multiply and add for most entries, and a tree over the lanes of
+ * a long row).
  */
 int gmres_get_format(gmres_ctx* ctx, int32_t* format, int64_t* stored_entries);
 

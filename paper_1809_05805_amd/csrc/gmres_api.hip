@@ -75,15 +75,20 @@ int pick_spmv_shape(int64_t n, int64_t nnz, int want) {
 
 // Sparse format of the SpMV. The sliced ELL copy (SELL-64, built at create)
 // makes every column-index and value load of a wavefront one contiguous
-// 512-byte block and needs no row pointers; by default it is used when
+// 512-byte block and needs no row pointers. By default it is stored by
+// diagonals when every row's columns are strictly increasing and giving each
+// slice a column per distinct diagonal (col - row value) among its rows costs
+// at most a quarter more entries than nnz (stencils): then no column index is
+// stored at all, only one diagonal per slice column. Otherwise it is used when
 // padding every slice to its longest row costs at most a quarter more
-// entries, no slice is wider than kSellMaxWidth and n < kSellMaxRows. Its
-// column indices are 16-bit deltas from a per-slice-column base (2 bytes per
-// entry instead of 4) when every slice column's col - row values span at
-// most kSellDeltaSpan, as for stencil and other banded matrices.
-// gmres_options.format forces CSR, the copy with int32 indices, or the copy
-// with deltas where they fit, whatever the padding (the width and row limits
-// still hold).
+// entries, with column indices as 16-bit deltas from a per-slice-column base
+// (2 bytes per entry instead of 4) when every slice column's col - row values
+// span at most kSellDeltaSpan (banded matrices), else int32. In every case no
+// slice may be wider than kSellMaxWidth and n < kSellMaxRows.
+// gmres_options.format forces CSR, the copy with int32 indices, the copy with
+// deltas where they fit, or the copy by diagonals where the rows are sorted
+// (else with deltas where they fit), whatever the padding (the width and row
+// limits still hold).
 constexpr int kSellMaxWidth = 4096;
 constexpr int64_t kSellMaxRows = (int64_t)1 << 28;  // gathers use 32-bit byte offsets
 enum { kFormatCsr = 0, kFormatSell = 1 };
@@ -91,7 +96,7 @@ enum { kFormatCsr = 0, kFormatSell = 1 };
 // The caller's options, checked; zero fields take the library's choices.
 bool check_options(const gmres_options* o, int scheme) {
   if (!o) return true;
-  if (o->format < GMRES_OPT_FORMAT_AUTO || o->format > GMRES_OPT_FORMAT_SELL64_D16) return false;
+  if (o->format < GMRES_OPT_FORMAT_AUTO || o->format > GMRES_OPT_FORMAT_SELL64_DIAG) return false;
   if (o->rows_per_lane != 0 && o->rows_per_lane != 1 && o->rows_per_lane != 2 &&
       o->rows_per_lane != 4 && o->rows_per_lane != 8)
     return false;
@@ -234,9 +239,9 @@ struct gmres_ctx {
   Sell sell;         // the sliced copy (format == kFormatSell), in caller memory
   std::vector<int64_t> sell_sp;  // planned slice offsets (empty: no copy planned)
   int64_t sell_entries;          // planned stored entries
-  bool sell_d16;                 // the planned copy holds 16-bit column deltas
+  int sell_sf;                   // the planned copy's SliceForm
   size_t sell_bytes, o_ci, o_va; // planned storage size and its layout (o_ci: indices or deltas)
-  size_t o_cb;                   // per-slice-column bases (16-bit deltas only)
+  size_t o_cb;                   // per-slice-column bases or diagonals (kSfD16, kSfDiag)
   Layout L;
   Ws ws;
   hipStream_t stream;
@@ -407,38 +412,61 @@ int plan_format(gmres_ctx* c) {
   c->sell = Sell{};
   c->sell_sp.clear();
   c->sell_entries = 0;
-  c->sell_d16 = false;
+  c->sell_sf = kSfI32;
   c->sell_bytes = 0;
   const int want = c->format_want;
   if (want == GMRES_OPT_FORMAT_CSR || c->nnz == 0 || c->A.n >= kSellMaxRows) return GMRES_OK;
   const int64_t ns = (c->A.n + 63) / 64;
-  // ns + 1 ints fit easily in the basis region (n (m+2) doubles, or floats)
+  // 2 (ns + 1) ints fit easily in the basis region (n (m+2) doubles, or floats,
+  // n rounded up to 64)
   int* dw = ir_scheme(c->scheme) ? reinterpret_cast<int*>(c->ws.Vf)
                                  : reinterpret_cast<int*>(c->ws.V);
-  std::vector<int> wh((size_t)ns + 1);
+  int* dd = dw + ns + 1;
+  std::vector<int> wh((size_t)ns + 1), dh((size_t)ns + 1);
   const bool deltas = want != GMRES_OPT_FORMAT_SELL64;
+  const bool diags = want == GMRES_OPT_FORMAT_AUTO || want == GMRES_OPT_FORMAT_SELL64_DIAG;
   if (hipMemsetAsync(dw + ns, 0, sizeof(int), c->stream) != hipSuccess ||
+      hipMemsetAsync(dd + ns, 0, sizeof(int), c->stream) != hipSuccess ||
       launch_sell_width(c->A, ns, dw, deltas ? dw + ns : nullptr, kSellMaxWidth, c->stream) ||
+      (diags && launch_sell_diags(c->A, ns, dd, dd + ns, kSellMaxWidth, c->stream)) ||
       hipMemcpyAsync(wh.data(), dw, sizeof(int) * (size_t)(ns + 1), hipMemcpyDeviceToHost,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(dh.data(), dd, sizeof(int) * (size_t)(ns + 1), hipMemcpyDeviceToHost,
                      c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return GMRES_ERR_HIP;
-  std::vector<int64_t> sp((size_t)ns + 1);
-  sp[0] = 0;
-  int wmax = 0;
-  for (int64_t i = 0; i < ns; ++i) {
-    sp[i + 1] = sp[i] + 64 * (int64_t)wh[i];
-    if (wh[i] > wmax) wmax = wh[i];
+  // slice offsets from slice widths; false if a slice is too wide
+  auto offsets = [&](const std::vector<int>& w, std::vector<int64_t>& sp) {
+    sp.assign((size_t)ns + 1, 0);
+    bool fits = true;
+    for (int64_t i = 0; i < ns; ++i) {
+      sp[i + 1] = sp[i] + 64 * (int64_t)w[i];
+      fits = fits && w[i] <= kSellMaxWidth;
+    }
+    return fits;
+  };
+  auto cheap = [&](int64_t total) { return total * 4 <= c->nnz * 5; };
+  std::vector<int64_t> sp, dsp;
+  const bool ell = offsets(wh, sp);
+  const bool diag = diags && dh[ns] == 0 && offsets(dh, dsp);
+  if (diag && (want != GMRES_OPT_FORMAT_AUTO || cheap(dsp[ns]))) {
+    c->sell_sf = kSfDiag;
+    c->sell_sp.swap(dsp);
+  } else if (ell && (want != GMRES_OPT_FORMAT_AUTO || cheap(sp[ns]))) {
+    c->sell_sf = deltas && wh[ns] <= kSellDeltaSpan ? kSfD16 : kSfI32;
+    c->sell_sp.swap(sp);
+  } else {
+    return GMRES_OK;
   }
-  const int64_t total = sp[ns];
-  const bool cheap = total * 4 <= c->nnz * 5;
-  if (wmax > kSellMaxWidth || (want == GMRES_OPT_FORMAT_AUTO && !cheap)) return GMRES_OK;
-  c->sell_sp.swap(sp);
+  const int64_t total = c->sell_sp[ns];
   c->sell_entries = total;
-  c->sell_d16 = deltas && wh[ns] <= kSellDeltaSpan;
   const size_t vsize = ir_scheme(c->scheme) ? sizeof(float) : sizeof(double);
   const size_t off_sp = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
-  if (c->sell_d16) {
+  if (c->sell_sf == kSfDiag) {
+    c->o_cb = off_sp;
+    c->o_ci = 0;
+    c->o_va = round_up(c->o_cb + sizeof(int) * (size_t)(total / 64), kAlign);
+  } else if (c->sell_sf == kSfD16) {
     c->o_cb = off_sp;
     c->o_ci = round_up(c->o_cb + sizeof(int) * (size_t)(total / 64), kAlign);
     c->o_va = round_up(c->o_ci + sizeof(uint16_t) * (size_t)total, kAlign);
@@ -533,7 +561,9 @@ int enqueue_cycle(gmres_ctx* c, const double* b, double* x, int m_eff) {
         // The last step of a cycle only finishes the lagged norm of column m_eff.
         const bool last = k == m_eff;
         int wsrc = last ? kWNone
-                        : c->format == kFormatSell ? (c->sell.cd ? kWSellD16 : kWSell)
+                        : c->format == kFormatSell ? (c->sell.sf == kSfDiag  ? kWSellDiag
+                                                      : c->sell.sf == kSfD16 ? kWSellD16
+                                                                             : kWSell)
                                                    : kWSpmv;
         // A; u read and w written by the SpMV; V[:,0:k+1] (u included) read by the projection
         double bytes = last ? n8 : csr + 2 * n8 + n8 * (k + 1);
@@ -899,9 +929,10 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
   const bool fv = ir_scheme(c->scheme);  // float32 values for the reduced-precision bases
   Sell S{};
   S.sp = (const int64_t*)base;
-  S.ci = c->sell_d16 ? nullptr : (int*)(base + c->o_ci);
-  S.cd = c->sell_d16 ? (uint16_t*)(base + c->o_ci) : nullptr;
-  S.cbase = c->sell_d16 ? (int*)(base + c->o_cb) : nullptr;
+  S.sf = c->sell_sf;
+  S.ci = S.sf == kSfI32 ? (int*)(base + c->o_ci) : nullptr;
+  S.cd = S.sf == kSfD16 ? (uint16_t*)(base + c->o_ci) : nullptr;
+  S.cbase = S.sf != kSfI32 ? (int*)(base + c->o_cb) : nullptr;
   S.va = fv ? nullptr : (double*)(base + c->o_va);
   S.vaf = fv ? (float*)(base + c->o_va) : nullptr;
   S.ns = ns;
@@ -921,9 +952,10 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
 
 int gmres_get_format(gmres_ctx* c, int32_t* format, int64_t* stored_entries) {
   if (!c || !format || !stored_entries) return GMRES_ERR_ARG;
-  *format = c->format != kFormatSell ? GMRES_FORMAT_CSR
-            : c->sell.cd              ? GMRES_FORMAT_SELL64_D16
-                                      : GMRES_FORMAT_SELL64;
+  *format = c->format != kFormatSell  ? GMRES_FORMAT_CSR
+            : c->sell.sf == kSfDiag ? GMRES_FORMAT_SELL64_DIAG
+            : c->sell.sf == kSfD16  ? GMRES_FORMAT_SELL64_D16
+                                    : GMRES_FORMAT_SELL64;
   *stored_entries = c->format == kFormatSell ? c->sell_entries : c->nnz;
   return GMRES_OK;
 }
@@ -1008,7 +1040,7 @@ int gmres_solve_noalloc(int64_t n, int64_t nnz, const int32_t* row_ptr, const in
   c.format = kFormatCsr;
   c.sell = Sell{};
   c.sell_entries = 0;
-  c.sell_d16 = false;
+  c.sell_sf = kSfI32;
   c.sell_bytes = 0;
   c.last_j = 0;
   c.timing = false;

@@ -913,6 +913,43 @@ __global__ __launch_bounds__(256) void k_sell_width(Csr A, int64_t ns, int* __re
   if (l == 0 && widest > 0) atomicMax(spread, widest);
 }
 
+// Number of distinct diagonals (col - row values) among each slice's entries,
+// wavefront per slice, lane per row. With every row's columns strictly
+// increasing, each lane's col - row values rise along its row, so taking the
+// smallest of the lanes' next values over and over (and advancing the lanes
+// that hold it) visits the slice's diagonals once each, in increasing order.
+// Rows that are not strictly increasing set bit 0 of *flag; a slice with
+// more than max_width diagonals stops counting and sets bit 1.
+__global__ __launch_bounds__(256) void k_sell_diags(Csr A, int64_t ns, int* __restrict__ width,
+                                                     int* __restrict__ flag, int max_width) {
+  const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= ns) return;  // uniform over the wavefront
+  const int l = threadIdx.x & 63;
+  const int64_t r = s * 64 + l;
+  const int e0 = r < A.n ? A.rp[r] : 0;
+  const int len = r < A.n ? A.rp[r + 1] - e0 : 0;
+  bool sorted = true;
+  for (int j = 1; j < len; ++j) sorted = sorted && A.ci[e0 + j] > A.ci[e0 + j - 1];
+  const int live = sorted ? len : 0;
+  int p = 0, count = 0, wide = 0;
+  for (;;) {
+    const int d = p < live ? A.ci[e0 + p] - (int)r : INT_MAX;
+    int mn = d;
+    for (int mask = 32; mask >= 1; mask >>= 1) mn = min(mn, __shfl_xor(mn, mask, 64));
+    if (mn == INT_MAX) break;  // uniform
+    if (++count > max_width) {
+      wide = 1;
+      break;
+    }
+    if (d == mn) ++p;
+  }
+  if (!sorted) atomicOr(flag, 1);
+  if (l == 0) {
+    width[s] = count < 1 ? 1 : count;
+    if (wide) atomicOr(flag, 2);
+  }
+}
+
 // Copy of A into slices with 16-bit column deltas (sp already set), values in
 // SVT: wavefront per slice, lane per row. Slice column j's base (the smallest
 // col - row of its entries, 0 if it has none) goes to cbase, each entry's
@@ -951,6 +988,49 @@ __global__ __launch_bounds__(256) void k_sell_fill_d16(Csr A, Sell S, SVT* __res
     S.cd[e] = real ? (uint16_t)(d - base) : (uint16_t)0;
     va[e] = real ? (SVT)A.va[e0 + j] : (SVT)0;
   }
+  if (bad) atomicOr(&st->bad_csr, 1);
+}
+
+// Copy of A into slices stored by diagonals (sp already set): wavefront per
+// slice, lane per row. Slice column j holds, for every row r of the slice, the
+// entry in column r + d_j, or 0 where the row has none; d_j, the slice's
+// diagonals in increasing order (the order k_sell_diags visits them), goes to
+// cbase. A row's entries thus keep their order, and padding zeros fall
+// between them. A row outside [0, nnz), a row whose columns are not strictly
+// increasing, or one with a diagonal beyond its slice's width (a changed
+// structure) sets st->bad_csr.
+template <typename SVT>
+__global__ __launch_bounds__(256) void k_sell_fill_diag(Csr A, Sell S, SVT* __restrict__ va,
+                                                         DevState* st) {
+  const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= S.ns) return;  // uniform over the wavefront
+  const int l = threadIdx.x & 63;
+  const int64_t r = s * 64 + l;
+  const int64_t b = S.sp[s];
+  const int W = (int)((S.sp[s + 1] - b) >> 6);
+  const int64_t e0 = r < A.n ? A.rp[r] : 0;
+  const int64_t e1 = r < A.n ? A.rp[r + 1] : 0;
+  int len = (int)(e1 - e0);
+  int bad = 0;
+  if (e0 < 0 || e1 < e0 || e1 > A.nnz || len > W) {
+    bad = 1;
+    len = 0;
+  }
+  int p = 0, prev = INT_MIN;
+  for (int j = 0; j < W; ++j) {
+    const int d = p < len ? A.ci[e0 + p] - (int)r : INT_MAX;
+    int mn = d;
+    for (int mask = 32; mask >= 1; mask >>= 1) mn = min(mn, __shfl_xor(mn, mask, 64));
+    const bool take = p < len && d == mn;
+    if (l == 0) S.cbase[(b >> 6) + j] = mn == INT_MAX ? 0 : mn;
+    va[b + (int64_t)j * 64 + l] = take ? (SVT)A.va[e0 + p] : (SVT)0;
+    if (take) {
+      if (d <= prev) bad = 1;
+      prev = d;
+      ++p;
+    }
+  }
+  if (p < len) bad = 1;
   if (bad) atomicOr(&st->bad_csr, 1);
 }
 
@@ -996,14 +1076,27 @@ __device__ inline const SVT* sell_vals(const Sell& S) {
 // Entries j0 .. j0+U-1 of lane l's row (row r) in the slice at entry offset
 // b, width W (>= 1): indices past W are clamped to W-1 (their products are
 // masked by the caller). Buffer loads over the slice's own entries (the
-// descriptors are scalar; a lane supplies a 32-bit byte offset). D16: the
-// column is r + the slice column's base + the 16-bit delta, as unsigned and
-// at most n - 1 (a padding entry's value is 0 whatever column it names).
-template <int U, typename SVT, bool D16>
+// descriptors are scalar; a lane supplies a 32-bit byte offset). SF (a
+// SliceForm): kSfD16, the column is r + the slice column's base + the 16-bit
+// delta; kSfDiag, r + the slice column's diagonal, with no per-entry index
+// load; both as unsigned and at most n - 1 (a padding entry's value is 0
+// whatever column it names).
+template <int U, typename SVT, int SF>
 __device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l, int r,
                                  int (&c)[U], SVT (&v)[U]) {
   const BufCol<SVT> vb(sell_vals<SVT>(S) + b, (int64_t)W * 64);
-  if constexpr (D16) {
+  if constexpr (SF == kSfDiag) {
+    const int* cb = S.cbase + (b >> 6);
+    const uint32_t last = (uint32_t)(S.n - 1);
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const int j = j0 + t < W ? j0 + t : W - 1;
+      const uint32_t e = (uint32_t)(j * 64 + l);
+      const uint32_t col = (uint32_t)(r + cb[j]);
+      c[t] = (int)(col < last ? col : last);
+      v[t] = vb.template load<GMRES_SELL_CPOL>(e * (uint32_t)sizeof(SVT));
+    }
+  } else if constexpr (SF == kSfD16) {
     const __amdgpu_buffer_rsrc_t rd =
         __builtin_amdgcn_make_buffer_rsrc(S.cd + b, (short)0, W * 64 * 2, 0x00020000);
     const int* cb = S.cbase + (b >> 6);
@@ -1039,7 +1132,7 @@ __device__ inline void sell_load(const Sell& S, int64_t b, int W, int j0, int l,
 // value loads of the next chunk (of this slice or the next) are issued before
 // the gathers of the current one are consumed, so one memory latency per
 // chunk is hidden.
-template <int NS, int U, typename XT, bool D16>
+template <int NS, int U, typename XT, int SF>
 __device__ inline void sell_slices(const Sell& S, const XT* __restrict__ x, int64_t s0,
                                    int64_t sstride, int l, arith_t<XT> (&out)[NS]) {
   using T = arith_t<XT>;
@@ -1059,7 +1152,7 @@ __device__ inline void sell_slices(const Sell& S, const XT* __restrict__ x, int6
   int r = (int)(sc * 64 + l);  // the lane's row in that slice
   int c[U];
   SVT v[U];
-  sell_load<U, SVT, D16>(S, b, W, 0, l, r, c, v);
+  sell_load<U, SVT, SF>(S, b, W, 0, l, r, c, v);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     int64_t bn = b;
@@ -1071,20 +1164,29 @@ __device__ inline void sell_slices(const Sell& S, const XT* __restrict__ x, int6
       Wn = (int)((S.sp[sn + 1] - bn) >> 6);
       rn = (int)(sn * 64 + l);
     }
+    // Every product is a fused multiply-add into the row's sum, entries past
+    // the width weighted 0: the rounding then does not depend on where in a
+    // chunk an entry falls, so the slice forms (whose padding zeros sit at
+    // different places in a row) give the same bits.
     T acc = (T)0;
     for (int j0 = 0; j0 < W; j0 += U) {
       T xv[U], vv[U];
 #pragma unroll
       for (int t = 0; t < U; ++t) {
         xv[t] = (T)xb((uint32_t)c[t] * (uint32_t)sizeof(XT));
-        vv[t] = (T)v[t];
+        vv[t] = j0 + t < W ? (T)v[t] : (T)0;
       }
       if (j0 + U < W)
-        sell_load<U, SVT, D16>(S, b, W, j0 + U, l, r, c, v);
+        sell_load<U, SVT, SF>(S, b, W, j0 + U, l, r, c, v);
       else if (i + 1 < NS)
-        sell_load<U, SVT, D16>(S, bn, Wn, 0, l, rn, c, v);
+        sell_load<U, SVT, SF>(S, bn, Wn, 0, l, rn, c, v);
 #pragma unroll
-      for (int t = 0; t < U; ++t) acc += (j0 + t < W) ? vv[t] * xv[t] : (T)0;
+      for (int t = 0; t < U; ++t) {
+        if constexpr (sizeof(T) == 8)
+          acc = __builtin_fma(vv[t], xv[t], acc);
+        else
+          acc = __builtin_fmaf(vv[t], xv[t], acc);
+      }
     }
     out[i] = acc;
     b = bn;
@@ -1095,7 +1197,7 @@ __device__ inline void sell_slices(const Sell& S, const XT* __restrict__ x, int6
 
 // y = A x (b == nullptr) or y = b - A x from the sliced copy: each wavefront
 // takes NS consecutive slices. Skipped when a state is given and its cycle is done.
-template <int NS, bool D16>
+template <int NS, int SF>
 __global__ __launch_bounds__(256) void k_spmv_sell(Sell S, int64_t n, const double* __restrict__ x,
                                                     const double* __restrict__ b,
                                                     double* __restrict__ y, const DevState* st) {
@@ -1103,7 +1205,7 @@ __global__ __launch_bounds__(256) void k_spmv_sell(Sell S, int64_t n, const doub
   const int l = threadIdx.x & 63;
   const int64_t s0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * NS;
   double out[NS];
-  sell_slices<NS, 8, double, D16>(S, x, s0, 1, l, out);
+  sell_slices<NS, 8, double, SF>(S, x, s0, 1, l, out);
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int64_t r = (s0 + i) * 64 + l;
@@ -1496,14 +1598,16 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
   const VT* __restrict__ u_g = V + (size_t)K * ldv;
   using CT = arith_t<VT>;  // arithmetic type of the basis
   constexpr bool HAS_SPMV = WSRC != kWNone;
-  // kWSell, kWSellD16: the lane's rows are row 64 s + lane of slices s = row0/64 + wv RPT + i
+  // the sliced copy (kWSell*): the lane's rows are row 64 s + lane of slices
+  // s = row0/64 + wv RPT + i
+  constexpr bool SELL = WSRC == kWSell || WSRC == kWSellD16 || WSRC == kWSellDiag;
   CT ws_out[RPT];
-  if constexpr (WSRC == kWSell || WSRC == kWSellD16) {
-    constexpr bool D16 = WSRC == kWSellD16;
+  if constexpr (SELL) {
+    constexpr int SF = WSRC == kWSellD16 ? kSfD16 : WSRC == kWSellDiag ? kSfDiag : kSfI32;
     if constexpr (GMRES_FUSED_ROWMAP == 1)
-      sell_slices<RPT, 8, VT, D16>(SA, u_g, (row0 >> 6) + wv, 4, lane, ws_out);
+      sell_slices<RPT, 8, VT, SF>(SA, u_g, (row0 >> 6) + wv, 4, lane, ws_out);
     else
-      sell_slices<RPT, 8, VT, D16>(SA, u_g, (row0 >> 6) + wv * RPT, 1, lane, ws_out);
+      sell_slices<RPT, 8, VT, SF>(SA, u_g, (row0 >> 6) + wv * RPT, 1, lane, ws_out);
   }
 
   if constexpr (WSRC == kWSpmv) {
@@ -1542,7 +1646,7 @@ __global__ __launch_bounds__(256) void k_fused(Csr A, Sell SA, Ws ws, int K, int
     if constexpr (WSRC == kWSpmv) {
       w[i] = ok ? (CT)wl[lr] : (CT)0;
       if (ok) st_stream<1>(wout + r, (VT)w[i]);
-    } else if constexpr (WSRC == kWSell || WSRC == kWSellD16) {
+    } else if constexpr (SELL) {
       w[i] = ok ? ws_out[i] : (CT)0;
       if (ok) st_stream<1>(wout + r, (VT)w[i]);
     } else if constexpr (WSRC == kWLoad) {
@@ -2139,9 +2243,23 @@ int launch_sell_width(const Csr& A, int64_t ns, int* width, int* spread, int max
   return 0;
 }
 
+int launch_sell_diags(const Csr& A, int64_t ns, int* width, int* flag, int max_width,
+                      hipStream_t s) {
+  const int64_t blocks = (ns + 3) / 4;
+  hipLaunchKernelGGL(k_sell_diags, dim3((unsigned)blocks), dim3(256), 0, s, A, ns, width, flag,
+                     max_width);
+  GMRES_CHECK_LAUNCH();
+  return 0;
+}
+
 int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s) {
   const int64_t blocks = (S.ns * 64 + 255) / 256;  // a wavefront per slice, or a thread per row
-  if (S.cd) {
+  if (S.sf == kSfDiag) {
+    if (S.vaf)
+      hipLaunchKernelGGL(k_sell_fill_diag<float>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.vaf, st);
+    else
+      hipLaunchKernelGGL(k_sell_fill_diag<double>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.va, st);
+  } else if (S.sf == kSfD16) {
     if (S.vaf)
       hipLaunchKernelGGL(k_sell_fill_d16<float>, dim3((unsigned)blocks), dim3(256), 0, s, A, S, S.vaf, st);
     else
@@ -2171,12 +2289,15 @@ int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b,
                      const DevState* st, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   constexpr int NS = 2;
   const int64_t blocks = (S.ns + 4 * NS - 1) / (4 * NS);
-  if (S.cd)
-    hipExtLaunchKernelGGL((k_spmv_sell<NS, true>), dim3((unsigned)blocks), dim3(256), 0u, s, e0, e1,
-                          0u, S, n, x, b, y, st);
+  if (S.sf == kSfDiag)
+    hipExtLaunchKernelGGL((k_spmv_sell<NS, kSfDiag>), dim3((unsigned)blocks), dim3(256), 0u, s, e0,
+                          e1, 0u, S, n, x, b, y, st);
+  else if (S.sf == kSfD16)
+    hipExtLaunchKernelGGL((k_spmv_sell<NS, kSfD16>), dim3((unsigned)blocks), dim3(256), 0u, s, e0,
+                          e1, 0u, S, n, x, b, y, st);
   else
-    hipExtLaunchKernelGGL((k_spmv_sell<NS, false>), dim3((unsigned)blocks), dim3(256), 0u, s, e0, e1,
-                          0u, S, n, x, b, y, st);
+    hipExtLaunchKernelGGL((k_spmv_sell<NS, kSfI32>), dim3((unsigned)blocks), dim3(256), 0u, s, e0,
+                          e1, 0u, S, n, x, b, y, st);
   GMRES_CHECK_LAUNCH();
   return 0;
 }
@@ -2201,6 +2322,7 @@ static int fused_r(const Csr& A, const Sell& SA, int shape, int wsrc, const Ws& 
     case kWLoad: fused_t<RPT, 1, 1, kWLoad, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
     case kWSell: fused_t<RPT, 1, 1, kWSell, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
     case kWSellD16: fused_t<RPT, 1, 1, kWSellD16, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
+    case kWSellDiag: fused_t<RPT, 1, 1, kWSellDiag, VT>(A, SA, ws, K, nproj, m_eff, tail, G, s, e0, e1); return 0;
     case kWSpmv: break;
     default: return -2;
   }

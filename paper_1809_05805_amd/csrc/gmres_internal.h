@@ -75,15 +75,23 @@ struct Csr {
 // than 2^16, 16-bit deltas (cd): the column of entry j of row r in slice s is
 // min(r + cbase[sp[s] / 64 + j] + cd[...], n - 1) taken as unsigned, so a
 // padding entry (delta 0) can never leave [0, n).
+// How a slice's column indices are stored.
+enum SliceForm {
+  kSfI32 = 0,   // an int32 column index per entry
+  kSfD16 = 1,   // per slice column a base, per entry a 16-bit delta: col = row + base + delta
+  kSfDiag = 2   // per slice column one diagonal d and no per-entry index: col = row + d
+};
 struct Sell {
   const int64_t* sp;  // ns + 1 slice offsets (entries)
-  int* ci;            // int32 column indices, or null with 16-bit deltas
+  int* ci;            // int32 column indices (kSfI32), else null
   double* va;         // float64 values (the FP64 schemes) ...
   float* vaf;         // ... or float32 values (the FP32-basis scheme)
   int64_t ns;         // slices, ceil(n / 64)
   int64_t n;          // rows (below 2^28: gathers take 32-bit byte offsets)
-  uint16_t* cd;       // 16-bit column deltas (null with int32 indices)
-  int* cbase;         // per slice column: the smallest col - row of its entries
+  uint16_t* cd;       // 16-bit column deltas (kSfD16), else null
+  int* cbase;         // per slice column: the smallest col - row of its entries (kSfD16), or
+                      // its diagonal (kSfDiag)
+  int sf;             // SliceForm
 };
 constexpr int kSellDeltaSpan = 65535;  // largest col - row spread a slice column may have for cd
 
@@ -200,7 +208,8 @@ enum WSource {
   kWSpmv = 1,  // w = A u computed in the kernel from the CSR arrays
   kWLoad = 2,  // w read from ws.w, written by a separate SpMV launch
   kWSell = 3,  // w = A u computed in the kernel from the sliced ELL copy (int32 indices)
-  kWSellD16 = 4  // the same from the sliced copy with 16-bit column deltas
+  kWSellD16 = 4,  // the same from the sliced copy with 16-bit column deltas
+  kWSellDiag = 5  // the same from the sliced copy stored by diagonals
 };
 // Sliced ELL construction: slice widths, then (with sp filled in) the copy;
 // rows longer than their slice's width set st->bad_csr.
@@ -208,6 +217,12 @@ enum WSource {
 // to 0 beforehand) = the largest col - row spread over the slice columns of
 // slices at most max_width wide (INT_MAX when a slice is wider).
 int launch_sell_width(const Csr& A, int64_t ns, int* width, int* spread, int max_width,
+                      hipStream_t s);
+// width[s] = max(1, the number of distinct col - row values (diagonals) among
+// slice s's entries); *flag (device, set to 0 beforehand) gets bit 0 when a
+// row's columns are not strictly increasing and bit 1 when a slice has more
+// than max_width diagonals (its count is then not finished).
+int launch_sell_diags(const Csr& A, int64_t ns, int* width, int* flag, int max_width,
                       hipStream_t s);
 int launch_sell_fill(const Csr& A, const Sell& S, DevState* st, hipStream_t s);
 int launch_spmv_sell(const Sell& S, int64_t n, const double* x, const double* b, double* y,

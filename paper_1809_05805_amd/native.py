@@ -41,16 +41,17 @@ EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destr
 GMRES_BATCH_ORDER_NATURAL, GMRES_BATCH_ORDER_LARGEST_FIRST = 0, 1
 GMRES_BATCH_LOADS_AUTO, GMRES_BATCH_LOADS_CACHED, GMRES_BATCH_LOADS_STREAMED = 0, 1, 2
 BATCH_LOADS = {"auto": 0, "cached": 1, "streamed": 2}
-GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64, GMRES_FORMAT_SELL64_D16 = 0, 1, 2
+GMRES_FORMAT_CSR, GMRES_FORMAT_SELL64, GMRES_FORMAT_SELL64_D16, GMRES_FORMAT_SELL64_DIAG = 0, 1, 2, 3
 GMRES_KSTAT_STEP, GMRES_KSTAT_MAXPY, GMRES_KSTAT_SPMV, GMRES_KSTAT_COUNT = 0, 1, 2, 3
 GMRES_OPT_FORMAT_AUTO, GMRES_OPT_FORMAT_CSR, GMRES_OPT_FORMAT_SELL64 = 0, 1, 2
-GMRES_OPT_FORMAT_SELL64_D16 = 3
+GMRES_OPT_FORMAT_SELL64_D16, GMRES_OPT_FORMAT_SELL64_DIAG = 3, 4
 OPT_FORMATS = {None: GMRES_OPT_FORMAT_AUTO, "auto": GMRES_OPT_FORMAT_AUTO,
                "csr": GMRES_OPT_FORMAT_CSR, "sell": GMRES_OPT_FORMAT_SELL64,
                "sell64": GMRES_OPT_FORMAT_SELL64, "sell_d16": GMRES_OPT_FORMAT_SELL64_D16,
-               "sell64_d16": GMRES_OPT_FORMAT_SELL64_D16}
+               "sell64_d16": GMRES_OPT_FORMAT_SELL64_D16, "sell_diag": GMRES_OPT_FORMAT_SELL64_DIAG,
+               "sell64_diag": GMRES_OPT_FORMAT_SELL64_DIAG}
 FORMAT_NAMES = {GMRES_FORMAT_CSR: "csr", GMRES_FORMAT_SELL64: "sell64",
-                GMRES_FORMAT_SELL64_D16: "sell64_d16"}
+                GMRES_FORMAT_SELL64_D16: "sell64_d16", GMRES_FORMAT_SELL64_DIAG: "sell64_diag"}
 GMRES_BATCH_WAIT_LIMIT = 1 << 23
 
 
@@ -63,7 +64,8 @@ class GmresOptions(ctypes.Structure):
 
 def make_options(format=None, rows_per_lane: int = 0, csr_spmv_shape: int = 0,
                  split_spmv: bool = False, pipeline_depth: int = 0) -> GmresOptions:
-    """A gmres_options from keyword values (format: None/"auto", "csr" or "sell")."""
+    """A gmres_options from keyword values (format: None/"auto", "csr", "sell",
+    "sell_d16" or "sell_diag")."""
     o = GmresOptions()
     o.format = OPT_FORMATS[format] if format in OPT_FORMATS else int(format)
     o.rows_per_lane = int(rows_per_lane)
@@ -490,7 +492,7 @@ class GmresSolver:
             raise GmresError(rc, "gmres_refresh_matrix")
 
     def format(self):
-        """("csr" | "sell64" | "sell64_d16", stored entries) of the context's SpMV."""
+        """("csr" | "sell64" | "sell64_d16" | "sell64_diag", stored entries) of the context's SpMV."""
         rc, fmt, stored = gmres_get_format(self.ctx)
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_get_format")

@@ -25,8 +25,9 @@ def dev(p):
 def gpu_run(p, scheme, m=None, rtol=None, max_iters=None, b=None, x0=None, basis=False, fmt=None,
             orth=False, **options):
     """One solve through the C ABI; returns a dict with x, info, hist and the last cycle.
-    fmt: None (the library's choice), "csr" or "sell"; further keyword options
-    (rows_per_lane, pipeline_depth, ...) go to gmres_create_ex."""
+    fmt: None (the library's choice), "csr", "sell", "sell_d16" or "sell_diag";
+    further keyword options (rows_per_lane, pipeline_depth, ...) go to
+    gmres_create_ex."""
     import torch
 
     from paper_1809_05805_amd.native import GmresSolver

@@ -1,12 +1,16 @@
 """The library's SpMV format: which one it picks, and its sliced copy of A.
 
-A context keeps a sliced-ELL copy of A (64 rows per slice, each row padded to
-its slice's longest row) when that costs at most a quarter more entries, and
-otherwise reads the CSR arrays. The copy's column indices are 16-bit deltas
-from a base per slice column when every slice column's col - row values span
-at most 65535, else int32. These tests check the choice on regular,
-wide-banded and irregular matrices, the stored-entry count against a count
-made here from the row lengths, the storage layout, and that
+A context keeps a sliced-ELL copy of A (64 rows per slice). Stored by
+diagonals (a slice column per distinct col - row value among the slice's
+rows, no per-entry column index) when every row's columns are strictly
+increasing and that costs at most a quarter more entries than nnz; else by
+rows (each row padded to its slice's longest) when that costs at most a
+quarter more, with column indices as 16-bit deltas from a base per slice
+column when every slice column's col - row values span at most 65535, else
+int32; else the SpMV reads the CSR arrays. These tests check the choice on
+stencil, banded, scattered, unsorted and irregular matrices, the stored-entry
+counts against counts made here from the CSR arrays, the storage layouts, that
+the three sliced forms give bitwise the same solve, and that
 gmres_refresh_matrix picks up new values (the solve then matches the oracle on
 the changed matrix) and refuses a structure that no longer fits the copy.
 """
@@ -27,6 +31,53 @@ def padded_entries(p):
     pad = np.zeros(ns * 64, dtype=np.int64)
     pad[: p.n] = lens
     return int(64 * np.maximum(pad.reshape(ns, 64).max(axis=1), 1).sum())
+
+
+def diag_entries(p):
+    """Entries of the sliced layout by diagonals: per slice 64 x max(1, distinct col - row)."""
+    n = p.n
+    rows = np.repeat(np.arange(n), np.diff(p.row_ptr))
+    d = p.col_idx.astype(np.int64) - rows
+    sl = rows // 64
+    ns = (n + 63) // 64
+    counts = np.zeros(ns, dtype=np.int64)
+    if d.size:
+        pairs = np.unique(np.stack([sl, d]), axis=1)
+        counts += np.bincount(pairs[0], minlength=ns)
+    return int(64 * np.maximum(counts, 1).sum())
+
+
+def scattered(n, reach, seed):
+    """The diagonal plus two columns per row drawn within `reach` of it (or
+    anywhere when reach is None): every row 3 long, so the copy by rows is
+    cheap, but a slice's rows share few diagonals."""
+    import scipy.sparse as sp
+
+    g = P.rng(seed, 2)
+    r = np.arange(n)
+    if reach is None:
+        c1, c2 = g.integers(0, n, n), g.integers(0, n, n)
+    else:
+        c1 = np.clip(r + g.integers(-reach, reach + 1, n), 0, n - 1)
+        c2 = np.clip(r + g.integers(-reach, reach + 1, n), 0, n - 1)
+    rr = np.concatenate([r, r, r])
+    cc = np.concatenate([r, c1, c2])
+    vv = np.concatenate([np.full(n, 8.0), np.full(n, -1.0), np.full(n, -1.0)])
+    A = sp.csr_matrix((vv, (rr, cc)), shape=(n, n))
+    rp, ci, va = P.csr_from_scipy(A)
+    name = f"scattered_{reach}"
+    return P.Problem(name, rp, ci, va, np.ones(n), np.zeros(n), None, 10, 0.0)
+
+
+def reversed_rows(p):
+    """The same matrix with each row's entries stored in decreasing column order."""
+    ci = p.col_idx.copy()
+    va = p.vals.copy()
+    for r in range(p.n):
+        a, b = p.row_ptr[r], p.row_ptr[r + 1]
+        ci[a:b] = ci[a:b][::-1]
+        va[a:b] = va[a:b][::-1]
+    return P.Problem(p.name + "_rev", p.row_ptr, ci, va, p.b, p.x0, p.x_true, p.m, p.rtol)
 
 
 def solver(p, m=10, scheme="mgs1r", fmt=None):
@@ -55,11 +106,14 @@ def test_format_choice():
     import scipy.sparse as sp
 
     cases = {
-        "convdiff2d": (P.make_config("convdiff2d"), "sell64_d16"),              # 5-point rows
-        "convdiff3d_24": (P.make_config("convdiff3d", N=24), "sell64_d16"),     # 7-point rows
-        "stencil27_12": (P.make_config("stencil27", N=12), "sell64_d16"),     # 27-point rows
-        "wide_band": (wide_band(), "sell64"),                       # col - row spread > 65535
+        "convdiff2d": (P.make_config("convdiff2d"), "sell64_diag"),             # 5-point rows
+        "convdiff3d_24": (P.make_config("convdiff3d", N=24), "sell64_diag"),    # 7-point rows
+        "stencil27_12": (P.make_config("stencil27", N=12), "sell64_diag"),      # 27-point rows
+        "wide_band": (wide_band(), "sell64_diag"),                  # 4 diagonals per slice
+        "near": (scattered(20_000, 1000, 1), "sell64_d16"),         # deltas span < 65536
+        "far": (scattered(140_000, None, 2), "sell64"),             # col - row spread > 65535
         "dense50": (P.random_dense(50, seed=3), "csr"),             # one slice, 14 padding rows
+        "convdiff2d_rev": (reversed_rows(P.make_config("convdiff2d", N=24)), "sell64_d16"),
     }
     A = sp.csr_matrix(sp.random(3000, 3000, density=0.003, random_state=4) + sp.identity(3000))
     rp, ci, va = P.csr_from_scipy(A)
@@ -68,29 +122,65 @@ def test_format_choice():
     for name, (p, want) in cases.items():
         s, _ = solver(p)
         fmt, stored = s.format()
-        log(f"format {name}: {fmt} stored={stored} nnz={p.nnz} padded={padded_entries(p)}")
+        log(f"format {name}: {fmt} stored={stored} nnz={p.nnz} padded={padded_entries(p)} "
+            f"diag={diag_entries(p)}")
         assert fmt == want, name
-        assert stored == (padded_entries(p) if fmt.startswith("sell") else p.nnz)
+        expect = {"sell64_diag": diag_entries, "sell64_d16": padded_entries,
+                  "sell64": padded_entries}.get(fmt, lambda q: q.nnz)(p)
+        assert stored == expect, name
         s.close()
-    # forced: int32 indices on a stencil; deltas where they do not fit fall back to int32
-    s, _ = solver(cases["convdiff2d"][0], fmt="sell")
-    assert s.format()[0] == "sell64"
-    s, _ = solver(cases["wide_band"][0], fmt="sell_d16")
-    assert s.format()[0] == "sell64"
-    s, _ = solver(cases["dense50"][0], fmt="sell_d16")
-    assert s.format()[0] == "sell64_d16"
+    # forced: int32 indices or deltas on a stencil; deltas where they do not fit
+    # fall back to int32; diagonals on unsorted rows fall back to deltas;
+    # diagonals and deltas whatever the padding
+    for name, fmt, want in [("convdiff2d", "sell", "sell64"), ("convdiff2d", "sell_d16", "sell64_d16"),
+                            ("wide_band", "sell_d16", "sell64"), ("dense50", "sell_d16", "sell64_d16"),
+                            ("convdiff2d_rev", "sell_diag", "sell64_d16"),
+                            ("dense50", "sell_diag", "sell64_diag"), ("far", "sell_diag", "sell64_diag")]:
+        s, _ = solver(cases[name][0], fmt=fmt)
+        got, stored = s.format()
+        assert got == want, (name, fmt)
+        if got == "sell64_diag":
+            assert stored == diag_entries(cases[name][0])
+        s.close()
+
+
+@pytest.mark.parametrize("name", ["convdiff3d", "stencil27", "wide_band", "far", "convdiff2d_rev"])
+def test_sliced_forms_bitwise(name):
+    """The sliced forms sum each row's products in the same order (padding adds
+    exact zeros), so a fixed-budget cycle gives the same bits in each, and the
+    oracle's iterate to 1e-10. Rows stored in decreasing column order keep that
+    order (the diagonal form is then refused and falls back to deltas)."""
+    p = {"convdiff3d": lambda: P.make_config("convdiff3d", N=20),
+         "stencil27": lambda: P.make_config("stencil27", N=14),
+         "wide_band": lambda: wide_band(n=70_000 + 3000, far=70_000),
+         "far": lambda: scattered(70_000, None, 5),
+         "convdiff2d_rev": lambda: reversed_rows(P.make_config("convdiff2d", N=30))}[name]()
+    log(f"forms {name} n={p.n}")
+    runs = {}
+    for fmt in ("sell", "sell_d16", "sell_diag"):
+        g = gpu_run(p, "mgs1r", m=12, rtol=0.0, max_iters=18, fmt=fmt)
+        runs[g["solver"].format()[0]] = g
+    o = oracle_run(p, "mgs1r", m=12, rtol=0.0, max_iters=18, dump=False)
+    ref = runs["sell64"]
+    for f, g in runs.items():
+        assert g["res"].iters == o.iters == 18, f
+        assert np.array_equal(g["x"], ref["x"]), f
+        assert rel(g["x"], o.x) <= 1e-10, f
 
 
 def test_wide_band_solve_matches_oracle():
-    """The int32 copy chosen for the wide band gives the oracle's cycle."""
+    """On the wide band (couplings 70,000 rows away), the copy by diagonals the
+    library picks and the int32 copy that deltas fall back to both give the
+    oracle's cycle."""
     p = wide_band(n=70_000 + 3000, far=70_000)
-    g = gpu_run(p, "mgs1r", m=10, rtol=0.0, max_iters=10)
-    assert g["solver"].format()[0] == "sell64"
     o = oracle_run(p, "mgs1r", m=10, rtol=0.0, max_iters=10)
-    assert rel(g["x"], o.x) <= 1e-10
+    for fmt, want in ((None, "sell64_diag"), ("sell_d16", "sell64")):
+        g = gpu_run(p, "mgs1r", m=10, rtol=0.0, max_iters=10, fmt=fmt)
+        assert g["solver"].format()[0] == want
+        assert rel(g["x"], o.x) <= 1e-10
 
 
-@pytest.mark.parametrize("fmt", ["csr", "sell", "sell_d16"])
+@pytest.mark.parametrize("fmt", ["csr", "sell", "sell_d16", "sell_diag"])
 def test_refresh_matrix(fmt):
     """Scale two rows' values in place: after refresh the solve is the one on the new matrix."""
     import torch
@@ -114,7 +204,7 @@ def test_refresh_matrix(fmt):
     assert rel(x.cpu().numpy(), o.x) <= 1e-10
 
 
-@pytest.mark.parametrize("fmt", ["sell", "sell_d16"])
+@pytest.mark.parametrize("fmt", ["sell", "sell_d16", "sell_diag"])
 def test_refresh_refuses_bad_structure(fmt):
     import torch
 
@@ -144,13 +234,13 @@ def test_refresh_refuses_bad_structure(fmt):
     s.close()
 
 
-@pytest.mark.parametrize("fmt", ["sell", "sell_d16"])
+@pytest.mark.parametrize("fmt", ["sell", "sell_d16", "sell_diag"])
 @pytest.mark.parametrize("scheme", ["mgs1r", "cgs2"])
 def test_sell_small_and_one_row(scheme, fmt):
     """The sliced copy on sizes that leave most of the one slice as padding."""
     import scipy.sparse as sp
 
-    name = {"sell": "sell64", "sell_d16": "sell64_d16"}[fmt]
+    name = {"sell": "sell64", "sell_d16": "sell64_d16", "sell_diag": "sell64_diag"}[fmt]
     rp, ci, va = P.csr_from_scipy(sp.csr_matrix(np.array([[3.0]])))
     p = P.Problem("one", rp, ci, va, np.array([6.0]), np.zeros(1), np.array([2.0]), m=1, rtol=1e-12)
     g = gpu_run(p, scheme, fmt=fmt)
@@ -183,12 +273,11 @@ def test_storage_calls():
     try:
         rc, nb = native.gmres_matrix_storage_bytes(ctx)
         ns = (p.n + 63) // 64
-        total = padded_entries(p)
+        total = diag_entries(p)
         up = lambda v: (v + 255) // 256 * 256
-        # the default for a stencil: offsets, a base per slice column, 16-bit deltas, values
+        # the default for a stencil: offsets, a diagonal per slice column, values
         o_cb = up(8 * (ns + 1))
-        o_cd = up(o_cb + 4 * (total // 64))
-        o_va = up(o_cd + 2 * total)
+        o_va = up(o_cb + 4 * (total // 64))
         assert rc == native.GMRES_OK and nb == o_va + 8 * total
         assert native.gmres_get_format(ctx)[1] == native.GMRES_FORMAT_CSR
         buf = torch.empty(nb + 512, dtype=torch.uint8, device="cuda")
@@ -199,7 +288,7 @@ def test_storage_calls():
         assert native.gmres_set_matrix_storage(ctx, host.ctypes.data, nb) == native.GMRES_ERR_ARG
         assert native.gmres_set_matrix_storage(ctx, bp, nb) == native.GMRES_OK
         rc, fmt, stored = native.gmres_get_format(ctx)
-        assert fmt == native.GMRES_FORMAT_SELL64_D16 and stored == total
+        assert fmt == native.GMRES_FORMAT_SELL64_DIAG and stored == total
         # the copy gives the same product as the CSR arrays
         x = torch.from_numpy(P.rng(5, 1).standard_normal(p.n)).cuda()
         y1 = torch.empty_like(x)
@@ -217,8 +306,10 @@ def test_storage_calls():
         native.gmres_destroy(ctx)
 
 
-def test_storage_layout_int32_indices():
-    """With the int32 copy forced through the options: offsets, indices, values."""
+@pytest.mark.parametrize("form", ["sell", "sell_d16"])
+def test_storage_layout_by_rows(form):
+    """With the copy by rows forced through the options: offsets, then int32
+    indices, or a base per slice column and 16-bit deltas; then values."""
     import torch
 
     from paper_1809_05805_amd import native
@@ -226,7 +317,7 @@ def test_storage_layout_int32_indices():
     p = P.make_config("convdiff2d", N=33)
     rp, ci, va = (torch.from_numpy(a).cuda() for a in (p.row_ptr, p.col_idx, p.vals))
     m = 10
-    opt = native.make_options(format="sell")
+    opt = native.make_options(format=form)
     need = native.gmres_workspace_bytes_ex(p.n, m, native.GMRES_MGS_1R, opt)
     ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
     wp = ws.data_ptr() + (-ws.data_ptr()) % 256
@@ -239,13 +330,16 @@ def test_storage_layout_int32_indices():
         ns = (p.n + 63) // 64
         total = padded_entries(p)
         up = lambda v: (v + 255) // 256 * 256
-        o_ci = up(8 * (ns + 1))
-        o_va = up(o_ci + 4 * total)
+        if form == "sell":
+            o_va = up(up(8 * (ns + 1)) + 4 * total)
+        else:
+            o_va = up(up(up(8 * (ns + 1)) + 4 * (total // 64)) + 2 * total)
         assert rc == native.GMRES_OK and nb == o_va + 8 * total
         buf = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
         bp = buf.data_ptr() + (-buf.data_ptr()) % 256
         assert native.gmres_set_matrix_storage(ctx, bp, nb) == native.GMRES_OK
         rc, fmt, stored = native.gmres_get_format(ctx)
-        assert fmt == native.GMRES_FORMAT_SELL64 and stored == total
+        want = native.GMRES_FORMAT_SELL64 if form == "sell" else native.GMRES_FORMAT_SELL64_D16
+        assert fmt == want and stored == total
     finally:
         native.gmres_destroy(ctx)

@@ -36,6 +36,34 @@ def test_every_declared_symbol_is_exported(lib):
         assert isinstance(getattr(lib, name), ctypes._CFuncPtr), name
 
 
+def declared_constants():
+    """Every GMRES_* enumerator of include/gmres.h with its value."""
+    src = open(os.path.join(ROOT, "include", "gmres.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for body in re.findall(r"enum\s*\w*\s*\{(.*?)\}", src, flags=re.S):
+        for name, val in re.findall(r"\b(GMRES_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            out[name] = int(val)
+    return out
+
+
+def test_binding_constants_match_header():
+    """The binding's copies of the header's enumerators (formats, options,
+    schemes, statuses, batch load forms) carry the header's values."""
+    consts = declared_constants()
+    assert "GMRES_FORMAT_SELL64_DIAG" in consts and "GMRES_OPT_FORMAT_SELL64_DIAG" in consts
+    checked = 0
+    for name, val in consts.items():
+        if hasattr(native, name):
+            assert getattr(native, name) == val, name
+            checked += 1
+    assert checked >= 10
+    for prefix in ("GMRES_FORMAT_", "GMRES_OPT_FORMAT_"):
+        for name in consts:
+            if name.startswith(prefix):
+                assert hasattr(native, name), name
+
+
 def test_workspace_sizing(lib):
     assert native.gmres_workspace_bytes(0, 30, 1) == 0
     assert native.gmres_workspace_bytes(100, 0, 1) == 0
@@ -127,12 +155,12 @@ def test_options_sizing_and_refusals(lib):
     # one row per lane: 8x the tiles of the default 8 rows per lane at 128^3
     one = native.gmres_workspace_bytes_ex(n, m, native.GMRES_MGS_1R, native.make_options(rows_per_lane=1))
     assert one > base
-    ok = [dict(format="csr"), dict(format="sell"), dict(format="sell_d16"), dict(rows_per_lane=2),
-          dict(csr_spmv_shape=804),
+    ok = [dict(format="csr"), dict(format="sell"), dict(format="sell_d16"), dict(format="sell_diag"),
+          dict(rows_per_lane=2), dict(csr_spmv_shape=804),
           dict(split_spmv=True), dict(pipeline_depth=2), dict(pipeline_depth=1)]
     for kw in ok:
         assert native.gmres_workspace_bytes_ex(4096, 30, native.GMRES_MGS_1R, native.make_options(**kw)) > 0, kw
-    bad = [dict(format=4), dict(format=-1), dict(rows_per_lane=3), dict(rows_per_lane=16), dict(csr_spmv_shape=107),
+    bad = [dict(format=5), dict(format=-1), dict(rows_per_lane=3), dict(rows_per_lane=16), dict(csr_spmv_shape=107),
            dict(pipeline_depth=-1), dict(pipeline_depth=native.GMRES_MAX_RESTART + 1)]
     for kw in bad:
         assert native.gmres_workspace_bytes_ex(4096, 30, native.GMRES_MGS_1R, native.make_options(**kw)) == 0, kw
