@@ -99,6 +99,11 @@ def _load(acc: str = "double"):
                                                  ctypes.POINTER(_Info), P, P, P, P, P, P, P]
         lib.oracle_spmv.restype = None
         lib.oracle_spmv.argtypes = [ctypes.c_int64, P, P, P, P, P]
+        lib.oracle_cgs_two_passes.restype = None
+        lib.oracle_cgs_two_passes.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P]
+        lib.oracle_cgs2_update.restype = None
+        lib.oracle_cgs2_update.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P,
+                                           ctypes.c_double, P, P, P, P, P]
         _libs[acc] = lib
     return _libs[acc]
 
@@ -169,6 +174,33 @@ def solve(row_ptr, col_idx, vals, b, x0, m: int, scheme: str = "mgs1r", rtol: fl
         res.g = g
         res.S2 = S2.T
     return res
+
+
+def cgs_two_passes(V, w):
+    """Alg 1's two CGS passes of w against the columns of V (n x (i+1)), as
+    the CGS-with-re-orthogonalization cycle runs them: (w after both passes,
+    the Hessenberg column = both passes' coefficients summed)."""
+    V = np.asfortranarray(V, dtype=np.float64)
+    n, c = V.shape
+    w = np.array(w, dtype=np.float64, copy=True)
+    hcol = np.zeros(c)
+    _load().oracle_cgs_two_passes(n, c - 1, _ptr(V), _ptr(w), _ptr(hcol))
+    return w, hcol
+
+
+def cgs2_update(V, L, r, rho, w):
+    """The lagged CGS2 update of one step (Alg 5), as its cycle runs it, for a
+    basis V (n x (k+1)) whose Gram matrix has strictly lower part L: (the new
+    column, h = (I - L) r, the second pass's s, the Hessenberg column h + s)."""
+    V = np.asfortranarray(V, dtype=np.float64)
+    n, c = V.shape
+    L = np.asfortranarray(np.tril(L, -1), dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    vnext, h, s, hcol = np.zeros(n), np.zeros(c), np.zeros(c), np.zeros(c)
+    _load().oracle_cgs2_update(n, c - 1, _ptr(V), _ptr(L), _ptr(r), float(rho), _ptr(w),
+                               _ptr(vnext), _ptr(h), _ptr(s), _ptr(hcol))
+    return vnext, h, s, hcol
 
 
 def omp_threads(n: int = 0) -> int:

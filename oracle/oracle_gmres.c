@@ -311,6 +311,78 @@ static int cycle_mgs(const csr_t* A, const double* b, double* x, int m_eff, doub
 }
 
 /*
+ * Alg 1's orthogonalization of a new column w against V[:,0:i+1] (columns
+ * of length n, ld = ldv), classical Gram-Schmidt run twice: each pass takes
+ * p = V^T w (one reduction), subtracts V p from w and adds p into the
+ * Hessenberg column hcol (which must hold zeros on entry), so hcol ends as
+ * the sum of both passes' coefficients and w = w_in - V hcol. p is scratch
+ * (i+1 doubles).
+ */
+static void cgs_two_passes(int64_t n, int i, const double* V, int64_t ldv, double* w,
+                           double* hcol, double* p) {
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = 0; q <= i; ++q) p[q] = dot(n, V + (size_t)q * (size_t)ldv, w);
+    for (int q = 0; q <= i; ++q) {
+      const double* vq = V + (size_t)q * (size_t)ldv;
+      double sq = p[q];
+      ORACLE_ROWS
+      for (int64_t e = 0; e < n; ++e) w[e] = w[e] - vq[e] * sq;
+      hcol[q] = hcol[q] + sq;
+    }
+  }
+}
+
+/*
+ * The lagged CGS2 update of step k (Alg 5 under reading 8), given the step's
+ * first-pass coefficients r = V[:,0:k+1]^T (w / rho) and the strictly lower
+ * L of V^T V = I + L + L^T on the leading (k+1) x (k+1) block (entry (a, q),
+ * a > q, at L[q * ldl + a]):
+ *   h = (I - L) r (the first-order correction, the uncorrected r on the right),
+ *   z = w / rho - V h, s = V^T z (the second reduction), vnext = z - V s,
+ *   hcol = h + s, the Hessenberg column.
+ * V has columns of length n, ld = ldv; h, s and hcol hold k+1 doubles.
+ */
+static void cgs2_update(int64_t n, int k, const double* V, int64_t ldv, const double* L,
+                        int64_t ldl, const double* r, double rho, const double* w,
+                        double* vnext, double* h, double* s, double* hcol) {
+  for (int i = k; i >= 0; --i) {
+    double a = r[i];
+    for (int q = 0; q < i; ++q) a -= L[(size_t)q * (size_t)ldl + (size_t)i] * r[q];
+    h[i] = a;
+  }
+  ORACLE_ROWS
+  for (int64_t e = 0; e < n; ++e) vnext[e] = w[e] / rho;
+  for (int q = 0; q <= k; ++q) {
+    const double* vq = V + (size_t)q * (size_t)ldv;
+    double hq = h[q];
+    ORACLE_ROWS
+    for (int64_t e = 0; e < n; ++e) vnext[e] = vnext[e] - vq[e] * hq;
+  }
+  for (int q = 0; q <= k; ++q) s[q] = dot(n, V + (size_t)q * (size_t)ldv, vnext);
+  for (int q = 0; q <= k; ++q) {
+    const double* vq = V + (size_t)q * (size_t)ldv;
+    double sq = s[q];
+    ORACLE_ROWS
+    for (int64_t e = 0; e < n; ++e) vnext[e] = vnext[e] - vq[e] * sq;
+  }
+  for (int q = 0; q <= k; ++q) hcol[q] = h[q] + s[q];
+}
+
+void oracle_cgs_two_passes(int64_t n, int32_t i, const double* V, double* w, double* hcol) {
+  double* p = (double*)malloc(sizeof(double) * (size_t)(i + 1));
+  if (!p) return;
+  for (int q = 0; q <= i; ++q) hcol[q] = 0.0;
+  cgs_two_passes(n, i, V, n, w, hcol, p);
+  free(p);
+}
+
+void oracle_cgs2_update(int64_t n, int32_t k, const double* V, const double* L, const double* r,
+                        double rho, const double* w, double* vnext, double* h, double* s,
+                        double* hcol) {
+  cgs2_update(n, k, V, n, L, k + 1, r, rho, w, vnext, h, s, hcol);
+}
+
+/*
  * Classical Gram-Schmidt cycles on a normalized basis, as in the level-1
  * listing: V[:,0] = r0 / ||r0||, and step i orthogonalizes w = A v_i against
  * V[:,0:i+1] with every coefficient taken from the same vector (classical),
@@ -329,14 +401,16 @@ static int cycle_mgs(const csr_t* A, const double* b, double* x, int m_eff, doub
  *   the listing's update step, which prints a - Q Q^T a: the update uses the
  *   corrected coefficients r, which is what the T derivation before it
  *   produces.)
- * Parity unpinned for one detail of ORACLE_CGS2_3R: the second pass's
- * coefficients s are O(eps) relative to the first pass's once V is
- * orthonormal to working precision, so adding them into H (r += s) changes H
- * only at the rounding level and no output distinguishes it from leaving them
- * out. Everything else in both schemes is pinned (same H as MGS, Krylov
- * minimizer, dense LU, orthogonality bounds that fail without the
- * re-orthogonalization or without either half of the T correction, reductions
- * per step).
+ * Within a cycle, where V is orthonormal to working precision, the second
+ * pass's coefficients s of ORACLE_CGS2_3R are O(eps) relative to the first
+ * pass's, so adding them into H (r += s) shows only at the rounding level; the
+ * pass itself (cgs_two_passes) is therefore also exposed as
+ * oracle_cgs_two_passes and pinned on a basis whose Gram matrix is I + E with
+ * E of size delta, where the projection coefficients G^{-1} V^T w must be met
+ * to O(delta^2), which one pass's coefficients miss by O(delta). The rest of
+ * both schemes is pinned on whole cycles (same H as MGS, Krylov minimizer,
+ * dense LU, orthogonality bounds that fail without the re-orthogonalization
+ * or without either half of the T correction, reductions per step).
  */
 static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, double tol_abs,
                      double bnorm, int scheme, ws_t* ws, double* hist, int64_t it0,
@@ -363,17 +437,8 @@ static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, doub
     double* w = VC(ws, i + 1);
     spmv(A, VC(ws, i), w);
     if (scheme == ORACLE_CGS2_3R) {
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int q = 0; q <= i; ++q) ws->p[q] = dot(n, VC(ws, q), w);
-        (*nred)++;
-        for (int q = 0; q <= i; ++q) {
-          const double* vq = VC(ws, q);
-          double sq = ws->p[q];
-          ORACLE_ROWS
-          for (int64_t e = 0; e < n; ++e) w[e] = w[e] - vq[e] * sq;
-          HH(ws, q, i) = HH(ws, q, i) + sq;
-        }
-      }
+      cgs_two_passes(n, i, ws->V, n, w, &HH(ws, 0, i), ws->p);
+      (*nred) += 2;
     } else {
       for (int q = 0; q <= i; ++q) ws->c[q] = dot(n, VC(ws, q), w);
       for (int q = 0; q < i; ++q) LL(ws, i, q) = dot(n, VC(ws, q), VC(ws, i));
@@ -436,10 +501,13 @@ static int cycle_cgs(const csr_t* A, const double* b, double* x, int m_eff, doub
  *   coefficients (Ruhe's loop invariant, Section II); V[:,k+1] = w/rho - V h.
  * CGS2: r <- (I - L) r (the first-order truncation of the same correction),
  *   z = w/rho - V r, second reduction s = V^T z, V[:,k+1] = z - V s, h = r + s.
- *   Parity unpinned for two details of this baseline: once the second pass
- *   keeps L at O(eps), both the (I - L) correction and the s term of h change
- *   H only at the rounding level, so no output distinguishes them from their
- *   absence (or from a sign error in the correction).
+ *   Within a cycle the second pass keeps L at O(eps), so the (I - L)
+ *   correction and the s term of h show only at the rounding level; the
+ *   update (cgs2_update) is therefore also exposed as oracle_cgs2_update and
+ *   pinned on a basis with L of size delta, where s must equal -L^T r to
+ *   O(delta^2) (without the correction it is -(L + L^T) r, with its sign
+ *   flipped -(2L + L^T) r) and the column h + s must reach the projection
+ *   coefficients to O(delta^2) with w / rho = V (h + s) + vnext exactly.
  *
  * Pipeline depth (the depth-L pipeline of Section III, shown there for L = 2):
  * the Givens rotations, and with them the stopping test, only consume
@@ -556,30 +624,10 @@ static int cycle_lagged(const csr_t* A, const double* b, double* x, int m_eff, d
       }
       for (int q = 0; q <= k; ++q) HH(ws, q, k) = ws->h[q];
     } else {
-      /* r <- (I - L) r, using the uncorrected r on the right-hand side */
-      for (int i = k; i >= 0; --i) {
-        double s = ws->r[i];
-        for (int q = 0; q < i; ++q) s -= LL(ws, i, q) * ws->r[q];
-        ws->h[i] = s;
-      }
-      ORACLE_ROWS
-      for (int64_t e = 0; e < n; ++e) vnext[e] = ws->w[e] / rho;
-      for (int q = 0; q <= k; ++q) {
-        const double* vq = VC(ws, q);
-        double hq = ws->h[q];
-        ORACLE_ROWS
-        for (int64_t e = 0; e < n; ++e) vnext[e] = vnext[e] - vq[e] * hq;
-      }
-      /* second reduction: s = V[:,0:k+1]^T z, then z = z - V s */
-      for (int q = 0; q <= k; ++q) ws->y[q] = dot(n, VC(ws, q), vnext);
+      /* the correction, the second reduction and the new column */
+      cgs2_update(n, k, ws->V, n, ws->L, ws->ldt, ws->r, rho, ws->w, vnext, ws->h, ws->y,
+                  &HH(ws, 0, k));
       (*nred)++;
-      for (int q = 0; q <= k; ++q) {
-        const double* vq = VC(ws, q);
-        double sq = ws->y[q];
-        ORACLE_ROWS
-        for (int64_t e = 0; e < n; ++e) vnext[e] = vnext[e] - vq[e] * sq;
-      }
-      for (int q = 0; q <= k; ++q) HH(ws, q, k) = ws->h[q] + ws->y[q];
       for (int q = 0; q <= k; ++q) ws->S2[(size_t)k * (size_t)ws->ldh + (size_t)q] = ws->y[q];
     }
     for (int q = 0; q <= k; ++q)

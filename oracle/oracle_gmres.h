@@ -92,6 +92,26 @@ int oracle_gmres_solve_depth(int64_t n, int64_t nnz, const int32_t* row_ptr,
                              double* V_out, double* H_out, double* T_out, double* g_out,
                              double* S2_out, int32_t* j_out);
 
+/*
+ * The column updates of two baselines, the very code their cycles run,
+ * exposed so that tests can drive them with a basis that is not orthonormal
+ * (where the terms they exist for act at first order). V: n x (k+1) (or
+ * i+1), column-major, ld = n.
+ *   oracle_cgs_two_passes: Alg 1's two classical Gram-Schmidt passes of w
+ *     against V[:,0:i+1]; w is updated in place, hcol (i+1) receives the sum
+ *     of both passes' coefficients.
+ *   oracle_cgs2_update: the lagged CGS2 update (Alg 5) of step k, given the
+ *     first-pass coefficients r (k+1), the strictly lower L of V^T V on the
+ *     leading (k+1) x (k+1) block (column-major, ld = k+1, entry (a, q) for
+ *     a > q), rho and the SpMV output w (n): vnext (n) the new column, h the
+ *     corrected coefficients (I - L) r, s the second pass's coefficients,
+ *     hcol = h + s the Hessenberg column (k+1 each).
+ */
+void oracle_cgs_two_passes(int64_t n, int32_t i, const double* V, double* w, double* hcol);
+void oracle_cgs2_update(int64_t n, int32_t k, const double* V, const double* L, const double* r,
+                        double rho, const double* w, double* vnext, double* h, double* s,
+                        double* hcol);
+
 /* y = A x, sequential sum over each row in CSR order. */
 void oracle_spmv(int64_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* vals,
                  const double* x, double* y);

@@ -3,7 +3,9 @@
 Each test checks the oracle against something other than itself: dense LU,
 the definition of the GMRES iterate as a Krylov least-squares minimizer, the
 Arnoldi relation, orthogonality bounds, exact special cases, the paper's
-printed Simonici behaviour (Section V-A), and Paige's S = I - T identity.
+printed Simonici behaviour (Section V-A), Paige's S = I - T identity, and the
+projection a CGS baseline's column update must reach on a basis that is not
+orthonormal.
 """
 
 import json
@@ -458,3 +460,88 @@ def test_openmp_timing_build_matches():
                      acc="openmp")
     assert b.converged and abs(a.iters - b.iters) <= 1
     assert np.linalg.norm(a.x - b.x) <= 1e-8 * np.linalg.norm(a.x)
+
+
+# ------------------------------- P11 the CGS baselines on a skewed basis
+# On an orthonormal basis the terms below act only at rounding level (the
+# second pass finds O(eps) to remove), so whole-cycle outputs cannot tell them
+# from their absence. Given a basis whose Gram matrix is G = I + E with E of
+# size delta (unit columns, E = L + L^T, L strictly lower), each acts at first
+# order, and the mathematics fixes what the update must return:
+#   - the coefficients of the orthogonal projection onto span(V) are
+#     h* = G^{-1} V^T z = (I - E + E^2 - ...) V^T z, so both schemes' Hessenberg
+#     column must match h* to O(delta^2) (one pass of classical Gram-Schmidt
+#     leaves an O(delta) error);
+#   - whatever a scheme subtracts from z it must also add into the Hessenberg
+#     column, so z = V hcol + (new column) holds to rounding;
+#   - the new column is orthogonal to V to O(delta^2);
+#   - for the lagged CGS2 (Alg 5), the corrected first-pass coefficients
+#     (I - L) r leave the second pass s = r - G (I - L) r = -L^T r + O(delta^2):
+#     without the correction s would be -(L + L^T) r, with its sign flipped
+#     -(2L + L^T) r, with L transposed -L r.
+
+
+def skewed_basis(n, c, delta, seed):
+    g = P.rng(41, seed)
+    Q, _ = np.linalg.qr(g.standard_normal((n, c)))
+    V = Q + delta * g.standard_normal((n, c)) / np.sqrt(n)
+    V /= np.linalg.norm(V, axis=0)
+    G = V.T @ V
+    return V, G, np.tril(G, -1)
+
+
+@pytest.mark.parametrize("delta", [3e-4, 3e-3])
+def test_p11_cgs2_update_on_skewed_basis(delta):
+    """Alg 5 step on a non-orthonormal basis: the (I - L) correction, its sign,
+    and the s term of the Hessenberg column each show at first order."""
+    n, c = 400, 9
+    V, G, L = skewed_basis(n, c, delta, 1)
+    e = np.linalg.norm(G - np.eye(c), 2)
+    g = P.rng(41, 2)
+    w, rho = g.standard_normal(n), 1.7
+    z = w / rho
+    r = V.T @ z
+    vnext, h, s, hcol = oracle.cgs2_update(V, L, r, rho, w)
+    hstar = np.linalg.solve(G, V.T @ z)
+    nr = np.linalg.norm(r)
+    assert np.linalg.norm(z - V @ hcol - vnext) <= 1e-13 * np.linalg.norm(z)
+    assert np.linalg.norm(hcol - hstar) <= 4 * e**2 * nr
+    assert np.linalg.norm(s + L.T @ r) <= 4 * e**2 * nr
+    assert np.linalg.norm(V.T @ vnext) <= 4 * e**2 * nr
+    # the bounds above leave the first-order terms far outside: what the
+    # mistakes would return misses them by an order of delta
+    for wrong in (-(L + L.T) @ r, -(2 * L + L.T) @ r, -L @ r):
+        assert np.linalg.norm(wrong + L.T @ r) > 20 * e**2 * nr
+    assert np.linalg.norm(h - hstar) > 20 * e**2 * nr
+
+
+def test_p11_cgs2_update_orthonormal_is_projection():
+    """On an orthonormal basis (L = 0) the update is the textbook projection:
+    hcol = V^T z and the new column z - V V^T z, with s at rounding level."""
+    n, c = 300, 6
+    V, G, L = skewed_basis(n, c, 0.0, 3)
+    w, rho = P.rng(41, 4).standard_normal(n), 0.6
+    z = w / rho
+    vnext, h, s, hcol = oracle.cgs2_update(V, np.zeros((c, c)), V.T @ z, rho, w)
+    assert np.linalg.norm(hcol - V.T @ z) <= 1e-13 * np.linalg.norm(z)
+    assert np.linalg.norm(vnext - (z - V @ (V.T @ z))) <= 1e-13 * np.linalg.norm(z)
+    assert np.linalg.norm(s) <= 1e-14 * np.linalg.norm(z)
+
+
+@pytest.mark.parametrize("delta", [3e-4, 3e-3])
+def test_p11_cgs_two_passes_on_skewed_basis(delta):
+    """Alg 1's re-orthogonalization on a non-orthonormal basis: the second
+    pass's coefficients must be added into H (r += s) to reach the projection
+    to O(delta^2), and everything subtracted from w is in H."""
+    n, c = 400, 9
+    V, G, L = skewed_basis(n, c, delta, 5)
+    e = np.linalg.norm(G - np.eye(c), 2)
+    w0 = P.rng(41, 6).standard_normal(n)
+    w2, hcol = oracle.cgs_two_passes(V, w0)
+    hstar = np.linalg.solve(G, V.T @ w0)
+    nh = np.linalg.norm(V.T @ w0)
+    assert np.linalg.norm(w0 - V @ hcol - w2) <= 1e-13 * np.linalg.norm(w0)
+    assert np.linalg.norm(hcol - hstar) <= 4 * e**2 * nh
+    assert np.linalg.norm(V.T @ w2) <= 4 * e**2 * nh
+    # one pass's coefficients alone are an O(delta) step away
+    assert np.linalg.norm(V.T @ w0 - hstar) > 20 * e**2 * nh
