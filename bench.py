@@ -511,6 +511,7 @@ def batch_result(args, dim=2):
                     "worst_rel_res_true_fp64_recomputed": float(res.max()),
                     "algorithmic_GBps": round(nbytes / dt / 1e9, 1),
                     "config": cfg,
+                    "spmv_format": s.format()[0],
                     "autotune_trials": [{"block_size": t[0], "grid": t[1],
                                          "order": "largest_first" if t[2] else "natural",
                                          "part_rows": t[4], "streamed": bool(t[5]),

@@ -451,6 +451,27 @@ int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, 
 /* Release the context and any captured graph (host resources only). */
 int gmres_batch_destroy(gmres_batch* bt);
 
+/*
+ * The batch's copy of A by diagonals (the form gmres_matrix_storage_bytes
+ * describes, over the whole block-diagonal matrix: 64-row slices of global
+ * rows, which may straddle two systems; a slice column per distinct col - row
+ * value among the slice's rows; float64 values). gmres_batch_create plans it
+ * when every row's columns are strictly increasing and it adds at most a
+ * quarter to nnz (stencil systems); *bytes is 0 otherwise.
+ * gmres_batch_set_matrix_storage builds it in a caller-owned device buffer of
+ * at least that size (256-byte aligned, untouched while in use) and blocks
+ * until done; from then on the batched SpMV reads it instead of the CSR
+ * arrays (each row's products are accumulated in the same order, by fused
+ * multiply-adds, in both forms, so the results are the same bits). storage ==
+ * NULL goes back to the CSR arrays. Either call discards a captured graph.
+ * GMRES_ERR_ARG if no copy is planned, the buffer is too small, misaligned or
+ * not device memory, or the structure no longer fits the plan.
+ */
+int gmres_batch_matrix_storage_bytes(gmres_batch* bt, size_t* bytes /* host */);
+int gmres_batch_set_matrix_storage(gmres_batch* bt, void* storage, size_t bytes);
+/* GMRES_FORMAT_CSR or GMRES_FORMAT_SELL64_DIAG, and the entries the SpMV reads. */
+int gmres_batch_get_format(gmres_batch* bt, int32_t* format, int64_t* stored_entries);
+
 /* Change the stream later work is enqueued on. */
 int gmres_batch_set_stream(gmres_batch* bt, void* hip_stream);
 

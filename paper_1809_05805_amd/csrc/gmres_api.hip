@@ -89,8 +89,6 @@ int pick_spmv_shape(int64_t n, int64_t nnz, int want) {
 // deltas where they fit, or the copy by diagonals where the rows are sorted
 // (else with deltas where they fit), whatever the padding (the width and row
 // limits still hold).
-constexpr int kSellMaxWidth = 4096;
-constexpr int64_t kSellMaxRows = (int64_t)1 << 28;  // gathers use 32-bit byte offsets
 enum { kFormatCsr = 0, kFormatSell = 1 };
 
 // The caller's options, checked; zero fields take the library's choices.

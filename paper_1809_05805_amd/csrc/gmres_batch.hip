@@ -138,6 +138,8 @@ struct gmres_batch {
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
   std::vector<int64_t> sizes;
+  std::vector<int64_t> sell_sp;  // planned slice offsets of the copy by diagonals (empty: none)
+  size_t sell_bytes, o_cb, o_va; // its size and layout
 };
 
 namespace {
@@ -149,6 +151,42 @@ void drop_graph(gmres_batch* bt) {
   if (bt->graph) (void)hipGraphDestroy(bt->graph);
   bt->graph_exec = nullptr;
   bt->graph = nullptr;
+}
+
+// Plan the copy of the block-diagonal matrix by diagonals (64-row slices of
+// global rows, a slice column per distinct col - row value among a slice's
+// rows; the layout of the single-system copy): when every row's columns are
+// strictly increasing and it costs at most a quarter more entries than nnz.
+// The slice widths are counted on the device in the basis region of the
+// workspace, which holds nothing before the first solve.
+int plan_diag(gmres_batch* bt) {
+  bt->sell_sp.clear();
+  bt->sell_bytes = bt->o_cb = bt->o_va = 0;
+  const Csr& A = bt->B.A;
+  if (A.nnz == 0 || A.n >= kSellMaxRows) return GMRES_OK;
+  const int64_t ns = (A.n + 63) / 64;
+  int* dd = (int*)bt->B.Vb;  // 2 (ns + 1) ints: far less than the basis region
+  std::vector<int> dh((size_t)ns + 1);
+  hipStream_t s = bt->stream;
+  if (hipMemsetAsync(dd + ns, 0, sizeof(int), s) != hipSuccess ||
+      launch_sell_diags(A, ns, dd, dd + ns, kSellMaxWidth, s) ||
+      hipMemcpyAsync(dh.data(), dd, sizeof(int) * (size_t)(ns + 1), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GMRES_ERR_HIP;
+  if (dh[(size_t)ns] != 0) return GMRES_OK;
+  std::vector<int64_t> sp((size_t)ns + 1, 0);
+  for (int64_t i = 0; i < ns; ++i) {
+    if (dh[(size_t)i] > kSellMaxWidth) return GMRES_OK;
+    sp[(size_t)i + 1] = sp[(size_t)i] + 64 * (int64_t)dh[(size_t)i];
+  }
+  const int64_t total = sp[(size_t)ns];
+  if (total * 4 > A.nnz * 5) return GMRES_OK;
+  bt->sell_sp.swap(sp);
+  bt->o_cb = round_up(sizeof(int64_t) * (size_t)(ns + 1), kAlign);
+  bt->o_va = round_up(bt->o_cb + sizeof(int) * (size_t)(total / 64), kAlign);
+  bt->sell_bytes = bt->o_va + sizeof(double) * (size_t)total;
+  return GMRES_OK;
 }
 
 // Team sizes, queue order and grid for a configuration; uploads the queue
@@ -303,6 +341,7 @@ int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, 
        hipStreamSynchronize(s) != hipSuccess))
     rc = GMRES_ERR_HIP;
   if (rc == GMRES_OK && st0.bad_csr) rc = GMRES_ERR_ARG;
+  if (rc == GMRES_OK) rc = plan_diag(bt);
   if (rc == GMRES_OK)
     rc = apply_config(bt, 256, 0, GMRES_BATCH_ORDER_LARGEST_FIRST, kDefaultPartRows);
   if (rc != GMRES_OK) {
@@ -310,6 +349,53 @@ int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, 
     return rc;
   }
   *out = bt;
+  return GMRES_OK;
+}
+
+int gmres_batch_matrix_storage_bytes(gmres_batch* bt, size_t* bytes) {
+  if (!bt || !bytes) return GMRES_ERR_ARG;
+  *bytes = bt->sell_bytes;
+  return GMRES_OK;
+}
+
+int gmres_batch_set_matrix_storage(gmres_batch* bt, void* storage, size_t bytes) {
+  if (!bt) return GMRES_ERR_ARG;
+  drop_graph(bt);  // a captured graph holds the matrix form it was captured with
+  if (!storage) {
+    bt->B.S = Sell{};
+    return GMRES_OK;
+  }
+  if (bt->sell_bytes == 0 || bytes < bt->sell_bytes || ((uintptr_t)storage % kAlign) != 0 ||
+      !is_device_ptr(storage))
+    return GMRES_ERR_ARG;
+  char* base = (char*)storage;
+  const int64_t ns = (int64_t)bt->sell_sp.size() - 1;
+  Sell S{};
+  S.sp = (const int64_t*)base;
+  S.cbase = (int*)(base + bt->o_cb);
+  S.va = (double*)(base + bt->o_va);
+  S.ns = ns;
+  S.n = bt->n;
+  S.sf = kSfDiag;
+  DevState st0;
+  hipStream_t s = bt->stream;
+  if (hipMemcpyAsync(base, bt->sell_sp.data(), sizeof(int64_t) * (size_t)(ns + 1),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemsetAsync(&bt->B.st->bad_csr, 0, sizeof(int32_t), s) != hipSuccess ||
+      launch_sell_fill(bt->B.A, S, bt->B.st, s) ||
+      hipMemcpyAsync(&st0, bt->B.st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GMRES_ERR_HIP;
+  if (st0.bad_csr) return GMRES_ERR_ARG;
+  bt->B.S = S;
+  return GMRES_OK;
+}
+
+int gmres_batch_get_format(gmres_batch* bt, int32_t* format, int64_t* stored_entries) {
+  if (!bt || !format || !stored_entries) return GMRES_ERR_ARG;
+  const bool diag = bt->B.S.va != nullptr;
+  *format = diag ? GMRES_FORMAT_SELL64_DIAG : GMRES_FORMAT_CSR;
+  *stored_entries = diag ? bt->sell_sp.back() : bt->B.A.nnz;
   return GMRES_OK;
 }
 

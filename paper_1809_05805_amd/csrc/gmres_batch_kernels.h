@@ -216,7 +216,39 @@ __device__ inline double batch_row(const int* __restrict__ rp, const int* __rest
       v = coh_ld(&at(x, c));
     else
       v = at(x, c);
-    a += va[e] * (double)v;
+    a = __builtin_fma(va[e], (double)v, a);
+  }
+  return a;
+}
+
+// The same row from the copy of the whole block-diagonal matrix by
+// diagonals (64-row slices of global rows, which may straddle two systems):
+// global row R = r0 + r lies in slice R / 64 at lane R % 64, and slice column
+// j holds its entry on diagonal d_j (0 where it has none). The column r + d_j
+// is clamped into the system's nloc rows, so a padding entry (value 0) never
+// leaves them; the products are accumulated by fused multiply-adds in the
+// diagonals' increasing order, which is the CSR order of a sorted row, so
+// both forms give the same bits.
+template <typename XT>
+__device__ inline double batch_row_diag(const Sell& S, int64_t r0, uint32_t r, uint32_t nloc,
+                                        const XT* __restrict__ x, bool COH, uint32_t lo,
+                                        uint32_t hi) {
+  const int64_t R = r0 + r;
+  const int64_t sl = R >> 6;
+  const int64_t b = S.sp[sl];
+  const int W = (int)((S.sp[sl + 1] - b) >> 6);
+  const double* __restrict__ va = S.va + b + (R & 63);
+  const int* __restrict__ cb = S.cbase + (b >> 6);
+  double a = 0.0;
+  for (int j = 0; j < W; ++j) {
+    uint32_t c = (uint32_t)((int)r + cb[j]);
+    c = c < nloc ? c : nloc - 1;
+    XT v;
+    if (COH && (c < lo || c >= hi))
+      v = coh_ld(&at(x, c));
+    else
+      v = at(x, c);
+    a = __builtin_fma(va[(size_t)j * 64], (double)v, a);
   }
   return a;
 }
@@ -472,8 +504,10 @@ __device__ void batch_part(const Batch& B, const BatchTicket K, double* red, dou
   const int nblk = (int)((hi - lo + BS * RB - 1) / (BS * RB));
   const int* __restrict__ rp_s = B.A.rp + r0;
   // row r of this system's A times x (x indexed locally)
+  const bool diag = B.S.va != nullptr;
   auto row = [&](uint32_t r, const auto* __restrict__ xx) {
-    return batch_row(rp_s, B.A.ci, B.A.va, (int)r0, r, xx, coh, lo, hi);
+    return diag ? batch_row_diag(B.S, r0, r, (uint32_t)n, xx, coh, lo, hi)
+                : batch_row(rp_s, B.A.ci, B.A.va, (int)r0, r, xx, coh, lo, hi);
   };
   double* loc = vals + P;  // team_sum's LDS (NW + 2 doubles after vals)
 

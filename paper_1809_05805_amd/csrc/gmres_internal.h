@@ -94,6 +94,8 @@ struct Sell {
   int sf;             // SliceForm
 };
 constexpr int kSellDeltaSpan = 65535;  // largest col - row spread a slice column may have for cd
+constexpr int kSellMaxWidth = 4096;    // widest slice of a sliced copy
+constexpr int64_t kSellMaxRows = (int64_t)1 << 28;  // gathers use 32-bit byte offsets
 
 // Views into the caller's workspace.
 struct Ws {
@@ -169,6 +171,7 @@ struct Batch {
   double rtol;
   int64_t max_iters;
   uint32_t spin_limit;       // polls of a team barrier before the team gives up
+  Sell S;                    // the copy of A by diagonals (S.va null: the SpMV reads the CSR arrays)
 };
 
 // Doubles of one system's small workspace: H and R ((m+1) m each), T and TT

@@ -37,7 +37,8 @@ EXPORTED = ["gmres_workspace_bytes", "gmres_create", "gmres_solve", "gmres_destr
             "gmres_batch_autotune", "gmres_batch_capture", "gmres_batch_replay",
             "gmres_solve_noalloc", "gmres_options_init", "gmres_workspace_bytes_ex",
             "gmres_create_ex", "gmres_batch_set_wait_limit", "gmres_batch_set_loads",
-            "gmres_batch_get_loads"]
+            "gmres_batch_get_loads", "gmres_batch_matrix_storage_bytes",
+            "gmres_batch_set_matrix_storage", "gmres_batch_get_format"]
 GMRES_BATCH_ORDER_NATURAL, GMRES_BATCH_ORDER_LARGEST_FIRST = 0, 1
 GMRES_BATCH_LOADS_AUTO, GMRES_BATCH_LOADS_CACHED, GMRES_BATCH_LOADS_STREAMED = 0, 1, 2
 BATCH_LOADS = {"auto": 0, "cached": 1, "streamed": 2}
@@ -167,6 +168,9 @@ def load() -> ctypes.CDLL:
                        ("gmres_batch_capture", [P, P, P, D, I64]),
                        ("gmres_batch_set_loads", [P, I32]),
                        ("gmres_batch_get_loads", [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+                       ("gmres_batch_matrix_storage_bytes", [P, ctypes.POINTER(ctypes.c_size_t)]),
+                       ("gmres_batch_set_matrix_storage", [P, P, ctypes.c_size_t]),
+                       ("gmres_batch_get_format", [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]),
                        ("gmres_batch_replay", [P])):
         getattr(lib, name).restype = ctypes.c_int
         getattr(lib, name).argtypes = args
@@ -361,6 +365,22 @@ def gmres_batch_get_loads(ctx):
     return rc, a.value, b.value
 
 
+def gmres_batch_matrix_storage_bytes(ctx):
+    nb = ctypes.c_size_t(0)
+    rc = load().gmres_batch_matrix_storage_bytes(ctx, ctypes.byref(nb))
+    return rc, nb.value
+
+
+def gmres_batch_set_matrix_storage(ctx, ptr, nbytes: int) -> int:
+    return load().gmres_batch_set_matrix_storage(ctx, ptr, nbytes)
+
+
+def gmres_batch_get_format(ctx):
+    fmt, stored = ctypes.c_int32(), ctypes.c_int64()
+    rc = load().gmres_batch_get_format(ctx, ctypes.byref(fmt), ctypes.byref(stored))
+    return rc, fmt.value, stored.value
+
+
 def gmres_batch_capture(ctx, b_ptr, x_ptr, rtol, max_iters) -> int:
     return load().gmres_batch_capture(ctx, b_ptr, x_ptr, float(rtol), int(max_iters))
 
@@ -538,9 +558,12 @@ class BatchSolver:
     """A batch context over a block-diagonal CSR matrix on a GPU, workspace allocated with torch.
 
     row_off: host int64[nsys+1] system boundaries. scheme "mgs1r" or "mgs1r_ir32".
+    format: None or "auto" (the copy of A by diagonals when the library plans
+    one, in a torch buffer), or "csr" (always the CSR arrays).
     """
 
-    def __init__(self, row_off, row_ptr, col_idx, vals, m: int, scheme: str = "mgs1r", stream=None):
+    def __init__(self, row_off, row_ptr, col_idx, vals, m: int, scheme: str = "mgs1r", stream=None,
+                 format: str | None = None):
         import torch
 
         if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32 or vals.dtype != torch.float64:
@@ -569,6 +592,25 @@ class BatchSolver:
         if rc != GMRES_OK:
             raise GmresError(rc, "gmres_batch_create")
         self.ctx = ctx
+        self.storage = None
+        if format not in (None, "auto", "csr"):
+            raise ValueError(format)
+        rc, sbytes = gmres_batch_matrix_storage_bytes(ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_matrix_storage_bytes")
+        if sbytes and format != "csr":
+            self.storage = torch.empty(sbytes + 256, dtype=torch.uint8, device=self.device)
+            sp = self.storage.data_ptr() + (-self.storage.data_ptr()) % 256
+            rc = gmres_batch_set_matrix_storage(ctx, sp, sbytes)
+            if rc != GMRES_OK:
+                raise GmresError(rc, "gmres_batch_set_matrix_storage")
+
+    def format(self):
+        """("csr" | "sell64_diag", stored entries) of the batched SpMV."""
+        rc, fmt, stored = gmres_batch_get_format(self.ctx)
+        if rc != GMRES_OK:
+            raise GmresError(rc, "gmres_batch_get_format")
+        return FORMAT_NAMES[fmt], stored
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -10,7 +10,10 @@ float64 oracle within 10 kappa_est rtol (as for the single-system float32
 scheme). Systems split over a team of workgroups (parts of 256 rows here, so
 that the small systems form teams of up to 6) are held to the same bounds.
 Results must not depend on the grid or the queue order, and a captured graph
-must reproduce the eager solve bit for bit on every replay.
+must reproduce the eager solve bit for bit on every replay. The batched SpMV
+reads a copy of the block-diagonal matrix by diagonals when the library plans
+one (stencil systems, so by default here), else the CSR arrays; both forms
+accumulate each row's products in the same order and give the same bits.
 """
 
 import numpy as np
@@ -50,17 +53,19 @@ def tensors(bp):
             torch.from_numpy(bp.vals).cuda())
 
 
-def solver(bp, scheme="mgs1r", m=None, stream=None):
+def solver(bp, scheme="mgs1r", m=None, stream=None, fmt=None):
     from paper_1809_05805_amd.native import BatchSolver
 
     rp, ci, va = tensors(bp)
-    return BatchSolver(bp.row_off, rp, ci, va, bp.m if m is None else m, scheme, stream=stream)
+    return BatchSolver(bp.row_off, rp, ci, va, bp.m if m is None else m, scheme, stream=stream,
+                       format=fmt)
 
 
-def run(bp, scheme="mgs1r", rtol=TOL, max_iters=20000, b=None, x0=None, config=None, m=None):
+def run(bp, scheme="mgs1r", rtol=TOL, max_iters=20000, b=None, x0=None, config=None, m=None,
+        fmt=None):
     import torch
 
-    s = solver(bp, scheme, m)
+    s = solver(bp, scheme, m, fmt=fmt)
     if config:
         s.set_config(*config)
     bt = torch.from_numpy(np.ascontiguousarray(bp.b if b is None else b)).cuda()
@@ -504,3 +509,93 @@ def test_full_batch3d(scheme):
         if scheme == "mgs1r":
             assert abs(int(info["iters"][i]) - o.iters) <= 1
         assert rel(x[bp.row_off[i]: bp.row_off[i + 1]], o.x) <= 10 * 1e4 * TOL
+
+
+def batch_diag_entries(bp):
+    """Entries of the block-diagonal matrix's copy by diagonals: per 64-row
+    slice of global rows, 64 x max(1, distinct col - row)."""
+    n = int(bp.row_ptr.shape[0] - 1)
+    rows = np.repeat(np.arange(n), np.diff(bp.row_ptr))
+    d = bp.col_idx.astype(np.int64) - rows
+    ns = (n + 63) // 64
+    pairs = np.unique(np.stack([rows // 64, d]), axis=1)
+    return int(64 * np.maximum(np.bincount(pairs[0], minlength=ns), 1).sum())
+
+
+def test_batch_format_choice():
+    """Stencil systems get the copy by diagonals (its entry count as counted
+    here); format "csr" keeps the CSR arrays; rows stored out of column order
+    rule the copy out."""
+    import torch
+
+    from paper_1809_05805_amd.native import BatchSolver
+
+    bp = SMALL
+    log("batch format choice")
+    s = solver(bp)
+    fmt, stored = s.format()
+    assert fmt == "sell64_diag" and stored == batch_diag_entries(bp)
+    assert solver(bp, fmt="csr").format() == ("csr", int(bp.col_idx.shape[0]))
+    # reverse the entries of one row of system 3
+    ci, va = bp.col_idx.copy(), bp.vals.copy()
+    r = int(bp.row_off[3]) + 5
+    a, b = bp.row_ptr[r], bp.row_ptr[r + 1]
+    ci[a:b], va[a:b] = ci[a:b][::-1].copy(), va[a:b][::-1].copy()
+    t = BatchSolver(bp.row_off, torch.from_numpy(bp.row_ptr).cuda(), torch.from_numpy(ci).cuda(),
+                    torch.from_numpy(va).cuda(), bp.m)
+    assert t.format()[0] == "csr"
+
+
+@pytest.mark.parametrize("scheme,config", [("mgs1r", (256, 0, 1, 0)), ("mgs1r", (1024, 0, 1, 256)),
+                                           ("mgs1r_ir32", (512, 0, 1, 256))])
+def test_batch_formats_bitwise(scheme, config):
+    """The copy by diagonals and the CSR arrays give the same bits: iterates
+    and iteration counts of a whole batch solved to tolerance, with one-part
+    systems and with teams (whose parts gather across part boundaries)."""
+    log(f"batch formats {scheme} {config}")
+    outs = []
+    for fmt in ("csr", None):
+        rc, info, x, s = run(SMALL, scheme, config=config, fmt=fmt)
+        assert rc == 0 and np.all(info["converged"] == 1)
+        outs.append((x, info["iters"], s.format()[0]))
+    assert outs[0][2] == "csr" and outs[1][2] == "sell64_diag"
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+def test_batch_storage_calls():
+    """The raw entry points: the planned size, refusals, going back to the CSR
+    arrays, and a captured graph discarded by either call."""
+    import torch
+
+    from paper_1809_05805_amd import native
+
+    bp = SMALL
+    log("batch storage calls")
+    stream = torch.cuda.Stream()  # a graph is captured from a stream of its own
+    s = solver(bp, stream=stream, fmt="csr")
+    rc, nb = native.gmres_batch_matrix_storage_bytes(s.ctx)
+    total = batch_diag_entries(bp)
+    ns = (bp.n + 63) // 64
+    up = lambda v: (v + 255) // 256 * 256
+    assert rc == 0 and nb == up(up(8 * (ns + 1)) + 4 * (total // 64)) + 8 * total
+    buf = torch.empty(nb + 512, dtype=torch.uint8, device="cuda")
+    bp_ = buf.data_ptr() + (-buf.data_ptr()) % 256
+    assert native.gmres_batch_set_matrix_storage(s.ctx, bp_, nb - 8) == native.GMRES_ERR_ARG
+    assert native.gmres_batch_set_matrix_storage(s.ctx, bp_ + 8, nb) == native.GMRES_ERR_ARG
+    host = np.zeros(nb // 8 + 64)
+    assert native.gmres_batch_set_matrix_storage(s.ctx, host.ctypes.data, nb) == native.GMRES_ERR_ARG
+    assert s.format()[0] == "csr"
+    bt = torch.from_numpy(bp.b).cuda()
+    x = torch.zeros(bp.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    s.capture(bt, x, TOL, 20000)
+    assert native.gmres_batch_set_matrix_storage(s.ctx, bp_, nb) == native.GMRES_OK
+    assert native.gmres_batch_replay(s.ctx) == native.GMRES_ERR_ARG
+    assert s.format() == ("sell64_diag", total)
+    with torch.cuda.stream(stream):
+        rc, info = s.solve(bt, x, TOL, 20000)
+    torch.cuda.synchronize()
+    assert rc == 0 and np.all(info["converged"] == 1)
+    assert native.gmres_batch_set_matrix_storage(s.ctx, None, 0) == native.GMRES_OK
+    assert s.format()[0] == "csr"
