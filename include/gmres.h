@@ -440,7 +440,9 @@ size_t gmres_batch_workspace_bytes(int32_t nsys, const int64_t* row_off, int32_t
  * ws_bytes >= gmres_batch_workspace_bytes) to a new batch context. Checks the
  * CSR structure and that every column index of a system's rows lies in the
  * system's own range; GMRES_ERR_ARG otherwise. Blocks until the checks are
- * done. The initial configuration is 256-thread workgroups, as many as the
+ * done and the copy of the matrix by diagonals is planned (see
+ * gmres_batch_matrix_storage_bytes; until it is built the SpMV reads the CSR
+ * arrays). The initial configuration is 256-thread workgroups, as many as the
  * GPU holds at once, systems largest first, parts of 8192 rows.
  */
 int gmres_batch_create(gmres_batch** out, int32_t nsys, const int64_t* row_off, int64_t nnz,
