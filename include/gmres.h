@@ -263,10 +263,11 @@ int gmres_destroy(gmres_ctx* ctx);
 /*
  * Device bytes the context's sliced-ELL copy of A needs (0 when no copy is
  * planned and the SpMV reads the CSR arrays): ceil(n/64) + 1 int64 slice
- * offsets, then the column indices and the float64 values (float32 for the
- * refinement schemes) of every stored entry (64 per slice and slice column;
- * padding entries hold value 0), each part 256-byte aligned. The column
- * indices are
+ * offsets, then the column indices and the values of every stored entry (64
+ * per slice and slice column; padding entries hold value 0): float64, or for
+ * the refinement schemes float32 values (their inner cycles' SpMV) followed
+ * by float64 ones (their float64 restart residual); each part 256-byte
+ * aligned. The column indices are
  *   - by diagonals: one int32 diagonal d per slice column and nothing per
  *     entry: slice column j of row r holds A[r, r + d_j] (0 where A has no
  *     such entry, or r + d_j is outside [0, n)); a slice's diagonals

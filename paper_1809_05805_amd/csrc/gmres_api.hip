@@ -245,6 +245,7 @@ struct gmres_ctx {
   int sell_sf;                   // the planned copy's SliceForm
   size_t sell_bytes, o_ci, o_va; // planned storage size and its layout (o_ci: indices or deltas)
   size_t o_cb;                   // per-slice-column bases or diagonals (kSfD16, kSfDiag)
+  size_t o_va64;                 // the float64 values (after the float32 ones for the refinement schemes)
   Layout L;
   Ws ws;
   hipStream_t stream;
@@ -478,16 +479,34 @@ int plan_format(gmres_ctx* c) {
     c->o_ci = off_sp;
     c->o_va = round_up(c->o_ci + sizeof(int) * (size_t)total, kAlign);
   }
-  c->sell_bytes = c->o_va + vsize * (size_t)total;
+  // the refinement schemes keep float64 values too, for the float64 restart residual
+  c->o_va64 = ir_scheme(c->scheme) ? round_up(c->o_va + vsize * (size_t)total, kAlign) : c->o_va;
+  c->sell_bytes = c->o_va64 + sizeof(double) * (size_t)total;
   return GMRES_OK;
 }
 
-// y = A x or y = b - A x in float64: from the sliced copy when it holds
-// float64 values, else from the CSR arrays (the FP32-basis scheme's copy
-// holds float32 values, so its float64 products read the CSR arrays).
+// Fill the copy's values (both value arrays for the refinement schemes) and
+// column part; a row that does not fit sets st->bad_csr.
+int fill_copy(gmres_ctx* c, const Sell& S) {
+  if (S.vaf) {
+    Sell Sf = S;
+    Sf.va = nullptr;
+    if (launch_sell_fill(c->A, Sf, c->ws.st, c->stream)) return 1;
+  }
+  if (S.va) {
+    Sell Sd = S;
+    Sd.vaf = nullptr;
+    if (launch_sell_fill(c->A, Sd, c->ws.st, c->stream)) return 1;
+  }
+  return 0;
+}
+
+// y = A x or y = b - A x in float64: from the sliced copy's float64 values
+// (every scheme's copy has them; the refinement schemes' also has float32
+// ones for their inner cycles), else from the CSR arrays.
 int spmv(gmres_ctx* c, const double* x, const double* b, double* y, const DevState* st,
          hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  if (c->format == kFormatSell && !ir_scheme(c->scheme))
+  if (c->format == kFormatSell && c->sell.va)
     return launch_spmv_sell(c->sell, c->A.n, x, b, y, st, s, e0, e1);
   return launch_spmv(c->A, c->S, x, b, y, st, s, e0, e1);
 }
@@ -901,8 +920,7 @@ int gmres_refresh_matrix(gmres_ctx* c) {
   if (hipMemsetAsync(&c->ws.st->bad_csr, 0, sizeof(int32_t), c->stream) != hipSuccess ||
       launch_validate(c->A, c->nnz, c->ws.st, c->stream))
     return GMRES_ERR_HIP;
-  if (c->format == kFormatSell && launch_sell_fill(c->A, c->sell, c->ws.st, c->stream))
-    return GMRES_ERR_HIP;
+  if (c->format == kFormatSell && fill_copy(c, c->sell)) return GMRES_ERR_HIP;
   c->matrix_ok = false;
   const int rc = sync_state(c, false);
   if (rc != GMRES_OK) return rc;
@@ -936,14 +954,14 @@ int gmres_set_matrix_storage(gmres_ctx* c, void* storage, size_t bytes) {
   S.ci = S.sf == kSfI32 ? (int*)(base + c->o_ci) : nullptr;
   S.cd = S.sf == kSfD16 ? (uint16_t*)(base + c->o_ci) : nullptr;
   S.cbase = S.sf != kSfI32 ? (int*)(base + c->o_cb) : nullptr;
-  S.va = fv ? nullptr : (double*)(base + c->o_va);
+  S.va = (double*)(base + c->o_va64);
   S.vaf = fv ? (float*)(base + c->o_va) : nullptr;
   S.ns = ns;
   S.n = c->A.n;
   if (hipMemcpyAsync(base, c->sell_sp.data(), sizeof(int64_t) * (size_t)(ns + 1),
                      hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemsetAsync(&c->ws.st->bad_csr, 0, sizeof(int32_t), c->stream) != hipSuccess ||
-      launch_sell_fill(c->A, S, c->ws.st, c->stream))
+      fill_copy(c, S))
     return GMRES_ERR_HIP;
   const int rc = sync_state(c, false);  // also keeps the offsets' host copy alive until done
   if (rc != GMRES_OK) return rc;
