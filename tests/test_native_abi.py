@@ -208,3 +208,19 @@ def test_probe_library_exports_its_header():
     assert f(9, 16, 16, 1024, 1, 1, None, ctypes.byref(ms)) == -1
     assert f(0, 16, 16, 1000, 1, 1, None, ctypes.byref(ms)) == -1
     assert f(0, None, 16, 1024, 1, 1, None, ctypes.byref(ms)) == -1
+
+
+def test_column_stride_padding(lib):
+    """Basis columns are n rounded up to 64 apart, plus 17 x 64 = 1088 elements
+    when that is a multiple of 1024 (a large power-of-two stride). The float64
+    one-reduce workspace holds m + 2 basis columns and w at that stride, so
+    between n = 4032 and n = 4096 it grows by (m + 3) x (64 + 1088) x 8 bytes,
+    and between n = 4096 and n = 5120 (both padded) by (m + 3) x 1024 x 8, up
+    to the 256-byte rounding of each part."""
+    m = 16
+    f = lambda n: native.gmres_workspace_bytes(n, m, native.GMRES_MGS_1R)
+    cols = m + 3
+    slack = 16 * 256
+    assert abs((f(4032) - f(3968)) - cols * 64 * 8) <= slack
+    assert abs((f(4096) - f(4032)) - cols * (64 + 1088) * 8) <= slack
+    assert abs((f(5120) - f(4096)) - cols * 1024 * 8) <= slack
