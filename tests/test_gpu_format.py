@@ -343,3 +343,36 @@ def test_storage_layout_by_rows(form):
         assert fmt == want and stored == total
     finally:
         native.gmres_destroy(ctx)
+
+
+@pytest.mark.parametrize("scheme", ["mgs1r_ir32", "mgs1r_ir16"])
+def test_refinement_copy_float64_values(scheme):
+    """The refinement schemes' copy holds float32 values (their inner cycles)
+    followed by float64 values: its size is laid out so, and the float64
+    SpMV (gmres_spmv, the restart residual) reads the float64 values and gives
+    the CSR arrays' product to rounding."""
+    import torch
+
+    from paper_1809_05805_amd import native
+
+    p = P.make_config("convdiff2d", N=33)  # n = 1089: 18 slices, the last one ragged
+    s, _ = solver(p, scheme=scheme)
+    log(f"refinement copy {scheme}")
+    assert s.format()[0] == "sell64_diag"
+    rc, nb = native.gmres_matrix_storage_bytes(s.ctx)
+    ns, total = (p.n + 63) // 64, diag_entries(p)
+    up = lambda v: (v + 255) // 256 * 256
+    o_va = up(up(8 * (ns + 1)) + 4 * (total // 64))
+    assert rc == 0 and nb == up(o_va + 4 * total) + 8 * total
+    x = torch.from_numpy(P.rng(5, 2).standard_normal(p.n)).cuda()
+    y = torch.empty_like(x)
+    s.spmv(x, y)
+    c, _ = solver(p, scheme=scheme, fmt="csr")
+    y0 = torch.empty_like(x)
+    c.spmv(x, y0)
+    torch.cuda.synchronize()
+    absA = p.scipy().copy()
+    absA.data = np.abs(absA.data)
+    bound = 8 * np.finfo(float).eps * (absA @ np.abs(x.cpu().numpy()))
+    assert np.all(np.abs((y - y0).cpu().numpy()) <= bound)
+    assert np.abs(y.cpu().numpy() - p.scipy() @ x.cpu().numpy()).max() <= bound.max()
